@@ -1,0 +1,183 @@
+"""Seeded synthetic inputs shared by the oracle-side tests and the HIP path.
+
+This module holds no arithmetic of the method (no vector product, no iteration,
+no normalisation of iterates): it only draws matrices, start vectors and graphs
+from a seed, in the shapes and distributions of the paper's workloads.  Both the
+oracle and the HIP library receive the same bytes from here.
+
+Host draws use numpy's PCG64 (``numpy.random.default_rng(seed)``) in the draw
+order written in each docstring.  The large dense covariance can instead be
+drawn on a torch device (``device="cuda"``) with torch's seeded generator; the
+two sources give different, equally valid, matrices for one seed.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _rng(seed):
+    return np.random.default_rng(int(seed))
+
+
+# --------------------------------------------------------------------------
+# Dense symmetric covariance inputs
+# --------------------------------------------------------------------------
+def dense_cov(n, N, seed, device=None):
+    """C = X X^T / N as float32, X of shape n x N with i.i.d. N(0,1) entries, rows centred.
+
+    Draw order (host): X = rng.standard_normal((n, N)).  The product is formed in
+    float64 and rounded once to float32.  With ``device`` set, X is drawn by
+    torch.randn on that device from torch.Generator(device).manual_seed(seed) and
+    the float64 product is formed there; a torch tensor is returned.
+    """
+    if device is None:
+        X = _rng(seed).standard_normal((n, N))
+        X -= X.mean(axis=1, keepdims=True)
+        return ((X @ X.T) / N).astype(np.float32)
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    X = torch.randn((n, N), generator=g, device=device, dtype=torch.float32).double()
+    X -= X.mean(dim=1, keepdim=True)
+    C = (X @ X.T) / N
+    del X
+    out = C.float().contiguous()
+    del C
+    return out
+
+
+def start_vector(n, seed):
+    """b0 ~ U(-1, 1)^n scaled to unit l2 norm (Algorithm 1 starts from ||w0|| = 1), float32."""
+    b = _rng(seed).uniform(-1.0, 1.0, size=n)
+    b /= np.sqrt(np.sum(b * b))
+    return b.astype(np.float32)
+
+
+def start_vectors(n, k, seed):
+    """k start vectors as the columns of an n x k float32 array (column i from seed + i)."""
+    return np.stack([start_vector(n, seed + i) for i in range(k)], axis=1)
+
+
+def uniform_start(n):
+    """The uniform PageRank start vector 1/n (float32)."""
+    return np.full(n, 1.0 / n, dtype=np.float32)
+
+
+def dyadic_matrix(n_rows, n_cols, seed, denom_pow=3, max_num=16):
+    """Entries k / 2^denom_pow with integer k uniform in [-max_num, max_num].
+
+    Such values keep every sign, min and partial sum of a few thousand terms exact
+    in float32, so a product over them has one correct float32 answer.
+    """
+    k = _rng(seed).integers(-max_num, max_num + 1, size=(n_rows, n_cols))
+    return (k / float(2 ** denom_pow)).astype(np.float32)
+
+
+def dyadic_vector(n, seed, denom_pow=3, max_num=16):
+    return dyadic_matrix(1, n, seed, denom_pow, max_num)[0]
+
+
+def planted_symmetric(n, gaps, seed):
+    """Q diag(lam) Q^T (float32) with a random orthogonal Q and eigenvalues
+    lam = [1, 1-g1, 1-g1-g2, ...] followed by a bulk uniform in [0, lam_last/2].
+
+    Draw order: G = rng.standard_normal((n, n)); Q from numpy's QR of G;
+    bulk = rng.uniform(size=n - len(gaps) - 1).
+    """
+    rng = _rng(seed)
+    G = rng.standard_normal((n, n))
+    Q, R = np.linalg.qr(G)
+    Q = Q * np.sign(np.diag(R))[None, :]
+    lam = [1.0]
+    for g in gaps:
+        lam.append(lam[-1] - g)
+    bulk = rng.uniform(size=n - len(lam)) * lam[-1] * 0.5
+    d = np.concatenate([np.array(lam), np.sort(bulk)[::-1]])
+    return ((Q * d[None, :]) @ Q.T).astype(np.float32), Q, d
+
+
+# --------------------------------------------------------------------------
+# PCA data matrix (low-rank factors + noise + Laplace outliers)
+# --------------------------------------------------------------------------
+def pca_data(D, N, seed, n_factors=16, noise=0.1, outlier_frac=0.05, laplace_b=10.0,
+             decay=0.8, lead=2.0):
+    """X of shape D x N (columns are samples), float32, rows zero-meaned.
+
+    x_k = sum_f u_f z_fk + noise * e_k with u_f ~ N(0, I_D) and
+    z_fk ~ N(0, (lead * decay^(f-1))^2); then a fraction ``outlier_frac`` of the
+    entries is replaced by Laplace(0, laplace_b) draws; then every row is centred.
+    Draw order: U (D x F), Z (F x N), E (D x N), outlier mask (D x N uniform),
+    Laplace values (one per masked entry).
+    """
+    rng = _rng(seed)
+    U = rng.standard_normal((D, n_factors))
+    sd = lead * decay ** np.arange(n_factors)
+    Z = rng.standard_normal((n_factors, N)) * sd[:, None]
+    X = U @ Z
+    X += noise * rng.standard_normal((D, N))
+    mask = rng.uniform(size=(D, N)) < outlier_frac
+    X[mask] = rng.laplace(0.0, laplace_b, size=int(mask.sum()))
+    X -= X.mean(axis=1, keepdims=True)
+    return X.astype(np.float32)
+
+
+def pca_clean(D, N, seed, n_factors=16, decay=0.8, lead=2.0):
+    """The noise- and outlier-free low-rank part U Z of ``pca_data`` for the same seed,
+    centred, float64 (for the reconstruction-error report)."""
+    rng = _rng(seed)
+    U = rng.standard_normal((D, n_factors))
+    sd = lead * decay ** np.arange(n_factors)
+    Z = rng.standard_normal((n_factors, N)) * sd[:, None]
+    X = U @ Z
+    X -= X.mean(axis=1, keepdims=True)
+    return X
+
+
+# --------------------------------------------------------------------------
+# Power-law directed graphs, CSR by destination row
+# --------------------------------------------------------------------------
+def powerlaw_graph(n, seed, avg_deg=16.0, zipf_a=2.1, dangling_frac=0.05):
+    """Directed graph with Zipf out-degrees and uniform destinations, as column-stochastic CSR.
+
+    Draw order: z = rng.zipf(zipf_a, n); out-degree d_i = min(n-1, floor(z_i *
+    avg_deg / mean(z))); a set of round(dangling_frac * n) nodes drawn by
+    rng.choice(n, size, replace=False) gets d_i = 0; then, for all edges at once,
+    u = rng.integers(0, n-1, sum(d)) and destination = u + (u >= source) (uniform
+    over the other nodes).  Repeated (source, destination) pairs are merged.
+    Value H_ij = 1 / (distinct out-degree of j), rounded to float32.
+
+    Returns dict(n, row_ptr int32[n+1], col int32[nnz] (sources), val float32[nnz],
+    outdeg int32[n]); rows are destinations, columns within a row ascend.
+    """
+    rng = _rng(seed)
+    z = rng.zipf(zipf_a, n).astype(np.float64)
+    d = np.minimum(n - 1, np.floor(z * avg_deg / z.mean())).astype(np.int64)
+    n_dang = int(round(dangling_frac * n))
+    if n_dang:
+        d[rng.choice(n, size=n_dang, replace=False)] = 0
+    src = np.repeat(np.arange(n, dtype=np.int64), d)
+    u = rng.integers(0, n - 1, size=src.shape[0], dtype=np.int64) if n > 1 else np.zeros(0, np.int64)
+    dst = u + (u >= src)
+    key = np.unique(dst * n + src)
+    dst = key // n
+    src = key % n
+    outdeg = np.bincount(src, minlength=n)
+    val = (1.0 / outdeg[src]).astype(np.float32)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(dst, minlength=n), out=row_ptr[1:])
+    return dict(n=n, row_ptr=row_ptr.astype(np.int32), col=src.astype(np.int32),
+                val=val, outdeg=outdeg.astype(np.int32))
+
+
+def tiny_graph(edges, n):
+    """Column-stochastic CSR (by destination) of an explicit edge list [(src, dst), ...]."""
+    src = np.array([e[0] for e in edges], dtype=np.int64)
+    dst = np.array([e[1] for e in edges], dtype=np.int64)
+    key = np.unique(dst * n + src)
+    dst, src = key // n, key % n
+    outdeg = np.bincount(src, minlength=n)
+    val = (1.0 / outdeg[src]).astype(np.float32)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(dst, minlength=n), out=row_ptr[1:])
+    return dict(n=n, row_ptr=row_ptr.astype(np.int32), col=src.astype(np.int32),
+                val=val, outdeg=outdeg.astype(np.int32))

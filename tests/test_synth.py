@@ -1,0 +1,50 @@
+"""Seeded input generators: determinism and the structure of the synthetic workloads (no GPU)."""
+import numpy as np
+
+import synth
+
+
+def test_generators_are_deterministic():
+    a = synth.dense_cov(32, 64, seed=3)
+    b = synth.dense_cov(32, 64, seed=3)
+    assert a.tobytes() == b.tobytes()
+    assert synth.dense_cov(32, 64, seed=4).tobytes() != a.tobytes()
+    g1 = synth.powerlaw_graph(1000, seed=5)
+    g2 = synth.powerlaw_graph(1000, seed=5)
+    for k in ("row_ptr", "col", "val"):
+        assert g1[k].tobytes() == g2[k].tobytes()
+    assert synth.pca_data(8, 50, 6).tobytes() == synth.pca_data(8, 50, 6).tobytes()
+
+
+def test_dense_cov_is_symmetric_psd():
+    C = synth.dense_cov(40, 200, seed=1).astype(np.float64)
+    np.testing.assert_allclose(C, C.T, rtol=1e-6, atol=1e-7)
+    assert np.linalg.eigvalsh(C).min() > -1e-5
+
+
+def test_start_vector_unit_l2():
+    w = synth.start_vector(1000, 2).astype(np.float64)
+    assert abs(np.linalg.norm(w) - 1) < 1e-6
+
+
+def test_powerlaw_graph_structure():
+    n = 1 << 14
+    g = synth.powerlaw_graph(n, seed=7)
+    rp, col, val, outdeg = g["row_ptr"], g["col"], g["val"], g["outdeg"]
+    assert rp[0] == 0 and rp[-1] == col.size and np.all(np.diff(rp) >= 0)
+    dst = np.repeat(np.arange(n), np.diff(rp))
+    assert not np.any(dst == col)                              # no self-links
+    key = dst.astype(np.int64) * n + col
+    assert np.unique(key).size == key.size                     # duplicates merged
+    sums = np.bincount(col, weights=val.astype(np.float64), minlength=n)
+    live = outdeg > 0
+    np.testing.assert_allclose(sums[live], 1.0, rtol=1e-6)     # column-stochastic
+    dang = (~live).mean()
+    assert 0.04 < dang < 0.08                                  # seeded 5 % plus Zipf zeros
+    assert 13 < col.size / n < 17                              # mean out-degree about 16 * 0.95
+    assert outdeg.max() > 200                                  # heavy tail
+
+
+def test_dyadic_values():
+    A = synth.dyadic_matrix(10, 20, seed=8)
+    assert np.all((A * 8) == np.round(A * 8)) and np.abs(A).max() <= 2
