@@ -1,0 +1,330 @@
+"""Python binding of libmapi.so: MAPI / RPI on one MI355X (gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C-ABI declared in include/mapi.h.  PyTorch supplies device
+memory and the stream.  There is no CPU fallback: if libmapi.so is missing or
+cannot be loaded, every call raises.
+
+The function names are those of the C-ABI (mapi_solve, rpi_solve, mapi_mavp,
+mapi_quantize, mapi_mingram, mapi_pca_topk, mapi_pagerank, ...).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmapi.so")
+
+MAPI_F32, MAPI_BF16, MAPI_FP8_E4M3 = 0, 1, 2
+OPS = {"min1": 0, "min2": 1, "diamond": 2, "dot": 3}
+METHODS = {"mapi": 0, "rpi": 1}
+KERNELS = {"mavp": 0, "finalize": 1, "gram": 2, "csr": 3, "deflate": 4, "batched": 5}
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_ALLOC", 3: "ERR_HIP", 4: "ERR_DEGENERATE", 5: "ERR_BUDGET",
+          6: "ERR_UNSUPPORTED", 7: "ERR_PENDING", 8: "ERR_TIMEOUT"}
+
+
+class MapiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Dense(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("n_rows", C.c_int64), ("n_cols", C.c_int64), ("ld", C.c_int64),
+                ("dtype", C.c_int32), ("row_scale", C.c_void_p)]
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col", C.c_void_p),
+                ("val", C.c_void_p)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("max_iters", C.c_int32), ("tol", C.c_double), ("final_l2", C.c_int32), ("op", C.c_int32),
+                ("check_every", C.c_int32), ("stall_iters", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("residual", C.c_double), ("norm", C.c_double),
+                ("status", C.c_int32)]
+
+    def as_dict(self):
+        return dict(iters=self.iters, converged=bool(self.converged), residual=self.residual, norm=self.norm,
+                    status=STATUS.get(self.status, self.status))
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "mapi_create": (C.c_int, [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mapi_destroy": (None, [C.c_void_p]),
+    "mapi_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mapi_last_error": (C.c_char_p, []),
+    "mapi_version": (C.c_char_p, []),
+    "mapi_timing_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "mapi_timing_get": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "mapi_timing_reset": (C.c_int, [C.c_void_p]),
+    "mapi_mavp": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.c_int32]),
+    "mapi_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]),
+    "rpi_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]),
+    "mapi_quantize": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_void_p,
+                                C.c_int64, C.c_void_p]),
+    "mapi_mingram": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_double, C.c_int32,
+                               C.c_void_p, C.c_int64]),
+    "mapi_pca_topk": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_double,
+                                C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]),
+    "mapi_pagerank": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
+                                C.POINTER(Opts), C.POINTER(Info)]),
+}
+
+
+def lib():
+    """The loaded libmapi.so (raises if it is missing)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2110_12065_amd.build` "
+                                   "(there is no CPU fallback)")
+            L = C.CDLL(LIB_PATH)
+            for name, (res, args) in _SIGS.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+        return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise MapiError(status, lib().mapi_last_error().decode(errors="replace"))
+
+
+# ------------------------------------------------------------------ context
+class Context:
+    """A libmapi context on one device, enqueuing on torch's current stream."""
+
+    def __init__(self, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: libmapi runs on the GPU only")
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self._stream = torch.cuda.current_stream(self.device).cuda_stream
+        h = C.c_void_p()
+        _check(lib().mapi_create(self.device, C.c_void_p(self._stream), C.byref(h)))
+        self.handle = h
+
+    def sync_stream(self):
+        import torch
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        if s != self._stream:
+            _check(lib().mapi_set_stream(self.handle, C.c_void_p(s)))
+            self._stream = s
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mapi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # kernel timing ---------------------------------------------------------
+    def timing(self, enable=True):
+        _check(lib().mapi_timing_enable(self.handle, int(bool(enable))))
+
+    def timing_reset(self):
+        _check(lib().mapi_timing_reset(self.handle))
+
+    def timing_get(self, kind):
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(lib().mapi_timing_get(self.handle, KERNELS[kind], C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+
+_ctx = {}
+
+
+def default_context(device=None):
+    import torch
+    d = torch.cuda.current_device() if device is None else int(device)
+    if d not in _ctx:
+        _ctx[d] = Context(d)
+    c = _ctx[d]
+    c.sync_stream()
+    return c
+
+
+def _ctx_of(ctx, t):
+    c = ctx if ctx is not None else default_context(t.device.index)
+    c.sync_stream()
+    return c
+
+
+# ------------------------------------------------------------------ marshalling
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return MAPI_F32
+    if t.dtype in (torch.bfloat16, torch.int16) or str(t.dtype) == "torch.uint16":
+        return MAPI_BF16
+    if t.dtype == torch.uint8 or t.dtype == getattr(torch, "float8_e4m3fn", None):
+        return MAPI_FP8_E4M3
+    raise TypeError(f"unsupported matrix dtype {t.dtype}")
+
+
+def _dense(A, row_scale=None):
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D tensor with unit column stride")
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
+    code = _dtype_code(A)
+    rs = None
+    if code == MAPI_FP8_E4M3:
+        if row_scale is None:
+            raise ValueError("FP8 storage needs row_scale")
+        rs = row_scale.data_ptr()
+    return Dense(A.data_ptr(), A.shape[0], A.shape[1], A.stride(0), code, rs)
+
+
+def _vec(t, n, name):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == n):
+        raise ValueError(f"{name} must be a contiguous float32 device tensor of length {n}")
+    return t.data_ptr()
+
+
+def _opts(max_iters, tol, op, final_l2, check_every, stall_iters):
+    return Opts(int(max_iters), float(tol), int(bool(final_l2)), OPS[op] if isinstance(op, str) else int(op),
+                int(check_every), int(stall_iters))
+
+
+# ------------------------------------------------------------------ entry points
+def mapi_mavp(A, w, op="min1", row_scale=None, y=None, ctx=None):
+    """y = A (+) w (one product, no normalisation)."""
+    import torch
+    c = _ctx_of(ctx, A)
+    d = _dense(A, row_scale)
+    if y is None:
+        y = torch.empty(A.shape[0], dtype=torch.float32, device=A.device)
+    _check(lib().mapi_mavp(c.handle, C.byref(d), C.c_void_p(_vec(w, A.shape[1], "w")),
+                           C.c_void_p(_vec(y, A.shape[0], "y")), OPS[op] if isinstance(op, str) else int(op)))
+    return y
+
+
+def _solve(fn, A, w0, max_iters, tol, op, final_l2, check_every, stall_iters, row_scale, w_out, ctx):
+    import torch
+    c = _ctx_of(ctx, A)
+    d = _dense(A, row_scale)
+    n = A.shape[0]
+    if w_out is None:
+        w_out = torch.empty(n, dtype=torch.float32, device=A.device)
+    o = _opts(max_iters, tol, op, final_l2, check_every, stall_iters)
+    info = Info()
+    st = fn(c.handle, C.byref(d), C.c_void_p(_vec(w0, n, "w0")), C.c_void_p(_vec(w_out, n, "w_out")),
+            C.byref(o), C.byref(info))
+    _check(st)
+    return w_out, info.as_dict()
+
+
+def mapi_solve(A, w0, max_iters=100, tol=0.0, op="min1", final_l2=False, check_every=0, stall_iters=0,
+               row_scale=None, w_out=None, ctx=None):
+    """MAPI (eq. 6, Algorithm 1) on a square dense matrix.  Returns (w, info)."""
+    return _solve(lib().mapi_solve, A, w0, max_iters, tol, op, final_l2, check_every, stall_iters, row_scale,
+                  w_out, ctx)
+
+
+def rpi_solve(A, w0, max_iters=100, tol=0.0, final_l2=False, check_every=0, stall_iters=0, row_scale=None,
+              w_out=None, ctx=None):
+    """RPI (eq. 1) on a square dense matrix.  Returns (w, info)."""
+    return _solve(lib().rpi_solve, A, w0, max_iters, tol, "dot", final_l2, check_every, stall_iters, row_scale,
+                  w_out, ctx)
+
+
+def mapi_quantize(A, dtype, ctx=None):
+    """Reduced storage of a float32 matrix: "bf16" -> uint16 codes; "fp8" -> (uint8 codes, float32 row scales)."""
+    import torch
+    c = _ctx_of(ctx, A)
+    if A.dtype != torch.float32 or A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D float32 tensor with unit column stride")
+    n, m = A.shape
+    if dtype == "bf16":
+        ld = (m + 7) // 8 * 8
+        out = torch.empty((n, ld), dtype=torch.int16, device=A.device)[:, :m]
+        _check(lib().mapi_quantize(c.handle, C.c_void_p(A.data_ptr()), n, m, A.stride(0), MAPI_BF16,
+                                   C.c_void_p(out.data_ptr()), ld, None))
+        return out, None
+    if dtype == "fp8":
+        ld = (m + 15) // 16 * 16
+        out = torch.empty((n, ld), dtype=torch.uint8, device=A.device)[:, :m]
+        scale = torch.empty(n, dtype=torch.float32, device=A.device)
+        _check(lib().mapi_quantize(c.handle, C.c_void_p(A.data_ptr()), n, m, A.stride(0), MAPI_FP8_E4M3,
+                                   C.c_void_p(out.data_ptr()), ld, C.c_void_p(scale.data_ptr())))
+        return out, scale
+    raise ValueError(dtype)
+
+
+def mapi_mingram(X, scale, op="min1", ctx=None):
+    """A = scale * X (+) X^T over the rows of X (eq. 5; op "dot" gives eq. 2).  Returns D x D float32."""
+    import torch
+    c = _ctx_of(ctx, X)
+    if X.dtype != torch.float32 or X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a 2-D float32 tensor with unit column stride")
+    D, N = X.shape
+    A = torch.empty((D, D), dtype=torch.float32, device=X.device)
+    _check(lib().mapi_mingram(c.handle, C.c_void_p(X.data_ptr()), D, N, X.stride(0), float(scale),
+                              OPS[op], C.c_void_p(A.data_ptr()), D))
+    return A
+
+
+def mapi_pca_topk(X, k, W0, method="mapi", scale=None, max_iters=100, tol=0.0, op="min1", check_every=0,
+                  stall_iters=0, ctx=None):
+    """Top-k principal vectors with deflation.  W0: D x k start vectors (columns).
+    Returns (P as a D x k tensor, [info per vector])."""
+    import torch
+    c = _ctx_of(ctx, X)
+    if X.dtype != torch.float32 or X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a 2-D float32 tensor with unit column stride")
+    D, N = X.shape
+    W0c = W0.t().contiguous()          # column i at offset i*D
+    if W0c.shape != (k, D) or W0c.dtype != torch.float32:
+        raise ValueError("W0 must be a D x k float32 tensor")
+    Pc = torch.empty((k, D), dtype=torch.float32, device=X.device)
+    o = _opts(max_iters, tol, op, False, check_every, stall_iters)
+    infos = (Info * k)()
+    _check(lib().mapi_pca_topk(c.handle, C.c_void_p(X.data_ptr()), D, N, X.stride(0), int(k),
+                               float(1.0 / N if scale is None else scale), METHODS[method],
+                               C.c_void_p(W0c.data_ptr()), C.c_void_p(Pc.data_ptr()), C.byref(o), infos))
+    return Pc.t(), [infos[i].as_dict() for i in range(k)]
+
+
+def mapi_pagerank(row_ptr, col, val, alpha=0.85, method="mapi", w0=None, max_iters=100, tol=0.0, final_l2=False,
+                  check_every=0, stall_iters=0, w_out=None, ctx=None):
+    """Power iteration on G = alpha H + (1 - alpha)/n 1 (eq. 11), H in CSR by destination row.
+    Returns (w, info)."""
+    import torch
+    c = _ctx_of(ctx, row_ptr)
+    n = row_ptr.numel() - 1
+    nnz = col.numel()
+    for t, dt, name in ((row_ptr, torch.int32, "row_ptr"), (col, torch.int32, "col"), (val, torch.float32, "val")):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {dt} device tensor")
+    if val.numel() != nnz:
+        raise ValueError("col and val differ in length")
+    H = Csr(n, nnz, row_ptr.data_ptr(), col.data_ptr() if nnz else None, val.data_ptr() if nnz else None)
+    if w_out is None:
+        w_out = torch.empty(n, dtype=torch.float32, device=row_ptr.device)
+    o = _opts(max_iters, tol, "min1", final_l2, check_every, stall_iters)
+    info = Info()
+    _check(lib().mapi_pagerank(c.handle, C.byref(H), float(alpha), METHODS[method],
+                               C.c_void_p(_vec(w0, n, "w0")) if w0 is not None else None,
+                               C.c_void_p(_vec(w_out, n, "w_out")), C.byref(o), C.byref(info)))
+    return w_out, info.as_dict()

@@ -1,0 +1,531 @@
+// C-ABI of libmapi: argument checks, device workspace, iteration drivers and
+// kernel timing.  Declarations and contracts are in include/mapi.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+using namespace mapi;
+
+namespace {
+
+thread_local std::string g_err;
+
+mapi_status fail(mapi_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(MAPI_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int64_t elem_size(int dtype) {
+  switch (dtype) {
+    case MAPI_F32: return 4;
+    case MAPI_BF16: return 2;
+    case MAPI_FP8_E4M3: return 1;
+    default: return 0;
+  }
+}
+
+}  // namespace
+
+struct mapi_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int cu_count = 256;
+  int max_lds = 65536;               // LDS bytes one block may use
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  SolveState* st_host = nullptr;     // pinned copy of the device state
+  // matrices owned by the PCA driver
+  void* big = nullptr;
+  size_t big_bytes = 0;
+  // timing
+  bool timing = false;
+  struct Rec { int kind; hipEvent_t a, b; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double t_ms[MAPI_K_KINDS] = {};
+  int64_t t_n[MAPI_K_KINDS] = {};
+};
+
+namespace {
+
+mapi_status ensure(void** buf, size_t* have, size_t need, mapi_ctx* c) {
+  if (*have >= need) return MAPI_OK;
+  if (*buf) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipFree(*buf));
+    *buf = nullptr;
+    *have = 0;
+  }
+  need = align_up(need, 1 << 20);
+  if (hipMalloc(buf, need) != hipSuccess) {
+    *buf = nullptr;
+    return fail(MAPI_ERR_ALLOC, "hipMalloc of %zu bytes failed", need);
+  }
+  *have = need;
+  return MAPI_OK;
+}
+
+// Bump layout over one allocation, 256-byte aligned pieces.
+struct Layout {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  }
+};
+
+hipEvent_t get_event(mapi_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events when timing is enabled.
+struct Timed {
+  mapi_ctx* c;
+  int kind;
+  hipEvent_t a = nullptr;
+  Timed(mapi_ctx* c_, int k) : c(c_), kind(k) {
+    if (c->timing) {
+      a = get_event(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~Timed() {
+    if (a) {
+      hipEvent_t b = get_event(c);
+      if (b) {
+        (void)hipEventRecord(b, c->stream);
+        c->pending.push_back({kind, a, b});
+      } else {
+        c->pool.push_back(a);
+      }
+    }
+  }
+};
+
+void collect_timing(mapi_ctx* c) {
+  for (auto& r : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->t_ms[r.kind] += ms;
+      c->t_n[r.kind] += 1;
+    }
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->pending.clear();
+}
+
+mapi_status sync_and_state(mapi_ctx* c, const SolveState* st_dev) {
+  HIP_TRY(hipMemcpyAsync(c->st_host, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  collect_timing(c);
+  return MAPI_OK;
+}
+
+mapi_status check_dense(const mapi_dense* A, bool square) {
+  if (!A || !A->data) return fail(MAPI_ERR_ARG, "matrix descriptor or data pointer is NULL");
+  if (A->n_rows <= 0 || A->n_cols <= 0) return fail(MAPI_ERR_ARG, "matrix is empty (%lld x %lld)",
+                                                    (long long)A->n_rows, (long long)A->n_cols);
+  if (A->n_rows > INT32_MAX || A->n_cols > INT32_MAX) return fail(MAPI_ERR_ARG, "matrix dimension exceeds 2^31-1");
+  if (square && A->n_rows != A->n_cols) return fail(MAPI_ERR_ARG, "matrix must be square for a solve");
+  const int64_t es = elem_size(A->dtype);
+  if (!es) return fail(MAPI_ERR_ARG, "unknown dtype %d", A->dtype);
+  if (A->ld < A->n_cols) return fail(MAPI_ERR_ARG, "ld (%lld) < n_cols (%lld)", (long long)A->ld, (long long)A->n_cols);
+  if (!aligned16(A->data) || (A->ld * es) % 16 != 0)
+    return fail(MAPI_ERR_ARG, "matrix base and row pitch must be 16-byte aligned");
+  if (A->dtype == MAPI_FP8_E4M3 && !A->row_scale) return fail(MAPI_ERR_ARG, "FP8 storage needs row_scale");
+  return MAPI_OK;
+}
+
+mapi_status check_opts(const mapi_opts* o) {
+  if (!o) return fail(MAPI_ERR_ARG, "opts is NULL");
+  if (o->max_iters < 0) return fail(MAPI_ERR_ARG, "max_iters < 0");
+  if (!(o->tol >= 0.0)) return fail(MAPI_ERR_ARG, "tol must be >= 0");
+  if (o->check_every < 0 || o->stall_iters < 0) return fail(MAPI_ERR_ARG, "check_every and stall_iters must be >= 0");
+  return MAPI_OK;
+}
+
+DenseArgs dense_args(const mapi_dense* A) {
+  return DenseArgs{A->data, A->ld, A->n_rows, A->n_cols, A->dtype, A->row_scale};
+}
+
+void fill_info(mapi_info* info, const SolveState& s) {
+  if (!info) return;
+  info->iters = s.iter;
+  info->converged = s.converged;
+  info->residual = s.r;
+  info->norm = s.nu;
+  info->status = s.status;
+}
+
+// Power iteration on a dense square matrix: MAPI (op, l1) or RPI (dot, l2).
+mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* w_out, const mapi_opts* o,
+                      mapi_info* info, bool rpi) {
+  mapi_status s;
+  if ((s = check_dense(A, true)) != MAPI_OK) return s;
+  if ((s = check_opts(o)) != MAPI_OK) return s;
+  if (!w0 || !w_out) return fail(MAPI_ERR_ARG, "w0 and w_out must be device pointers");
+  const int op = rpi ? MAPI_OP_DOT : o->op;
+  if (op < MAPI_OP_MIN1 || op > MAPI_OP_DOT || (!rpi && op == MAPI_OP_DOT))
+    return fail(MAPI_ERR_ARG, "op %d is not a MAPI product", o->op);
+  const int64_t n = A->n_rows;
+  const DenseArgs da = dense_args(A);
+  const DenseTuning t = dense_default_tuning(da, c->cu_count, c->max_lds);
+  const int P = dense_part_count(da, t, c->cu_count);
+  const int F = finalize_blocks(n);
+  Layout L;
+  const size_t o_st = L.take(sizeof(SolveState));
+  const size_t o_part = L.take(sizeof(double) * (size_t)std::max(P, 3 * F));
+  const size_t o_w0 = L.take(sizeof(float) * n);
+  const size_t o_w1 = L.take(sizeof(float) * n);
+  const size_t o_y = L.take(sizeof(float) * n);
+  if ((s = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return s;
+  char* base = static_cast<char*>(c->ws);
+  SolveState* st = reinterpret_cast<SolveState*>(base + o_st);
+  double* part = reinterpret_cast<double*>(base + o_part);
+  float* wb[2] = {reinterpret_cast<float*>(base + o_w0), reinterpret_cast<float*>(base + o_w1)};
+  float* y = reinterpret_cast<float*>(base + o_y);
+
+  HIP_TRY(hipMemcpyAsync(wb[0], w0, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(launch_state_init(st, o->max_iters, o->tol, o->stall_iters, c->stream));
+  const int check = o->check_every > 0 ? o->check_every : 16;
+  const int norm = rpi ? NORM_L2 : NORM_L1;
+  for (int it = 0; it < o->max_iters; ++it) {
+    float* wc = wb[it & 1];
+    float* wn = wb[(it & 1) ^ 1];
+    {
+      Timed tm(c, MAPI_K_MAVP);
+      HIP_TRY(launch_mavp_dense(da, op, wc, y, part, st, norm, t, c->cu_count, c->stream));
+    }
+    {
+      Timed tm(c, MAPI_K_FINALIZE);
+      HIP_TRY(launch_finalize(0, y, wc, wn, n, st, part, nullptr, 0.0, 0.0, c->stream));
+    }
+    if ((it + 1) % check == 0 && it + 1 < o->max_iters) {
+      if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
+      if (c->st_host->done) break;
+    }
+  }
+  HIP_TRY(launch_finish(wb[0], wb[1], w_out, n, st, o->final_l2, c->stream));
+  if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
+  fill_info(info, *c->st_host);
+  if (c->st_host->status == MAPI_ERR_DEGENERATE)
+    return fail(MAPI_ERR_DEGENERATE, "normaliser was zero or not finite after %d iterations", c->st_host->iter);
+  return MAPI_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C-ABI
+extern "C" {
+
+const char* mapi_last_error(void) { return g_err.c_str(); }
+const char* mapi_version(void) { return "mapi-gfx950 0.1"; }
+
+mapi_status mapi_create(int device, void* hip_stream, mapi_ctx** out) {
+  if (!out) return fail(MAPI_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(MAPI_ERR_ARG, "device %d not present (%d devices)", device, ndev);
+  HIP_TRY(hipSetDevice(device));
+  mapi_ctx* c = new (std::nothrow) mapi_ctx();
+  if (!c) return fail(MAPI_ERR_ALLOC, "context allocation failed");
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0) {
+    c->cu_count = prop.multiProcessorCount;
+    if (prop.sharedMemPerBlock > 0) c->max_lds = (int)prop.sharedMemPerBlock;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->st_host), sizeof(SolveState), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return fail(MAPI_ERR_ALLOC, "pinned host allocation failed");
+  }
+  *out = c;
+  return MAPI_OK;
+}
+
+void mapi_destroy(mapi_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  collect_timing(c);
+  for (auto e : c->pool) (void)hipEventDestroy(e);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->big) (void)hipFree(c->big);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  delete c;
+}
+
+mapi_status mapi_set_stream(mapi_ctx* c, void* hip_stream) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  return MAPI_OK;
+}
+
+mapi_status mapi_timing_enable(mapi_ctx* c, int enable) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  c->timing = enable != 0;
+  return MAPI_OK;
+}
+
+mapi_status mapi_timing_get(mapi_ctx* c, int kind, double* total_ms, int64_t* launches) {
+  if (!c || kind < 0 || kind >= MAPI_K_KINDS) return fail(MAPI_ERR_ARG, "bad context or kernel kind");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  collect_timing(c);
+  if (total_ms) *total_ms = c->t_ms[kind];
+  if (launches) *launches = c->t_n[kind];
+  return MAPI_OK;
+}
+
+mapi_status mapi_timing_reset(mapi_ctx* c) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  collect_timing(c);
+  for (int k = 0; k < MAPI_K_KINDS; ++k) {
+    c->t_ms[k] = 0.0;
+    c->t_n[k] = 0;
+  }
+  return MAPI_OK;
+}
+
+mapi_status mapi_mavp(mapi_ctx* c, const mapi_dense* A, const float* w, float* y, int32_t op) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  mapi_status s;
+  if ((s = check_dense(A, false)) != MAPI_OK) return s;
+  if (!w || !y) return fail(MAPI_ERR_ARG, "w and y must be device pointers");
+  if (op < MAPI_OP_MIN1 || op > MAPI_OP_DOT) return fail(MAPI_ERR_ARG, "unknown op %d", op);
+  HIP_TRY(hipSetDevice(c->device));
+  const DenseArgs da = dense_args(A);
+  const DenseTuning t = dense_default_tuning(da, c->cu_count, c->max_lds);
+  const float* wv = w;
+  if (!aligned16(w)) {
+    if ((s = ensure(&c->ws, &c->ws_bytes, sizeof(float) * (size_t)A->n_cols, c)) != MAPI_OK) return s;
+    HIP_TRY(hipMemcpyAsync(c->ws, w, sizeof(float) * A->n_cols, hipMemcpyDeviceToDevice, c->stream));
+    wv = static_cast<const float*>(c->ws);
+  }
+  {
+    Timed tm(c, MAPI_K_MAVP);
+    HIP_TRY(launch_mavp_dense(da, op, wv, y, nullptr, nullptr, NORM_NONE, t, c->cu_count, c->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  collect_timing(c);
+  return MAPI_OK;
+}
+
+mapi_status mapi_solve(mapi_ctx* c, const mapi_dense* A, const float* w0, float* w_out, const mapi_opts* opts,
+                       mapi_info* info) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  return run_dense(c, A, w0, w_out, opts, info, false);
+}
+
+mapi_status rpi_solve(mapi_ctx* c, const mapi_dense* A, const float* w0, float* w_out, const mapi_opts* opts,
+                      mapi_info* info) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  return run_dense(c, A, w0, w_out, opts, info, true);
+}
+
+mapi_status mapi_quantize(mapi_ctx* c, const float* A, int64_t n_rows, int64_t n_cols, int64_t lda, int32_t dtype,
+                          void* out, int64_t ld_out, float* row_scale) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  if (!A || !out) return fail(MAPI_ERR_ARG, "A and out must be device pointers");
+  if (n_rows <= 0 || n_cols <= 0 || lda < n_cols || ld_out < n_cols) return fail(MAPI_ERR_ARG, "bad shape");
+  HIP_TRY(hipSetDevice(c->device));
+  if (dtype == MAPI_BF16) {
+    HIP_TRY(launch_quant_bf16(A, n_rows, n_cols, lda, static_cast<uint16_t*>(out), ld_out, c->stream));
+  } else if (dtype == MAPI_FP8_E4M3) {
+    if (!row_scale) return fail(MAPI_ERR_ARG, "FP8 storage needs row_scale");
+    HIP_TRY(launch_quant_fp8(A, n_rows, n_cols, lda, static_cast<uint8_t*>(out), ld_out, row_scale, c->stream));
+  } else {
+    return fail(MAPI_ERR_ARG, "dtype %d is not a reduced storage format", dtype);
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return MAPI_OK;
+}
+
+mapi_status mapi_mingram(mapi_ctx* c, const float* X, int64_t D, int64_t N, int64_t ldx, double scale, int32_t op,
+                         float* A_out, int64_t lda) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  if (!X || !A_out) return fail(MAPI_ERR_ARG, "X and A_out must be device pointers");
+  if (D <= 0 || N <= 0 || ldx < N || lda < D) return fail(MAPI_ERR_ARG, "bad shape");
+  if (D > 65536) return fail(MAPI_ERR_UNSUPPORTED, "D > 65536");
+  if (!aligned16(X) || ldx % 4 != 0) return fail(MAPI_ERR_ARG, "X base and row pitch must be 16-byte aligned");
+  if (op != MAPI_OP_MIN1 && op != MAPI_OP_MIN2 && op != MAPI_OP_DOT) return fail(MAPI_ERR_ARG, "op %d", op);
+  HIP_TRY(hipSetDevice(c->device));
+  {
+    Timed tm(c, MAPI_K_GRAM);
+    HIP_TRY(launch_gram(X, D, N, ldx, scale, op, A_out, lda, nullptr, c->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  collect_timing(c);
+  return MAPI_OK;
+}
+
+mapi_status mapi_pca_topk(mapi_ctx* c, const float* X, int64_t D, int64_t N, int64_t ldx, int32_t k, double scale,
+                          int32_t method, const float* W0, float* P_out, const mapi_opts* opts, mapi_info* info_k) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  if (!X || !W0 || !P_out) return fail(MAPI_ERR_ARG, "X, W0 and P_out must be device pointers");
+  if (D <= 0 || N <= 0 || ldx < N) return fail(MAPI_ERR_ARG, "bad shape");
+  if (k < 1 || k > D) return fail(MAPI_ERR_ARG, "k must be in [1, D]");
+  if (method != MAPI_METHOD_MAPI && method != MAPI_METHOD_RPI) return fail(MAPI_ERR_ARG, "method %d", method);
+  if (!aligned16(X) || ldx % 4 != 0) return fail(MAPI_ERR_ARG, "X base and row pitch must be 16-byte aligned");
+  if (D > 32768) return fail(MAPI_ERR_UNSUPPORTED, "D > 32768");
+  mapi_status s;
+  if ((s = check_opts(opts)) != MAPI_OK) return s;
+  HIP_TRY(hipSetDevice(c->device));
+  const int64_t ldA = (D + 3) / 4 * 4;
+  Layout L;
+  const size_t o_A = L.take(sizeof(float) * D * ldA);
+  const size_t o_Ai = L.take(sizeof(float) * D * ldA);
+  const size_t o_P = L.take(sizeof(double) * D * k);
+  const size_t o_Q = L.take(sizeof(double) * D * k);
+  const size_t o_qp = L.take(sizeof(double) * D * deflate_qpart_count());
+  const size_t o_w = L.take(sizeof(float) * D);
+  if ((s = ensure(&c->big, &c->big_bytes, L.off, c)) != MAPI_OK) return s;
+  char* base = static_cast<char*>(c->big);
+  float* A = reinterpret_cast<float*>(base + o_A);
+  float* Ai = reinterpret_cast<float*>(base + o_Ai);
+  double* P = reinterpret_cast<double*>(base + o_P);
+  double* Q = reinterpret_cast<double*>(base + o_Q);
+  double* qpart = reinterpret_cast<double*>(base + o_qp);
+  float* wtmp = reinterpret_cast<float*>(base + o_w);
+  const bool rpi = method == MAPI_METHOD_RPI;
+  {
+    Timed tm(c, MAPI_K_GRAM);
+    HIP_TRY(launch_gram(X, D, N, ldx, scale, rpi ? MAPI_OP_DOT : opts->op, A, ldA, nullptr, c->stream));
+  }
+  mapi_opts o = *opts;
+  o.final_l2 = 0;
+  for (int i = 0; i < k; ++i) {
+    const float* Acur = A;
+    if (i > 0) {
+      Timed tm(c, MAPI_K_DEFLATE);
+      HIP_TRY(launch_deflate_apply(A, D, ldA, P, Q, i, Ai, ldA, c->stream));
+      Acur = Ai;
+    }
+    mapi_dense desc{Acur, D, D, ldA, MAPI_F32, nullptr};
+    mapi_info inf{};
+    s = run_dense(c, &desc, W0 + (int64_t)i * D, wtmp, &o, &inf, rpi);
+    if (info_k) info_k[i] = inf;
+    if (s != MAPI_OK) return s;
+    {
+      Timed tm(c, MAPI_K_DEFLATE);
+      HIP_TRY(launch_mgs_append(P, D, i, wtmp, P_out + (int64_t)i * D, c->stream));
+      HIP_TRY(launch_deflate_q(A, D, ldA, P + (int64_t)i * D, Q + (int64_t)i * D, qpart, c->stream));
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  collect_timing(c);
+  return MAPI_OK;
+}
+
+mapi_status mapi_pagerank(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t method, const float* w0,
+                          float* w_out, const mapi_opts* o, mapi_info* info) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  if (!H || !H->row_ptr || !w_out) return fail(MAPI_ERR_ARG, "H, H->row_ptr and w_out are required");
+  if (H->n <= 0 || H->n > INT32_MAX || H->nnz < 0 || H->nnz > INT32_MAX) return fail(MAPI_ERR_ARG, "bad n or nnz");
+  if (H->nnz > 0 && (!H->col || !H->val)) return fail(MAPI_ERR_ARG, "col and val are required when nnz > 0");
+  if (!(alpha > 0.0 && alpha < 1.0)) return fail(MAPI_ERR_ARG, "alpha must be in (0, 1)");
+  if (method != MAPI_METHOD_MAPI && method != MAPI_METHOD_RPI) return fail(MAPI_ERR_ARG, "method %d", method);
+  mapi_status s;
+  if ((s = check_opts(o)) != MAPI_OK) return s;
+  HIP_TRY(hipSetDevice(c->device));
+  const int64_t n = H->n;
+  const int F = finalize_blocks(n);
+  const int P = std::max(std::max(csr_part_count(n), 3 * F), 2 * pr_scalar_blocks(n));
+  Layout L;
+  const size_t o_st = L.take(sizeof(SolveState));
+  const size_t o_part = L.take(sizeof(double) * P);
+  const size_t o_w0 = L.take(sizeof(float) * n);
+  const size_t o_w1 = L.take(sizeof(float) * n);
+  const size_t o_y = L.take(sizeof(float) * n);
+  const size_t o_d = L.take(n);
+  const size_t o_err = L.take(sizeof(int32_t));
+  if ((s = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return s;
+  char* base = static_cast<char*>(c->ws);
+  SolveState* st = reinterpret_cast<SolveState*>(base + o_st);
+  double* part = reinterpret_cast<double*>(base + o_part);
+  float* wb[2] = {reinterpret_cast<float*>(base + o_w0), reinterpret_cast<float*>(base + o_w1)};
+  float* y = reinterpret_cast<float*>(base + o_y);
+  uint8_t* dangling = reinterpret_cast<uint8_t*>(base + o_d);
+  int32_t* err = reinterpret_cast<int32_t*>(base + o_err);
+
+  HIP_TRY(hipMemsetAsync(err, 0, sizeof(int32_t), c->stream));
+  HIP_TRY(launch_csr_prep(H->row_ptr, H->col, n, H->nnz, dangling, err, c->stream));
+  int32_t err_h = 0;
+  HIP_TRY(hipMemcpyAsync(&err_h, err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (err_h) return fail(MAPI_ERR_ARG, "invalid CSR arrays (code %d)", err_h);
+
+  const double inv_n = 1.0 / (double)n;
+  const double cc = (1.0 - alpha) * inv_n;
+  if (w0) {
+    HIP_TRY(hipMemcpyAsync(wb[0], w0, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
+  } else {
+    HIP_TRY(launch_fill_f32(wb[0], n, (float)inv_n, c->stream));
+  }
+  HIP_TRY(launch_state_init(st, o->max_iters, o->tol, o->stall_iters, c->stream));
+  HIP_TRY(launch_pr_scalars(method, wb[0], n, dangling, cc, inv_n, st, part, c->stream));
+  const int check = o->check_every > 0 ? o->check_every : 16;
+  const int mode = method == MAPI_METHOD_MAPI ? 1 : 2;
+  for (int it = 0; it < o->max_iters; ++it) {
+    float* wc = wb[it & 1];
+    float* wn = wb[(it & 1) ^ 1];
+    {
+      Timed tm(c, MAPI_K_CSR);
+      HIP_TRY(launch_csr_product(method, H->row_ptr, H->col, H->val, n, wc, y, part, st, (float)alpha, (float)cc,
+                                 inv_n, c->stream));
+    }
+    {
+      Timed tm(c, MAPI_K_FINALIZE);
+      HIP_TRY(launch_finalize(mode, y, wc, wn, n, st, part, dangling, cc, inv_n, c->stream));
+    }
+    if ((it + 1) % check == 0 && it + 1 < o->max_iters) {
+      if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
+      if (c->st_host->done) break;
+    }
+  }
+  HIP_TRY(launch_finish(wb[0], wb[1], w_out, n, st, o->final_l2, c->stream));
+  if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
+  fill_info(info, *c->st_host);
+  if (c->st_host->status == MAPI_ERR_DEGENERATE)
+    return fail(MAPI_ERR_DEGENERATE, "normaliser was zero or not finite after %d iterations", c->st_host->iter);
+  return MAPI_OK;
+}
+
+}  // extern "C"

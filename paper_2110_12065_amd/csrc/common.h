@@ -1,0 +1,197 @@
+// Shared device helpers and launcher declarations of libmapi (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mapi.h"
+
+namespace mapi {
+
+constexpr int kWave = 64;
+
+// Device-resident state of one power-iteration solve.  Kernels read `done` on
+// entry and return at once when it is set, so a host loop may enqueue more
+// iterations than are needed and poll rarely.
+struct SolveState {
+  double nu;          // normaliser of the latest product (l1 or l2)
+  double r;           // residual ||w_t - w_{t-1}||_1 of the latest iteration
+  double best_r;      // smallest residual so far (stall rule)
+  double ex[2];       // PageRank scalars of the current iterate
+  double tol;
+  int32_t iter;       // completed iterations
+  int32_t done;
+  int32_t converged;
+  int32_t status;     // mapi_status of the solve
+  int32_t stall;
+  int32_t max_iters;
+  int32_t stall_iters;
+  uint32_t cnt_a;     // arrival counters of the two grid-wide reductions
+  uint32_t cnt_b;
+  int32_t pad;
+};
+
+enum NormKind { NORM_NONE = 0, NORM_L1 = 1, NORM_L2 = 2 };
+
+// ---------------------------------------------------------------- vector products
+// One term of each product, written without multiplication for the min forms:
+// with s = signbit(w), x = a ^ s carries sign(a) sign(w), and
+//   min1(a, w) = med3(x, -|w|, |w|)   (eq. 3)
+//   min2(a, w) = med3(x,  0,   |w|)   (eq. 4)
+// The negation and absolute value are free source modifiers of v_med3_f32.
+__device__ __forceinline__ float flip_sign(float a, uint32_t s) {
+  return __uint_as_float(__float_as_uint(a) ^ s);
+}
+__device__ __forceinline__ uint32_t sign_bit(float w) { return __float_as_uint(w) & 0x80000000u; }
+
+template <int OP>
+__device__ __forceinline__ float op_acc(float acc, float a, float w, uint32_t ws) {
+  if constexpr (OP == MAPI_OP_MIN1) {
+    const float wa = fabsf(w);
+    return acc + __builtin_amdgcn_fmed3f(flip_sign(a, ws), -wa, wa);
+  } else if constexpr (OP == MAPI_OP_MIN2) {
+    return acc + __builtin_amdgcn_fmed3f(flip_sign(a, ws), 0.0f, fabsf(w));
+  } else if constexpr (OP == MAPI_OP_DIAMOND) {
+    // eq. (7): sign(a) w + a sign(w); zero when either operand is zero
+    const float sa = (a > 0.0f) ? 1.0f : ((a < 0.0f) ? -1.0f : 0.0f);
+    const float sw = (w > 0.0f) ? 1.0f : ((w < 0.0f) ? -1.0f : 0.0f);
+    return acc + (sa * w + a * sw);
+  } else {
+    return fmaf(a, w, acc);
+  }
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Fixed-order block sum of one double per thread (blockDim.x <= 1024).  Result
+// valid in every thread.  `sh` holds at least blockDim.x / 64 doubles.
+__device__ __forceinline__ double block_sum_f64(double v, double* sh) {
+  v = wave_sum_f64(v);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += sh[i];
+  return s;
+}
+
+__device__ __forceinline__ void store_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish this block's partial(s) and report whether it arrived last.  The
+// last block then sees every other block's partials.  Call from all threads.
+__device__ __forceinline__ bool arrive_last(uint32_t* counter, int* sh_flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t prev = atomicAdd(counter, 1u);
+    *sh_flag = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = *sh_flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// Fixed-order sum of part[0..count) (stride `stride`, offset `off`) by one block.
+__device__ __forceinline__ double block_sum_parts(const double* part, int count, int stride, int off,
+                                                  double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) s += load_agent(&part[(size_t)i * stride + off]);
+  return block_sum_f64(s, sh);
+}
+
+__device__ __forceinline__ bool state_done(const SolveState* st) {
+  return __hip_atomic_load(const_cast<int32_t*>(&st->done), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// Advance the stop rule after an iteration's residual r is known (one thread).
+__device__ __forceinline__ void state_advance(SolveState* st, double r) {
+  st->iter += 1;
+  st->r = r;
+  if (r < st->tol) {
+    st->converged = 1;
+    st->done = 1;
+  } else if (st->iter >= st->max_iters) {
+    st->done = 1;
+  } else if (st->stall_iters > 0) {
+    if (r < st->best_r) {
+      st->best_r = r;
+      st->stall = 0;
+    } else if (++st->stall >= st->stall_iters) {
+      st->done = 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+struct DenseArgs {
+  const void* A;
+  int64_t ld;
+  int64_t n_rows, n_cols;
+  int32_t dtype;
+  const float* row_scale;
+};
+
+struct DenseTuning {
+  int rows_per_wave;   // 1, 2 or 4 rows share each staged w value
+  int waves;           // waves per block (4 or 8)
+  int blocks;          // grid size (persistent loop over row groups); 0 = auto
+  int w_in_lds;        // stage w in LDS (needs n_cols * 4 bytes of LDS per block)
+};
+
+hipError_t launch_state_init(SolveState* st, int max_iters, double tol, int stall_iters, hipStream_t s);
+hipError_t launch_mavp_dense(const DenseArgs& a, int op, const float* w, float* y, double* part,
+                             SolveState* st, int norm, const DenseTuning& t, int cu_count, hipStream_t s);
+int dense_part_count(const DenseArgs& a, const DenseTuning& t, int cu_count);
+DenseTuning dense_default_tuning(const DenseArgs& a, int cu_count, int max_lds_bytes);
+hipError_t launch_finalize(int mode, const float* y, const float* w_old, float* w_new, int64_t n,
+                           SolveState* st, double* part, const uint8_t* dangling, double c, double inv_n,
+                           hipStream_t s);
+int finalize_blocks(int64_t n);
+hipError_t launch_finish(const float* w0buf, const float* w1buf, float* out, int64_t n, SolveState* st, int final_l2,
+                         hipStream_t s);
+
+hipError_t launch_quant_bf16(const float* A, int64_t n_rows, int64_t n_cols, int64_t lda, uint16_t* out,
+                             int64_t ldo, hipStream_t s);
+hipError_t launch_quant_fp8(const float* A, int64_t n_rows, int64_t n_cols, int64_t lda, uint8_t* out,
+                            int64_t ldo, float* scale, hipStream_t s);
+
+hipError_t launch_gram(const float* X, int64_t D, int64_t N, int64_t ldx, double scale, int op, float* A,
+                       int64_t lda, double* acc64, hipStream_t s);
+
+hipError_t launch_csr_prep(const int32_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz, uint8_t* dangling,
+                           int32_t* err, hipStream_t s);
+hipError_t launch_pr_scalars(int method, const float* w, int64_t n, const uint8_t* dangling, double c,
+                             double inv_n, SolveState* st, double* part, hipStream_t s);
+hipError_t launch_csr_product(int method, const int32_t* row_ptr, const int32_t* col, const float* val, int64_t n,
+                              const float* w, float* y, double* part, SolveState* st, float alpha, float c,
+                              double inv_n, hipStream_t s);
+int csr_part_count(int64_t n);
+
+hipError_t launch_deflate_q(const float* A, int64_t D, int64_t lda, const double* p, double* q, double* qpart,
+                            hipStream_t s);
+int deflate_qpart_count();
+hipError_t launch_deflate_apply(const float* A, int64_t D, int64_t lda, const double* P, const double* Q, int k,
+                                float* out, int64_t ldo, hipStream_t s);
+hipError_t launch_mgs_append(double* P, int64_t D, int k, const float* w, float* p_out, hipStream_t s);
+int pr_scalar_blocks(int64_t n);
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+
+}  // namespace mapi

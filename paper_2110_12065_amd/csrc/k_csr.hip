@@ -1,0 +1,178 @@
+// PageRank products on G = alpha H + (1 - alpha)/n 1 (eq. 11) without forming G.
+//
+// With c = (1 - alpha)/n, every column of row i of G holds c except the
+// dangling columns (1/n) and the in-links j of i (alpha H_ij + c).  For the
+// min1 product (eq. 3) with G >= 0 each term is t(g, w_j) = clamp(w_j, -g, g),
+// so
+//   y_i = T + Dg + sum_{j in in(i)} [clamp(w_j, +-(alpha H_ij + c)) - clamp(w_j, +-c)]
+//   T   = sum_j clamp(w_j, +-c),  Dg = sum_{j dangling} [clamp(w_j, +-1/n) - clamp(w_j, +-c)].
+// For RPI, y_i = alpha sum_{j in in(i)} H_ij w_j + (alpha/n) sum_{dangling} w_j + c sum_j w_j.
+// T, Dg (or the two sums) are float64 scalars of the current iterate, reduced by
+// the normalisation kernel of the previous iteration (or k_pr_scalars for w0).
+//
+// Rows are destinations; G lanes of a wave share one row, stride along its
+// in-links and reduce with a fixed butterfly.  In-degrees of graphs with
+// uniformly drawn destinations are nearly Poisson, so short rows dominate.
+#include "common.h"
+
+namespace mapi {
+
+__global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Validate the CSR arrays and clear the dangling flag of every node that is a
+// source.  Out-of-range entries set *err and are never used as an address.
+__global__ void k_csr_check(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, int64_t n,
+                            int64_t nnz, uint8_t* __restrict__ dangling, int32_t* __restrict__ err) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (tid == 0 && (row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz)) atomicOr(err, 1);
+  for (int64_t i = tid; i < n; i += stride)
+    if (row_ptr[i] > row_ptr[i + 1]) atomicOr(err, 2);
+  for (int64_t p = tid; p < nnz; p += stride) {
+    const int32_t j = col[p];
+    if (j < 0 || (int64_t)j >= n) {
+      atomicOr(err, 4);
+    } else {
+      dangling[j] = 0;
+    }
+  }
+}
+
+// T/Dg (MAPI) or sum/dangling-sum (RPI) of an iterate, into st->ex.
+template <int METHOD>
+__global__ void __launch_bounds__(256)
+k_pr_scalars(const float* __restrict__ w, int64_t n, const uint8_t* __restrict__ dangling, double c, double inv_n,
+             SolveState* __restrict__ st, double* __restrict__ part) {
+  __shared__ double sh[16];
+  __shared__ int sh_flag;
+  double e0 = 0.0, e1 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double wd = (double)w[i];
+    if constexpr (METHOD == MAPI_METHOD_MAPI) {
+      const double tc = fmin(fmax(wd, -c), c);
+      e0 += tc;
+      if (dangling[i]) e1 += fmin(fmax(wd, -inv_n), inv_n) - tc;
+    } else {
+      e0 += wd;
+      if (dangling[i]) e1 += wd;
+    }
+  }
+  e0 = block_sum_f64(e0, sh);
+  e1 = block_sum_f64(e1, sh);
+  if (threadIdx.x == 0) {
+    store_agent(&part[2 * (size_t)blockIdx.x], e0);
+    store_agent(&part[2 * (size_t)blockIdx.x + 1], e1);
+  }
+  if (arrive_last(&st->cnt_b, &sh_flag)) {
+    const double E0 = block_sum_parts(part, gridDim.x, 2, 0, sh);
+    const double E1 = block_sum_parts(part, gridDim.x, 2, 1, sh);
+    if (threadIdx.x == 0) {
+      st->ex[0] = E0;
+      st->ex[1] = E1;
+      st->cnt_b = 0;
+    }
+  }
+}
+
+template <int METHOD, int G>
+__global__ void __launch_bounds__(256)
+k_csr_product(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const float* __restrict__ val,
+              int64_t n, const float* __restrict__ w, float* __restrict__ y, double* __restrict__ part,
+              SolveState* __restrict__ st, float alpha, float c, double inv_n) {
+  __shared__ double sh[16];
+  __shared__ int sh_flag;
+  if (state_done(st)) return;
+  const double base = (METHOD == MAPI_METHOD_MAPI) ? st->ex[0] + st->ex[1]
+                                                   : ((double)alpha * inv_n) * st->ex[1] + (double)c * st->ex[0];
+  const int sub = threadIdx.x % G;
+  const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int64_t ng = ((int64_t)gridDim.x * blockDim.x) / G;
+  double nrm = 0.0;
+  for (int64_t i = gid; i < n; i += ng) {
+    const int32_t p0 = row_ptr[i], p1 = row_ptr[i + 1];
+    float acc = 0.0f;
+    for (int32_t p = p0 + sub; p < p1; p += G) {
+      const float wj = w[col[p]];
+      const float h = val[p];
+      if constexpr (METHOD == MAPI_METHOD_MAPI) {
+        const float g = fmaf(alpha, h, c);
+        acc += __builtin_amdgcn_fmed3f(wj, -g, g) - __builtin_amdgcn_fmed3f(wj, -c, c);
+      } else {
+        acc = fmaf(h, wj, acc);
+      }
+    }
+#pragma unroll
+    for (int off = G / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, G);
+    if (sub == 0) {
+      const float yi = (METHOD == MAPI_METHOD_MAPI) ? (float)(base + (double)acc)
+                                                    : (float)((double)alpha * (double)acc + base);
+      y[i] = yi;
+      nrm += fabs((double)yi);
+    }
+  }
+  const double bsum = block_sum_f64(nrm, sh);
+  if (threadIdx.x == 0) store_agent(&part[blockIdx.x], bsum);
+  if (arrive_last(&st->cnt_a, &sh_flag)) {
+    const double tot = block_sum_parts(part, gridDim.x, 1, 0, sh);
+    if (threadIdx.x == 0) {
+      st->nu = tot;
+      st->cnt_a = 0;
+    }
+  }
+}
+
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+static int grid_for(int64_t work, int per_block, int cap) {
+  int64_t b = (work + per_block - 1) / per_block;
+  if (b > cap) b = cap;
+  return (int)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_prep(const int32_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz, uint8_t* dangling,
+                           int32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, dangling, n, (uint8_t)1);
+  hipLaunchKernelGGL(k_csr_check, dim3(grid_for(n > nnz ? n : nnz, 256, 8192)), dim3(256), 0, s, row_ptr, col, n,
+                     nnz, dangling, err);
+  return hipGetLastError();
+}
+
+int pr_scalar_blocks(int64_t n) { return grid_for(n, 1024, 1024); }
+
+hipError_t launch_pr_scalars(int method, const float* w, int64_t n, const uint8_t* dangling, double c, double inv_n,
+                             SolveState* st, double* part, hipStream_t s) {
+  const int b = pr_scalar_blocks(n);
+  if (method == MAPI_METHOD_MAPI)
+    hipLaunchKernelGGL(k_pr_scalars<MAPI_METHOD_MAPI>, dim3(b), dim3(256), 0, s, w, n, dangling, c, inv_n, st, part);
+  else
+    hipLaunchKernelGGL(k_pr_scalars<MAPI_METHOD_RPI>, dim3(b), dim3(256), 0, s, w, n, dangling, c, inv_n, st, part);
+  return hipGetLastError();
+}
+
+constexpr int kCsrGroup = 8;
+
+int csr_part_count(int64_t n) { return grid_for(n, 256 / kCsrGroup, 4096); }
+
+hipError_t launch_csr_product(int method, const int32_t* row_ptr, const int32_t* col, const float* val, int64_t n,
+                              const float* w, float* y, double* part, SolveState* st, float alpha, float c,
+                              double inv_n, hipStream_t s) {
+  const int b = csr_part_count(n);
+  if (method == MAPI_METHOD_MAPI)
+    hipLaunchKernelGGL((k_csr_product<MAPI_METHOD_MAPI, kCsrGroup>), dim3(b), dim3(256), 0, s, row_ptr, col, val, n, w,
+                       y, part, st, alpha, c, inv_n);
+  else
+    hipLaunchKernelGGL((k_csr_product<MAPI_METHOD_RPI, kCsrGroup>), dim3(b), dim3(256), 0, s, row_ptr, col, val, n, w,
+                       y, part, st, alpha, c, inv_n);
+  return hipGetLastError();
+}
+
+}  // namespace mapi

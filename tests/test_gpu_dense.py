@@ -1,0 +1,227 @@
+"""GPU parity of the dense path (product, MAPI, RPI, storage formats) against the FP64 oracle.
+
+Calls go through the C-ABI (libmapi.so via the ctypes binding).  Tolerances:
+bit-exact where every partial sum is exact in float32 (dyadic inputs) and for
+the storage encoders; otherwise relative l1 <= 1e-5 and cosine > 1 - 1e-6
+against the oracle iterate at the same iteration count.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import cosine, rel_l1, report, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2110_12065_amd as mp  # noqa: E402
+
+TOL = 1e-5
+COS = 1 - 1e-6
+
+
+def _stored(A32, dtype):
+    """Device copy of A in storage `dtype` plus the float32 matrix it decodes to (oracle side)."""
+    if dtype == "f32":
+        return to_dev(A32), None, A32
+    if dtype == "bf16":
+        q = oracle.bf16_encode(A32)
+        return to_dev(q.view(np.int16)), None, oracle.bf16_decode(q)
+    q = oracle.e4m3fn_encode(A32)
+    s = np.ones(A32.shape[0], np.float32)
+    return to_dev(q), to_dev(s), oracle.fp8_rows_dequantize(q, s)
+
+
+SHAPES = [(1, 1), (3, 5), (64, 100), (257, 1031), (1000, 4099), (4096, 256), (33, 16400)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("op", ["min1", "min2", "diamond", "dot"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_mavp_dyadic_bitexact(dtype, op, shape):
+    m, n = shape
+    print(f"[case] mavp dyadic {dtype} {op} {shape}", flush=True)
+    A = synth.dyadic_matrix(m, n, seed=m * 7 + n)
+    w = synth.dyadic_vector(n, seed=m + 3 * n + 1)
+    Ad, rs, Aref = _stored(A, dtype)
+    np.testing.assert_array_equal(Aref, A)          # dyadic values are exact in every format
+    y = mp.mapi_mavp(Ad, to_dev(w), op=op, row_scale=rs).cpu().numpy()
+    ref = oracle.mavp(A, w, op).astype(np.float32)
+    np.testing.assert_array_equal(y, ref)
+
+
+def test_fp8_decode_every_code():
+    codes = np.arange(256, dtype=np.uint8)
+    codes[[0x7F, 0xFF]] = 0
+    A = np.zeros((256, 16), np.uint8)
+    A[:, 0] = codes
+    w = np.full(16, 1e30, np.float32)               # min1(a, w) = a for every finite a
+    for scale in (1.0, 3.0):
+        s = np.full(256, scale, np.float32)
+        y = mp.mapi_mavp(to_dev(A), to_dev(w), "min1", row_scale=to_dev(s)).cpu().numpy()
+        ref = (np.float32(scale) * oracle.e4m3fn_decode(codes)).astype(np.float32)
+        np.testing.assert_array_equal(y, ref)
+
+
+def test_quantizers_bitexact():
+    rng = np.random.default_rng(5)
+    A = (rng.standard_normal((300, 1001)) * np.exp(rng.uniform(-8, 8, (300, 1)))).astype(np.float32)
+    A[7] = 0.0
+    A[8, :5] = [448.0 * 3, -1e-30, 0.0, -0.0, 1e-8]
+    Ad = to_dev(A)
+    qb, _ = mp.mapi_quantize(Ad, "bf16")
+    np.testing.assert_array_equal(qb.cpu().numpy().view(np.uint16), oracle.bf16_encode(A))
+    q8, s8 = mp.mapi_quantize(Ad, "fp8")
+    q_ref, s_ref = oracle.fp8_rows_quantize(A)
+    np.testing.assert_array_equal(s8.cpu().numpy(), s_ref)
+    np.testing.assert_array_equal(q8.cpu().numpy(), q_ref)
+
+
+@pytest.mark.parametrize("T", [1, 3, 20, 200])
+def test_mapi_and_rpi_match_oracle_n256(T):
+    # the n = 256 workload: C = X X^T / 1024, rows of X centred, b0 ~ U(-1, 1) scaled to unit l2
+    C = synth.dense_cov(256, 1024, seed=11)
+    w0 = synth.start_vector(256, 12)
+    Cd, wd = to_dev(C), to_dev(w0)
+    w, info = mp.mapi_solve(Cd, wd, max_iters=T)
+    assert info["iters"] == T and info["status"] == "OK"
+    ref = oracle.mapi(C.astype(np.float64), w0, T)
+    e, c = report(f"mapi n=256 T={T}", w.cpu().numpy(), ref.w)
+    assert e <= TOL and c > COS
+    assert abs(info["residual"] - ref.residuals[-1]) <= 1e-4 * ref.residuals[-1] + 1e-7
+    b, info_r = mp.rpi_solve(Cd, wd, max_iters=T)
+    ref_r = oracle.rpi(C.astype(np.float64), w0, T)
+    e, c = report(f"rpi n=256 T={T}", b.cpu().numpy(), ref_r.w)
+    assert e <= TOL and c > COS
+    assert info_r["norm"] == pytest.approx(ref_r.norms[-1], rel=1e-6)
+
+
+def test_tolerance_stop_compared_at_gpu_iteration_count():
+    A, Q, d = synth.planted_symmetric(300, [0.4], seed=21)
+    w0 = synth.start_vector(300, 22)
+    for solver, ref_fn in ((mp.mapi_solve, oracle.mapi), (mp.rpi_solve, oracle.rpi)):
+        w, info = solver(to_dev(A), to_dev(w0), max_iters=500, tol=1e-6, check_every=7)
+        assert info["converged"] and info["residual"] < 1e-6
+        t = info["iters"]
+        ref = ref_fn(A.astype(np.float64), w0, t)
+        assert rel_l1(w.cpu().numpy(), ref.w) <= TOL
+        stop = ref_fn(A.astype(np.float64), w0, 500, tol=1e-6)
+        assert abs(stop.iters - t) <= 2
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 65, 1000, 3001])
+def test_ragged_sizes(n):
+    C = synth.dense_cov(n, 2 * n + 3, seed=n)
+    w0 = synth.start_vector(n, n + 1)
+    for op in ("min1", "min2"):
+        w, info = mp.mapi_solve(to_dev(C), to_dev(w0), max_iters=30, op=op)
+        ref = oracle.mapi(C.astype(np.float64), w0, 30, op=op)
+        assert rel_l1(w.cpu().numpy(), ref.w) <= TOL, op
+    b, _ = mp.rpi_solve(to_dev(C), to_dev(w0), max_iters=30)
+    assert rel_l1(b.cpu().numpy(), oracle.rpi(C.astype(np.float64), w0, 30).w) <= TOL
+
+
+def test_zero_iterations_returns_start():
+    C = synth.dense_cov(40, 80, seed=1)
+    w0 = synth.start_vector(40, 2)
+    w, info = mp.mapi_solve(to_dev(C), to_dev(w0), max_iters=0)
+    np.testing.assert_array_equal(w.cpu().numpy(), w0)
+    assert info["iters"] == 0
+
+
+def test_degenerate_matrix_is_reported():
+    A = np.zeros((64, 64), np.float32)
+    with pytest.raises(mp.MapiError) as ei:
+        mp.mapi_solve(to_dev(A), to_dev(synth.start_vector(64, 1)), max_iters=5)
+    assert ei.value.status == 4
+
+
+def test_final_l2_and_alias():
+    C = synth.dense_cov(128, 300, seed=3)
+    w0 = synth.start_vector(128, 4)
+    wd = to_dev(w0)
+    w, _ = mp.mapi_solve(to_dev(C), wd, max_iters=15, final_l2=True, w_out=wd)
+    ref = oracle.mapi(C.astype(np.float64), w0, 15, final_l2=True)
+    assert rel_l1(wd.cpu().numpy(), ref.w) <= TOL
+    assert abs(np.linalg.norm(wd.cpu().numpy().astype(np.float64)) - 1) < 1e-6
+
+
+def test_diamond_proposition1_on_gpu():
+    rng = np.random.default_rng(10)
+    A = rng.uniform(0.1, 2.0, size=(200, 200)).astype(np.float32)
+    w0 = rng.uniform(0.1, 1.0, size=200).astype(np.float32)
+    row = 1.0 + np.abs(A.astype(np.float64)).sum(axis=1)
+    target = row / row.sum()
+    w, _ = mp.mapi_solve(to_dev(A), to_dev(w0), max_iters=2, op="diamond")
+    assert rel_l1(w.cpu().numpy(), target) <= 1e-6
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_reduced_storage_solve_matches_oracle_on_stored_matrix(dtype):
+    C = synth.dense_cov(512, 1024, seed=31)
+    w0 = synth.start_vector(512, 32)
+    q, s = mp.mapi_quantize(to_dev(C), dtype)
+    if dtype == "bf16":
+        Aref = oracle.bf16_decode(oracle.bf16_encode(C))
+    else:
+        qo, so = oracle.fp8_rows_quantize(C)
+        Aref = oracle.fp8_rows_dequantize(qo, so)
+    for T in (1, 50):
+        w, _ = mp.mapi_solve(q, to_dev(w0), max_iters=T, row_scale=s)
+        ref = oracle.mapi(Aref.astype(np.float64), w0, T)
+        e, c = report(f"mapi {dtype} T={T} vs oracle on stored matrix", w.cpu().numpy(), ref.w)
+        assert e <= TOL and c > COS
+        full = oracle.mapi(C.astype(np.float64), w0, T)
+        report(f"mapi {dtype} T={T} vs oracle on float32 matrix (reported)", w.cpu().numpy(), full.w)
+        b, _ = mp.rpi_solve(q, to_dev(w0), max_iters=T, row_scale=s)
+        ref_b = oracle.rpi(Aref.astype(np.float64), w0, T)
+        assert rel_l1(b.cpu().numpy(), ref_b.w) <= TOL
+
+
+def test_timing_counts_product_launches():
+    C = synth.dense_cov(256, 512, seed=5)
+    ctx = mp.default_context()
+    ctx.timing(True)
+    ctx.timing_reset()
+    mp.mapi_solve(to_dev(C), to_dev(synth.start_vector(256, 6)), max_iters=9)
+    ms, n = ctx.timing_get("mavp")
+    ctx.timing(False)
+    assert n == 9 and ms > 0
+
+
+def test_full_size_n16384_sampled_rows_and_iterates():
+    # the n = 16384 workload (C = X X^T / 32768), float32 storage, as the benchmark runs it
+    n = 16384
+    print("[case] full n=16384 generate", flush=True)
+    C = synth.dense_cov(n, 32768, seed=2024, device="cuda")
+    w0 = synth.start_vector(n, 2025)
+    wd = to_dev(w0)
+    y = mp.mapi_mavp(C, wd).cpu().numpy()
+    Ch = C.cpu().numpy()
+    rng = np.random.default_rng(0)
+    rows = np.concatenate([[0, n - 1], rng.choice(n, 62, replace=False)])
+    for i in rows:
+        terms = oracle.term_min1(Ch[i], w0)
+        assert abs(y[i] - terms.sum()) <= TOL * np.abs(terms).sum()
+    print("[case] full n=16384 T=3 vs oracle", flush=True)
+    w, _ = mp.mapi_solve(C, wd, max_iters=3)
+    ref = oracle.mapi(Ch.astype(np.float64), w0, 3)
+    e, c = report("mapi n=16384 T=3", w.cpu().numpy(), ref.w)
+    assert e <= TOL and c > COS
+    for dtype in ("bf16", "fp8"):
+        q, s = mp.mapi_quantize(C, dtype)
+        qh = q.cpu().numpy()
+        y = mp.mapi_mavp(q, wd, row_scale=s).cpu().numpy()
+        for i in rows[:16]:
+            if dtype == "bf16":
+                qi = oracle.bf16_encode(Ch[i])
+                np.testing.assert_array_equal(qh[i].view(np.uint16), qi)
+                ai = oracle.bf16_decode(qi)
+            else:
+                qi, si = oracle.fp8_rows_quantize(Ch[i][None, :])
+                np.testing.assert_array_equal(qh[i], qi[0])
+                assert s[i].item() == si[0]
+                ai = oracle.fp8_rows_dequantize(qi, si)[0]
+            terms = oracle.term_min1(ai, w0)
+            assert abs(y[i] - terms.sum()) <= TOL * np.abs(terms).sum()
