@@ -1,0 +1,91 @@
+"""GPU parity of the Gram builds (eq. 5 min-covariance, eq. 2 covariance) and top-k PCA with deflation."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import cosine, rel_l1, report, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2110_12065_amd as mp  # noqa: E402
+
+TOL = 1e-5
+
+
+@pytest.mark.parametrize("op", ["min1", "min2", "dot"])
+@pytest.mark.parametrize("shape", [(1, 1), (5, 7), (64, 300), (130, 1000), (200, 4099)])
+def test_gram_dyadic_bitexact(op, shape):
+    D, N = shape
+    print(f"[case] gram dyadic {op} {shape}", flush=True)
+    X = synth.dyadic_matrix(D, N, seed=D * 13 + N)
+    A = mp.mapi_mingram(to_dev(X), 0.25, op).cpu().numpy()
+    ref = oracle.mingram(X, 0.25, op).astype(np.float32)
+    np.testing.assert_array_equal(A, ref)
+
+
+@pytest.mark.parametrize("op", ["min1", "dot"])
+def test_gram_random_within_bound(op):
+    D, N = 256, 4096
+    X = synth.pca_data(D, N, seed=3)
+    scale = 1.0 / N
+    A = mp.mapi_mingram(to_dev(X), scale, op).cpu().numpy().astype(np.float64)
+    ref = oracle.mingram(X, scale, op)
+    absum = oracle.mingram(np.abs(X), scale, "min1" if op == "min1" else "dot")
+    assert np.all(np.abs(A - ref) <= TOL * absum + 1e-30)
+    np.testing.assert_array_equal(A, A.T)
+    if op == "min1":
+        np.testing.assert_allclose(np.diag(A), scale * np.abs(X.astype(np.float64)).sum(axis=1), rtol=1e-6)
+
+
+@pytest.mark.parametrize("method", ["mapi", "rpi"])
+def test_pca_topk_matches_oracle(method):
+    D, N, k, T = 256, 4096, 4, 40
+    X = synth.pca_data(D, N, seed=5)
+    W0 = synth.start_vectors(D, k, seed=6)
+    P, infos = mp.mapi_pca_topk(to_dev(X), k, to_dev(W0), method=method, max_iters=T)
+    P = P.cpu().numpy().astype(np.float64)
+    Pr, res = oracle.pca_topk(X, k, W0, method=method, T=T)
+    for i in range(k):
+        assert infos[i]["iters"] == T
+        e, c = report(f"pca {method} vector {i}", P[:, i], Pr[:, i])
+        assert e <= TOL and c > 1 - 1e-6
+    np.testing.assert_allclose(P.T @ P, np.eye(k), atol=1e-6)
+
+
+def test_pca_topk_tolerance_per_vector():
+    D, N, k = 128, 2048, 3
+    X = synth.pca_data(D, N, seed=7)
+    W0 = synth.start_vectors(D, k, seed=8)
+    P, infos = mp.mapi_pca_topk(to_dev(X), k, to_dev(W0), method="rpi", max_iters=2000, tol=1e-6, check_every=8)
+    A = oracle.covariance(X, 1.0 / N)
+    lam, V = np.linalg.eigh(A)
+    P = P.cpu().numpy()
+    for i in range(k):
+        assert infos[i]["converged"]
+        assert abs(cosine(P[:, i], V[:, -1 - i])) > 1 - 1e-5
+
+
+def test_full_size_gram_sampled_entries():
+    # the PCA workload: D = 4096 coordinates x N = 65536 samples, 16 factors + noise + 5 % Laplace outliers
+    D, N = 4096, 65536
+    print("[case] full PCA generate", flush=True)
+    X = synth.pca_data(D, N, seed=77)
+    Xd = to_dev(X)
+    print("[case] full PCA gram", flush=True)
+    A = mp.mapi_mingram(Xd, 1.0 / N, "min1").cpu().numpy()
+    np.testing.assert_array_equal(A, A.T)
+    rng = np.random.default_rng(1)
+    pairs = [(0, 0), (D - 1, D - 1), (0, D - 1), (63, 64), (64, 63)] + [tuple(p) for p in rng.integers(0, D, (40, 2))]
+    for i, j in pairs:
+        ref = oracle.mingram_entry(X, i, j, 1.0 / N)
+        bound = oracle.mingram_entry(np.abs(X[[i]]), 0, 0, 1.0 / N) if i == j else \
+            float(np.sum(np.minimum(np.abs(X[i].astype(np.float64)), np.abs(X[j].astype(np.float64)))) / N)
+        assert abs(A[i, j] - ref) <= TOL * bound, (i, j)
+    print("[case] full PCA top-8", flush=True)
+    W0 = synth.start_vectors(D, 8, seed=78)
+    P, infos = mp.mapi_pca_topk(Xd, 8, to_dev(W0), method="mapi", max_iters=50)
+    P = P.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(P.T @ P, np.eye(8), atol=1e-6)
+    assert all(i["iters"] == 50 for i in infos)
