@@ -135,6 +135,40 @@ mapi_status mapi_timing_reset(mapi_ctx* ctx);
  * A: n_rows x n_cols (any dtype); w: device float[n_cols]; y: device float[n_rows]. */
 mapi_status mapi_mavp(mapi_ctx* ctx, const mapi_dense* A, const float* w, float* y, int32_t op);
 
+/* ---------------------------------------------------------------- launch shapes */
+
+/* Launch shape of the dense product kernel.  Results of the product y are
+ * bitwise independent of the shape; the float64 normaliser's summation order
+ * depends on it, so one shape is kept per size bucket.                          */
+typedef struct mapi_tuning {
+  int32_t rows_per_wave;     /* 1, 2, 4 or 8 rows share each staged w value      */
+  int32_t waves;             /* waves per block: 4 or 8                            */
+  int32_t blocks_per_cu;     /* grid = compute units * blocks_per_cu (1..16)       */
+  int32_t unroll;            /* 16-byte loads in flight per row and lane: 2 or 4   */
+  int32_t w_in_lds;          /* stage w in LDS (needs 4 * n_cols bytes per block)  */
+  int32_t nontemporal;       /* non-temporal matrix loads                          */
+} mapi_tuning;
+
+/* Autotuner (project-written): times every admissible launch shape on A with
+ * product `op` (`reps` launches each, HIP events on the context stream) and
+ * stores the fastest in the context's table for A's bucket (storage type,
+ * ceil(log2 n_rows), ceil(log2 n_cols)); later products and solves in that
+ * bucket use it.  If the environment variable MAPI_TUNE_CACHE names a file,
+ * tuned entries are appended to it and read back by mapi_create.
+ * best / best_ms (optional, host) receive the choice and its mean time.        */
+mapi_status mapi_autotune_dense(mapi_ctx* ctx, const mapi_dense* A, int32_t op, int32_t reps,
+                                mapi_tuning* best, double* best_ms);
+/* Read or overwrite the table entry used for a (dtype, n_rows, n_cols) bucket. */
+mapi_status mapi_tuning_get(mapi_ctx* ctx, int32_t dtype, int64_t n_rows, int64_t n_cols, mapi_tuning* out);
+mapi_status mapi_tuning_set(mapi_ctx* ctx, int32_t dtype, int64_t n_rows, int64_t n_cols, const mapi_tuning* t);
+/* Mean time in ms of `reps` products y = A (+) w with an explicit launch shape. */
+mapi_status mapi_mavp_timed(mapi_ctx* ctx, const mapi_dense* A, const float* w, float* y, int32_t op,
+                            const mapi_tuning* t, int32_t reps, double* avg_ms);
+/* Bandwidth reference: mean time in ms of `reps` plain 16-byte-vector copies of
+ * `bytes` (multiple of 16) from src to dst (device, 16-byte aligned).            */
+mapi_status mapi_copy_reference(mapi_ctx* ctx, const void* src, void* dst, size_t bytes, int32_t reps,
+                                double* avg_ms);
+
 /* ---------------------------------------------------------------- solvers */
 
 /* MAPI, eq. (6) and Algorithm 1: w <- (A (+) w) / ||A (+) w||_1 for at most

@@ -46,6 +46,14 @@ class Opts(C.Structure):
                 ("check_every", C.c_int32), ("stall_iters", C.c_int32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("rows_per_wave", C.c_int32), ("waves", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("unroll", C.c_int32), ("w_in_lds", C.c_int32), ("nontemporal", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("residual", C.c_double), ("norm", C.c_double),
                 ("status", C.c_int32)]
@@ -69,6 +77,14 @@ _SIGS = {
     "mapi_timing_get": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "mapi_timing_reset": (C.c_int, [C.c_void_p]),
     "mapi_mavp": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.c_int32]),
+    "mapi_autotune_dense": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_int32, C.c_int32, C.POINTER(Tuning),
+                                      C.POINTER(C.c_double)]),
+    "mapi_tuning_get": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.POINTER(Tuning)]),
+    "mapi_tuning_set": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.POINTER(Tuning)]),
+    "mapi_mavp_timed": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.c_int32,
+                                  C.POINTER(Tuning), C.c_int32, C.POINTER(C.c_double)]),
+    "mapi_copy_reference": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32,
+                                      C.POINTER(C.c_double)]),
     "mapi_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]),
     "rpi_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]),
     "mapi_quantize": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_void_p,
@@ -328,3 +344,54 @@ def mapi_pagerank(row_ptr, col, val, alpha=0.85, method="mapi", w0=None, max_ite
                                C.c_void_p(_vec(w0, n, "w0")) if w0 is not None else None,
                                C.c_void_p(_vec(w_out, n, "w_out")), C.byref(o), C.byref(info)))
     return w_out, info.as_dict()
+
+
+# ------------------------------------------------------------------ launch shapes
+def mapi_autotune_dense(A, op="min1", reps=3, row_scale=None, ctx=None):
+    """Time every launch shape of the dense product on A and keep the fastest for A's size bucket.
+    Returns (shape dict, mean ms)."""
+    c = _ctx_of(ctx, A)
+    d = _dense(A, row_scale)
+    best = Tuning()
+    ms = C.c_double()
+    _check(lib().mapi_autotune_dense(c.handle, C.byref(d), OPS[op], int(reps), C.byref(best), C.byref(ms)))
+    return best.as_dict(), ms.value
+
+
+def mapi_tuning_get(dtype_code, n_rows, n_cols, ctx=None):
+    c = ctx if ctx is not None else default_context()
+    t = Tuning()
+    _check(lib().mapi_tuning_get(c.handle, int(dtype_code), int(n_rows), int(n_cols), C.byref(t)))
+    return t.as_dict()
+
+
+def mapi_tuning_set(dtype_code, n_rows, n_cols, shape, ctx=None):
+    c = ctx if ctx is not None else default_context()
+    t = Tuning(**shape)
+    _check(lib().mapi_tuning_set(c.handle, int(dtype_code), int(n_rows), int(n_cols), C.byref(t)))
+
+
+def mapi_mavp_timed(A, w, shape, op="min1", reps=5, row_scale=None, y=None, ctx=None):
+    """Mean ms of `reps` products with an explicit launch shape (dict of mapi_tuning fields)."""
+    import torch
+    c = _ctx_of(ctx, A)
+    d = _dense(A, row_scale)
+    if y is None:
+        y = torch.empty(A.shape[0], dtype=torch.float32, device=A.device)
+    t = Tuning(**shape)
+    ms = C.c_double()
+    _check(lib().mapi_mavp_timed(c.handle, C.byref(d), C.c_void_p(_vec(w, A.shape[1], "w")),
+                                 C.c_void_p(_vec(y, A.shape[0], "y")), OPS[op], C.byref(t), int(reps), C.byref(ms)))
+    return ms.value
+
+
+def mapi_copy_reference(src, dst, reps=5, ctx=None):
+    """Mean ms of a plain 16-byte-vector copy of src into dst (the bandwidth reference)."""
+    c = _ctx_of(ctx, src)
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst smaller than src")
+    ms = C.c_double()
+    _check(lib().mapi_copy_reference(c.handle, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
+                                     int(reps), C.byref(ms)))
+    return ms.value

@@ -3,8 +3,11 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "common.h"
@@ -64,6 +67,8 @@ struct mapi_ctx {
   std::vector<hipEvent_t> pool;
   double t_ms[MAPI_K_KINDS] = {};
   int64_t t_n[MAPI_K_KINDS] = {};
+  // autotuned launch shapes of the dense product per (dtype, log2 rows, log2 cols)
+  std::map<std::tuple<int, int, int>, DenseTuning> tuned;
 };
 
 namespace {
@@ -177,6 +182,77 @@ DenseArgs dense_args(const mapi_dense* A) {
   return DenseArgs{A->data, A->ld, A->n_rows, A->n_cols, A->dtype, A->row_scale};
 }
 
+int ceil_log2(int64_t x) {
+  int k = 0;
+  while ((int64_t(1) << k) < x) ++k;
+  return k;
+}
+
+std::tuple<int, int, int> bucket(int dtype, int64_t rows, int64_t cols) {
+  return std::make_tuple(dtype, ceil_log2(rows), ceil_log2(cols));
+}
+
+DenseTuning tuning_for(mapi_ctx* c, const DenseArgs& a) {
+  DenseTuning t = dense_default_tuning(a, c->cu_count, c->max_lds);
+  auto it = c->tuned.find(bucket(a.dtype, a.n_rows, a.n_cols));
+  if (it != c->tuned.end()) {
+    t = it->second;
+    if (t.w_in_lds && a.n_cols * 4 + 1024 > c->max_lds) t.w_in_lds = 0;   // bucket spans sizes past the LDS
+  }
+  return t;
+}
+
+mapi_status to_dense_tuning(const mapi_tuning* u, DenseTuning* t) {
+  if (!u) return fail(MAPI_ERR_ARG, "tuning is NULL");
+  const int rw = u->rows_per_wave;
+  if (!(rw == 1 || rw == 2 || rw == 4 || rw == 8)) return fail(MAPI_ERR_ARG, "rows_per_wave must be 1, 2, 4 or 8");
+  if (u->waves != 4 && u->waves != 8) return fail(MAPI_ERR_ARG, "waves must be 4 or 8");
+  if (u->blocks_per_cu < 1 || u->blocks_per_cu > 16) return fail(MAPI_ERR_ARG, "blocks_per_cu must be in 1..16");
+  if (u->unroll != 2 && u->unroll != 4) return fail(MAPI_ERR_ARG, "unroll must be 2 or 4");
+  t->rows_per_wave = rw;
+  t->waves = u->waves;
+  t->blocks = 0;
+  t->blocks_per_cu = u->blocks_per_cu;
+  t->unroll = u->unroll;
+  t->w_in_lds = u->w_in_lds ? 1 : 0;
+  t->nontemporal = u->nontemporal ? 1 : 0;
+  return MAPI_OK;
+}
+
+void from_dense_tuning(const DenseTuning& t, int cu_count, mapi_tuning* u) {
+  u->rows_per_wave = t.rows_per_wave;
+  u->waves = t.waves;
+  u->blocks_per_cu = t.blocks_per_cu > 0 ? t.blocks_per_cu : (t.blocks > 0 ? (t.blocks + cu_count - 1) / cu_count : 0);
+  u->unroll = t.unroll;
+  u->w_in_lds = t.w_in_lds;
+  u->nontemporal = t.nontemporal;
+}
+
+void load_tune_cache(mapi_ctx* c) {
+  const char* path = std::getenv("MAPI_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  int dt, rb, cb, rw, wv, bpc, un, lds, nt;
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d", &dt, &rb, &cb, &rw, &wv, &bpc, &un, &lds, &nt) == 9) {
+    mapi_tuning u{rw, wv, bpc, un, lds, nt};
+    DenseTuning t;
+    if (to_dense_tuning(&u, &t) == MAPI_OK) c->tuned[std::make_tuple(dt, rb, cb)] = t;
+  }
+  std::fclose(f);
+  g_err.clear();
+}
+
+void save_tune_entry(const std::tuple<int, int, int>& k, const DenseTuning& t) {
+  const char* path = std::getenv("MAPI_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), t.rows_per_wave,
+               t.waves, t.blocks_per_cu, t.unroll, t.w_in_lds, t.nontemporal);
+  std::fclose(f);
+}
+
 void fill_info(mapi_info* info, const SolveState& s) {
   if (!info) return;
   info->iters = s.iter;
@@ -198,7 +274,7 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
     return fail(MAPI_ERR_ARG, "op %d is not a MAPI product", o->op);
   const int64_t n = A->n_rows;
   const DenseArgs da = dense_args(A);
-  const DenseTuning t = dense_default_tuning(da, c->cu_count, c->max_lds);
+  const DenseTuning t = tuning_for(c, da);
   const int P = dense_part_count(da, t, c->cu_count);
   const int F = finalize_blocks(n);
   Layout L;
@@ -266,6 +342,7 @@ mapi_status mapi_create(int device, void* hip_stream, mapi_ctx** out) {
     c->cu_count = prop.multiProcessorCount;
     if (prop.sharedMemPerBlock > 0) c->max_lds = (int)prop.sharedMemPerBlock;
   }
+  load_tune_cache(c);
   if (hipHostMalloc(reinterpret_cast<void**>(&c->st_host), sizeof(SolveState), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return fail(MAPI_ERR_ALLOC, "pinned host allocation failed");
@@ -330,7 +407,7 @@ mapi_status mapi_mavp(mapi_ctx* c, const mapi_dense* A, const float* w, float* y
   if (op < MAPI_OP_MIN1 || op > MAPI_OP_DOT) return fail(MAPI_ERR_ARG, "unknown op %d", op);
   HIP_TRY(hipSetDevice(c->device));
   const DenseArgs da = dense_args(A);
-  const DenseTuning t = dense_default_tuning(da, c->cu_count, c->max_lds);
+  const DenseTuning t = tuning_for(c, da);
   const float* wv = w;
   if (!aligned16(w)) {
     if ((s = ensure(&c->ws, &c->ws_bytes, sizeof(float) * (size_t)A->n_cols, c)) != MAPI_OK) return s;
@@ -343,6 +420,123 @@ mapi_status mapi_mavp(mapi_ctx* c, const mapi_dense* A, const float* w, float* y
   }
   HIP_TRY(hipStreamSynchronize(c->stream));
   collect_timing(c);
+  return MAPI_OK;
+}
+
+static mapi_status time_product(mapi_ctx* c, const DenseArgs& da, int op, const float* w, float* y,
+                                const DenseTuning& t, int reps, double* avg_ms) {
+  hipEvent_t a = get_event(c), b = get_event(c);
+  if (!a || !b) return fail(MAPI_ERR_HIP, "event creation failed");
+  HIP_TRY(launch_mavp_dense(da, op, w, y, nullptr, nullptr, NORM_NONE, t, c->cu_count, c->stream));   // warm
+  HIP_TRY(hipEventRecord(a, c->stream));
+  for (int r = 0; r < reps; ++r)
+    HIP_TRY(launch_mavp_dense(da, op, w, y, nullptr, nullptr, NORM_NONE, t, c->cu_count, c->stream));
+  HIP_TRY(hipEventRecord(b, c->stream));
+  HIP_TRY(hipEventSynchronize(b));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, a, b));
+  c->pool.push_back(a);
+  c->pool.push_back(b);
+  *avg_ms = ms / reps;
+  return MAPI_OK;
+}
+
+mapi_status mapi_mavp_timed(mapi_ctx* c, const mapi_dense* A, const float* w, float* y, int32_t op,
+                            const mapi_tuning* tu, int32_t reps, double* avg_ms) {
+  if (!c || !avg_ms) return fail(MAPI_ERR_ARG, "ctx or avg_ms is NULL");
+  mapi_status s;
+  if ((s = check_dense(A, false)) != MAPI_OK) return s;
+  if (!w || !y || !aligned16(w)) return fail(MAPI_ERR_ARG, "w (16-byte aligned) and y must be device pointers");
+  if (op < MAPI_OP_MIN1 || op > MAPI_OP_DOT) return fail(MAPI_ERR_ARG, "unknown op %d", op);
+  if (reps < 1) return fail(MAPI_ERR_ARG, "reps must be >= 1");
+  DenseTuning t;
+  if ((s = to_dense_tuning(tu, &t)) != MAPI_OK) return s;
+  const DenseArgs da = dense_args(A);
+  if (t.w_in_lds && da.n_cols * 4 + 1024 > c->max_lds) return fail(MAPI_ERR_ARG, "w does not fit in LDS");
+  HIP_TRY(hipSetDevice(c->device));
+  return time_product(c, da, op, w, y, t, reps, avg_ms);
+}
+
+mapi_status mapi_autotune_dense(mapi_ctx* c, const mapi_dense* A, int32_t op, int32_t reps, mapi_tuning* best,
+                                double* best_ms) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  mapi_status s;
+  if ((s = check_dense(A, false)) != MAPI_OK) return s;
+  if (op < MAPI_OP_MIN1 || op > MAPI_OP_DOT) return fail(MAPI_ERR_ARG, "unknown op %d", op);
+  if (reps < 1) reps = 3;
+  HIP_TRY(hipSetDevice(c->device));
+  const DenseArgs da = dense_args(A);
+  Layout L;
+  const size_t o_w = L.take(sizeof(float) * da.n_cols);
+  const size_t o_y = L.take(sizeof(float) * da.n_rows);
+  if ((s = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return s;
+  float* w = reinterpret_cast<float*>(static_cast<char*>(c->ws) + o_w);
+  float* y = reinterpret_cast<float*>(static_cast<char*>(c->ws) + o_y);
+  HIP_TRY(launch_fill_f32(w, da.n_cols, 1.0f / (float)da.n_cols, c->stream));
+  const bool lds_ok = da.n_cols * 4 + 1024 <= c->max_lds;
+  DenseTuning bt = dense_default_tuning(da, c->cu_count, c->max_lds);
+  double bms = 1e30;
+  for (int rw : {1, 2, 4, 8}) {
+    if (rw > 1 && rw > da.n_rows) continue;
+    for (int waves : {4, 8})
+      for (int bpc : {1, 2, 4, 8})
+        for (int un : {2, 4})
+          for (int lds = 0; lds <= (lds_ok ? 1 : 0); ++lds)
+            for (int nt = 0; nt <= 1; ++nt) {
+              DenseTuning t{rw, waves, 0, lds, bpc, un, nt};
+              double ms = 0.0;
+              if ((s = time_product(c, da, op, w, y, t, reps, &ms)) != MAPI_OK) return s;
+              if (ms < bms) {
+                bms = ms;
+                bt = t;
+              }
+            }
+  }
+  const auto key = bucket(da.dtype, da.n_rows, da.n_cols);
+  c->tuned[key] = bt;
+  save_tune_entry(key, bt);
+  if (best) from_dense_tuning(bt, c->cu_count, best);
+  if (best_ms) *best_ms = bms;
+  return MAPI_OK;
+}
+
+mapi_status mapi_tuning_get(mapi_ctx* c, int32_t dtype, int64_t n_rows, int64_t n_cols, mapi_tuning* out) {
+  if (!c || !out) return fail(MAPI_ERR_ARG, "ctx or out is NULL");
+  if (n_rows <= 0 || n_cols <= 0 || elem_size(dtype) == 0) return fail(MAPI_ERR_ARG, "bad bucket");
+  DenseArgs da{nullptr, n_cols, n_rows, n_cols, dtype, nullptr};
+  from_dense_tuning(tuning_for(c, da), c->cu_count, out);
+  return MAPI_OK;
+}
+
+mapi_status mapi_tuning_set(mapi_ctx* c, int32_t dtype, int64_t n_rows, int64_t n_cols, const mapi_tuning* tu) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  if (n_rows <= 0 || n_cols <= 0 || elem_size(dtype) == 0) return fail(MAPI_ERR_ARG, "bad bucket");
+  DenseTuning t;
+  mapi_status s;
+  if ((s = to_dense_tuning(tu, &t)) != MAPI_OK) return s;
+  c->tuned[bucket(dtype, n_rows, n_cols)] = t;
+  return MAPI_OK;
+}
+
+mapi_status mapi_copy_reference(mapi_ctx* c, const void* src, void* dst, size_t bytes, int32_t reps,
+                                double* avg_ms) {
+  if (!c || !src || !dst || !avg_ms) return fail(MAPI_ERR_ARG, "NULL argument");
+  if (bytes == 0 || bytes % 16 != 0 || !aligned16(src) || !aligned16(dst))
+    return fail(MAPI_ERR_ARG, "bytes must be a non-zero multiple of 16 and buffers 16-byte aligned");
+  if (reps < 1) return fail(MAPI_ERR_ARG, "reps must be >= 1");
+  HIP_TRY(hipSetDevice(c->device));
+  hipEvent_t a = get_event(c), b = get_event(c);
+  if (!a || !b) return fail(MAPI_ERR_HIP, "event creation failed");
+  HIP_TRY(launch_copy16(src, dst, bytes / 16, c->cu_count, c->stream));
+  HIP_TRY(hipEventRecord(a, c->stream));
+  for (int r = 0; r < reps; ++r) HIP_TRY(launch_copy16(src, dst, bytes / 16, c->cu_count, c->stream));
+  HIP_TRY(hipEventRecord(b, c->stream));
+  HIP_TRY(hipEventSynchronize(b));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, a, b));
+  c->pool.push_back(a);
+  c->pool.push_back(b);
+  *avg_ms = ms / reps;
   return MAPI_OK;
 }
 

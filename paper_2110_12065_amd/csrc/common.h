@@ -150,10 +150,13 @@ struct DenseArgs {
 };
 
 struct DenseTuning {
-  int rows_per_wave;   // 1, 2 or 4 rows share each staged w value
+  int rows_per_wave;   // 1, 2, 4 or 8 rows share each staged w value
   int waves;           // waves per block (4 or 8)
-  int blocks;          // grid size (persistent loop over row groups); 0 = auto
+  int blocks;          // grid size (persistent loop over row groups); 0 = from blocks_per_cu
   int w_in_lds;        // stage w in LDS (needs n_cols * 4 bytes of LDS per block)
+  int blocks_per_cu;   // grid = CUs * blocks_per_cu (0 = default)
+  int unroll;          // 16-byte loads in flight per row per lane (2 or 4)
+  int nontemporal;     // non-temporal matrix loads
 };
 
 hipError_t launch_state_init(SolveState* st, int max_iters, double tol, int stall_iters, hipStream_t s);
@@ -193,5 +196,6 @@ hipError_t launch_deflate_apply(const float* A, int64_t D, int64_t lda, const do
 hipError_t launch_mgs_append(double* P, int64_t D, int k, const float* w, float* p_out, hipStream_t s);
 int pr_scalar_blocks(int64_t n);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_copy16(const void* src, void* dst, int64_t n16, int cu_count, hipStream_t s);
 
 }  // namespace mapi

@@ -1,0 +1,248 @@
+// Dense product kernel y = A (+) w (Sec. 2.1 matrix extension of eqs. 3, 4, 7;
+// the ordinary product for RPI, eq. 1), templated on storage type, product,
+// rows per wave, loads in flight, LDS staging of w and non-temporal loads.
+// Included by one translation unit per storage type.
+//
+// Layout: A row-major, rows 16-byte aligned.  Each wave owns RW rows at a time
+// and its lanes stride along the columns with 16-byte loads (4 float32, 8 bf16
+// or 16 e4m3 values per lane per load), so one wave load covers 1 KiB of a row.
+// The RW rows share every staged w value and its sign.  Row sums use a fixed
+// butterfly across the wave; the block partials of the norm are summed in a
+// fixed order by the block that arrives last, so results do not depend on
+// timing.
+#pragma once
+#include "common.h"
+
+namespace mapi {
+
+template <int DT> struct Traits;
+template <> struct Traits<MAPI_F32> { static constexpr int VE = 4; static constexpr int ESZ = 4; };
+template <> struct Traits<MAPI_BF16> { static constexpr int VE = 8; static constexpr int ESZ = 2; };
+template <> struct Traits<MAPI_FP8_E4M3> { static constexpr int VE = 16; static constexpr int ESZ = 1; };
+
+// Decode one 16-byte vector of stored elements to float32 (FP8: times the row scale).
+template <int DT>
+__device__ __forceinline__ void decode_vec(const uint4 raw, float scale, float* out) {
+  const uint32_t wd[4] = {raw.x, raw.y, raw.z, raw.w};
+  if constexpr (DT == MAPI_F32) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = __uint_as_float(wd[k]);
+  } else if constexpr (DT == MAPI_BF16) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      out[2 * k] = __uint_as_float(wd[k] << 16);
+      out[2 * k + 1] = __uint_as_float(wd[k] & 0xFFFF0000u);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)wd[k], false);
+      const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)wd[k], true);
+      out[4 * k + 0] = scale * lo[0];
+      out[4 * k + 1] = scale * lo[1];
+      out[4 * k + 2] = scale * hi[0];
+      out[4 * k + 3] = scale * hi[1];
+    }
+  }
+}
+
+template <int DT>
+__device__ __forceinline__ float decode_one(const unsigned char* row, int64_t j, float scale) {
+  if constexpr (DT == MAPI_F32) {
+    return reinterpret_cast<const float*>(row)[j];
+  } else if constexpr (DT == MAPI_BF16) {
+    return __uint_as_float(((uint32_t)reinterpret_cast<const uint16_t*>(row)[j]) << 16);
+  } else {
+    return scale * __builtin_amdgcn_cvt_f32_fp8((int)row[j], 0);
+  }
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// One 16-byte load of the matrix; NT marks it non-temporal (streamed once).
+template <bool NT>
+__device__ __forceinline__ uint4 load16(const unsigned char* p) {
+  u32x4 v;
+  if constexpr (NT) {
+    v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+  } else {
+    v = *reinterpret_cast<const u32x4*>(p);
+  }
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+template <int DT, int OP, int RW, int U, bool WLDS, bool NT>
+__global__ void __launch_bounds__(512)
+k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, int n_cols,
+             const float* __restrict__ rscale, const float* __restrict__ w, float* __restrict__ y,
+             double* __restrict__ part, SolveState* __restrict__ st, int norm) {
+  constexpr int VE = Traits<DT>::VE;
+  extern __shared__ float4 w_lds4[];
+  float* w_lds = reinterpret_cast<float*>(w_lds4);
+  __shared__ double sh[16];
+  __shared__ int sh_flag;
+
+  if (st != nullptr && state_done(st)) return;
+
+  const float* wv = w;
+  if constexpr (WLDS) {
+    const int nv4 = n_cols >> 2;
+    for (int v = threadIdx.x; v < nv4; v += blockDim.x)
+      reinterpret_cast<float4*>(w_lds)[v] = reinterpret_cast<const float4*>(w)[v];
+    for (int j = (nv4 << 2) + threadIdx.x; j < n_cols; j += blockDim.x) w_lds[j] = w[j];
+    __syncthreads();
+    wv = w_lds;
+  }
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  const int ngroups = (n_rows + RW - 1) / RW;
+  const int nvec = n_cols / VE;
+  double nrm = 0.0;
+
+  for (int g = blockIdx.x * nw + wave; g < ngroups; g += gridDim.x * nw) {
+    const unsigned char* rp[RW];
+    float sc[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int row = min(g * RW + r, n_rows - 1);     // padded rows re-read the last row
+      rp[r] = A + (int64_t)row * ld_bytes;
+      sc[r] = (DT == MAPI_FP8_E4M3) ? rscale[row] : 1.0f;
+    }
+    float acc[RW][2];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) acc[r][0] = acc[r][1] = 0.0f;
+
+    int v = lane;
+    for (; v + kWave * (U - 1) < nvec; v += kWave * U) {
+      uint4 raw[U][RW];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+          raw[u][r] = load16<NT>(rp[r] + (int64_t)(v + kWave * u) * 16);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        float wf[VE];
+        uint32_t ws[VE];
+        const float4* wp = reinterpret_cast<const float4*>(wv + (int64_t)(v + kWave * u) * VE);
+#pragma unroll
+        for (int q = 0; q < VE / 4; ++q) {
+          const float4 t = wp[q];
+          wf[4 * q] = t.x; wf[4 * q + 1] = t.y; wf[4 * q + 2] = t.z; wf[4 * q + 3] = t.w;
+        }
+#pragma unroll
+        for (int e = 0; e < VE; ++e) ws[e] = sign_bit(wf[e]);
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+          float a[VE];
+          decode_vec<DT>(raw[u][r], sc[r], a);
+#pragma unroll
+          for (int e = 0; e < VE; ++e) acc[r][e & 1] = op_acc<OP>(acc[r][e & 1], a[e], wf[e], ws[e]);
+        }
+      }
+    }
+    for (; v < nvec; v += kWave) {
+      float wf[VE];
+      uint32_t ws[VE];
+      const float4* wp = reinterpret_cast<const float4*>(wv + (int64_t)v * VE);
+#pragma unroll
+      for (int q = 0; q < VE / 4; ++q) {
+        const float4 t = wp[q];
+        wf[4 * q] = t.x; wf[4 * q + 1] = t.y; wf[4 * q + 2] = t.z; wf[4 * q + 3] = t.w;
+      }
+#pragma unroll
+      for (int e = 0; e < VE; ++e) ws[e] = sign_bit(wf[e]);
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const uint4 raw = load16<NT>(rp[r] + (int64_t)v * 16);
+        float a[VE];
+        decode_vec<DT>(raw, sc[r], a);
+#pragma unroll
+        for (int e = 0; e < VE; ++e) acc[r][e & 1] = op_acc<OP>(acc[r][e & 1], a[e], wf[e], ws[e]);
+      }
+    }
+    // ragged tail: fewer than VE columns past the last full vector
+    const int j = nvec * VE + lane;
+    if (j < n_cols) {
+      const float wj = wv[j];
+      const uint32_t sj = sign_bit(wj);
+#pragma unroll
+      for (int r = 0; r < RW; ++r) acc[r][0] = op_acc<OP>(acc[r][0], decode_one<DT>(rp[r], j, sc[r]), wj, sj);
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const float s = wave_sum_f32(acc[r][0] + acc[r][1]);
+      const int row = g * RW + r;
+      if (lane == 0 && row < n_rows) {
+        y[row] = s;
+        nrm += (norm == NORM_L2) ? (double)s * (double)s : fabs((double)s);
+      }
+    }
+  }
+
+  if (st == nullptr || norm == NORM_NONE) return;
+  const double bsum = block_sum_f64(nrm, sh);
+  if (threadIdx.x == 0) store_agent(&part[blockIdx.x], bsum);
+  if (arrive_last(&st->cnt_a, &sh_flag)) {
+    const double tot = block_sum_parts(part, gridDim.x, 1, 0, sh);
+    if (threadIdx.x == 0) {
+      st->nu = (norm == NORM_L2) ? sqrt(tot) : tot;
+      st->cnt_a = 0;
+    }
+  }
+}
+
+template <int DT, int OP, int RW, int U, bool WLDS, bool NT>
+static hipError_t launch_k(const DenseArgs& a, const float* w, float* y, double* part, SolveState* st, int norm,
+                           int blocks, int waves, hipStream_t s) {
+  const unsigned char* A = static_cast<const unsigned char*>(a.A);
+  const int64_t ldb = a.ld * Traits<DT>::ESZ;
+  const size_t lds = WLDS ? (size_t)a.n_cols * sizeof(float) : 0;
+  hipLaunchKernelGGL((k_mavp_dense<DT, OP, RW, U, WLDS, NT>), dim3(blocks), dim3(waves * kWave), lds, s, A, ldb,
+                     (int)a.n_rows, (int)a.n_cols, a.row_scale, w, y, part, st, norm);
+  return hipGetLastError();
+}
+
+template <int DT, int OP, int RW>
+static hipError_t launch_rw(const DenseArgs& a, const float* w, float* y, double* part, SolveState* st, int norm,
+                            const DenseTuning& t, int blocks, hipStream_t s) {
+  const int key = (t.unroll == 4 ? 4 : 0) | (t.w_in_lds ? 2 : 0) | (t.nontemporal ? 1 : 0);
+  switch (key) {
+    case 0: return launch_k<DT, OP, RW, 2, false, false>(a, w, y, part, st, norm, blocks, t.waves, s);
+    case 1: return launch_k<DT, OP, RW, 2, false, true>(a, w, y, part, st, norm, blocks, t.waves, s);
+    case 2: return launch_k<DT, OP, RW, 2, true, false>(a, w, y, part, st, norm, blocks, t.waves, s);
+    case 3: return launch_k<DT, OP, RW, 2, true, true>(a, w, y, part, st, norm, blocks, t.waves, s);
+    case 4: return launch_k<DT, OP, RW, 4, false, false>(a, w, y, part, st, norm, blocks, t.waves, s);
+    case 5: return launch_k<DT, OP, RW, 4, false, true>(a, w, y, part, st, norm, blocks, t.waves, s);
+    case 6: return launch_k<DT, OP, RW, 4, true, false>(a, w, y, part, st, norm, blocks, t.waves, s);
+    default: return launch_k<DT, OP, RW, 4, true, true>(a, w, y, part, st, norm, blocks, t.waves, s);
+  }
+}
+
+template <int DT, int OP>
+static hipError_t launch_op(const DenseArgs& a, const float* w, float* y, double* part, SolveState* st, int norm,
+                            const DenseTuning& t, int blocks, hipStream_t s) {
+  switch (t.rows_per_wave) {
+    case 1: return launch_rw<DT, OP, 1>(a, w, y, part, st, norm, t, blocks, s);
+    case 2: return launch_rw<DT, OP, 2>(a, w, y, part, st, norm, t, blocks, s);
+    case 4: return launch_rw<DT, OP, 4>(a, w, y, part, st, norm, t, blocks, s);
+    case 8: return launch_rw<DT, OP, 8>(a, w, y, part, st, norm, t, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int DT>
+static hipError_t launch_dt(const DenseArgs& a, int op, const float* w, float* y, double* part, SolveState* st,
+                            int norm, const DenseTuning& t, int blocks, hipStream_t s) {
+  switch (op) {
+    case MAPI_OP_MIN1: return launch_op<DT, MAPI_OP_MIN1>(a, w, y, part, st, norm, t, blocks, s);
+    case MAPI_OP_MIN2: return launch_op<DT, MAPI_OP_MIN2>(a, w, y, part, st, norm, t, blocks, s);
+    case MAPI_OP_DIAMOND: return launch_op<DT, MAPI_OP_DIAMOND>(a, w, y, part, st, norm, t, blocks, s);
+    case MAPI_OP_DOT: return launch_op<DT, MAPI_OP_DOT>(a, w, y, part, st, norm, t, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace mapi
