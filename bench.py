@@ -91,7 +91,7 @@ def setup(autotune=True):
             shape, ms = mp.mapi_autotune_dense(A, "min1", reps=3, row_scale=rs, ctx=ctx)
             log(f"autotuned {dt}: {shape} {ms * 1e3:.1f} us")
         else:
-            log(f"launch shape {dt}: {mp.mapi_tuning_get(A.dtype and mp._dtype_code(A), N, N, ctx=ctx)}")
+            log(f"launch shape {dt}: {mp.mapi_tuning_get(mp._dtype_code(A), N, N, ctx=ctx)}")
     return torch, mp, ctx, C, w0, mats
 
 
