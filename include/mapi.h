@@ -228,6 +228,104 @@ mapi_status mapi_pca_topk(mapi_ctx* ctx, const float* X, int64_t D, int64_t N, i
 mapi_status mapi_pagerank(mapi_ctx* ctx, const mapi_csr* H, double alpha, int32_t method,
                           const float* w0, float* w_out, const mapi_opts* opts, mapi_info* info);
 
+/* ---------------------------------------------------------------- batched */
+
+typedef enum mapi_problem_kind {
+  MAPI_PROB_DENSE = 0,       /* caller's square matrix (any storage)               */
+  MAPI_PROB_CSR = 1,         /* PageRank on the caller's CSR link matrix           */
+  MAPI_PROB_GENERATED = 2    /* dense matrix generated on the device from a seed   */
+} mapi_problem_kind;
+
+/* One instance of a batched solve.  Generated matrices: symmetric, entries
+ * x_ij * sqrt(3) / (2^23 sqrt(n)) + sigma_i sigma_j * 6 / n with x_ij uniform
+ * integers in [-2^23, 2^23) and sigma_i = +-1, both from SplitMix64 of the seed
+ * (a Wigner bulk of radius 2 plus a planted spike); start vector
+ * w0_i = +-1/sqrt(n) from the seed.  mapi_generate_dense writes both.           */
+typedef struct mapi_problem {
+  int32_t kind;              /* mapi_problem_kind                                  */
+  int32_t method;            /* mapi_method                                        */
+  mapi_dense A;              /* MAPI_PROB_DENSE                                    */
+  mapi_csr H;                /* MAPI_PROB_CSR                                      */
+  double alpha;              /* MAPI_PROB_CSR damping, in (0, 1)                   */
+  int64_t gen_n;             /* MAPI_PROB_GENERATED size (<= 16384)                */
+  int32_t gen_dtype;         /* MAPI_PROB_GENERATED storage: MAPI_F32 or MAPI_BF16 */
+  uint64_t seed;             /* MAPI_PROB_GENERATED seed                           */
+  const float* w0;           /* device start vector or NULL (CSR: 1/n; generated: from the seed) */
+  float* w_out;              /* device result (n floats); batched solves only      */
+  mapi_opts opts;            /* final_l2 must be 0; check_every is ignored         */
+} mapi_problem;
+
+/* Persistent batched solve (MAPI, eq. 6, or RPI, eq. 1; PageRank per eq. 11):
+ * all `count` instances are iterated to their own stop rule by one persistent
+ * kernel launched from a captured hipGraph; each instance's arithmetic (tile
+ * shapes, reduction order) depends only on its own kind, storage and size, so
+ * a result is the same alone and in any mix.  infos: host array of count.
+ * The call allocates a device arena for the batch (kept by the context).       */
+mapi_status mapi_solve_batched(mapi_ctx* ctx, int32_t count, const mapi_problem* probs, mapi_info* infos);
+/* Persistent grid: compute units * blocks_per_cu blocks (1..8, default 2).      */
+mapi_status mapi_batched_config(mapi_ctx* ctx, int32_t blocks_per_cu);
+/* Product tile height (row split) used for dense instances of a storage type and
+ * size bucket (ceil(log2 n)); the autotuner sets it from measurements.          */
+mapi_status mapi_batched_rows_set(mapi_ctx* ctx, int32_t dtype, int64_t n, int32_t rows_per_tile);
+mapi_status mapi_batched_rows_get(mapi_ctx* ctx, int32_t dtype, int64_t n, int32_t* rows_per_tile);
+/* Autotuner for the row split: solves `count` generated instances of size n with
+ * each candidate tile height (fixed `iters` MAPI iterations) and keeps the fastest. */
+mapi_status mapi_autotune_batched(mapi_ctx* ctx, int32_t dtype, int64_t n, int32_t count, int32_t iters,
+                                  int32_t* best_rows, double* best_ms);
+/* Materialise a generated problem: A (device float32, n x ld) and w0 (device, n). */
+mapi_status mapi_generate_dense(mapi_ctx* ctx, int64_t n, uint64_t seed, float* A, int64_t ld, float* w0);
+
+/* ---------------------------------------------------------------- serving */
+
+typedef struct mapi_server mapi_server;
+
+typedef struct mapi_serve_cfg {
+  int32_t blocks_per_cu;     /* persistent grid (0 = 2)                            */
+  int32_t max_slots;         /* concurrently admitted instances (0 = 2048)         */
+  double idle_exit_ms;       /* an idle block exits after this long (0 = 20)       */
+} mapi_serve_cfg;
+
+/* A request: the problem (w_out ignored) and the host buffer that receives the
+ * n-float result; the caller keeps the CSR arrays (host memory for
+ * MAPI_PROB_CSR requests: row_ptr, col, val are HOST pointers here) and
+ * host_out alive until the request completes.                                   */
+typedef struct mapi_request {
+  mapi_problem prob;
+  float* host_out;
+} mapi_request;
+
+typedef struct mapi_result {
+  int32_t status;            /* mapi_status of the solve                           */
+  int32_t iters, converged;
+  double residual, norm;
+  double t_submit_ms, t_admit_ms, t_done_ms;   /* host clock, ms since server creation */
+} mapi_result;
+
+typedef struct mapi_serve_summary {
+  int64_t submitted, admitted, completed, rejected;
+  double solves_per_s;       /* completed / (last completion - first submission)   */
+  double p50_ms, p99_ms;     /* submission -> result in host memory                */
+  size_t budget_bytes, peak_bytes;
+  int64_t kernel_launches;   /* persistent-kernel graph launches                   */
+} mapi_serve_summary;
+
+/* Continuous-batching server on `device`: admits requests while a device memory
+ * budget of hbm_budget bytes (matrix, iterates, partials) and an instance slot
+ * are free; admitted requests join the running persistent kernel through a
+ * host-to-device inbox, so work of requests arriving at different times
+ * overlaps on the device.  The server owns its memory and threads.              */
+mapi_status mapi_serve_create(int device, size_t hbm_budget, const mapi_serve_cfg* cfg, mapi_server** out);
+/* Non-blocking: queue a request, returns its ticket.  MAPI_ERR_BUDGET (at once)
+ * if its footprint alone exceeds the budget.                                     */
+mapi_status mapi_serve_submit(mapi_server* s, const mapi_request* req, uint64_t* ticket);
+/* MAPI_ERR_PENDING until the result is in host memory. */
+mapi_status mapi_serve_poll(mapi_server* s, uint64_t ticket, mapi_result* res);
+/* Block up to timeout_us (< 0: forever); MAPI_ERR_TIMEOUT if not done. */
+mapi_status mapi_serve_wait(mapi_server* s, uint64_t ticket, int64_t timeout_us, mapi_result* res);
+mapi_status mapi_serve_stats(mapi_server* s, mapi_serve_summary* out);
+/* Waits for admitted work, stops the threads and frees everything. */
+void mapi_serve_destroy(mapi_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -395,3 +395,267 @@ def mapi_copy_reference(src, dst, reps=5, ctx=None):
     _check(lib().mapi_copy_reference(c.handle, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
                                      int(reps), C.byref(ms)))
     return ms.value
+
+
+# ------------------------------------------------------------------ batched
+class Problem(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("method", C.c_int32), ("A", Dense), ("H", Csr), ("alpha", C.c_double),
+                ("gen_n", C.c_int64), ("gen_dtype", C.c_int32), ("seed", C.c_uint64), ("w0", C.c_void_p),
+                ("w_out", C.c_void_p), ("opts", Opts)]
+
+
+PROB_DENSE, PROB_CSR, PROB_GENERATED = 0, 1, 2
+
+_SIGS.update({
+    "mapi_solve_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Problem), C.POINTER(Info)]),
+    "mapi_batched_config": (C.c_int, [C.c_void_p, C.c_int32]),
+    "mapi_batched_rows_set": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int32]),
+    "mapi_batched_rows_get": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_int32)]),
+    "mapi_autotune_batched": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
+                                        C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "mapi_generate_dense": (C.c_int, [C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p, C.c_int64, C.c_void_p]),
+})
+
+
+def problem_dense(A, method="mapi", w0=None, w_out=None, row_scale=None, max_iters=100, tol=0.0, op="min1",
+                  stall_iters=0):
+    """Describe a dense instance for mapi_solve_batched (keeps its tensors alive on the object)."""
+    import torch
+    p = Problem()
+    p.kind = PROB_DENSE
+    p.method = METHODS[method]
+    p.A = _dense(A, row_scale)
+    n = A.shape[0]
+    w_out = torch.empty(n, dtype=torch.float32, device=A.device) if w_out is None else w_out
+    p.w0 = _vec(w0, n, "w0") if w0 is not None else None
+    p.w_out = _vec(w_out, n, "w_out")
+    p.opts = _opts(max_iters, tol, op, False, 0, stall_iters)
+    p._keep = (A, w0, w_out, row_scale)
+    p.out = w_out
+    p.n = n
+    return p
+
+
+def problem_csr(row_ptr, col, val, alpha=0.85, method="mapi", w0=None, w_out=None, max_iters=100, tol=0.0,
+                stall_iters=0):
+    import torch
+    p = Problem()
+    p.kind = PROB_CSR
+    p.method = METHODS[method]
+    n = row_ptr.numel() - 1
+    p.H = Csr(n, col.numel(), row_ptr.data_ptr(), col.data_ptr() if col.numel() else None,
+              val.data_ptr() if val.numel() else None)
+    p.alpha = float(alpha)
+    w_out = torch.empty(n, dtype=torch.float32, device=row_ptr.device) if w_out is None else w_out
+    p.w0 = _vec(w0, n, "w0") if w0 is not None else None
+    p.w_out = _vec(w_out, n, "w_out")
+    p.opts = _opts(max_iters, tol, "min1", False, 0, stall_iters)
+    p._keep = (row_ptr, col, val, w0, w_out)
+    p.out = w_out
+    p.n = n
+    return p
+
+
+def problem_generated(n, seed, dtype="f32", method="mapi", w_out=None, max_iters=100, tol=0.0, op="min1",
+                      stall_iters=0, device=None):
+    import torch
+    p = Problem()
+    p.kind = PROB_GENERATED
+    p.method = METHODS[method]
+    p.gen_n = int(n)
+    p.gen_dtype = {"f32": MAPI_F32, "bf16": MAPI_BF16}[dtype]
+    p.seed = int(seed)
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    w_out = torch.empty(n, dtype=torch.float32, device=dev) if w_out is None else w_out
+    p.w0 = None
+    p.w_out = _vec(w_out, n, "w_out")
+    p.opts = _opts(max_iters, tol, op, False, 0, stall_iters)
+    p._keep = (w_out,)
+    p.out = w_out
+    p.n = int(n)
+    return p
+
+
+def mapi_solve_batched(problems, ctx=None):
+    """Solve a ragged list of problems with the persistent batched kernel.
+    Returns the list of info dicts; results are in each problem's `.out` tensor."""
+    c = ctx if ctx is not None else default_context()
+    c.sync_stream()
+    k = len(problems)
+    arr = (Problem * k)(*problems)
+    infos = (Info * k)()
+    st = lib().mapi_solve_batched(c.handle, k, arr, infos)
+    res = [infos[i].as_dict() for i in range(k)]
+    if st not in (0, 4):
+        _check(st)
+    return res
+
+
+def mapi_batched_config(blocks_per_cu, ctx=None):
+    c = ctx if ctx is not None else default_context()
+    _check(lib().mapi_batched_config(c.handle, int(blocks_per_cu)))
+
+
+def mapi_batched_rows_set(dtype_code, n, rows, ctx=None):
+    c = ctx if ctx is not None else default_context()
+    _check(lib().mapi_batched_rows_set(c.handle, int(dtype_code), int(n), int(rows)))
+
+
+def mapi_batched_rows_get(dtype_code, n, ctx=None):
+    c = ctx if ctx is not None else default_context()
+    r = C.c_int32()
+    _check(lib().mapi_batched_rows_get(c.handle, int(dtype_code), int(n), C.byref(r)))
+    return r.value
+
+
+def mapi_autotune_batched(dtype_code, n, count=32, iters=5, ctx=None):
+    """Pick the product tile height of batched dense instances of size n; returns (rows, ms)."""
+    c = ctx if ctx is not None else default_context()
+    r = C.c_int32()
+    ms = C.c_double()
+    _check(lib().mapi_autotune_batched(c.handle, int(dtype_code), int(n), int(count), int(iters), C.byref(r),
+                                       C.byref(ms)))
+    return r.value, ms.value
+
+
+def mapi_generate_dense(n, seed, ctx=None):
+    """The seed-generated problem materialised on the device: (A float32 n x n, w0)."""
+    import torch
+    c = ctx if ctx is not None else default_context()
+    c.sync_stream()
+    ld = (n + 3) // 4 * 4
+    A = torch.empty((n, ld), dtype=torch.float32, device=torch.device("cuda", c.device))[:, :n]
+    w0 = torch.empty(n, dtype=torch.float32, device=A.device)
+    _check(lib().mapi_generate_dense(c.handle, int(n), int(seed), C.c_void_p(A.data_ptr()), ld,
+                                     C.c_void_p(w0.data_ptr())))
+    return A, w0
+
+
+# ------------------------------------------------------------------ serving
+class ServeCfg(C.Structure):
+    _fields_ = [("blocks_per_cu", C.c_int32), ("max_slots", C.c_int32), ("idle_exit_ms", C.c_double)]
+
+
+class Request(C.Structure):
+    _fields_ = [("prob", Problem), ("host_out", C.c_void_p)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("converged", C.c_int32), ("residual", C.c_double),
+                ("norm", C.c_double), ("t_submit_ms", C.c_double), ("t_admit_ms", C.c_double),
+                ("t_done_ms", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["status"] = STATUS.get(self.status, self.status)
+        d["converged"] = bool(self.converged)
+        return d
+
+
+class ServeSummary(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("rejected", C.c_int64), ("solves_per_s", C.c_double), ("p50_ms", C.c_double),
+                ("p99_ms", C.c_double), ("budget_bytes", C.c_size_t), ("peak_bytes", C.c_size_t),
+                ("kernel_launches", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_SIGS.update({
+    "mapi_serve_create": (C.c_int, [C.c_int, C.c_size_t, C.POINTER(ServeCfg), C.POINTER(C.c_void_p)]),
+    "mapi_serve_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "mapi_serve_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Result)]),
+    "mapi_serve_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int64, C.POINTER(Result)]),
+    "mapi_serve_stats": (C.c_int, [C.c_void_p, C.POINTER(ServeSummary)]),
+    "mapi_serve_destroy": (None, [C.c_void_p]),
+})
+
+
+def request_generated(n, seed, dtype="f32", method="mapi", max_iters=1000, tol=1e-6, op="min1"):
+    """A device-generated dense request (matrix and start vector from the seed)."""
+    p = Problem()
+    p.kind = PROB_GENERATED
+    p.method = METHODS[method]
+    p.gen_n = int(n)
+    p.gen_dtype = {"f32": MAPI_F32, "bf16": MAPI_BF16}[dtype]
+    p.seed = int(seed)
+    p.opts = _opts(max_iters, tol, op, False, 0, 0)
+    p.n = int(n)
+    return p
+
+
+def request_csr_host(row_ptr, col, val, alpha=0.85, method="mapi", max_iters=1000, tol=1e-6):
+    """A PageRank request whose CSR arrays are host numpy arrays (copied by the server at admission)."""
+    import numpy as np
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float32)
+    p = Problem()
+    p.kind = PROB_CSR
+    p.method = METHODS[method]
+    n = row_ptr.size - 1
+    p.H = Csr(n, col.size, row_ptr.ctypes.data, col.ctypes.data if col.size else None,
+              val.ctypes.data if val.size else None)
+    p.alpha = float(alpha)
+    p.opts = _opts(max_iters, tol, "min1", False, 0, 0)
+    p._keep = (row_ptr, col, val)
+    p.n = n
+    return p
+
+
+class Server:
+    """Continuous-batching server (mapi_serve_*) on one device."""
+
+    def __init__(self, budget_bytes, device=0, blocks_per_cu=0, max_slots=0, idle_exit_ms=0.0):
+        cfg = ServeCfg(int(blocks_per_cu), int(max_slots), float(idle_exit_ms))
+        h = C.c_void_p()
+        _check(lib().mapi_serve_create(int(device), int(budget_bytes), C.byref(cfg), C.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, prob, host_out):
+        """Queue a request; host_out is a float32 numpy array of length n that receives the result."""
+        import numpy as np
+        if not (isinstance(host_out, np.ndarray) and host_out.dtype == np.float32 and host_out.flags.c_contiguous
+                and host_out.size == prob.n):
+            raise ValueError("host_out must be a contiguous float32 array of length n")
+        req = Request(prob, host_out.ctypes.data)
+        t = C.c_uint64()
+        _check(lib().mapi_serve_submit(self.handle, C.byref(req), C.byref(t)))
+        self._keep[t.value] = (prob, host_out)
+        return t.value
+
+    def poll(self, ticket):
+        r = Result()
+        st = lib().mapi_serve_poll(self.handle, int(ticket), C.byref(r))
+        if st == 7:
+            return None
+        _check(st)
+        self._keep.pop(ticket, None)
+        return r.as_dict()
+
+    def wait(self, ticket, timeout_us=-1):
+        r = Result()
+        st = lib().mapi_serve_wait(self.handle, int(ticket), int(timeout_us), C.byref(r))
+        if st == 8:
+            return None
+        _check(st)
+        self._keep.pop(ticket, None)
+        return r.as_dict()
+
+    def stats(self):
+        s = ServeSummary()
+        _check(lib().mapi_serve_stats(self.handle, C.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mapi_serve_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

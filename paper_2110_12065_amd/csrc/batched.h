@@ -1,0 +1,143 @@
+// Persistent batched solver: instance descriptors, the device work queue and
+// the control block shared by the persistent kernel and the host runtime.
+//
+// Work is a stream of items (instance, phase, tile).  Blocks of the persistent
+// kernel pop items from a multi-producer multi-consumer ring in device memory,
+// run them, and the block that finishes the last tile of a phase pushes the
+// next phase's tiles.  No block ever waits on another block's progress: a block
+// only holds an item while it is working on it, so the grid drains whatever the
+// number of resident blocks.  Every wait has a wall-clock limit.
+#pragma once
+
+#include "common.h"
+
+namespace mapi {
+
+enum BKind { BK_DENSE = 0, BK_CSR = 1, BK_GEN = 2 };
+enum BPhase { PH_GEN = 0, PH_INIT = 1, PH_PROD = 2, PH_FIN = 3, PH_OUT = 4 };
+
+constexpr int kVecTile = 8192;      // elements per INIT / FIN / OUT tile
+constexpr int kGenRows = 32;        // rows per generation tile
+constexpr int kSoloMaxN = 1024;     // instances up to this size iterate inside one block
+constexpr int kSoloBurst = 16;      // iterations a solo block runs before yielding
+constexpr int kBatchLdsFloats = 8192;   // w staged in LDS up to this many columns
+
+struct BInst {
+  // ---- description (written by the host)
+  int32_t kind, method, op, dtype;
+  int32_t n;
+  int32_t rows_per_tile;     // product tile height
+  int32_t ntiles;            // product tiles per iteration
+  int32_t vtiles;            // INIT / FIN / OUT tiles
+  int32_t gtiles;            // generation tiles (BK_GEN)
+  int32_t solo;              // whole iterations inside one block
+  int32_t max_iters, stall_iters;
+  double tol;
+  int64_t ld;                // elements
+  const void* A;             // BK_DENSE: caller's matrix; BK_GEN: generated into workspace
+  const float* row_scale;
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const float* val;
+  const uint8_t* dangling;
+  float alpha, c;
+  double inv_n;
+  uint64_t seed;             // BK_GEN and generated start vectors
+  const float* w0;           // NULL: generated (BK_GEN) or uniform (BK_CSR)
+  float* wb0;
+  float* wb1;
+  float* y;
+  double* part;              // ntiles + 3 * vtiles doubles
+  float* out;                // result (device or host-mapped)
+  int32_t slot_gen;          // reuse generation of this slot (serving)
+  int32_t pad0;
+  // ---- dynamic state
+  SolveState st;
+  uint32_t arrive;           // tiles finished in the current phase
+  uint32_t pad1;
+  int64_t t_admit, t_start, t_done;   // wall clock (device realtime counter) of the life cycle
+};
+
+struct BQueue {
+  unsigned long long head;   // next position to consume
+  unsigned long long tail;   // next position to reserve for producing
+  unsigned long long* item;  // cap entries
+  unsigned long long* seq;   // seq[p & mask] == p + 1 once the item at p is ready
+  uint32_t mask;             // cap - 1, cap a power of two
+  uint32_t live;             // instances admitted and not finished
+  uint32_t error;            // bit 0: blocks stopped at the run limit with work left
+  uint32_t pad;
+};
+
+// Completion record written to host-visible memory when an instance finishes.
+struct BDone {
+  int32_t slot, slot_gen, status, iters, converged, pad;
+  double residual, norm;
+  int64_t t_admit, t_start, t_done;
+  unsigned long long seq;    // written last: position + 1
+};
+
+struct BCtl {
+  int32_t mode;              // 0: batch, exit when live == 0; 1: serving, exit on quit or idle
+  int32_t pad;
+  int64_t run_limit;         // realtime ticks after its start at which a block stops taking items
+  int64_t idle_limit;        // realtime ticks a block waits for an item before it exits
+  // serving inbox: host-written ring of items in host memory, drained by block 0
+  const unsigned long long* inbox;       // host-mapped
+  const volatile unsigned long long* inbox_tail;   // host-mapped, written by the host
+  volatile unsigned long long* inbox_head_host;    // host-mapped, written by block 0
+  unsigned long long inbox_head;         // device copy
+  uint32_t inbox_mask;
+  uint32_t pad2;
+  const volatile int32_t* quit;          // host-mapped
+  // completion ring in host memory
+  BDone* done;                           // host-mapped
+  unsigned long long done_pos;           // device counter
+  uint32_t done_mask;
+  uint32_t pad3;
+};
+
+__host__ __device__ inline unsigned long long bitem(uint32_t inst, int phase, uint32_t tile) {
+  return (unsigned long long)inst | ((unsigned long long)phase << 24) | ((unsigned long long)tile << 28);
+}
+
+// SplitMix64 output function (Steele, Lea and Flood, 2014), used as a
+// counter-based generator: value = splitmix64(splitmix64(seed) + counter).
+__host__ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// Generated symmetric matrix: a_ij = x_ij * s_n + sigma_i sigma_j * theta / n with
+// x_ij the top 24 bits of splitmix64(splitmix64(seed) + (min(i,j) << 32 | max(i,j)))
+// minus 2^23 (uniform integers), s_n = fl32(sqrt(3) / (2^23 sqrt(n))) (unit-variance
+// entries over sqrt(n): semicircle bulk of radius 2), theta = 6 and sigma_i the top
+// bit of splitmix64(splitmix64(seed ^ 0x5BD1E995) + i) as a sign.  Rounded in float32,
+// product then sum.
+__device__ __forceinline__ float gen_entry(uint64_t base, uint64_t sbase, int i, int j, float s_n, float spike) {
+  const uint64_t lo = (uint64_t)min(i, j), hi = (uint64_t)max(i, j);
+  const uint64_t h = splitmix64(base + ((lo << 32) | hi));
+  const float x = (float)((int32_t)(h >> 40) - 8388608);
+  const bool si = (splitmix64(sbase + (uint64_t)i) >> 63) != 0;
+  const bool sj = (splitmix64(sbase + (uint64_t)j) >> 63) != 0;
+  return __fadd_rn(__fmul_rn(x, s_n), (si == sj) ? spike : -spike);
+}
+
+hipError_t launch_persistent(BQueue* q, BInst* inst, BCtl* ctl, int blocks, hipStream_t s);
+
+// host helpers shared by the batched solve and the server (batch.hip)
+}  // namespace mapi
+struct mapi_ctx;
+namespace mapi {
+mapi_status describe(mapi_ctx* c, const mapi_problem& p, BInst* I, int64_t* matrix_bytes);
+size_t instance_bytes(const BInst& I, int64_t matrix_bytes);
+char* place(BInst* I, char* base, int64_t matrix_bytes);
+uint32_t first_phase_tiles(const BInst& I, int* phase);
+uint32_t max_tiles(const BInst& I);
+int64_t realtime_hz();
+int persistent_threads();
+hipError_t launch_gen_dense(int n, uint64_t seed, float* A, int64_t ld, float* w0, hipStream_t s);
+
+}  // namespace mapi

@@ -147,6 +147,8 @@ struct DenseArgs {
   int64_t n_rows, n_cols;
   int32_t dtype;
   const float* row_scale;
+  hipEvent_t ev_start = nullptr;   // when set, attached to the launch's dispatch (kernel time)
+  hipEvent_t ev_stop = nullptr;
 };
 
 struct DenseTuning {

@@ -1,0 +1,184 @@
+// Private host-side definitions of libmapi: the context, error reporting,
+// device workspace and kernel timing, shared by the C-ABI translation units.
+#pragma once
+
+#include <cstdarg>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "common.h"
+
+namespace mapi {
+struct BatchState;
+struct ServerImpl;
+}
+
+namespace mapi {
+
+mapi_status fail(mapi_status s, const char* fmt, ...);
+
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(MAPI_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+inline int64_t elem_size(int dtype) {
+  switch (dtype) {
+    case MAPI_F32: return 4;
+    case MAPI_BF16: return 2;
+    case MAPI_FP8_E4M3: return 1;
+    default: return 0;
+  }
+}
+
+}  // namespace mapi
+
+struct mapi_ctx;
+// Frees the batched solver's arena and stream of a context (batch.hip).
+void mapi_batch_release(mapi_ctx* c);
+
+struct mapi_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int cu_count = 256;
+  int max_lds = 65536;               // LDS bytes one block may use
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  mapi::SolveState* st_host = nullptr;     // pinned copy of the device state
+  // matrices owned by the PCA driver
+  void* big = nullptr;
+  size_t big_bytes = 0;
+  // timing
+  bool timing = false;
+  struct Rec { int kind; hipEvent_t a, b; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double t_ms[MAPI_K_KINDS] = {};
+  int64_t t_n[MAPI_K_KINDS] = {};
+  // autotuned launch shapes of the dense product per (dtype, log2 rows, log2 cols)
+  std::map<std::tuple<int, int, int>, mapi::DenseTuning> tuned;
+  // persistent batched solver: arena and launch settings
+  mapi::BatchState* batch = nullptr;
+  hipStream_t side = nullptr;        // stream the batched graph is captured on
+  int batch_blocks_per_cu = 2;
+  std::map<std::tuple<int, int>, int> batch_rows;   // (dtype, log2 n) -> product tile rows
+};
+
+namespace mapi {
+
+inline mapi_status ensure(void** buf, size_t* have, size_t need, mapi_ctx* c) {
+  if (*have >= need) return MAPI_OK;
+  if (*buf) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipFree(*buf));
+    *buf = nullptr;
+    *have = 0;
+  }
+  need = align_up(need, 1 << 20);
+  if (hipMalloc(buf, need) != hipSuccess) {
+    *buf = nullptr;
+    return fail(MAPI_ERR_ALLOC, "hipMalloc of %zu bytes failed", need);
+  }
+  *have = need;
+  return MAPI_OK;
+}
+
+// Bump layout over one allocation, 256-byte aligned pieces.
+struct Layout {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  }
+};
+
+inline hipEvent_t get_event(mapi_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events when timing is enabled.
+struct Timed {
+  mapi_ctx* c;
+  int kind;
+  hipEvent_t a = nullptr;
+  Timed(mapi_ctx* c_, int k) : c(c_), kind(k) {
+    if (c->timing) {
+      a = get_event(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~Timed() {
+    if (a) {
+      hipEvent_t b = get_event(c);
+      if (b) {
+        (void)hipEventRecord(b, c->stream);
+        c->pending.push_back({kind, a, b});
+      } else {
+        c->pool.push_back(a);
+      }
+    }
+  }
+};
+
+// Kernel time of one dense product: the events ride on the launch's own dispatch.
+struct TimedLaunch {
+  mapi_ctx* c;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  TimedLaunch(mapi_ctx* c_, int k, DenseArgs* da) : c(c_), kind(k) {
+    if (c->timing) {
+      a = get_event(c);
+      b = get_event(c);
+      if (a && b) {
+        da->ev_start = a;
+        da->ev_stop = b;
+      }
+    }
+  }
+  ~TimedLaunch() {
+    if (a && b) {
+      c->pending.push_back({kind, a, b});
+    } else {
+      if (a) c->pool.push_back(a);
+      if (b) c->pool.push_back(b);
+    }
+  }
+};
+
+inline void collect_timing(mapi_ctx* c) {
+  for (auto& r : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->t_ms[r.kind] += ms;
+      c->t_n[r.kind] += 1;
+    }
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->pending.clear();
+}
+
+inline mapi_status sync_and_state(mapi_ctx* c, const SolveState* st_dev) {
+  HIP_TRY(hipMemcpyAsync(c->st_host, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  collect_timing(c);
+  return MAPI_OK;
+}
+
+}  // namespace mapi

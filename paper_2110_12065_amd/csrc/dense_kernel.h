@@ -11,6 +11,8 @@
 // fixed order by the block that arrives last, so results do not depend on
 // timing.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace mapi {
@@ -71,12 +73,84 @@ __device__ __forceinline__ uint4 load16(const unsigned char* p) {
   return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+// Row products of RW rows (byte pointers rp, FP8 row scales sc) against w (wv,
+// n_cols floats, 16-byte aligned) by one wave: lanes stride along the columns in
+// 16-byte vectors, then a fixed butterfly; out[r] is valid in every lane.
+template <int DT, int OP, int RW, int U, bool NT>
+__device__ __forceinline__ void rows_product(const unsigned char* const* rp, const float* sc, const float* wv,
+                                             int n_cols, int lane, float* out) {
+  constexpr int VE = Traits<DT>::VE;
+  const int nvec = n_cols / VE;
+  float acc[RW][2];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) acc[r][0] = acc[r][1] = 0.0f;
+
+  int v = lane;
+  for (; v + kWave * (U - 1) < nvec; v += kWave * U) {
+    uint4 raw[U][RW];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < RW; ++r)
+        raw[u][r] = load16<NT>(rp[r] + (int64_t)(v + kWave * u) * 16);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      float wf[VE];
+      uint32_t ws[VE];
+      const float4* wp = reinterpret_cast<const float4*>(wv + (int64_t)(v + kWave * u) * VE);
+#pragma unroll
+      for (int q = 0; q < VE / 4; ++q) {
+        const float4 t = wp[q];
+        wf[4 * q] = t.x; wf[4 * q + 1] = t.y; wf[4 * q + 2] = t.z; wf[4 * q + 3] = t.w;
+      }
+#pragma unroll
+      for (int e = 0; e < VE; ++e) ws[e] = sign_bit(wf[e]);
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        float a[VE];
+        decode_vec<DT>(raw[u][r], sc[r], a);
+#pragma unroll
+        for (int e = 0; e < VE; ++e) acc[r][e & 1] = op_acc<OP>(acc[r][e & 1], a[e], wf[e], ws[e]);
+      }
+    }
+  }
+  for (; v < nvec; v += kWave) {
+    float wf[VE];
+    uint32_t ws[VE];
+    const float4* wp = reinterpret_cast<const float4*>(wv + (int64_t)v * VE);
+#pragma unroll
+    for (int q = 0; q < VE / 4; ++q) {
+      const float4 t = wp[q];
+      wf[4 * q] = t.x; wf[4 * q + 1] = t.y; wf[4 * q + 2] = t.z; wf[4 * q + 3] = t.w;
+    }
+#pragma unroll
+    for (int e = 0; e < VE; ++e) ws[e] = sign_bit(wf[e]);
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const uint4 raw = load16<NT>(rp[r] + (int64_t)v * 16);
+      float a[VE];
+      decode_vec<DT>(raw, sc[r], a);
+#pragma unroll
+      for (int e = 0; e < VE; ++e) acc[r][e & 1] = op_acc<OP>(acc[r][e & 1], a[e], wf[e], ws[e]);
+    }
+  }
+  // ragged tail: fewer than VE columns past the last full vector
+  const int j = nvec * VE + lane;
+  if (j < n_cols) {
+    const float wj = wv[j];
+    const uint32_t sj = sign_bit(wj);
+#pragma unroll
+    for (int r = 0; r < RW; ++r) acc[r][0] = op_acc<OP>(acc[r][0], decode_one<DT>(rp[r], j, sc[r]), wj, sj);
+  }
+#pragma unroll
+  for (int r = 0; r < RW; ++r) out[r] = wave_sum_f32(acc[r][0] + acc[r][1]);
+}
+
 template <int DT, int OP, int RW, int U, bool WLDS, bool NT>
 __global__ void __launch_bounds__(512)
 k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, int n_cols,
              const float* __restrict__ rscale, const float* __restrict__ w, float* __restrict__ y,
              double* __restrict__ part, SolveState* __restrict__ st, int norm) {
-  constexpr int VE = Traits<DT>::VE;
   extern __shared__ float4 w_lds4[];
   float* w_lds = reinterpret_cast<float*>(w_lds4);
   __shared__ double sh[16];
@@ -98,7 +172,6 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
   const int wave = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
   const int ngroups = (n_rows + RW - 1) / RW;
-  const int nvec = n_cols / VE;
   double nrm = 0.0;
 
   for (int g = blockIdx.x * nw + wave; g < ngroups; g += gridDim.x * nw) {
@@ -110,70 +183,11 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
       rp[r] = A + (int64_t)row * ld_bytes;
       sc[r] = (DT == MAPI_FP8_E4M3) ? rscale[row] : 1.0f;
     }
-    float acc[RW][2];
-#pragma unroll
-    for (int r = 0; r < RW; ++r) acc[r][0] = acc[r][1] = 0.0f;
-
-    int v = lane;
-    for (; v + kWave * (U - 1) < nvec; v += kWave * U) {
-      uint4 raw[U][RW];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int r = 0; r < RW; ++r)
-          raw[u][r] = load16<NT>(rp[r] + (int64_t)(v + kWave * u) * 16);
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        float wf[VE];
-        uint32_t ws[VE];
-        const float4* wp = reinterpret_cast<const float4*>(wv + (int64_t)(v + kWave * u) * VE);
-#pragma unroll
-        for (int q = 0; q < VE / 4; ++q) {
-          const float4 t = wp[q];
-          wf[4 * q] = t.x; wf[4 * q + 1] = t.y; wf[4 * q + 2] = t.z; wf[4 * q + 3] = t.w;
-        }
-#pragma unroll
-        for (int e = 0; e < VE; ++e) ws[e] = sign_bit(wf[e]);
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-          float a[VE];
-          decode_vec<DT>(raw[u][r], sc[r], a);
-#pragma unroll
-          for (int e = 0; e < VE; ++e) acc[r][e & 1] = op_acc<OP>(acc[r][e & 1], a[e], wf[e], ws[e]);
-        }
-      }
-    }
-    for (; v < nvec; v += kWave) {
-      float wf[VE];
-      uint32_t ws[VE];
-      const float4* wp = reinterpret_cast<const float4*>(wv + (int64_t)v * VE);
-#pragma unroll
-      for (int q = 0; q < VE / 4; ++q) {
-        const float4 t = wp[q];
-        wf[4 * q] = t.x; wf[4 * q + 1] = t.y; wf[4 * q + 2] = t.z; wf[4 * q + 3] = t.w;
-      }
-#pragma unroll
-      for (int e = 0; e < VE; ++e) ws[e] = sign_bit(wf[e]);
-#pragma unroll
-      for (int r = 0; r < RW; ++r) {
-        const uint4 raw = load16<NT>(rp[r] + (int64_t)v * 16);
-        float a[VE];
-        decode_vec<DT>(raw, sc[r], a);
-#pragma unroll
-        for (int e = 0; e < VE; ++e) acc[r][e & 1] = op_acc<OP>(acc[r][e & 1], a[e], wf[e], ws[e]);
-      }
-    }
-    // ragged tail: fewer than VE columns past the last full vector
-    const int j = nvec * VE + lane;
-    if (j < n_cols) {
-      const float wj = wv[j];
-      const uint32_t sj = sign_bit(wj);
-#pragma unroll
-      for (int r = 0; r < RW; ++r) acc[r][0] = op_acc<OP>(acc[r][0], decode_one<DT>(rp[r], j, sc[r]), wj, sj);
-    }
+    float sums[RW];
+    rows_product<DT, OP, RW, U, NT>(rp, sc, wv, n_cols, lane, sums);
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
-      const float s = wave_sum_f32(acc[r][0] + acc[r][1]);
+      const float s = sums[r];
       const int row = g * RW + r;
       if (lane == 0 && row < n_rows) {
         y[row] = s;
@@ -200,8 +214,14 @@ static hipError_t launch_k(const DenseArgs& a, const float* w, float* y, double*
   const unsigned char* A = static_cast<const unsigned char*>(a.A);
   const int64_t ldb = a.ld * Traits<DT>::ESZ;
   const size_t lds = WLDS ? (size_t)a.n_cols * sizeof(float) : 0;
-  hipLaunchKernelGGL((k_mavp_dense<DT, OP, RW, U, WLDS, NT>), dim3(blocks), dim3(waves * kWave), lds, s, A, ldb,
-                     (int)a.n_rows, (int)a.n_cols, a.row_scale, w, y, part, st, norm);
+  if (a.ev_start) {
+    hipExtLaunchKernelGGL((k_mavp_dense<DT, OP, RW, U, WLDS, NT>), dim3(blocks), dim3(waves * kWave), (uint32_t)lds, s,
+                          a.ev_start, a.ev_stop, 0u, A, ldb, (int)a.n_rows, (int)a.n_cols, a.row_scale, w, y, part,
+                          st, norm);
+  } else {
+    hipLaunchKernelGGL((k_mavp_dense<DT, OP, RW, U, WLDS, NT>), dim3(blocks), dim3(waves * kWave), lds, s, A, ldb,
+                       (int)a.n_rows, (int)a.n_cols, a.row_scale, w, y, part, st, norm);
+  }
   return hipGetLastError();
 }
 

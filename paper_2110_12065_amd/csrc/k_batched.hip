@@ -1,0 +1,486 @@
+// Persistent batched kernel: ragged MAPI / RPI instances (dense float32, bf16 or
+// fp8 storage, device-generated dense matrices, CSR PageRank) iterated to
+// convergence by one long-lived grid that pops (instance, phase, tile) items
+// from a device work queue.
+//
+// Per instance the phases are: GEN (generated matrices only) -> INIT (start
+// vector, PageRank scalars) -> { PROD (product rows and the normaliser's
+// partial) -> FIN (normalise, residual, stop rule) } * -> OUT (copy the result).
+// The block that completes the last tile of a phase reduces the partials in
+// tile order and pushes the next phase, so an instance's arithmetic does not
+// depend on which block ran which tile or on what else is in the batch.
+// Instances of at most kSoloMaxN rows run whole iterations inside one block.
+#include <hip/hip_runtime.h>
+
+#include "batched.h"
+#include "dense_kernel.h"
+
+namespace mapi {
+
+constexpr int kBT = 256;   // threads per block
+
+__device__ __forceinline__ int64_t now_ticks() { return (int64_t)__builtin_amdgcn_s_memrealtime(); }
+
+// ---------------------------------------------------------------- queue
+__device__ __forceinline__ void q_store_item(BQueue* q, unsigned long long p, unsigned long long v) {
+  __hip_atomic_store(&q->item[p & q->mask], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&q->seq[p & q->mask], p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Push `count` tiles of one phase; called by every thread of the block after
+// the block's results are written.
+__device__ void q_push(BQueue* q, uint32_t inst, int phase, uint32_t count, unsigned long long* sh_base) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) *sh_base = atomicAdd(&q->tail, (unsigned long long)count);
+  __syncthreads();
+  const unsigned long long base = *sh_base;
+  for (uint32_t t = threadIdx.x; t < count; t += blockDim.x) q_store_item(q, base + t, bitem(inst, phase, t));
+  __syncthreads();
+}
+
+// Serving: move newly submitted items from the host inbox into the queue (block 0, thread 0).
+__device__ void drain_inbox(BQueue* q, const BInst* insts, BCtl* ctl) {
+  const unsigned long long tail = *ctl->inbox_tail;
+  unsigned long long h = ctl->inbox_head;
+  if (h == tail) return;
+  __threadfence_system();
+  for (; h < tail; ++h) {
+    const unsigned long long v = ctl->inbox[h & ctl->inbox_mask];
+    const int ph = (int)((v >> 24) & 0xFull);
+    if ((v >> 28) == 0 && (ph == PH_GEN || (ph == PH_INIT && insts[v & 0xFFFFFFull].kind != BK_GEN)))
+      atomicAdd(&q->live, 1u);   // first item of a newly admitted instance
+    const unsigned long long p = atomicAdd(&q->tail, 1ull);
+    q_store_item(q, p, v);
+  }
+  ctl->inbox_head = h;
+  *ctl->inbox_head_host = h;
+  __threadfence_system();
+}
+
+// Pop one item (thread 0).  Returns false when the block should exit.
+__device__ bool q_pop(BQueue* q, const BInst* insts, BCtl* ctl, int64_t deadline, unsigned long long* out) {
+  const int64_t t0 = now_ticks();
+  for (;;) {
+    if (ctl->mode == 1 && blockIdx.x == 0) drain_inbox(q, insts, ctl);
+    const unsigned long long h = __hip_atomic_load(&q->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long sq = __hip_atomic_load(&q->seq[h & q->mask], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (sq == h + 1) {
+      unsigned long long expected = h;
+      if (__hip_atomic_compare_exchange_strong(&q->head, &expected, h + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)) {
+        *out = __hip_atomic_load(&q->item[h & q->mask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+      }
+      continue;
+    }
+    // Nothing ready.  A block that holds no item may leave: whoever pushes the next
+    // item is running and pops it itself, so work is never stranded.
+    const int64_t now = now_ticks();
+    const uint32_t live = __hip_atomic_load(&q->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (now > deadline) {
+      if (live) atomicOr(&q->error, 1u);
+      return false;
+    }
+    if (ctl->mode == 0 && live == 0) return false;
+    if (ctl->mode == 1 && *ctl->quit && live == 0) return false;
+    // block 0 drains the serving inbox: it stays while admitted work is live
+    if (now - t0 > ctl->idle_limit && !(ctl->mode == 1 && blockIdx.x == 0 && live)) return false;
+    __builtin_amdgcn_s_sleep(8);
+  }
+}
+
+// Count a finished tile of the current phase; true in every thread of the block
+// that finished the last one.  That block sees every other tile's results.
+__device__ bool tile_arrive(BInst* I, uint32_t tiles, int* sh_flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t prev = atomicAdd(&I->arrive, 1u);
+    const bool last = prev == tiles - 1;
+    if (last) __hip_atomic_store(&I->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *sh_flag = last ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = *sh_flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// ---------------------------------------------------------------- row products
+template <int DT, int OP>
+__device__ double dense_rows_t(const BInst* I, const float* wv, int r0, int r1, float* y, bool l2) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const unsigned char* A = static_cast<const unsigned char*>(I->A);
+  const int64_t ldb = I->ld * Traits<DT>::ESZ;
+  double nrm = 0.0;
+  for (int g = r0 + 2 * wave; g < r1; g += 2 * nw) {
+    const unsigned char* rp[2];
+    float sc[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int row = min(g + r, r1 - 1);
+      rp[r] = A + (int64_t)row * ldb;
+      sc[r] = (DT == MAPI_FP8_E4M3) ? I->row_scale[row] : 1.0f;
+    }
+    float s[2];
+    rows_product<DT, OP, 2, 2, false>(rp, sc, wv, I->n, lane, s);
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+      if (lane == 0 && g + r < r1) {
+        y[g + r] = s[r];
+        nrm += l2 ? (double)s[r] * (double)s[r] : fabs((double)s[r]);
+      }
+  }
+  return nrm;
+}
+
+template <int DT>
+__device__ double dense_rows_op(const BInst* I, int op, const float* wv, int r0, int r1, float* y, bool l2) {
+  switch (op) {
+    case MAPI_OP_MIN2: return dense_rows_t<DT, MAPI_OP_MIN2>(I, wv, r0, r1, y, l2);
+    case MAPI_OP_DOT: return dense_rows_t<DT, MAPI_OP_DOT>(I, wv, r0, r1, y, l2);
+    default: return dense_rows_t<DT, MAPI_OP_MIN1>(I, wv, r0, r1, y, l2);
+  }
+}
+
+__device__ double dense_rows(const BInst* I, const float* wv, int r0, int r1, float* y) {
+  const bool rpi = I->method == MAPI_METHOD_RPI;
+  const int op = rpi ? MAPI_OP_DOT : I->op;
+  switch (I->dtype) {
+    case MAPI_BF16: return dense_rows_op<MAPI_BF16>(I, op, wv, r0, r1, y, rpi);
+    case MAPI_FP8_E4M3: return dense_rows_op<MAPI_FP8_E4M3>(I, op, wv, r0, r1, y, rpi);
+    default: return dense_rows_op<MAPI_F32>(I, op, wv, r0, r1, y, rpi);
+  }
+}
+
+// PageRank rows (eq. 11 split sums, as in the single-solve kernel), 8 lanes per row.
+__device__ double csr_rows(const BInst* I, const float* w, int r0, int r1, float* y) {
+  constexpr int G = 8;
+  const bool mapi = I->method == MAPI_METHOD_MAPI;
+  const double base = mapi ? I->st.ex[0] + I->st.ex[1]
+                           : ((double)I->alpha * I->inv_n) * I->st.ex[1] + (double)I->c * I->st.ex[0];
+  const float alpha = I->alpha, c = I->c;
+  const int sub = threadIdx.x % G;
+  double nrm = 0.0;
+  for (int i = r0 + (int)threadIdx.x / G; i < r1; i += (int)blockDim.x / G) {
+    const int32_t p0 = I->row_ptr[i], p1 = I->row_ptr[i + 1];
+    float acc = 0.0f;
+    for (int32_t p = p0 + sub; p < p1; p += G) {
+      const float wj = w[I->col[p]];
+      const float h = I->val[p];
+      if (mapi) {
+        const float g = fmaf(alpha, h, c);
+        acc += __builtin_amdgcn_fmed3f(wj, -g, g) - __builtin_amdgcn_fmed3f(wj, -c, c);
+      } else {
+        acc = fmaf(h, wj, acc);
+      }
+    }
+#pragma unroll
+    for (int off = G / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, G);
+    if (sub == 0) {
+      const float yi = mapi ? (float)(base + (double)acc) : (float)((double)alpha * (double)acc + base);
+      y[i] = yi;
+      nrm += fabs((double)yi);
+    }
+  }
+  return nrm;
+}
+
+__device__ const float* stage_w(const BInst* I, const float* w, float* lds) {
+  if (I->kind == BK_CSR || I->n > kBatchLdsFloats) return w;
+  const int n = I->n, nv4 = n >> 2;
+  for (int v = threadIdx.x; v < nv4; v += blockDim.x)
+    reinterpret_cast<float4*>(lds)[v] = reinterpret_cast<const float4*>(w)[v];
+  for (int j = (nv4 << 2) + threadIdx.x; j < n; j += blockDim.x) lds[j] = w[j];
+  __syncthreads();
+  return lds;
+}
+
+// Normalise rows [r0, r1) of y by nu into w_new; returns the residual and PageRank partials.
+__device__ void fin_rows(const BInst* I, const float* y, const float* w_old, float* w_new, int r0, int r1, double nu,
+                         double* r, double* e0, double* e1) {
+  const double c = (double)I->c;
+  const double inv_n = I->inv_n;
+  for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    const float wn = (float)((double)y[i] / nu);
+    w_new[i] = wn;
+    const double wd = (double)wn;
+    *r += fabs(wd - (double)w_old[i]);
+    if (I->kind == BK_CSR) {
+      if (I->method == MAPI_METHOD_MAPI) {
+        const double tc = fmin(fmax(wd, -c), c);
+        *e0 += tc;
+        if (I->dangling[i]) *e1 += fmin(fmax(wd, -inv_n), inv_n) - tc;
+      } else {
+        *e0 += wd;
+        if (I->dangling[i]) *e1 += wd;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ bool bad_norm(double nu) { return !(nu > 0.0) || !(nu < INFINITY); }
+
+// ---------------------------------------------------------------- phases
+__device__ void phase_gen(BInst* I, uint32_t tile) {
+  const int n = I->n;
+  const int r0 = tile * kGenRows, r1 = min(n, r0 + kGenRows);
+  const uint64_t base = splitmix64(I->seed), sbase = splitmix64(I->seed ^ 0x5BD1E995ull);
+  const float s_n = (float)(1.7320508075688772 / (8388608.0 * sqrt((double)n)));
+  const float spike = (float)(6.0 / (double)n);
+  for (int i = r0; i < r1; ++i) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const float a = gen_entry(base, sbase, i, j, s_n, spike);
+      if (I->dtype == MAPI_BF16) {
+        uint32_t u = __float_as_uint(a);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        reinterpret_cast<uint16_t*>(const_cast<void*>(I->A))[(int64_t)i * I->ld + j] = (uint16_t)(u >> 16);
+      } else {
+        reinterpret_cast<float*>(const_cast<void*>(I->A))[(int64_t)i * I->ld + j] = a;
+      }
+    }
+  }
+}
+
+// Start vector rows; PageRank scalars of w0 into part.
+__device__ void phase_init(BInst* I, uint32_t tile, double* sh) {
+  const int n = I->n;
+  const int r0 = tile * kVecTile, r1 = min(n, r0 + kVecTile);
+  const uint64_t vbase = splitmix64(I->seed ^ 0x1B873593ull);
+  const float inv_sqrt_n = (float)(1.0 / sqrt((double)n));
+  double e0 = 0.0, e1 = 0.0;
+  const double c = (double)I->c, inv_n = I->inv_n;
+  for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    float v;
+    if (I->w0) v = I->w0[i];
+    else if (I->kind == BK_CSR) v = (float)inv_n;
+    else v = (splitmix64(vbase + (uint64_t)i) >> 63) ? -inv_sqrt_n : inv_sqrt_n;   // unit l2 norm
+    I->wb0[i] = v;
+    if (I->kind == BK_CSR) {
+      const double wd = (double)v;
+      if (I->method == MAPI_METHOD_MAPI) {
+        const double tc = fmin(fmax(wd, -c), c);
+        e0 += tc;
+        if (I->dangling[i]) e1 += fmin(fmax(wd, -inv_n), inv_n) - tc;
+      } else {
+        e0 += wd;
+        if (I->dangling[i]) e1 += wd;
+      }
+    }
+  }
+  e0 = block_sum_f64(e0, sh);
+  e1 = block_sum_f64(e1, sh);
+  if (threadIdx.x == 0) {
+    store_agent(&I->part[I->ntiles + 3 * tile + 1], e0);
+    store_agent(&I->part[I->ntiles + 3 * tile + 2], e1);
+  }
+}
+
+// One block iterates a small instance: product, normaliser, normalisation,
+// residual, stop rule, up to kSoloBurst times.  Returns whether it is done.
+__device__ bool phase_solo(BInst* I, float* lds, double* sh) {
+  const int n = I->n;
+  const bool rpi = I->method == MAPI_METHOD_RPI;
+  for (int k = 0; k < kSoloBurst; ++k) {
+    const int it = I->st.iter;
+    const float* wc = (it & 1) ? I->wb1 : I->wb0;
+    float* wn = (it & 1) ? I->wb0 : I->wb1;
+    double nrm;
+    if (I->kind == BK_CSR) {
+      nrm = csr_rows(I, wc, 0, n, I->y);
+    } else {
+      const float* wv = stage_w(I, wc, lds);
+      nrm = dense_rows(I, wv, 0, n, I->y);
+    }
+    double nu = block_sum_f64(nrm, sh);
+    if (rpi && I->kind != BK_CSR) nu = sqrt(nu);
+    __threadfence_block();
+    __syncthreads();
+    if (bad_norm(nu)) {
+      if (threadIdx.x == 0) {
+        I->st.status = MAPI_ERR_DEGENERATE;
+        I->st.done = 1;
+        I->st.nu = nu;
+      }
+      __syncthreads();
+      return true;
+    }
+    double r = 0.0, e0 = 0.0, e1 = 0.0;
+    fin_rows(I, I->y, wc, wn, 0, n, nu, &r, &e0, &e1);
+    r = block_sum_f64(r, sh);
+    e0 = block_sum_f64(e0, sh);
+    e1 = block_sum_f64(e1, sh);
+    if (threadIdx.x == 0) {
+      I->st.nu = nu;
+      I->st.ex[0] = e0;
+      I->st.ex[1] = e1;
+      state_advance(&I->st, r);
+    }
+    __threadfence_block();
+    __syncthreads();
+    if (I->st.done) return true;
+  }
+  return false;
+}
+
+__global__ void __launch_bounds__(kBT) k_persistent(BQueue* q, BInst* insts, BCtl* ctl) {
+  __shared__ float4 lds4[kBatchLdsFloats / 4];
+  __shared__ double sh[16];
+  __shared__ unsigned long long sh_item;
+  __shared__ unsigned long long sh_base;
+  __shared__ int sh_ok;
+  __shared__ int sh_flag;
+  float* lds = reinterpret_cast<float*>(lds4);
+  const int64_t deadline = now_ticks() + ctl->run_limit;
+
+  for (;;) {
+    if (threadIdx.x == 0) {
+      unsigned long long v = 0;
+      sh_ok = (now_ticks() <= deadline && q_pop(q, insts, ctl, deadline, &v)) ? 1 : 0;
+      sh_item = v;
+    }
+    __syncthreads();
+    if (!sh_ok) return;
+    const unsigned long long item = sh_item;
+    const uint32_t ii = (uint32_t)(item & 0xFFFFFFull);
+    const int ph = (int)((item >> 24) & 0xFull);
+    const uint32_t tile = (uint32_t)(item >> 28);
+    BInst* I = insts + ii;
+    const int n = I->n;
+
+    if (ph == PH_GEN) {
+      if (threadIdx.x == 0 && tile == 0) I->t_start = now_ticks();
+      phase_gen(I, tile);
+      if (tile_arrive(I, I->gtiles, &sh_flag)) q_push(q, ii, PH_INIT, I->vtiles, &sh_base);
+    } else if (ph == PH_INIT) {
+      if (threadIdx.x == 0 && tile == 0 && I->kind != BK_GEN) I->t_start = now_ticks();
+      phase_init(I, tile, sh);
+      if (tile_arrive(I, I->vtiles, &sh_flag)) {
+        const double E0 = block_sum_parts(I->part + I->ntiles, I->vtiles, 3, 1, sh);
+        const double E1 = block_sum_parts(I->part + I->ntiles, I->vtiles, 3, 2, sh);
+        if (threadIdx.x == 0) {
+          I->st.ex[0] = E0;
+          I->st.ex[1] = E1;
+          if (I->max_iters <= 0) I->st.done = 1;
+        }
+        __syncthreads();
+        if (I->st.done) q_push(q, ii, PH_OUT, I->vtiles, &sh_base);
+        else q_push(q, ii, PH_PROD, I->solo ? 1u : (uint32_t)I->ntiles, &sh_base);
+      }
+    } else if (ph == PH_PROD) {
+      if (I->solo) {
+        const bool done = phase_solo(I, lds, sh);
+        q_push(q, ii, done ? PH_OUT : PH_PROD, done ? I->vtiles : 1u, &sh_base);
+      } else {
+        const int it = I->st.iter;
+        const float* wc = (it & 1) ? I->wb1 : I->wb0;
+        const int r0 = tile * I->rows_per_tile, r1 = min(n, r0 + I->rows_per_tile);
+        double nrm;
+        if (I->kind == BK_CSR) {
+          nrm = csr_rows(I, wc, r0, r1, I->y);
+        } else {
+          const float* wv = stage_w(I, wc, lds);
+          nrm = dense_rows(I, wv, r0, r1, I->y);
+        }
+        nrm = block_sum_f64(nrm, sh);
+        if (threadIdx.x == 0) store_agent(&I->part[tile], nrm);
+        if (tile_arrive(I, I->ntiles, &sh_flag)) {
+          double nu = block_sum_parts(I->part, I->ntiles, 1, 0, sh);
+          if (I->method == MAPI_METHOD_RPI && I->kind != BK_CSR) nu = sqrt(nu);
+          if (threadIdx.x == 0) I->st.nu = nu;
+          q_push(q, ii, PH_FIN, I->vtiles, &sh_base);
+        }
+      }
+    } else if (ph == PH_FIN) {
+      const int it = I->st.iter;
+      const float* wc = (it & 1) ? I->wb1 : I->wb0;
+      float* wn = (it & 1) ? I->wb0 : I->wb1;
+      const double nu = I->st.nu;
+      double r = 0.0, e0 = 0.0, e1 = 0.0;
+      if (!bad_norm(nu)) fin_rows(I, I->y, wc, wn, tile * kVecTile, min(n, (int)(tile + 1) * kVecTile), nu, &r, &e0, &e1);
+      r = block_sum_f64(r, sh);
+      e0 = block_sum_f64(e0, sh);
+      e1 = block_sum_f64(e1, sh);
+      if (threadIdx.x == 0) {
+        store_agent(&I->part[I->ntiles + 3 * tile + 0], r);
+        store_agent(&I->part[I->ntiles + 3 * tile + 1], e0);
+        store_agent(&I->part[I->ntiles + 3 * tile + 2], e1);
+      }
+      if (tile_arrive(I, I->vtiles, &sh_flag)) {
+        const double R = block_sum_parts(I->part + I->ntiles, I->vtiles, 3, 0, sh);
+        const double E0 = block_sum_parts(I->part + I->ntiles, I->vtiles, 3, 1, sh);
+        const double E1 = block_sum_parts(I->part + I->ntiles, I->vtiles, 3, 2, sh);
+        if (threadIdx.x == 0) {
+          if (bad_norm(nu)) {
+            I->st.status = MAPI_ERR_DEGENERATE;
+            I->st.done = 1;
+          } else {
+            I->st.ex[0] = E0;
+            I->st.ex[1] = E1;
+            state_advance(&I->st, R);
+          }
+        }
+        __syncthreads();
+        if (I->st.done) q_push(q, ii, PH_OUT, I->vtiles, &sh_base);
+        else q_push(q, ii, PH_PROD, (uint32_t)I->ntiles, &sh_base);
+      }
+    } else {   // PH_OUT
+      const float* src = (I->st.iter & 1) ? I->wb1 : I->wb0;
+      const int r0 = tile * kVecTile, r1 = min(n, r0 + kVecTile);
+      for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) I->out[i] = src[i];
+      __threadfence_system();
+      if (tile_arrive(I, I->vtiles, &sh_flag)) {
+        if (threadIdx.x == 0) {
+          I->t_done = now_ticks();
+          if (ctl->mode == 1) {
+            const unsigned long long p = atomicAdd(&ctl->done_pos, 1ull);
+            BDone* d = ctl->done + (p & ctl->done_mask);
+            d->slot = (int32_t)ii;
+            d->slot_gen = I->slot_gen;
+            d->status = I->st.status;
+            d->iters = I->st.iter;
+            d->converged = I->st.converged;
+            d->residual = I->st.r;
+            d->norm = I->st.nu;
+            d->t_admit = I->t_admit;
+            d->t_start = I->t_start;
+            d->t_done = I->t_done;
+            __threadfence_system();
+            __hip_atomic_store(&d->seq, p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+          }
+          __threadfence();
+          atomicSub(&q->live, 1u);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Generated problem written out: A (float32, row pitch ld) and its start vector.
+__global__ void __launch_bounds__(256) k_gen_dense(int n, uint64_t seed, float* A, int64_t ld, float* w0) {
+  const uint64_t base = splitmix64(seed), sbase = splitmix64(seed ^ 0x5BD1E995ull);
+  const uint64_t vbase = splitmix64(seed ^ 0x1B873593ull);
+  const float s_n = (float)(1.7320508075688772 / (8388608.0 * sqrt((double)n)));
+  const float spike = (float)(6.0 / (double)n);
+  const float inv_sqrt_n = (float)(1.0 / sqrt((double)n));
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) A[(int64_t)i * ld + j] = gen_entry(base, sbase, i, j, s_n, spike);
+    if (threadIdx.x == 0 && w0) w0[i] = (splitmix64(vbase + (uint64_t)i) >> 63) ? -inv_sqrt_n : inv_sqrt_n;
+  }
+}
+
+hipError_t launch_gen_dense(int n, uint64_t seed, float* A, int64_t ld, float* w0, hipStream_t s) {
+  hipLaunchKernelGGL(k_gen_dense, dim3(n < 8192 ? n : 8192), dim3(256), 0, s, n, seed, A, ld, w0);
+  return hipGetLastError();
+}
+
+int persistent_threads() { return kBT; }
+
+hipError_t launch_persistent(BQueue* q, BInst* inst, BCtl* ctl, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_persistent, dim3(blocks), dim3(kBT), 0, s, q, inst, ctl);
+  return hipGetLastError();
+}
+
+}  // namespace mapi

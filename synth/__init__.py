@@ -181,3 +181,52 @@ def tiny_graph(edges, n):
     np.cumsum(np.bincount(dst, minlength=n), out=row_ptr[1:])
     return dict(n=n, row_ptr=row_ptr.astype(np.int32), col=src.astype(np.int32),
                 val=val, outdeg=outdeg.astype(np.int32))
+
+
+# --------------------------------------------------------------------------
+# Counter-based generated problems (the device generator's definition)
+# --------------------------------------------------------------------------
+_U64 = np.uint64
+
+
+def splitmix64(x):
+    """SplitMix64 output function (Steele, Lea and Flood, 2014) on uint64 arrays, mod 2^64."""
+    x = np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        x = x + _U64(0x9E3779B97F4A7C15)
+        x = (x ^ (x >> _U64(30))) * _U64(0xBF58476D1CE4E5B9)
+        x = (x ^ (x >> _U64(27))) * _U64(0x94D049BB133111EB)
+    return x ^ (x >> _U64(31))
+
+
+def _counter(base, k):
+    with np.errstate(over="ignore"):
+        return splitmix64(base + np.asarray(k, dtype=np.uint64))
+
+
+def generated_dense(n, seed):
+    """The seed-generated symmetric problem: (A float32 n x n, w0 float32 n).
+
+    a_ij = fl32(fl32(x_ij * s_n) + sigma_i sigma_j * fl32(6 / n)), x_ij = (top 24 bits of
+    splitmix64(splitmix64(seed) + (min(i,j) << 32 | max(i,j)))) - 2^23, s_n = fl32(sqrt(3) /
+    (2^23 sqrt(n))), sigma_i = -1 if the top bit of splitmix64(splitmix64(seed ^ 0x5BD1E995) + i)
+    is set else +1.  w0_i = -+fl32(1 / sqrt(n)) by the top bit of
+    splitmix64(splitmix64(seed ^ 0x1B873593) + i).
+    """
+    seed = _U64(seed)
+    base = splitmix64(seed)
+    sbase = splitmix64(seed ^ _U64(0x5BD1E995))
+    vbase = splitmix64(seed ^ _U64(0x1B873593))
+    idx = np.arange(n, dtype=np.uint64)
+    lo = np.minimum(idx[:, None], idx[None, :])
+    hi = np.maximum(idx[:, None], idx[None, :])
+    h = _counter(base, (lo << _U64(32)) | hi)
+    x = ((h >> _U64(40)).astype(np.int64) - 8388608).astype(np.float32)
+    s_n = np.float32(1.7320508075688772 / (8388608.0 * np.sqrt(float(n))))
+    spike = np.float32(6.0 / float(n))
+    sig = (_counter(sbase, idx) >> _U64(63)).astype(bool)
+    same = sig[:, None] == sig[None, :]
+    A = (x * s_n).astype(np.float32) + np.where(same, spike, -spike).astype(np.float32)
+    inv = np.float32(1.0 / np.sqrt(float(n)))
+    w0 = np.where((_counter(vbase, idx) >> _U64(63)).astype(bool), -inv, inv).astype(np.float32)
+    return A.astype(np.float32), w0
