@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -186,6 +188,211 @@ def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write):
     print(json.dumps(out, indent=1))
 
 
+# ------------------------------------------------------------------ other workloads
+def _loguniform_sizes(rng, k, lo, hi):
+    return [int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi)))))) for _ in range(k)]
+
+
+def bench_batched(mp, ctx, torch, k=128, seed=5):
+    """Ragged generated problems (n log-uniform in [64, 8192], tol 1e-6): batched BF16 MAPI in one
+    persistent launch versus one-at-a-time float32 MAPI and RPI (generation included in both)."""
+    rng = np.random.default_rng(seed)
+    sizes = _loguniform_sizes(rng, k, 64, 8192)
+    seeds = [70000 + i for i in range(k)]
+    out = {"instances": k, "sizes": "log-uniform 64..8192", "tol": 1e-6}
+
+    def batched(dt, meth):
+        probs = [mp.problem_generated(n, s, dt, meth, max_iters=1000, tol=1e-6) for n, s in zip(sizes, seeds)]
+        mp.mapi_solve_batched(probs[:4], ctx=ctx)                  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = mp.mapi_solve_batched(probs, ctx=ctx)
+        torch.cuda.synchronize()
+        dt_s = time.perf_counter() - t0
+        return k / dt_s, infos, probs
+
+    def plain(meth):
+        fn = mp.mapi_solve if meth == "mapi" else mp.rpi_solve
+        res = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n, s in zip(sizes, seeds):
+            A, w0 = mp.mapi_generate_dense(n, s, ctx=ctx)
+            w, info = fn(A, w0, max_iters=1000, tol=1e-6, check_every=4, ctx=ctx)
+            res.append((w, info))
+        torch.cuda.synchronize()
+        return k / (time.perf_counter() - t0), res
+
+    for dt, meth in (("bf16", "mapi"), ("f32", "mapi"), ("f32", "rpi")):
+        sps, infos, probs = batched(dt, meth)
+        out[f"batched_{dt}_{meth}_solves_s"] = sps
+        out[f"batched_{dt}_{meth}_mean_iters"] = float(np.mean([i["iters"] for i in infos]))
+        out[f"batched_{dt}_{meth}_converged"] = int(sum(i["converged"] for i in infos))
+        if (dt, meth) == ("bf16", "mapi"):
+            bf16_probs = probs
+    for meth in ("mapi", "rpi"):
+        sps, res = plain(meth)
+        out[f"plain_f32_{meth}_solves_s"] = sps
+        out[f"plain_f32_{meth}_mean_iters"] = float(np.mean([r[1]["iters"] for r in res]))
+        if meth == "mapi":
+            errs = [float((p.out - w).abs().sum() / w.abs().sum()) for p, (w, _) in zip(bf16_probs, res)]
+            out["bf16_batched_vs_f32_plain_mapi_max_rel_l1"] = max(errs)
+    return out
+
+
+def bench_pca(mp, ctx, torch, D=4096, N=65536, k=8, seed=77):
+    import synth
+    log("PCA: generating X 4096 x 65536 on the GPU")
+    X, clean = synth.pca_data_device(D, N, seed, "cuda")
+    W0 = torch.from_numpy(synth.start_vectors(D, k, seed + 1)).cuda()
+    terms = D * (D + 1) / 2 * N
+    out = {"D": D, "N": N, "k": k}
+    for op in ("min1", "dot"):
+        mp.mapi_mingram(X, 1.0 / N, op, ctx=ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A = mp.mapi_mingram(X, 1.0 / N, op, ctx=ctx)
+        torch.cuda.synchronize()
+        s = time.perf_counter() - t0
+        ops = 3.125 if op == "min1" else 1.0
+        out[f"gram_{op}_ms"] = s * 1e3
+        out[f"gram_{op}_gterms_s"] = terms / s / 1e9
+        out[f"gram_{op}_valu_frac"] = terms * ops / s / 39.3e12
+        del A
+    cn = torch.linalg.norm(clean)
+    for meth in ("mapi", "rpi"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P, infos = mp.mapi_pca_topk(X, k, W0, method=meth, max_iters=1000, tol=1e-6, check_every=8, ctx=ctx)
+        torch.cuda.synchronize()
+        out[f"pca_{meth}_ms"] = (time.perf_counter() - t0) * 1e3
+        out[f"pca_{meth}_iters"] = [i["iters"] for i in infos]
+        out[f"pca_{meth}_converged"] = int(sum(i["converged"] for i in infos))
+        recon = P @ (P.t() @ clean)
+        out[f"pca_{meth}_reconstruction_error"] = float(torch.linalg.norm(clean - recon) / cn)
+    del X, clean
+    return out
+
+
+def bench_pagerank(mp, ctx, torch, n=1 << 22, seed=2022):
+    import synth
+    log("PageRank: generating the 2^22-node graph on the host")
+    g = synth.powerlaw_graph(n, seed)
+    rp, col, val = (torch.from_numpy(g[x]).cuda() for x in ("row_ptr", "col", "val"))
+    nnz = int(g["col"].size)
+    bytes_iter = 8.0 * nnz + 4.0 * (n + 1) + 8.0 * n        # links, row pointers, w once, y once
+    out = {"n": n, "nnz": nnz}
+    for meth in ("mapi", "rpi"):
+        mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=2, ctx=ctx)
+        ctx.timing(True)
+        ctx.timing_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w, info = mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=300, tol=1e-8, stall_iters=10,
+                                   check_every=4, ctx=ctx)
+        torch.cuda.synchronize()
+        s = time.perf_counter() - t0
+        ms, launches = ctx.timing_get("csr")
+        ctx.timing(False)
+        kms = ms / max(launches, 1)
+        out[f"{meth}_iters"] = info["iters"]
+        out[f"{meth}_converged"] = info["converged"]
+        out[f"{meth}_final_residual"] = info["residual"]
+        out[f"{meth}_ms_total"] = s * 1e3
+        out[f"{meth}_csr_kernel_us"] = kms * 1e3
+        out[f"{meth}_gedges_s"] = nnz / (kms * 1e-3) / 1e9
+        out[f"{meth}_csr_kernel_gbs"] = bytes_iter / (kms * 1e-3) / 1e9
+    return out
+
+
+def bench_serving(mp, torch, n_req=20000, rate=2000.0, seed=11, budget=64 << 30, plain_sample=400):
+    """Poisson arrivals; 70 % dense generated problems (n log-uniform 64..8192, BF16/F32, MAPI/RPI),
+    30 % PageRank on power-law graphs with 2^10..2^20 nodes (a resident pool of 11 graphs, one per
+    power of two, in pinned host memory), tolerance 1e-6 each; compared with the one-at-a-time
+    plain path (FIFO, float32) whose latencies are simulated from measured service times."""
+    import synth
+    rng = np.random.default_rng(seed)
+    log("serving: building the graph pool")
+    pool = {}
+    for e in range(10, 21):
+        g = synth.powerlaw_graph(1 << e, seed=900 + e)
+        pinned = {}
+        for key in ("row_ptr", "col", "val"):
+            t = torch.empty(g[key].shape, dtype=torch.from_numpy(g[key][:1]).dtype, pin_memory=True)
+            t.numpy()[...] = g[key]
+            pinned[key] = t
+        pool[e] = pinned
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    reqs = []
+    for i in range(n_req):
+        if rng.uniform() < 0.7:
+            n = int(round(float(np.exp(rng.uniform(np.log(64), np.log(8192))))))
+            reqs.append(("gen", n, ["f32", "bf16"][rng.integers(2)], ["mapi", "rpi"][rng.integers(2)], 10_000_000 + i))
+        else:
+            e = int(rng.integers(10, 21))
+            reqs.append(("csr", 1 << e, "f32", ["mapi", "rpi"][rng.integers(2)], e))
+
+    def make(r):
+        kind, n, dt, meth, s = r
+        if kind == "gen":
+            return mp.request_generated(n, s, dt, meth, max_iters=1000, tol=1e-6)
+        p = pool[s]
+        return mp.request_csr_host(p["row_ptr"].numpy(), p["col"].numpy(), p["val"].numpy(), 0.85, meth,
+                                   max_iters=1000, tol=1e-6)
+
+    log(f"serving: {n_req} requests at {rate:.0f}/s")
+    srv = mp.Server(budget_bytes=budget)
+    tickets = []
+    t_start = time.perf_counter()
+    for i, r in enumerate(reqs):
+        wait = arrivals[i] - (time.perf_counter() - t_start)
+        if wait > 0:
+            time.sleep(wait)
+        tickets.append(srv.submit(make(r), np.empty(r[1], np.float32)))
+    res = [srv.wait(t, timeout_us=120_000_000) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    ok = sum(1 for x in res if x is not None and x["status"] == "OK")
+    out = {"requests": n_req, "rate_per_s": rate, "completed_ok": ok, "solves_s": st["solves_per_s"],
+           "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "peak_pool_bytes": st["peak_bytes"],
+           "budget_bytes": budget, "kernel_launches": st["kernel_launches"],
+           "converged": int(sum(1 for x in res if x and x["converged"]))}
+    # one-at-a-time plain path on a sample: float32, one solve after another on one stream
+    log(f"serving: timing the one-at-a-time path on {plain_sample} requests")
+    ctx = mp.Context()
+    idx = rng.choice(n_req, size=min(plain_sample, n_req), replace=False)
+    service = []
+    for i in idx:
+        kind, n, dt, meth, s = reqs[i]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if kind == "gen":
+            A, w0 = mp.mapi_generate_dense(n, s, ctx=ctx)
+            fn = mp.mapi_solve if meth == "mapi" else mp.rpi_solve
+            w, _ = fn(A, w0, max_iters=1000, tol=1e-6, check_every=4, ctx=ctx)
+        else:
+            p = pool[s]
+            rp, col, val = (p[k].cuda(non_blocking=True) for k in ("row_ptr", "col", "val"))
+            w, _ = mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=1000, tol=1e-6, check_every=4, ctx=ctx)
+        w.cpu()
+        service.append(time.perf_counter() - t0)
+    ctx.close()
+    service = np.array(service)
+    # FIFO single server fed by the same arrival process, service times drawn from the sample
+    draws = service[rng.integers(0, service.size, n_req)]
+    free = 0.0
+    lat = np.empty(n_req)
+    for i in range(n_req):
+        start = max(arrivals[i], free)
+        free = start + draws[i]
+        lat[i] = free - arrivals[i]
+    out["plain_f32_solves_s"] = 1.0 / float(service.mean())
+    out["plain_f32_p50_ms_simulated"] = float(np.percentile(lat, 50) * 1e3)
+    out["plain_f32_p99_ms_simulated"] = float(np.percentile(lat, 99) * 1e3)
+    out["plain_sample"] = int(service.size)
+    return out
+
+
 # ------------------------------------------------------------------ benchmark
 def main():
     ap = argparse.ArgumentParser()
@@ -194,6 +401,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="bench", choices=["bench", "kernels"])
+    ap.add_argument("--sections", default="batched,pca,pagerank,serving",
+                    help="other workloads reported under detail (comma list; empty for none)")
     ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--commands", nargs=3, default=["", "", ""], help="commands that produced the three dirs")
     args = ap.parse_args()
@@ -208,7 +417,6 @@ def main():
         run_kernels_mode()
         return
 
-    import numpy as np
     torch, mp, ctx, C, w0, mats = setup()
     sync = torch.cuda.synchronize
     elems = float(N) * N * ITERS
@@ -247,6 +455,16 @@ def main():
     sec, k_ms, launches, achieved = head
     value = elems / sec / 1e9
     traffic = load_traffic("f32")
+
+    sections = [x for x in args.sections.split(",") if x]
+    for name, fn in (("batched", lambda: bench_batched(mp, ctx, torch)), ("pca", lambda: bench_pca(mp, ctx, torch)),
+                     ("pagerank", lambda: bench_pagerank(mp, ctx, torch)), ("serving", lambda: bench_serving(mp, torch))):
+        if name in sections:
+            log(f"section {name}")
+            t0 = time.perf_counter()
+            detail[name] = fn()
+            detail[name]["section_wall_s"] = time.perf_counter() - t0
+            log(f"section {name} done in {detail[name]['section_wall_s']:.1f} s")
 
     cpu = None
     if not args.no_cpu_baseline:

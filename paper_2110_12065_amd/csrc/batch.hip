@@ -91,6 +91,10 @@ mapi_status describe(mapi_ctx* c, const mapi_problem& p, BInst* I, int64_t* matr
     I->dtype = p.gen_dtype;
     I->ld = (n + 7) / 8 * 8;
     *matrix_bytes = I->ld * n * elem_size(p.gen_dtype);
+    const GenConsts g = gen_consts(n);
+    I->gen_scale = g.scale;
+    I->gen_spike = g.spike;
+    I->gen_w0 = g.w0;
   } else {
     return fail(MAPI_ERR_ARG, "unknown problem kind %d", p.kind);
   }

@@ -43,6 +43,7 @@ struct BInst {
   float alpha, c;
   double inv_n;
   uint64_t seed;             // BK_GEN and generated start vectors
+  float gen_scale, gen_spike, gen_w0;   // generator constants, rounded on the host (GenConsts)
   const float* w0;           // NULL: generated (BK_GEN) or uniform (BK_CSR)
   float* wb0;
   float* wb1;
@@ -126,6 +127,16 @@ __device__ __forceinline__ float gen_entry(uint64_t base, uint64_t sbase, int i,
 }
 
 hipError_t launch_persistent(BQueue* q, BInst* inst, BCtl* ctl, int blocks, hipStream_t s);
+
+// Generator constants, computed on the host in float64 with correctly rounded
+// sqrt and division and rounded once to float32.
+struct GenConsts {
+  float scale, spike, w0;
+};
+inline GenConsts gen_consts(int64_t n) {
+  const double rn = __builtin_sqrt((double)n);
+  return GenConsts{(float)(1.7320508075688772 / (8388608.0 * rn)), (float)(6.0 / (double)n), (float)(1.0 / rn)};
+}
 
 // host helpers shared by the batched solve and the server (batch.hip)
 }  // namespace mapi

@@ -227,8 +227,7 @@ __device__ void phase_gen(BInst* I, uint32_t tile) {
   const int n = I->n;
   const int r0 = tile * kGenRows, r1 = min(n, r0 + kGenRows);
   const uint64_t base = splitmix64(I->seed), sbase = splitmix64(I->seed ^ 0x5BD1E995ull);
-  const float s_n = (float)(1.7320508075688772 / (8388608.0 * sqrt((double)n)));
-  const float spike = (float)(6.0 / (double)n);
+  const float s_n = I->gen_scale, spike = I->gen_spike;
   for (int i = r0; i < r1; ++i) {
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
       const float a = gen_entry(base, sbase, i, j, s_n, spike);
@@ -248,7 +247,7 @@ __device__ void phase_init(BInst* I, uint32_t tile, double* sh) {
   const int n = I->n;
   const int r0 = tile * kVecTile, r1 = min(n, r0 + kVecTile);
   const uint64_t vbase = splitmix64(I->seed ^ 0x1B873593ull);
-  const float inv_sqrt_n = (float)(1.0 / sqrt((double)n));
+  const float inv_sqrt_n = I->gen_w0;
   double e0 = 0.0, e1 = 0.0;
   const double c = (double)I->c, inv_n = I->inv_n;
   for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
@@ -459,12 +458,10 @@ __global__ void __launch_bounds__(kBT) k_persistent(BQueue* q, BInst* insts, BCt
 }
 
 // Generated problem written out: A (float32, row pitch ld) and its start vector.
-__global__ void __launch_bounds__(256) k_gen_dense(int n, uint64_t seed, float* A, int64_t ld, float* w0) {
+__global__ void __launch_bounds__(256) k_gen_dense(int n, uint64_t seed, float* A, int64_t ld, float* w0, float s_n,
+                                                 float spike, float inv_sqrt_n) {
   const uint64_t base = splitmix64(seed), sbase = splitmix64(seed ^ 0x5BD1E995ull);
   const uint64_t vbase = splitmix64(seed ^ 0x1B873593ull);
-  const float s_n = (float)(1.7320508075688772 / (8388608.0 * sqrt((double)n)));
-  const float spike = (float)(6.0 / (double)n);
-  const float inv_sqrt_n = (float)(1.0 / sqrt((double)n));
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     for (int j = threadIdx.x; j < n; j += blockDim.x) A[(int64_t)i * ld + j] = gen_entry(base, sbase, i, j, s_n, spike);
     if (threadIdx.x == 0 && w0) w0[i] = (splitmix64(vbase + (uint64_t)i) >> 63) ? -inv_sqrt_n : inv_sqrt_n;
@@ -472,7 +469,8 @@ __global__ void __launch_bounds__(256) k_gen_dense(int n, uint64_t seed, float* 
 }
 
 hipError_t launch_gen_dense(int n, uint64_t seed, float* A, int64_t ld, float* w0, hipStream_t s) {
-  hipLaunchKernelGGL(k_gen_dense, dim3(n < 8192 ? n : 8192), dim3(256), 0, s, n, seed, A, ld, w0);
+  const GenConsts g = gen_consts(n);
+  hipLaunchKernelGGL(k_gen_dense, dim3(n < 8192 ? n : 8192), dim3(256), 0, s, n, seed, A, ld, w0, g.scale, g.spike, g.w0);
   return hipGetLastError();
 }
 

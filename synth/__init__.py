@@ -121,6 +121,28 @@ def pca_data(D, N, seed, n_factors=16, noise=0.1, outlier_frac=0.05, laplace_b=1
     return X.astype(np.float32)
 
 
+def pca_data_device(D, N, seed, device, n_factors=16, noise=0.1, outlier_frac=0.05, laplace_b=10.0,
+                    decay=0.8, lead=2.0):
+    """``pca_data`` drawn with torch's seeded generator on ``device``; returns (X, X_clean)
+    as float32 tensors (X_clean: the centred low-rank part U Z).  Same recipe and draw
+    order as ``pca_data``; the Laplace draws are inverse-CDF transforms of uniforms."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    U = torch.randn((D, n_factors), generator=g, device=device, dtype=torch.float32)
+    sd = lead * decay ** torch.arange(n_factors, device=device, dtype=torch.float32)
+    Z = torch.randn((n_factors, N), generator=g, device=device, dtype=torch.float32) * sd[:, None]
+    clean = U @ Z
+    X = clean + noise * torch.randn((D, N), generator=g, device=device, dtype=torch.float32)
+    mask = torch.rand((D, N), generator=g, device=device) < outlier_frac
+    u = torch.rand((D, N), generator=g, device=device, dtype=torch.float32) - 0.5
+    lap = -laplace_b * torch.sign(u) * torch.log1p(-2.0 * torch.abs(u))
+    X = torch.where(mask, lap, X)
+    X -= X.mean(dim=1, keepdim=True)
+    clean -= clean.mean(dim=1, keepdim=True)
+    return X.contiguous(), clean.contiguous()
+
+
 def pca_clean(D, N, seed, n_factors=16, decay=0.8, lead=2.0):
     """The noise- and outlier-free low-rank part U Z of ``pca_data`` for the same seed,
     centred, float64 (for the reconstruction-error report)."""

@@ -106,7 +106,7 @@ def test_serve_invalid_request_fails_alone():
     out_bad = np.zeros(800, np.float32)
     out_ok = np.zeros(900, np.float32)
     t_bad = srv.submit(mp.request_csr_host(g["row_ptr"], bad_col, g["val"], 0.85, "mapi"), out_bad)
-    t_ok = srv.submit(mp.request_generated(900, 5, "f32", "mapi", max_iters=50), out_ok)
+    t_ok = srv.submit(mp.request_generated(900, 5, "f32", "mapi", max_iters=50, tol=0.0), out_ok)
     r_bad = srv.wait(t_bad, timeout_us=30_000_000)
     r_ok = srv.wait(t_ok, timeout_us=30_000_000)
     srv.close()
