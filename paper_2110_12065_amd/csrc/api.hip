@@ -75,7 +75,7 @@ DenseTuning tuning_for(mapi_ctx* c, const DenseArgs& a) {
   auto it = c->tuned.find(bucket(a.dtype, a.n_rows, a.n_cols));
   if (it != c->tuned.end()) {
     t = it->second;
-    if (t.w_in_lds && a.n_cols * 4 + 1024 > c->max_lds) t.w_in_lds = 0;   // bucket spans sizes past the LDS
+    if (t.w_in_lds && (int64_t)dense_lds_bytes(a.dtype, a.n_cols) + 1024 > c->max_lds) t.w_in_lds = 0;   // bucket spans sizes past the LDS
   }
   return t;
 }
@@ -333,7 +333,7 @@ mapi_status mapi_mavp_timed(mapi_ctx* c, const mapi_dense* A, const float* w, fl
   DenseTuning t;
   if ((s = to_dense_tuning(tu, &t)) != MAPI_OK) return s;
   const DenseArgs da = dense_args(A);
-  if (t.w_in_lds && da.n_cols * 4 + 1024 > c->max_lds) return fail(MAPI_ERR_ARG, "w does not fit in LDS");
+  if (t.w_in_lds && (int64_t)dense_lds_bytes(da.dtype, da.n_cols) + 1024 > c->max_lds) return fail(MAPI_ERR_ARG, "w does not fit in LDS");
   HIP_TRY(hipSetDevice(c->device));
   return time_product(c, da, op, w, y, t, reps, avg_ms);
 }
@@ -354,7 +354,7 @@ mapi_status mapi_autotune_dense(mapi_ctx* c, const mapi_dense* A, int32_t op, in
   float* w = reinterpret_cast<float*>(static_cast<char*>(c->ws) + o_w);
   float* y = reinterpret_cast<float*>(static_cast<char*>(c->ws) + o_y);
   HIP_TRY(launch_fill_f32(w, da.n_cols, 1.0f / (float)da.n_cols, c->stream));
-  const bool lds_ok = da.n_cols * 4 + 1024 <= c->max_lds;
+  const bool lds_ok = (int64_t)dense_lds_bytes(da.dtype, da.n_cols) + 1024 <= c->max_lds;
   DenseTuning bt = dense_default_tuning(da, c->cu_count, c->max_lds);
   double bms = 1e30;
   for (int rw : {1, 2, 4, 8}) {

@@ -118,12 +118,14 @@ __host__ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
 // bit of splitmix64(splitmix64(seed ^ 0x5BD1E995) + i) as a sign.  Rounded in float32,
 // product then sum.
 __device__ __forceinline__ float gen_entry(uint64_t base, uint64_t sbase, int i, int j, float s_n, float spike) {
+#pragma clang fp contract(off)
   const uint64_t lo = (uint64_t)min(i, j), hi = (uint64_t)max(i, j);
   const uint64_t h = splitmix64(base + ((lo << 32) | hi));
   const float x = (float)((int32_t)(h >> 40) - 8388608);
   const bool si = (splitmix64(sbase + (uint64_t)i) >> 63) != 0;
   const bool sj = (splitmix64(sbase + (uint64_t)j) >> 63) != 0;
-  return __fadd_rn(__fmul_rn(x, s_n), (si == sj) ? spike : -spike);
+  const float prod = x * s_n;          // rounded on its own: no fused multiply-add here
+  return prod + ((si == sj) ? spike : -spike);
 }
 
 hipError_t launch_persistent(BQueue* q, BInst* inst, BCtl* ctl, int blocks, hipStream_t s);

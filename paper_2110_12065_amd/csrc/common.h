@@ -161,6 +161,13 @@ struct DenseTuning {
   int nontemporal;     // non-temporal matrix loads
 };
 
+// LDS bytes of the dense product kernel when w is staged there: w (FP8: |w| plus one
+// sign word per 4 columns).
+inline size_t dense_lds_bytes(int dtype, int64_t n_cols) {
+  const size_t wbytes = (size_t)((n_cols + 3) & ~int64_t(3)) * 4;
+  return dtype == MAPI_FP8_E4M3 ? wbytes + (size_t)((n_cols >> 2) + 4) * 4 : (size_t)n_cols * 4;
+}
+
 hipError_t launch_state_init(SolveState* st, int max_iters, double tol, int stall_iters, hipStream_t s);
 hipError_t launch_mavp_dense(const DenseArgs& a, int op, const float* w, float* y, double* part,
                              SolveState* st, int norm, const DenseTuning& t, int cu_count, hipStream_t s);

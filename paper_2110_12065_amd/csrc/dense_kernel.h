@@ -76,14 +76,53 @@ __device__ __forceinline__ uint4 load16(const unsigned char* p) {
 // Row products of RW rows (byte pointers rp, FP8 row scales sc) against w (wv,
 // n_cols floats, 16-byte aligned) by one wave: lanes stride along the columns in
 // 16-byte vectors, then a fixed butterfly; out[r] is valid in every lane.
-template <int DT, int OP, int RW, int U, bool NT>
+//
+// PF (FP8 with w staged in LDS): wv holds |w| and smask one word per 4 stored
+// values whose bits 7, 15, 23, 31 are the signs of those columns' w.  One xor
+// flips the signs of four stored values before decoding, so each term is
+// op(a * sign(w), |w|) -- the same value as op(a, w) -- without per-element sign
+// work.  wsign: the signed w, used for the ragged tail.
+template <int DT, int OP, int RW, int U, bool NT, bool PF = false>
 __device__ __forceinline__ void rows_product(const unsigned char* const* rp, const float* sc, const float* wv,
-                                             int n_cols, int lane, float* out) {
+                                             int n_cols, int lane, float* out, const uint32_t* smask = nullptr,
+                                             const float* wsign = nullptr) {
   constexpr int VE = Traits<DT>::VE;
   const int nvec = n_cols / VE;
   float acc[RW][2];
 #pragma unroll
   for (int r = 0; r < RW; ++r) acc[r][0] = acc[r][1] = 0.0f;
+
+  // terms of one 16-byte vector index vv for every row
+  auto vec = [&](int vv, const uint4* raws) {
+    float wf[VE];
+    uint32_t ws[VE];
+    const float4* wp = reinterpret_cast<const float4*>(wv + (int64_t)vv * VE);
+#pragma unroll
+    for (int q = 0; q < VE / 4; ++q) {
+      const float4 t = wp[q];
+      wf[4 * q] = t.x; wf[4 * q + 1] = t.y; wf[4 * q + 2] = t.z; wf[4 * q + 3] = t.w;
+    }
+    uint4 m = make_uint4(0u, 0u, 0u, 0u);
+    if constexpr (PF) {
+      m = *reinterpret_cast<const uint4*>(smask + (int64_t)vv * 4);
+#pragma unroll
+      for (int e = 0; e < VE; ++e) ws[e] = 0u;
+    } else {
+#pragma unroll
+      for (int e = 0; e < VE; ++e) ws[e] = sign_bit(wf[e]);
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      uint4 rr = raws[r];
+      if constexpr (PF) {
+        rr.x ^= m.x; rr.y ^= m.y; rr.z ^= m.z; rr.w ^= m.w;
+      }
+      float a[VE];
+      decode_vec<DT>(rr, sc[r], a);
+#pragma unroll
+      for (int e = 0; e < VE; ++e) acc[r][e & 1] = op_acc<OP>(acc[r][e & 1], a[e], wf[e], ws[e]);
+    }
+  };
 
   int v = lane;
   for (; v + kWave * (U - 1) < nvec; v += kWave * U) {
@@ -94,50 +133,18 @@ __device__ __forceinline__ void rows_product(const unsigned char* const* rp, con
       for (int r = 0; r < RW; ++r)
         raw[u][r] = load16<NT>(rp[r] + (int64_t)(v + kWave * u) * 16);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      float wf[VE];
-      uint32_t ws[VE];
-      const float4* wp = reinterpret_cast<const float4*>(wv + (int64_t)(v + kWave * u) * VE);
-#pragma unroll
-      for (int q = 0; q < VE / 4; ++q) {
-        const float4 t = wp[q];
-        wf[4 * q] = t.x; wf[4 * q + 1] = t.y; wf[4 * q + 2] = t.z; wf[4 * q + 3] = t.w;
-      }
-#pragma unroll
-      for (int e = 0; e < VE; ++e) ws[e] = sign_bit(wf[e]);
-#pragma unroll
-      for (int r = 0; r < RW; ++r) {
-        float a[VE];
-        decode_vec<DT>(raw[u][r], sc[r], a);
-#pragma unroll
-        for (int e = 0; e < VE; ++e) acc[r][e & 1] = op_acc<OP>(acc[r][e & 1], a[e], wf[e], ws[e]);
-      }
-    }
+    for (int u = 0; u < U; ++u) vec(v + kWave * u, raw[u]);
   }
   for (; v < nvec; v += kWave) {
-    float wf[VE];
-    uint32_t ws[VE];
-    const float4* wp = reinterpret_cast<const float4*>(wv + (int64_t)v * VE);
+    uint4 raw[RW];
 #pragma unroll
-    for (int q = 0; q < VE / 4; ++q) {
-      const float4 t = wp[q];
-      wf[4 * q] = t.x; wf[4 * q + 1] = t.y; wf[4 * q + 2] = t.z; wf[4 * q + 3] = t.w;
-    }
-#pragma unroll
-    for (int e = 0; e < VE; ++e) ws[e] = sign_bit(wf[e]);
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-      const uint4 raw = load16<NT>(rp[r] + (int64_t)v * 16);
-      float a[VE];
-      decode_vec<DT>(raw, sc[r], a);
-#pragma unroll
-      for (int e = 0; e < VE; ++e) acc[r][e & 1] = op_acc<OP>(acc[r][e & 1], a[e], wf[e], ws[e]);
-    }
+    for (int r = 0; r < RW; ++r) raw[r] = load16<NT>(rp[r] + (int64_t)v * 16);
+    vec(v, raw);
   }
   // ragged tail: fewer than VE columns past the last full vector
   const int j = nvec * VE + lane;
   if (j < n_cols) {
-    const float wj = wv[j];
+    const float wj = PF ? wsign[j] : wv[j];
     const uint32_t sj = sign_bit(wj);
 #pragma unroll
     for (int r = 0; r < RW; ++r) acc[r][0] = op_acc<OP>(acc[r][0], decode_one<DT>(rp[r], j, sc[r]), wj, sj);
@@ -158,8 +165,23 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
 
   if (st != nullptr && state_done(st)) return;
 
+  constexpr bool PF = WLDS && DT == MAPI_FP8_E4M3;
   const float* wv = w;
-  if constexpr (WLDS) {
+  const uint32_t* smask = nullptr;
+  if constexpr (PF) {
+    // |w| and one sign word per 4 columns
+    const int nw4 = n_cols >> 2;
+    uint32_t* sm = reinterpret_cast<uint32_t*>(w_lds + ((n_cols + 3) & ~3));
+    for (int k = threadIdx.x; k < nw4; k += blockDim.x) {
+      const float4 t = reinterpret_cast<const float4*>(w)[k];
+      reinterpret_cast<float4*>(w_lds)[k] = make_float4(fabsf(t.x), fabsf(t.y), fabsf(t.z), fabsf(t.w));
+      sm[k] = (sign_bit(t.x) >> 24) | (sign_bit(t.y) >> 16) | (sign_bit(t.z) >> 8) | sign_bit(t.w);
+    }
+    for (int j = (nw4 << 2) + threadIdx.x; j < n_cols; j += blockDim.x) w_lds[j] = fabsf(w[j]);
+    __syncthreads();
+    wv = w_lds;
+    smask = sm;
+  } else if constexpr (WLDS) {
     const int nv4 = n_cols >> 2;
     for (int v = threadIdx.x; v < nv4; v += blockDim.x)
       reinterpret_cast<float4*>(w_lds)[v] = reinterpret_cast<const float4*>(w)[v];
@@ -184,7 +206,7 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
       sc[r] = (DT == MAPI_FP8_E4M3) ? rscale[row] : 1.0f;
     }
     float sums[RW];
-    rows_product<DT, OP, RW, U, NT>(rp, sc, wv, n_cols, lane, sums);
+    rows_product<DT, OP, RW, U, NT, PF>(rp, sc, wv, n_cols, lane, sums, smask, w);
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
       const float s = sums[r];
@@ -213,7 +235,7 @@ static hipError_t launch_k(const DenseArgs& a, const float* w, float* y, double*
                            int blocks, int waves, hipStream_t s) {
   const unsigned char* A = static_cast<const unsigned char*>(a.A);
   const int64_t ldb = a.ld * Traits<DT>::ESZ;
-  const size_t lds = WLDS ? (size_t)a.n_cols * sizeof(float) : 0;
+  const size_t lds = WLDS ? dense_lds_bytes(DT, a.n_cols) : 0;
   if (a.ev_start) {
     hipExtLaunchKernelGGL((k_mavp_dense<DT, OP, RW, U, WLDS, NT>), dim3(blocks), dim3(waves * kWave), (uint32_t)lds, s,
                           a.ev_start, a.ev_stop, 0u, A, ldb, (int)a.n_rows, (int)a.n_cols, a.row_scale, w, y, part,

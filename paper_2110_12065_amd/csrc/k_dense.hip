@@ -113,7 +113,7 @@ DenseTuning dense_default_tuning(const DenseArgs& a, int cu_count, int max_lds_b
   // them per size bucket): the matrix is streamed once per product, so
   // non-temporal loads and 8 waves per block keep the most bytes in flight.
   DenseTuning t;
-  const bool lds_fits = a.n_cols * 4 + 1024 <= (int64_t)max_lds_bytes;
+  const bool lds_fits = (int64_t)dense_lds_bytes(a.dtype, a.n_cols) + 1024 <= (int64_t)max_lds_bytes;
   t.blocks = 0;
   t.waves = 8;
   t.nontemporal = 1;
