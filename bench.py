@@ -224,14 +224,18 @@ def bench_batched(mp, ctx, torch, k=128, seed=5):
         return k / (time.perf_counter() - t0), res
 
     for dt, meth in (("bf16", "mapi"), ("f32", "mapi"), ("f32", "rpi")):
+        log(f"batched {dt} {meth}: {k} instances")
         sps, infos, probs = batched(dt, meth)
+        log(f"batched {dt} {meth}: {sps:.1f} solves/s, mean iters {np.mean([i['iters'] for i in infos]):.1f}")
         out[f"batched_{dt}_{meth}_solves_s"] = sps
         out[f"batched_{dt}_{meth}_mean_iters"] = float(np.mean([i["iters"] for i in infos]))
         out[f"batched_{dt}_{meth}_converged"] = int(sum(i["converged"] for i in infos))
         if (dt, meth) == ("bf16", "mapi"):
             bf16_probs = probs
     for meth in ("mapi", "rpi"):
+        log(f"one-at-a-time f32 {meth}")
         sps, res = plain(meth)
+        log(f"one-at-a-time f32 {meth}: {sps:.1f} solves/s")
         out[f"plain_f32_{meth}_solves_s"] = sps
         out[f"plain_f32_{meth}_mean_iters"] = float(np.mean([r[1]["iters"] for r in res]))
         if meth == "mapi":
@@ -261,6 +265,7 @@ def bench_pca(mp, ctx, torch, D=4096, N=65536, k=8, seed=77):
         del A
     cn = torch.linalg.norm(clean)
     for meth in ("mapi", "rpi"):
+        log(f"PCA top-{k} {meth}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         P, infos = mp.mapi_pca_topk(X, k, W0, method=meth, max_iters=1000, tol=1e-6, check_every=8, ctx=ctx)
@@ -283,6 +288,7 @@ def bench_pagerank(mp, ctx, torch, n=1 << 22, seed=2022):
     bytes_iter = 8.0 * nnz + 4.0 * (n + 1) + 8.0 * n        # links, row pointers, w once, y once
     out = {"n": n, "nnz": nnz}
     for meth in ("mapi", "rpi"):
+        log(f"PageRank {meth}")
         mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=2, ctx=ctx)
         ctx.timing(True)
         ctx.timing_reset()
@@ -349,6 +355,8 @@ def bench_serving(mp, torch, n_req=20000, rate=2000.0, seed=11, budget=64 << 30,
         if wait > 0:
             time.sleep(wait)
         tickets.append(srv.submit(make(r), np.empty(r[1], np.float32)))
+        if i % 2000 == 0:
+            log(f"serving: submitted {i}")
     res = [srv.wait(t, timeout_us=120_000_000) for t in tickets]
     st = srv.stats()
     srv.close()
@@ -376,6 +384,8 @@ def bench_serving(mp, torch, n_req=20000, rate=2000.0, seed=11, budget=64 << 30,
             w, _ = mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=1000, tol=1e-6, check_every=4, ctx=ctx)
         w.cpu()
         service.append(time.perf_counter() - t0)
+        if len(service) % 100 == 0:
+            log(f"serving: one-at-a-time {len(service)} done")
     ctx.close()
     service = np.array(service)
     # FIFO single server fed by the same arrival process, service times drawn from the sample

@@ -19,7 +19,7 @@ struct BatchState {
 };
 
 int batch_default_rows(int kind, int dtype, int64_t n) {
-  if (kind == BK_CSR) return 4096;
+  if (kind == BK_CSR) return (int)std::max<int64_t>(4096, (n + kMaxTiles - 1) / kMaxTiles);
   const int64_t es = elem_size(dtype);
   int64_t r = (256 * 1024) / std::max<int64_t>(1, n * es);      // about 256 KiB of matrix per tile
   r = std::max<int64_t>(2, std::min<int64_t>(r, 256));
@@ -104,6 +104,8 @@ mapi_status describe(mapi_ctx* c, const mapi_problem& p, BInst* I, int64_t* matr
   I->ntiles = (int)((n + I->rows_per_tile - 1) / I->rows_per_tile);
   I->vtiles = (int)((n + kVecTile - 1) / kVecTile);
   I->gtiles = I->kind == BK_GEN ? (int)((n + kGenRows - 1) / kGenRows) : 0;
+  if ((uint32_t)std::max(std::max(I->ntiles, I->vtiles), I->gtiles) > kMaxTiles)
+    return fail(MAPI_ERR_UNSUPPORTED, "problem needs more than %u tiles per phase", kMaxTiles);
   I->solo = n <= kSoloMaxN ? 1 : 0;
   SolveState& st = I->st;
   st = SolveState{};
@@ -210,7 +212,7 @@ mapi_status mapi_generate_dense(mapi_ctx* c, int64_t n, uint64_t seed, float* A,
 mapi_status mapi_solve_batched(mapi_ctx* c, int32_t count, const mapi_problem* probs, mapi_info* infos) {
   if (!c || count < 0 || (count > 0 && !probs)) return fail(MAPI_ERR_ARG, "bad arguments");
   if (count == 0) return MAPI_OK;
-  if (count > (1 << 24)) return fail(MAPI_ERR_ARG, "too many instances");
+  if ((uint32_t)count > kMaxInstances) return fail(MAPI_ERR_ARG, "too many instances");
   HIP_TRY(hipSetDevice(c->device));
   mapi_status s;
   std::vector<BInst> H(count);
@@ -231,7 +233,6 @@ mapi_status mapi_solve_batched(mapi_ctx* c, int32_t count, const mapi_problem* p
   const size_t o_q = L.take(sizeof(BQueue));
   const size_t o_ctl = L.take(sizeof(BCtl));
   const size_t o_item = L.take(sizeof(unsigned long long) * cap);
-  const size_t o_seq = L.take(sizeof(unsigned long long) * cap);
   const size_t o_err = L.take(sizeof(int32_t) * count);
   const size_t o_bufs = L.take(inst_total);
   if (!c->batch) c->batch = new BatchState();
@@ -241,7 +242,6 @@ mapi_status mapi_solve_batched(mapi_ctx* c, int32_t count, const mapi_problem* p
   BQueue* d_q = reinterpret_cast<BQueue*>(base + o_q);
   BCtl* d_ctl = reinterpret_cast<BCtl*>(base + o_ctl);
   unsigned long long* d_item = reinterpret_cast<unsigned long long*>(base + o_item);
-  unsigned long long* d_seq = reinterpret_cast<unsigned long long*>(base + o_seq);
   int32_t* d_err = reinterpret_cast<int32_t*>(base + o_err);
   char* buf = base + o_bufs;
   for (int i = 0; i < count; ++i) buf = place(&H[i], buf, mbytes[i]);
@@ -265,21 +265,17 @@ mapi_status mapi_solve_batched(mapi_ctx* c, int32_t count, const mapi_problem* p
   HIP_TRY(hipMemcpyAsync(errs.data(), d_err, sizeof(int32_t) * count, hipMemcpyDeviceToHost, ss));
 
   // queue: the first phase of every instance, in instance order
-  std::vector<unsigned long long> h_item(cap, 0ull), h_seq(cap, 0ull);
+  std::vector<unsigned long long> h_item(cap, 0ull);
   unsigned long long pos = 0;
   for (int i = 0; i < count; ++i) {
     int ph;
     const uint32_t t = first_phase_tiles(H[i], &ph);
-    for (uint32_t k = 0; k < t; ++k, ++pos) {
-      h_item[pos] = bitem((uint32_t)i, ph, k);
-      h_seq[pos] = pos + 1;
-    }
+    for (uint32_t k = 0; k < t; ++k, ++pos) h_item[pos] = bslot(pos, bitem((uint32_t)i, ph, k));
   }
   BQueue hq{};
   hq.head = 0;
   hq.tail = pos;
   hq.item = d_item;
-  hq.seq = d_seq;
   hq.mask = cap - 1;
   hq.live = (uint32_t)count;
   BCtl hc{};
@@ -288,7 +284,6 @@ mapi_status mapi_solve_batched(mapi_ctx* c, int32_t count, const mapi_problem* p
   hc.idle_limit = realtime_hz() / 200;   // 5 ms without work
   HIP_TRY(hipMemcpyAsync(d_inst, H.data(), sizeof(BInst) * count, hipMemcpyHostToDevice, ss));
   HIP_TRY(hipMemcpyAsync(d_item, h_item.data(), sizeof(unsigned long long) * cap, hipMemcpyHostToDevice, ss));
-  HIP_TRY(hipMemcpyAsync(d_seq, h_seq.data(), sizeof(unsigned long long) * cap, hipMemcpyHostToDevice, ss));
   HIP_TRY(hipMemcpyAsync(d_q, &hq, sizeof(BQueue), hipMemcpyHostToDevice, ss));
   HIP_TRY(hipMemcpyAsync(d_ctl, &hc, sizeof(BCtl), hipMemcpyHostToDevice, ss));
   HIP_TRY(hipStreamSynchronize(ss));

@@ -62,9 +62,8 @@ struct BInst {
 struct BQueue {
   unsigned long long head;   // next position to consume
   unsigned long long tail;   // next position to reserve for producing
-  unsigned long long* item;  // cap entries
-  unsigned long long* seq;   // seq[p & mask] == p + 1 once the item at p is ready
-  uint32_t mask;             // cap - 1, cap a power of two
+  unsigned long long* item;  // cap slots (item | position tag)
+  uint32_t mask;             // cap - 1, cap a power of two, at most 2^24
   uint32_t live;             // instances admitted and not finished
   uint32_t error;            // bit 0: blocks stopped at the run limit with work left
   uint32_t pad;
@@ -98,9 +97,22 @@ struct BCtl {
   uint32_t pad3;
 };
 
+// Work item: instance (20 bits), phase (3 bits), tile (16 bits).  A ring slot holds
+// the item and, in its top 25 bits, the low bits of (position + 1), so a consumer
+// recognises the item of the position it claims from one 64-bit load.
+constexpr int kTagShift = 39;
+constexpr unsigned long long kItemMask = (1ull << kTagShift) - 1;
+constexpr uint32_t kMaxInstances = 1u << 20;
+constexpr uint32_t kMaxTiles = 65535;
 __host__ __device__ inline unsigned long long bitem(uint32_t inst, int phase, uint32_t tile) {
-  return (unsigned long long)inst | ((unsigned long long)phase << 24) | ((unsigned long long)tile << 28);
+  return (unsigned long long)inst | ((unsigned long long)phase << 20) | ((unsigned long long)tile << 23);
 }
+__host__ __device__ inline unsigned long long bslot(unsigned long long pos, unsigned long long item) {
+  return item | (((pos + 1) & 0x1FFFFFFull) << kTagShift);
+}
+__host__ __device__ inline uint32_t item_inst(unsigned long long v) { return (uint32_t)(v & 0xFFFFFull); }
+__host__ __device__ inline int item_phase(unsigned long long v) { return (int)((v >> 20) & 0x7ull); }
+__host__ __device__ inline uint32_t item_tile(unsigned long long v) { return (uint32_t)((v >> 23) & 0xFFFFull); }
 
 // SplitMix64 output function (Steele, Lea and Flood, 2014), used as a
 // counter-based generator: value = splitmix64(splitmix64(seed) + counter).

@@ -22,20 +22,26 @@ constexpr int kBT = 256;   // threads per block
 __device__ __forceinline__ int64_t now_ticks() { return (int64_t)__builtin_amdgcn_s_memrealtime(); }
 
 // ---------------------------------------------------------------- queue
-__device__ __forceinline__ void q_store_item(BQueue* q, unsigned long long p, unsigned long long v) {
-  __hip_atomic_store(&q->item[p & q->mask], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&q->seq[p & q->mask], p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// Polling uses relaxed loads only: on gfx950 an agent-scope acquire invalidates
+// the XCD's L2, so idle blocks must not acquire while they spin.  A block that
+// claims an item acquires once (the CAS); a block that publishes results
+// releases once (one fence by one thread after the block barrier).
+
+__device__ __forceinline__ void q_store_slot(BQueue* q, unsigned long long p, unsigned long long item) {
+  __hip_atomic_store(&q->item[p & q->mask], bslot(p, item), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Push `count` tiles of one phase; called by every thread of the block after
 // the block's results are written.
 __device__ void q_push(BQueue* q, uint32_t inst, int phase, uint32_t count, unsigned long long* sh_base) {
-  __threadfence();
   __syncthreads();
-  if (threadIdx.x == 0) *sh_base = atomicAdd(&q->tail, (unsigned long long)count);
+  if (threadIdx.x == 0) {
+    __threadfence();   // release this block's results
+    *sh_base = atomicAdd(&q->tail, (unsigned long long)count);
+  }
   __syncthreads();
   const unsigned long long base = *sh_base;
-  for (uint32_t t = threadIdx.x; t < count; t += blockDim.x) q_store_item(q, base + t, bitem(inst, phase, t));
+  for (uint32_t t = threadIdx.x; t < count; t += blockDim.x) q_store_slot(q, base + t, bitem(inst, phase, t));
   __syncthreads();
 }
 
@@ -47,11 +53,11 @@ __device__ void drain_inbox(BQueue* q, const BInst* insts, BCtl* ctl) {
   __threadfence_system();
   for (; h < tail; ++h) {
     const unsigned long long v = ctl->inbox[h & ctl->inbox_mask];
-    const int ph = (int)((v >> 24) & 0xFull);
-    if ((v >> 28) == 0 && (ph == PH_GEN || (ph == PH_INIT && insts[v & 0xFFFFFFull].kind != BK_GEN)))
+    const int ph = item_phase(v);
+    if (item_tile(v) == 0 && (ph == PH_GEN || (ph == PH_INIT && insts[item_inst(v)].kind != BK_GEN)))
       atomicAdd(&q->live, 1u);   // first item of a newly admitted instance
     const unsigned long long p = atomicAdd(&q->tail, 1ull);
-    q_store_item(q, p, v);
+    q_store_slot(q, p, v);
   }
   ctl->inbox_head = h;
   *ctl->inbox_head_host = h;
@@ -61,15 +67,15 @@ __device__ void drain_inbox(BQueue* q, const BInst* insts, BCtl* ctl) {
 // Pop one item (thread 0).  Returns false when the block should exit.
 __device__ bool q_pop(BQueue* q, const BInst* insts, BCtl* ctl, int64_t deadline, unsigned long long* out) {
   const int64_t t0 = now_ticks();
-  for (;;) {
+  for (int polls = 0;; ++polls) {
     if (ctl->mode == 1 && blockIdx.x == 0) drain_inbox(q, insts, ctl);
     const unsigned long long h = __hip_atomic_load(&q->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long sq = __hip_atomic_load(&q->seq[h & q->mask], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    if (sq == h + 1) {
+    const unsigned long long v = __hip_atomic_load(&q->item[h & q->mask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((v >> kTagShift) == ((h + 1) & 0x1FFFFFFull)) {
       unsigned long long expected = h;
       if (__hip_atomic_compare_exchange_strong(&q->head, &expected, h + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT)) {
-        *out = __hip_atomic_load(&q->item[h & q->mask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *out = v & kItemMask;
         return true;
       }
       continue;
@@ -86,25 +92,27 @@ __device__ bool q_pop(BQueue* q, const BInst* insts, BCtl* ctl, int64_t deadline
     if (ctl->mode == 1 && *ctl->quit && live == 0) return false;
     // block 0 drains the serving inbox: it stays while admitted work is live
     if (now - t0 > ctl->idle_limit && !(ctl->mode == 1 && blockIdx.x == 0 && live)) return false;
-    __builtin_amdgcn_s_sleep(8);
+    if (polls < 16) __builtin_amdgcn_s_sleep(2);
+    else __builtin_amdgcn_s_sleep(32);
   }
 }
 
 // Count a finished tile of the current phase; true in every thread of the block
-// that finished the last one.  That block sees every other tile's results.
+// that finished the last one.  That block then sees every other tile's results.
 __device__ bool tile_arrive(BInst* I, uint32_t tiles, int* sh_flag) {
-  __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
+    __threadfence();   // release this tile's results
     const uint32_t prev = atomicAdd(&I->arrive, 1u);
     const bool last = prev == tiles - 1;
-    if (last) __hip_atomic_store(&I->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (last) {
+      __hip_atomic_store(&I->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();   // acquire the other tiles' results
+    }
     *sh_flag = last ? 1 : 0;
   }
   __syncthreads();
-  const bool last = *sh_flag != 0;
-  if (last) __threadfence();
-  return last;
+  return *sh_flag != 0;
 }
 
 // ---------------------------------------------------------------- row products
@@ -342,9 +350,9 @@ __global__ void __launch_bounds__(kBT) k_persistent(BQueue* q, BInst* insts, BCt
     __syncthreads();
     if (!sh_ok) return;
     const unsigned long long item = sh_item;
-    const uint32_t ii = (uint32_t)(item & 0xFFFFFFull);
-    const int ph = (int)((item >> 24) & 0xFull);
-    const uint32_t tile = (uint32_t)(item >> 28);
+    const uint32_t ii = item_inst(item);
+    const int ph = item_phase(item);
+    const uint32_t tile = item_tile(item);
     BInst* I = insts + ii;
     const int n = I->n;
 

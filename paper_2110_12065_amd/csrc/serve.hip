@@ -103,7 +103,6 @@ struct mapi_server {
   BQueue* d_q = nullptr;
   BCtl* d_ctl = nullptr;
   unsigned long long* d_item = nullptr;
-  unsigned long long* d_seq = nullptr;
   int32_t* d_err = nullptr;
   // host-visible (pinned, coherent)
   unsigned long long* inbox = nullptr;
@@ -364,7 +363,7 @@ mapi_status mapi_serve_create(int device, size_t hbm_budget, const mapi_serve_cf
   const int bpc = (cfg && cfg->blocks_per_cu > 0) ? cfg->blocks_per_cu : 2;
   s->blocks = s->ctx->cu_count * bpc;
   s->idle_ms = (cfg && cfg->idle_exit_ms > 0) ? cfg->idle_exit_ms : 20.0;
-  if (s->max_slots > (1 << 20)) s->max_slots = 1 << 20;
+  if (s->max_slots > (int)kMaxInstances) s->max_slots = (int)kMaxInstances;
   s->done_cap = 1024;
   while (s->done_cap < (uint32_t)(2 * s->max_slots)) s->done_cap <<= 1;
   auto bail = [&](mapi_status code, const char* what) {
@@ -380,7 +379,6 @@ mapi_status mapi_serve_create(int device, size_t hbm_budget, const mapi_serve_cf
   const size_t o_q = L.take(sizeof(BQueue));
   const size_t o_ctl = L.take(sizeof(BCtl));
   const size_t o_item = L.take(sizeof(unsigned long long) * kQueueCap);
-  const size_t o_seq = L.take(sizeof(unsigned long long) * kQueueCap);
   const size_t o_err = L.take(sizeof(int32_t));
   char* dev = nullptr;
   if (hipMalloc(reinterpret_cast<void**>(&dev), L.off) != hipSuccess) return bail(MAPI_ERR_ALLOC, "device control");
@@ -388,7 +386,6 @@ mapi_status mapi_serve_create(int device, size_t hbm_budget, const mapi_serve_cf
   s->d_q = reinterpret_cast<BQueue*>(dev + o_q);
   s->d_ctl = reinterpret_cast<BCtl*>(dev + o_ctl);
   s->d_item = reinterpret_cast<unsigned long long*>(dev + o_item);
-  s->d_seq = reinterpret_cast<unsigned long long*>(dev + o_seq);
   s->d_err = reinterpret_cast<int32_t*>(dev + o_err);
   // host-visible control: inbox ring, its two positions, quit flag, completion ring
   s->inbox = static_cast<unsigned long long*>(host_mapped(sizeof(unsigned long long) * (kInboxCap + 32)));
@@ -403,7 +400,6 @@ mapi_status mapi_serve_create(int device, size_t hbm_budget, const mapi_serve_cf
     return bail(MAPI_ERR_HIP, "stream creation");
   BQueue hq{};
   hq.item = s->d_item;
-  hq.seq = s->d_seq;
   hq.mask = kQueueCap - 1;
   BCtl hc{};
   hc.mode = 1;
@@ -419,7 +415,7 @@ mapi_status mapi_serve_create(int device, size_t hbm_budget, const mapi_serve_cf
   if (hipHostGetDevicePointer(&dp, s->done, 0) != hipSuccess) return bail(MAPI_ERR_HIP, "completion mapping");
   hc.done = static_cast<BDone*>(dp);
   hc.done_mask = s->done_cap - 1;
-  if (hipMemsetAsync(s->d_seq, 0, sizeof(unsigned long long) * kQueueCap, s->copy) != hipSuccess ||
+  if (hipMemsetAsync(s->d_item, 0, sizeof(unsigned long long) * kQueueCap, s->copy) != hipSuccess ||
       hipMemcpyAsync(s->d_q, &hq, sizeof(hq), hipMemcpyHostToDevice, s->copy) != hipSuccess ||
       hipMemcpyAsync(s->d_ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s->copy) != hipSuccess ||
       hipStreamSynchronize(s->copy) != hipSuccess)
