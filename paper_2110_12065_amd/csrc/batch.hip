@@ -106,7 +106,7 @@ mapi_status describe(mapi_ctx* c, const mapi_problem& p, BInst* I, int64_t* matr
   I->gtiles = I->kind == BK_GEN ? (int)((n + kGenRows - 1) / kGenRows) : 0;
   if ((uint32_t)std::max(std::max(I->ntiles, I->vtiles), I->gtiles) > kMaxTiles)
     return fail(MAPI_ERR_UNSUPPORTED, "problem needs more than %u tiles per phase", kMaxTiles);
-  I->solo = n <= kSoloMaxN ? 1 : 0;
+  I->solo = I->ntiles == 1 ? 1 : 0;
   SolveState& st = I->st;
   st = SolveState{};
   st.best_r = INFINITY;

@@ -2,11 +2,13 @@
 // the control block shared by the persistent kernel and the host runtime.
 //
 // Work is a stream of items (instance, phase, tile).  Blocks of the persistent
-// kernel pop items from a multi-producer multi-consumer ring in device memory,
-// run them, and the block that finishes the last tile of a phase pushes the
-// next phase's tiles.  No block ever waits on another block's progress: a block
-// only holds an item while it is working on it, so the grid drains whatever the
-// number of resident blocks.  Every wait has a wall-clock limit.
+// kernel take tickets (positions) of a multi-producer multi-consumer ring in
+// device memory with one fetch-add each, wait for the item of their position,
+// run it, and the block that finishes the last tile of a phase pushes the next
+// phase's tiles.  A block that leaves while its position is still empty marks
+// the position skipped, and a producer that finds its position skipped takes a
+// new one, so no item is stranded whatever the number of resident blocks.
+// Items never wait on other items.  Every wait has a wall-clock limit.
 #pragma once
 
 #include "common.h"
@@ -14,11 +16,10 @@
 namespace mapi {
 
 enum BKind { BK_DENSE = 0, BK_CSR = 1, BK_GEN = 2 };
-enum BPhase { PH_GEN = 0, PH_INIT = 1, PH_PROD = 2, PH_FIN = 3, PH_OUT = 4 };
+enum BPhase { PH_GEN = 0, PH_INIT = 1, PH_PROD = 2, PH_FIN = 3, PH_OUT = 4, PH_SKIP = 7 };
 
 constexpr int kVecTile = 8192;      // elements per INIT / FIN / OUT tile
 constexpr int kGenRows = 32;        // rows per generation tile
-constexpr int kSoloMaxN = 1024;     // instances up to this size iterate inside one block
 constexpr int kSoloBurst = 16;      // iterations a solo block runs before yielding
 constexpr int kBatchLdsFloats = 8192;   // w staged in LDS up to this many columns
 
@@ -30,7 +31,7 @@ struct BInst {
   int32_t ntiles;            // product tiles per iteration
   int32_t vtiles;            // INIT / FIN / OUT tiles
   int32_t gtiles;            // generation tiles (BK_GEN)
-  int32_t solo;              // whole iterations inside one block
+  int32_t solo;              // one product tile: whole iterations inside one block
   int32_t max_iters, stall_iters;
   double tol;
   int64_t ld;                // elements

@@ -9,7 +9,9 @@
 // The block that completes the last tile of a phase reduces the partials in
 // tile order and pushes the next phase, so an instance's arithmetic does not
 // depend on which block ran which tile or on what else is in the batch.
-// Instances of at most kSoloMaxN rows run whole iterations inside one block.
+// Instances whose product is one tile run whole iterations inside one block,
+// and the block that completes a phase of a one-tile vector runs the next step
+// itself instead of queueing it.
 #include <hip/hip_runtime.h>
 
 #include "batched.h"
@@ -22,13 +24,35 @@ constexpr int kBT = 256;   // threads per block
 __device__ __forceinline__ int64_t now_ticks() { return (int64_t)__builtin_amdgcn_s_memrealtime(); }
 
 // ---------------------------------------------------------------- queue
-// Polling uses relaxed loads only: on gfx950 an agent-scope acquire invalidates
-// the XCD's L2, so idle blocks must not acquire while they spin.  A block that
-// claims an item acquires once (the CAS); a block that publishes results
-// releases once (one fence by one thread after the block barrier).
+// A consumer claims a position with one fetch-add of `head` (no retry loop, so
+// claims do not serialise under contention) and polls that position's slot with
+// relaxed loads: on gfx950 an agent-scope acquire invalidates the XCD's L2, so
+// only a block that has its item acquires, once.  A block that publishes
+// results releases once (one fence by one thread after the block barrier).
 
-__device__ __forceinline__ void q_store_slot(BQueue* q, unsigned long long p, unsigned long long item) {
-  __hip_atomic_store(&q->item[p & q->mask], bslot(p, item), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ unsigned long long* q_slot(BQueue* q, unsigned long long p) {
+  return &q->item[p & q->mask];
+}
+__device__ __forceinline__ bool slot_is(unsigned long long v, unsigned long long p) {
+  return (v >> kTagShift) == ((p + 1) & 0x1FFFFFFull);
+}
+__device__ __forceinline__ unsigned long long slot_load(const unsigned long long* s) {
+  return __hip_atomic_load(const_cast<unsigned long long*>(s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Write `item` at position p; if p's consumer has already given p up, write it at
+// a newly reserved position instead.  Terminates: each skipped position belongs
+// to a block that has left.
+__device__ void q_put(BQueue* q, unsigned long long p, unsigned long long item) {
+  for (;;) {
+    unsigned long long* s = q_slot(q, p);
+    unsigned long long old = slot_load(s);
+    while (!slot_is(old, p))
+      if (__hip_atomic_compare_exchange_strong(s, &old, bslot(p, item), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT))
+        return;
+    p = atomicAdd(&q->tail, 1ull);
+  }
 }
 
 // Push `count` tiles of one phase; called by every thread of the block after
@@ -41,7 +65,7 @@ __device__ void q_push(BQueue* q, uint32_t inst, int phase, uint32_t count, unsi
   }
   __syncthreads();
   const unsigned long long base = *sh_base;
-  for (uint32_t t = threadIdx.x; t < count; t += blockDim.x) q_store_slot(q, base + t, bitem(inst, phase, t));
+  for (uint32_t t = threadIdx.x; t < count; t += blockDim.x) q_put(q, base + t, bitem(inst, phase, t));
   __syncthreads();
 }
 
@@ -51,55 +75,65 @@ __device__ void drain_inbox(BQueue* q, const BInst* insts, BCtl* ctl) {
   unsigned long long h = ctl->inbox_head;
   if (h == tail) return;
   __threadfence_system();
-  for (; h < tail; ++h) {
+  const unsigned long long base = atomicAdd(&q->tail, tail - h);
+  for (unsigned long long k = 0; h < tail; ++h, ++k) {
     const unsigned long long v = ctl->inbox[h & ctl->inbox_mask];
     const int ph = item_phase(v);
-    if (item_tile(v) == 0 && (ph == PH_GEN || (ph == PH_INIT && insts[item_inst(v)].kind != BK_GEN)))
-      atomicAdd(&q->live, 1u);   // first item of a newly admitted instance
-    const unsigned long long p = atomicAdd(&q->tail, 1ull);
-    q_store_slot(q, p, v);
+    if (item_tile(v) == 0 && (ph == PH_GEN || (ph == PH_INIT && insts[item_inst(v)].kind != BK_GEN))) {
+      atomicAdd(&q->live, 1u);   // first item of a newly admitted instance: counted before it is visible
+      __threadfence();
+    }
+    q_put(q, base + k, v);
   }
   ctl->inbox_head = h;
   *ctl->inbox_head_host = h;
   __threadfence_system();
 }
 
-// Pop one item (thread 0).  Returns false when the block should exit.
-__device__ bool q_pop(BQueue* q, const BInst* insts, BCtl* ctl, int64_t deadline, unsigned long long* out) {
+// Wait for the item of position p (thread 0).  Returns false when the block
+// should leave; p is then marked skipped, unless its item arrived first.
+__device__ bool q_take(BQueue* q, const BInst* insts, BCtl* ctl, unsigned long long p, int64_t deadline,
+                       unsigned long long* out) {
+  unsigned long long* s = q_slot(q, p);
   const int64_t t0 = now_ticks();
   for (int polls = 0;; ++polls) {
     if (ctl->mode == 1 && blockIdx.x == 0) drain_inbox(q, insts, ctl);
-    const unsigned long long h = __hip_atomic_load(&q->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long v = __hip_atomic_load(&q->item[h & q->mask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((v >> kTagShift) == ((h + 1) & 0x1FFFFFFull)) {
-      unsigned long long expected = h;
-      if (__hip_atomic_compare_exchange_strong(&q->head, &expected, h + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT)) {
-        *out = v & kItemMask;
-        return true;
+    unsigned long long v = slot_load(s);
+    if (!slot_is(v, p)) {
+      const int64_t now = now_ticks();
+      const uint32_t live = __hip_atomic_load(&q->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      bool leave = false;
+      if (now > deadline) {
+        if (live) atomicOr(&q->error, 1u);
+        leave = true;
+      } else if (live == 0 && (ctl->mode == 0 || *ctl->quit)) {
+        leave = true;
+      } else if (now - t0 > ctl->idle_limit && !(ctl->mode == 1 && blockIdx.x == 0 && live)) {
+        leave = true;   // block 0 drains the serving inbox: it stays while admitted work is live
       }
-      continue;
+      if (!leave) {
+        if (polls < 16) __builtin_amdgcn_s_sleep(2);
+        else __builtin_amdgcn_s_sleep(32);
+        continue;
+      }
+      if (__hip_atomic_compare_exchange_strong(s, &v, bslot(p, bitem(0, PH_SKIP, 0)), __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        return false;
+      // the item arrived meanwhile: v holds it
     }
-    // Nothing ready.  A block that holds no item may leave: whoever pushes the next
-    // item is running and pops it itself, so work is never stranded.
-    const int64_t now = now_ticks();
-    const uint32_t live = __hip_atomic_load(&q->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (now > deadline) {
-      if (live) atomicOr(&q->error, 1u);
-      return false;
-    }
-    if (ctl->mode == 0 && live == 0) return false;
-    if (ctl->mode == 1 && *ctl->quit && live == 0) return false;
-    // block 0 drains the serving inbox: it stays while admitted work is live
-    if (now - t0 > ctl->idle_limit && !(ctl->mode == 1 && blockIdx.x == 0 && live)) return false;
-    if (polls < 16) __builtin_amdgcn_s_sleep(2);
-    else __builtin_amdgcn_s_sleep(32);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // see the producer's results
+    *out = v & kItemMask;
+    return true;
   }
 }
 
 // Count a finished tile of the current phase; true in every thread of the block
 // that finished the last one.  That block then sees every other tile's results.
 __device__ bool tile_arrive(BInst* I, uint32_t tiles, int* sh_flag) {
+  if (tiles == 1) {
+    __syncthreads();
+    return true;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();   // release this tile's results
@@ -284,15 +318,41 @@ __device__ void phase_init(BInst* I, uint32_t tile, double* sh) {
   }
 }
 
-// One block iterates a small instance: product, normaliser, normalisation,
+// Normalise the whole iterate by nu, then residual and stop rule, by one block
+// (instances whose vectors are one tile).  Returns whether the solve is done.
+__device__ bool fin_whole(BInst* I, double nu, double* sh) {
+  const int it = I->st.iter;
+  const float* wc = (it & 1) ? I->wb1 : I->wb0;
+  float* wn = (it & 1) ? I->wb0 : I->wb1;
+  double r = 0.0, e0 = 0.0, e1 = 0.0;
+  const bool bad = bad_norm(nu);
+  if (!bad) fin_rows(I, I->y, wc, wn, 0, I->n, nu, &r, &e0, &e1);
+  r = block_sum_f64(r, sh);
+  e0 = block_sum_f64(e0, sh);
+  e1 = block_sum_f64(e1, sh);
+  if (threadIdx.x == 0) {
+    I->st.nu = nu;
+    if (bad) {
+      I->st.status = MAPI_ERR_DEGENERATE;
+      I->st.done = 1;
+    } else {
+      I->st.ex[0] = e0;
+      I->st.ex[1] = e1;
+      state_advance(&I->st, r);
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  return I->st.done != 0;
+}
+
+// One block iterates a one-tile instance: product, normaliser, normalisation,
 // residual, stop rule, up to kSoloBurst times.  Returns whether it is done.
 __device__ bool phase_solo(BInst* I, float* lds, double* sh) {
   const int n = I->n;
   const bool rpi = I->method == MAPI_METHOD_RPI;
   for (int k = 0; k < kSoloBurst; ++k) {
-    const int it = I->st.iter;
-    const float* wc = (it & 1) ? I->wb1 : I->wb0;
-    float* wn = (it & 1) ? I->wb0 : I->wb1;
+    const float* wc = (I->st.iter & 1) ? I->wb1 : I->wb0;
     double nrm;
     if (I->kind == BK_CSR) {
       nrm = csr_rows(I, wc, 0, n, I->y);
@@ -304,47 +364,104 @@ __device__ bool phase_solo(BInst* I, float* lds, double* sh) {
     if (rpi && I->kind != BK_CSR) nu = sqrt(nu);
     __threadfence_block();
     __syncthreads();
-    if (bad_norm(nu)) {
-      if (threadIdx.x == 0) {
-        I->st.status = MAPI_ERR_DEGENERATE;
-        I->st.done = 1;
-        I->st.nu = nu;
-      }
-      __syncthreads();
-      return true;
-    }
-    double r = 0.0, e0 = 0.0, e1 = 0.0;
-    fin_rows(I, I->y, wc, wn, 0, n, nu, &r, &e0, &e1);
-    r = block_sum_f64(r, sh);
-    e0 = block_sum_f64(e0, sh);
-    e1 = block_sum_f64(e1, sh);
-    if (threadIdx.x == 0) {
-      I->st.nu = nu;
-      I->st.ex[0] = e0;
-      I->st.ex[1] = e1;
-      state_advance(&I->st, r);
-    }
-    __threadfence_block();
-    __syncthreads();
-    if (I->st.done) return true;
+    if (fin_whole(I, nu, sh)) return true;
   }
   return false;
 }
 
+// Copy rows [r0, r1) of the final iterate to the caller's output.
+__device__ void out_rows(const BInst* I, int r0, int r1) {
+  const float* src = (I->st.iter & 1) ? I->wb1 : I->wb0;
+  for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) I->out[i] = src[i];
+  __threadfence_system();
+}
+
+// Retire a finished instance (after every output tile is written): completion
+// record for the server, then one instance fewer live.
+__device__ void retire(BInst* I, uint32_t ii, BQueue* q, BCtl* ctl) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    I->t_done = now_ticks();
+    if (ctl->mode == 1) {
+      const unsigned long long p = atomicAdd(&ctl->done_pos, 1ull);
+      BDone* d = ctl->done + (p & ctl->done_mask);
+      d->slot = (int32_t)ii;
+      d->slot_gen = I->slot_gen;
+      d->status = I->st.status;
+      d->iters = I->st.iter;
+      d->converged = I->st.converged;
+      d->residual = I->st.r;
+      d->norm = I->st.nu;
+      d->t_admit = I->t_admit;
+      d->t_start = I->t_start;
+      d->t_done = I->t_done;
+      __threadfence_system();
+      __hip_atomic_store(&d->seq, p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __threadfence();
+    atomicSub(&q->live, 1u);
+  }
+  __syncthreads();
+}
+
+struct Shared {
+  double sh[16];
+  unsigned long long base;
+  int flag;
+};
+
+// Continue an instance whose state this block has just brought up to date: a
+// one-tile instance runs its next burst here; a finished one writes its output
+// (here when it is one tile, else as queued tiles); otherwise its next product
+// phase is queued.
+__device__ void advance(BQueue* q, BInst* I, uint32_t ii, BCtl* ctl, float* lds, Shared* S) {
+  if (!I->st.done && I->solo && !phase_solo(I, lds, S->sh)) {
+    q_push(q, ii, PH_PROD, 1u, &S->base);
+    return;
+  }
+  if (I->st.done) {
+    if (I->vtiles == 1) {
+      out_rows(I, 0, I->n);
+      retire(I, ii, q, ctl);
+    } else {
+      q_push(q, ii, PH_OUT, I->vtiles, &S->base);
+    }
+    return;
+  }
+  q_push(q, ii, PH_PROD, (uint32_t)I->ntiles, &S->base);
+}
+
+// Start-vector tile; the block that completes the last one starts the iterations.
+__device__ void run_init(BQueue* q, BInst* I, uint32_t ii, uint32_t tile, BCtl* ctl, float* lds, Shared* S) {
+  phase_init(I, tile, S->sh);
+  if (!tile_arrive(I, I->vtiles, &S->flag)) return;
+  const double E0 = block_sum_parts(I->part + I->ntiles, I->vtiles, 3, 1, S->sh);
+  const double E1 = block_sum_parts(I->part + I->ntiles, I->vtiles, 3, 2, S->sh);
+  if (threadIdx.x == 0) {
+    I->st.ex[0] = E0;
+    I->st.ex[1] = E1;
+    if (I->max_iters <= 0) I->st.done = 1;
+  }
+  __threadfence_block();
+  __syncthreads();
+  advance(q, I, ii, ctl, lds, S);
+}
+
 __global__ void __launch_bounds__(kBT) k_persistent(BQueue* q, BInst* insts, BCtl* ctl) {
   __shared__ float4 lds4[kBatchLdsFloats / 4];
-  __shared__ double sh[16];
+  __shared__ Shared S;
   __shared__ unsigned long long sh_item;
-  __shared__ unsigned long long sh_base;
   __shared__ int sh_ok;
-  __shared__ int sh_flag;
   float* lds = reinterpret_cast<float*>(lds4);
+  double* sh = S.sh;
   const int64_t deadline = now_ticks() + ctl->run_limit;
 
   for (;;) {
     if (threadIdx.x == 0) {
       unsigned long long v = 0;
-      sh_ok = (now_ticks() <= deadline && q_pop(q, insts, ctl, deadline, &v)) ? 1 : 0;
+      bool ok = false;
+      if (now_ticks() <= deadline) ok = q_take(q, insts, ctl, atomicAdd(&q->head, 1ull), deadline, &v);
+      sh_ok = ok ? 1 : 0;
       sh_item = v;
     }
     __syncthreads();
@@ -359,29 +476,18 @@ __global__ void __launch_bounds__(kBT) k_persistent(BQueue* q, BInst* insts, BCt
     if (ph == PH_GEN) {
       if (threadIdx.x == 0 && tile == 0) I->t_start = now_ticks();
       phase_gen(I, tile);
-      if (tile_arrive(I, I->gtiles, &sh_flag)) q_push(q, ii, PH_INIT, I->vtiles, &sh_base);
+      if (tile_arrive(I, I->gtiles, &S.flag)) {
+        if (I->vtiles == 1) run_init(q, I, ii, 0, ctl, lds, &S);
+        else q_push(q, ii, PH_INIT, I->vtiles, &S.base);
+      }
     } else if (ph == PH_INIT) {
       if (threadIdx.x == 0 && tile == 0 && I->kind != BK_GEN) I->t_start = now_ticks();
-      phase_init(I, tile, sh);
-      if (tile_arrive(I, I->vtiles, &sh_flag)) {
-        const double E0 = block_sum_parts(I->part + I->ntiles, I->vtiles, 3, 1, sh);
-        const double E1 = block_sum_parts(I->part + I->ntiles, I->vtiles, 3, 2, sh);
-        if (threadIdx.x == 0) {
-          I->st.ex[0] = E0;
-          I->st.ex[1] = E1;
-          if (I->max_iters <= 0) I->st.done = 1;
-        }
-        __syncthreads();
-        if (I->st.done) q_push(q, ii, PH_OUT, I->vtiles, &sh_base);
-        else q_push(q, ii, PH_PROD, I->solo ? 1u : (uint32_t)I->ntiles, &sh_base);
-      }
+      run_init(q, I, ii, tile, ctl, lds, &S);
     } else if (ph == PH_PROD) {
       if (I->solo) {
-        const bool done = phase_solo(I, lds, sh);
-        q_push(q, ii, done ? PH_OUT : PH_PROD, done ? I->vtiles : 1u, &sh_base);
+        advance(q, I, ii, ctl, lds, &S);
       } else {
-        const int it = I->st.iter;
-        const float* wc = (it & 1) ? I->wb1 : I->wb0;
+        const float* wc = (I->st.iter & 1) ? I->wb1 : I->wb0;
         const int r0 = tile * I->rows_per_tile, r1 = min(n, r0 + I->rows_per_tile);
         double nrm;
         if (I->kind == BK_CSR) {
@@ -392,11 +498,16 @@ __global__ void __launch_bounds__(kBT) k_persistent(BQueue* q, BInst* insts, BCt
         }
         nrm = block_sum_f64(nrm, sh);
         if (threadIdx.x == 0) store_agent(&I->part[tile], nrm);
-        if (tile_arrive(I, I->ntiles, &sh_flag)) {
+        if (tile_arrive(I, I->ntiles, &S.flag)) {
           double nu = block_sum_parts(I->part, I->ntiles, 1, 0, sh);
           if (I->method == MAPI_METHOD_RPI && I->kind != BK_CSR) nu = sqrt(nu);
-          if (threadIdx.x == 0) I->st.nu = nu;
-          q_push(q, ii, PH_FIN, I->vtiles, &sh_base);
+          if (I->vtiles == 1) {
+            fin_whole(I, nu, sh);
+            advance(q, I, ii, ctl, lds, &S);
+          } else {
+            if (threadIdx.x == 0) I->st.nu = nu;
+            q_push(q, ii, PH_FIN, I->vtiles, &S.base);
+          }
         }
       }
     } else if (ph == PH_FIN) {
@@ -414,7 +525,7 @@ __global__ void __launch_bounds__(kBT) k_persistent(BQueue* q, BInst* insts, BCt
         store_agent(&I->part[I->ntiles + 3 * tile + 1], e0);
         store_agent(&I->part[I->ntiles + 3 * tile + 2], e1);
       }
-      if (tile_arrive(I, I->vtiles, &sh_flag)) {
+      if (tile_arrive(I, I->vtiles, &S.flag)) {
         const double R = block_sum_parts(I->part + I->ntiles, I->vtiles, 3, 0, sh);
         const double E0 = block_sum_parts(I->part + I->ntiles, I->vtiles, 3, 1, sh);
         const double E1 = block_sum_parts(I->part + I->ntiles, I->vtiles, 3, 2, sh);
@@ -428,38 +539,13 @@ __global__ void __launch_bounds__(kBT) k_persistent(BQueue* q, BInst* insts, BCt
             state_advance(&I->st, R);
           }
         }
+        __threadfence_block();
         __syncthreads();
-        if (I->st.done) q_push(q, ii, PH_OUT, I->vtiles, &sh_base);
-        else q_push(q, ii, PH_PROD, (uint32_t)I->ntiles, &sh_base);
+        advance(q, I, ii, ctl, lds, &S);
       }
-    } else {   // PH_OUT
-      const float* src = (I->st.iter & 1) ? I->wb1 : I->wb0;
-      const int r0 = tile * kVecTile, r1 = min(n, r0 + kVecTile);
-      for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) I->out[i] = src[i];
-      __threadfence_system();
-      if (tile_arrive(I, I->vtiles, &sh_flag)) {
-        if (threadIdx.x == 0) {
-          I->t_done = now_ticks();
-          if (ctl->mode == 1) {
-            const unsigned long long p = atomicAdd(&ctl->done_pos, 1ull);
-            BDone* d = ctl->done + (p & ctl->done_mask);
-            d->slot = (int32_t)ii;
-            d->slot_gen = I->slot_gen;
-            d->status = I->st.status;
-            d->iters = I->st.iter;
-            d->converged = I->st.converged;
-            d->residual = I->st.r;
-            d->norm = I->st.nu;
-            d->t_admit = I->t_admit;
-            d->t_start = I->t_start;
-            d->t_done = I->t_done;
-            __threadfence_system();
-            __hip_atomic_store(&d->seq, p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-          }
-          __threadfence();
-          atomicSub(&q->live, 1u);
-        }
-      }
+    } else if (ph == PH_OUT) {
+      out_rows(I, tile * kVecTile, min(n, (int)(tile + 1) * kVecTile));
+      if (tile_arrive(I, I->vtiles, &S.flag)) retire(I, ii, q, ctl);
     }
     __syncthreads();
   }
