@@ -145,7 +145,10 @@ typedef struct mapi_tuning {
   int32_t waves;             /* waves per block: 4 or 8                            */
   int32_t blocks_per_cu;     /* grid = compute units * blocks_per_cu (1..16)       */
   int32_t unroll;            /* 16-byte loads in flight per row and lane: 2 or 4   */
-  int32_t w_in_lds;          /* stage w in LDS (needs 4 * n_cols bytes per block)  */
+  int32_t w_in_lds;          /* 0: w read from global memory; 1: w staged in LDS
+                                (4 * n_cols bytes per block); 2, FP8 storage only:
+                                |w| and one sign word per 4 columns in LDS
+                                (5 * n_cols bytes), one xor flips 4 stored values */
   int32_t nontemporal;       /* non-temporal matrix loads                          */
 } mapi_tuning;
 

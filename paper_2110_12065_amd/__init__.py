@@ -572,7 +572,7 @@ _SIGS.update({
 })
 
 
-def request_generated(n, seed, dtype="f32", method="mapi", max_iters=1000, tol=1e-6, op="min1"):
+def request_generated(n, seed, dtype="f32", method="mapi", max_iters=1000, tol=1e-6, op="min1", stall_iters=0):
     """A device-generated dense request (matrix and start vector from the seed)."""
     p = Problem()
     p.kind = PROB_GENERATED
@@ -580,12 +580,12 @@ def request_generated(n, seed, dtype="f32", method="mapi", max_iters=1000, tol=1
     p.gen_n = int(n)
     p.gen_dtype = {"f32": MAPI_F32, "bf16": MAPI_BF16}[dtype]
     p.seed = int(seed)
-    p.opts = _opts(max_iters, tol, op, False, 0, 0)
+    p.opts = _opts(max_iters, tol, op, False, 0, stall_iters)
     p.n = int(n)
     return p
 
 
-def request_csr_host(row_ptr, col, val, alpha=0.85, method="mapi", max_iters=1000, tol=1e-6):
+def request_csr_host(row_ptr, col, val, alpha=0.85, method="mapi", max_iters=1000, tol=1e-6, stall_iters=0):
     """A PageRank request whose CSR arrays are host numpy arrays (copied by the server at admission)."""
     import numpy as np
     row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
@@ -598,7 +598,7 @@ def request_csr_host(row_ptr, col, val, alpha=0.85, method="mapi", max_iters=100
     p.H = Csr(n, col.size, row_ptr.ctypes.data, col.ctypes.data if col.size else None,
               val.ctypes.data if val.size else None)
     p.alpha = float(alpha)
-    p.opts = _opts(max_iters, tol, "min1", False, 0, 0)
+    p.opts = _opts(max_iters, tol, "min1", False, 0, stall_iters)
     p._keep = (row_ptr, col, val)
     p.n = n
     return p

@@ -75,7 +75,7 @@ DenseTuning tuning_for(mapi_ctx* c, const DenseArgs& a) {
   auto it = c->tuned.find(bucket(a.dtype, a.n_rows, a.n_cols));
   if (it != c->tuned.end()) {
     t = it->second;
-    if (t.w_in_lds && (int64_t)dense_lds_bytes(a.dtype, a.n_cols) + 1024 > c->max_lds) t.w_in_lds = 0;   // bucket spans sizes past the LDS
+    if ((int64_t)dense_lds_bytes(a.dtype, a.n_cols, t.w_in_lds) + 1024 > c->max_lds) t.w_in_lds = 0;   // bucket spans sizes past the LDS
   }
   return t;
 }
@@ -92,7 +92,8 @@ mapi_status to_dense_tuning(const mapi_tuning* u, DenseTuning* t) {
   t->blocks = 0;
   t->blocks_per_cu = u->blocks_per_cu;
   t->unroll = u->unroll;
-  t->w_in_lds = u->w_in_lds ? 1 : 0;
+  if (u->w_in_lds < 0 || u->w_in_lds > 2) return fail(MAPI_ERR_ARG, "w_in_lds must be 0, 1 or 2");
+  t->w_in_lds = u->w_in_lds;
   t->nontemporal = u->nontemporal ? 1 : 0;
   return MAPI_OK;
 }
@@ -115,7 +116,7 @@ void load_tune_cache(mapi_ctx* c) {
   while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d", &dt, &rb, &cb, &rw, &wv, &bpc, &un, &lds, &nt) == 9) {
     mapi_tuning u{rw, wv, bpc, un, lds, nt};
     DenseTuning t;
-    if (to_dense_tuning(&u, &t) == MAPI_OK) c->tuned[std::make_tuple(dt, rb, cb)] = t;
+    if (to_dense_tuning(&u, &t) == MAPI_OK && lds_mode_ok(dt, t.w_in_lds)) c->tuned[std::make_tuple(dt, rb, cb)] = t;
   }
   std::fclose(f);
   g_err.clear();
@@ -157,13 +158,15 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
   const int F = finalize_blocks(n);
   Layout L;
   const size_t o_st = L.take(sizeof(SolveState));
-  const size_t o_part = L.take(sizeof(double) * (size_t)std::max(P, 3 * F));
+  const size_t o_pp = L.take(sizeof(double) * (size_t)P);
+  const size_t o_part = L.take(sizeof(double) * 3 * (size_t)F);
   const size_t o_w0 = L.take(sizeof(float) * n);
   const size_t o_w1 = L.take(sizeof(float) * n);
   const size_t o_y = L.take(sizeof(float) * n);
   if ((s = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return s;
   char* base = static_cast<char*>(c->ws);
   SolveState* st = reinterpret_cast<SolveState*>(base + o_st);
+  double* pprod = reinterpret_cast<double*>(base + o_pp);
   double* part = reinterpret_cast<double*>(base + o_part);
   float* wb[2] = {reinterpret_cast<float*>(base + o_w0), reinterpret_cast<float*>(base + o_w1)};
   float* y = reinterpret_cast<float*>(base + o_y);
@@ -178,11 +181,11 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
     {
       DenseArgs dl = da;
       TimedLaunch tm(c, MAPI_K_MAVP, &dl);
-      HIP_TRY(launch_mavp_dense(dl, op, wc, y, part, st, norm, t, c->cu_count, c->stream));
+      HIP_TRY(launch_mavp_dense(dl, op, wc, y, pprod, st, norm, t, c->cu_count, c->stream));
     }
     {
       Timed tm(c, MAPI_K_FINALIZE);
-      HIP_TRY(launch_finalize(0, y, wc, wn, n, st, part, nullptr, 0.0, 0.0, c->stream));
+      HIP_TRY(launch_finalize(0, y, wc, wn, n, st, pprod, P, norm, part, nullptr, 0.0, 0.0, c->stream));
     }
     if ((it + 1) % check == 0 && it + 1 < o->max_iters) {
       if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
@@ -333,7 +336,8 @@ mapi_status mapi_mavp_timed(mapi_ctx* c, const mapi_dense* A, const float* w, fl
   DenseTuning t;
   if ((s = to_dense_tuning(tu, &t)) != MAPI_OK) return s;
   const DenseArgs da = dense_args(A);
-  if (t.w_in_lds && (int64_t)dense_lds_bytes(da.dtype, da.n_cols) + 1024 > c->max_lds) return fail(MAPI_ERR_ARG, "w does not fit in LDS");
+  if (!lds_mode_ok(da.dtype, t.w_in_lds)) return fail(MAPI_ERR_ARG, "w_in_lds 2 needs FP8 storage");
+  if ((int64_t)dense_lds_bytes(da.dtype, da.n_cols, t.w_in_lds) + 1024 > c->max_lds) return fail(MAPI_ERR_ARG, "w does not fit in LDS");
   HIP_TRY(hipSetDevice(c->device));
   return time_product(c, da, op, w, y, t, reps, avg_ms);
 }
@@ -354,7 +358,6 @@ mapi_status mapi_autotune_dense(mapi_ctx* c, const mapi_dense* A, int32_t op, in
   float* w = reinterpret_cast<float*>(static_cast<char*>(c->ws) + o_w);
   float* y = reinterpret_cast<float*>(static_cast<char*>(c->ws) + o_y);
   HIP_TRY(launch_fill_f32(w, da.n_cols, 1.0f / (float)da.n_cols, c->stream));
-  const bool lds_ok = (int64_t)dense_lds_bytes(da.dtype, da.n_cols) + 1024 <= c->max_lds;
   DenseTuning bt = dense_default_tuning(da, c->cu_count, c->max_lds);
   double bms = 1e30;
   for (int rw : {1, 2, 4, 8}) {
@@ -362,8 +365,11 @@ mapi_status mapi_autotune_dense(mapi_ctx* c, const mapi_dense* A, int32_t op, in
     for (int waves : {4, 8})
       for (int bpc : {1, 2, 4, 8})
         for (int un : {2, 4})
-          for (int lds = 0; lds <= (lds_ok ? 1 : 0); ++lds)
+          for (int lds = 0; lds <= 2; ++lds)
             for (int nt = 0; nt <= 1; ++nt) {
+              if (!lds_mode_ok(da.dtype, lds) ||
+                  (int64_t)dense_lds_bytes(da.dtype, da.n_cols, lds) + 1024 > c->max_lds)
+                continue;
               DenseTuning t{rw, waves, 0, lds, bpc, un, nt};
               double ms = 0.0;
               if ((s = time_product(c, da, op, w, y, t, reps, &ms)) != MAPI_OK) return s;
@@ -395,6 +401,7 @@ mapi_status mapi_tuning_set(mapi_ctx* c, int32_t dtype, int64_t n_rows, int64_t 
   DenseTuning t;
   mapi_status s;
   if ((s = to_dense_tuning(tu, &t)) != MAPI_OK) return s;
+  if (!lds_mode_ok(dtype, t.w_in_lds)) return fail(MAPI_ERR_ARG, "w_in_lds 2 needs FP8 storage");
   c->tuned[bucket(dtype, n_rows, n_cols)] = t;
   return MAPI_OK;
 }
@@ -542,9 +549,11 @@ mapi_status mapi_pagerank(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t 
   HIP_TRY(hipSetDevice(c->device));
   const int64_t n = H->n;
   const int F = finalize_blocks(n);
-  const int P = std::max(std::max(csr_part_count(n), 3 * F), 2 * pr_scalar_blocks(n));
+  const int PP = csr_part_count(n);
+  const int P = std::max(3 * F, 2 * pr_scalar_blocks(n));
   Layout L;
   const size_t o_st = L.take(sizeof(SolveState));
+  const size_t o_pp = L.take(sizeof(double) * PP);
   const size_t o_part = L.take(sizeof(double) * P);
   const size_t o_w0 = L.take(sizeof(float) * n);
   const size_t o_w1 = L.take(sizeof(float) * n);
@@ -554,6 +563,7 @@ mapi_status mapi_pagerank(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t 
   if ((s = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return s;
   char* base = static_cast<char*>(c->ws);
   SolveState* st = reinterpret_cast<SolveState*>(base + o_st);
+  double* pprod = reinterpret_cast<double*>(base + o_pp);
   double* part = reinterpret_cast<double*>(base + o_part);
   float* wb[2] = {reinterpret_cast<float*>(base + o_w0), reinterpret_cast<float*>(base + o_w1)};
   float* y = reinterpret_cast<float*>(base + o_y);
@@ -583,12 +593,12 @@ mapi_status mapi_pagerank(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t 
     float* wn = wb[(it & 1) ^ 1];
     {
       Timed tm(c, MAPI_K_CSR);
-      HIP_TRY(launch_csr_product(method, H->row_ptr, H->col, H->val, n, wc, y, part, st, (float)alpha, (float)cc,
+      HIP_TRY(launch_csr_product(method, H->row_ptr, H->col, H->val, n, wc, y, pprod, st, (float)alpha, (float)cc,
                                  inv_n, c->stream));
     }
     {
       Timed tm(c, MAPI_K_FINALIZE);
-      HIP_TRY(launch_finalize(mode, y, wc, wn, n, st, part, dangling, cc, inv_n, c->stream));
+      HIP_TRY(launch_finalize(mode, y, wc, wn, n, st, pprod, PP, NORM_L1, part, dangling, cc, inv_n, c->stream));
     }
     if ((it + 1) % check == 0 && it + 1 < o->max_iters) {
       if ((s = sync_and_state(c, st)) != MAPI_OK) return s;

@@ -26,8 +26,8 @@ struct SolveState {
   int32_t stall;
   int32_t max_iters;
   int32_t stall_iters;
-  uint32_t cnt_a;     // arrival counters of the two grid-wide reductions
-  uint32_t cnt_b;
+  uint32_t cnt_a;     // arrival counter (spare)
+  uint32_t cnt_b;     // arrival counter of the normalisation kernel's reduction
   int32_t pad;
 };
 
@@ -155,18 +155,21 @@ struct DenseTuning {
   int rows_per_wave;   // 1, 2, 4 or 8 rows share each staged w value
   int waves;           // waves per block (4 or 8)
   int blocks;          // grid size (persistent loop over row groups); 0 = from blocks_per_cu
-  int w_in_lds;        // stage w in LDS (needs n_cols * 4 bytes of LDS per block)
+  int w_in_lds;        // 0: w from global memory; 1: w staged in LDS; 2 (FP8 only): |w| and sign words in LDS
   int blocks_per_cu;   // grid = CUs * blocks_per_cu (0 = default)
   int unroll;          // 16-byte loads in flight per row per lane (2 or 4)
   int nontemporal;     // non-temporal matrix loads
 };
 
-// LDS bytes of the dense product kernel when w is staged there: w (FP8: |w| plus one
-// sign word per 4 columns).
-inline size_t dense_lds_bytes(int dtype, int64_t n_cols) {
+// LDS bytes of the dense product kernel for a w_in_lds mode: w (mode 1) or |w|
+// plus one sign word per 4 columns (mode 2, FP8 storage).
+inline size_t dense_lds_bytes(int dtype, int64_t n_cols, int mode) {
   const size_t wbytes = (size_t)((n_cols + 3) & ~int64_t(3)) * 4;
-  return dtype == MAPI_FP8_E4M3 ? wbytes + (size_t)((n_cols >> 2) + 4) * 4 : (size_t)n_cols * 4;
+  if (mode == 0) return 0;
+  return (mode == 2 && dtype == MAPI_FP8_E4M3) ? wbytes + (size_t)((n_cols >> 2) + 4) * 4 : wbytes;
 }
+// Admissible w_in_lds modes for a storage type.
+inline bool lds_mode_ok(int dtype, int mode) { return mode == 0 || mode == 1 || (mode == 2 && dtype == MAPI_FP8_E4M3); }
 
 hipError_t launch_state_init(SolveState* st, int max_iters, double tol, int stall_iters, hipStream_t s);
 hipError_t launch_mavp_dense(const DenseArgs& a, int op, const float* w, float* y, double* part,
@@ -174,8 +177,8 @@ hipError_t launch_mavp_dense(const DenseArgs& a, int op, const float* w, float* 
 int dense_part_count(const DenseArgs& a, const DenseTuning& t, int cu_count);
 DenseTuning dense_default_tuning(const DenseArgs& a, int cu_count, int max_lds_bytes);
 hipError_t launch_finalize(int mode, const float* y, const float* w_old, float* w_new, int64_t n,
-                           SolveState* st, double* part, const uint8_t* dangling, double c, double inv_n,
-                           hipStream_t s);
+                           SolveState* st, const double* pprod, int nprod, int norm, double* part,
+                           const uint8_t* dangling, double c, double inv_n, hipStream_t s);
 int finalize_blocks(int64_t n);
 hipError_t launch_finish(const float* w0buf, const float* w1buf, float* out, int64_t n, SolveState* st, int final_l2,
                          hipStream_t s);

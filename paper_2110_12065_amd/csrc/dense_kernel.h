@@ -8,8 +8,7 @@
 // or 16 e4m3 values per lane per load), so one wave load covers 1 KiB of a row.
 // The RW rows share every staged w value and its sign.  Row sums use a fixed
 // butterfly across the wave; the block partials of the norm are summed in a
-// fixed order by the block that arrives last, so results do not depend on
-// timing.
+// fixed order by the next kernel, so results do not depend on timing.
 #pragma once
 #include <hip/hip_ext.h>
 
@@ -77,7 +76,7 @@ __device__ __forceinline__ uint4 load16(const unsigned char* p) {
 // n_cols floats, 16-byte aligned) by one wave: lanes stride along the columns in
 // 16-byte vectors, then a fixed butterfly; out[r] is valid in every lane.
 //
-// PF (FP8 with w staged in LDS): wv holds |w| and smask one word per 4 stored
+// PF (FP8 with w_in_lds mode 2): wv holds |w| and smask one word per 4 stored
 // values whose bits 7, 15, 23, 31 are the signs of those columns' w.  One xor
 // flips the signs of four stored values before decoding, so each term is
 // op(a * sign(w), |w|) -- the same value as op(a, w) -- without per-element sign
@@ -153,7 +152,7 @@ __device__ __forceinline__ void rows_product(const unsigned char* const* rp, con
   for (int r = 0; r < RW; ++r) out[r] = wave_sum_f32(acc[r][0] + acc[r][1]);
 }
 
-template <int DT, int OP, int RW, int U, bool WLDS, bool NT>
+template <int DT, int OP, int RW, int U, int WL, bool NT>
 __global__ void __launch_bounds__(512)
 k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, int n_cols,
              const float* __restrict__ rscale, const float* __restrict__ w, float* __restrict__ y,
@@ -161,11 +160,11 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
   extern __shared__ float4 w_lds4[];
   float* w_lds = reinterpret_cast<float*>(w_lds4);
   __shared__ double sh[16];
-  __shared__ int sh_flag;
 
   if (st != nullptr && state_done(st)) return;
 
-  constexpr bool PF = WLDS && DT == MAPI_FP8_E4M3;
+  constexpr bool PF = WL == 2 && DT == MAPI_FP8_E4M3;
+  constexpr bool WLDS = WL != 0;
   const float* wv = w;
   const uint32_t* smask = nullptr;
   if constexpr (PF) {
@@ -218,49 +217,55 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
     }
   }
 
-  if (st == nullptr || norm == NORM_NONE) return;
+  // One partial of the normaliser per block; the normalisation kernel that
+  // follows sums them in block order (no grid-wide atomics here).
+  if (part == nullptr || norm == NORM_NONE) return;
   const double bsum = block_sum_f64(nrm, sh);
-  if (threadIdx.x == 0) store_agent(&part[blockIdx.x], bsum);
-  if (arrive_last(&st->cnt_a, &sh_flag)) {
-    const double tot = block_sum_parts(part, gridDim.x, 1, 0, sh);
-    if (threadIdx.x == 0) {
-      st->nu = (norm == NORM_L2) ? sqrt(tot) : tot;
-      st->cnt_a = 0;
-    }
-  }
+  if (threadIdx.x == 0) part[blockIdx.x] = bsum;
 }
 
-template <int DT, int OP, int RW, int U, bool WLDS, bool NT>
+template <int DT, int OP, int RW, int U, int WL, bool NT>
 static hipError_t launch_k(const DenseArgs& a, const float* w, float* y, double* part, SolveState* st, int norm,
                            int blocks, int waves, hipStream_t s) {
   const unsigned char* A = static_cast<const unsigned char*>(a.A);
   const int64_t ldb = a.ld * Traits<DT>::ESZ;
-  const size_t lds = WLDS ? dense_lds_bytes(DT, a.n_cols) : 0;
+  const size_t lds = dense_lds_bytes(DT, a.n_cols, WL);
   if (a.ev_start) {
-    hipExtLaunchKernelGGL((k_mavp_dense<DT, OP, RW, U, WLDS, NT>), dim3(blocks), dim3(waves * kWave), (uint32_t)lds, s,
+    hipExtLaunchKernelGGL((k_mavp_dense<DT, OP, RW, U, WL, NT>), dim3(blocks), dim3(waves * kWave), (uint32_t)lds, s,
                           a.ev_start, a.ev_stop, 0u, A, ldb, (int)a.n_rows, (int)a.n_cols, a.row_scale, w, y, part,
                           st, norm);
   } else {
-    hipLaunchKernelGGL((k_mavp_dense<DT, OP, RW, U, WLDS, NT>), dim3(blocks), dim3(waves * kWave), lds, s, A, ldb,
+    hipLaunchKernelGGL((k_mavp_dense<DT, OP, RW, U, WL, NT>), dim3(blocks), dim3(waves * kWave), lds, s, A, ldb,
                        (int)a.n_rows, (int)a.n_cols, a.row_scale, w, y, part, st, norm);
   }
   return hipGetLastError();
 }
 
+template <int DT, int OP, int RW, int U, int WL>
+static hipError_t launch_nt(const DenseArgs& a, const float* w, float* y, double* part, SolveState* st, int norm,
+                            const DenseTuning& t, int blocks, hipStream_t s) {
+  return t.nontemporal ? launch_k<DT, OP, RW, U, WL, true>(a, w, y, part, st, norm, blocks, t.waves, s)
+                       : launch_k<DT, OP, RW, U, WL, false>(a, w, y, part, st, norm, blocks, t.waves, s);
+}
+
+template <int DT, int OP, int RW, int U>
+static hipError_t launch_wl(const DenseArgs& a, const float* w, float* y, double* part, SolveState* st, int norm,
+                            const DenseTuning& t, int blocks, hipStream_t s) {
+  switch (t.w_in_lds) {
+    case 0: return launch_nt<DT, OP, RW, U, 0>(a, w, y, part, st, norm, t, blocks, s);
+    case 1: return launch_nt<DT, OP, RW, U, 1>(a, w, y, part, st, norm, t, blocks, s);
+    case 2:
+      if constexpr (DT == MAPI_FP8_E4M3) return launch_nt<DT, OP, RW, U, 2>(a, w, y, part, st, norm, t, blocks, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int DT, int OP, int RW>
 static hipError_t launch_rw(const DenseArgs& a, const float* w, float* y, double* part, SolveState* st, int norm,
                             const DenseTuning& t, int blocks, hipStream_t s) {
-  const int key = (t.unroll == 4 ? 4 : 0) | (t.w_in_lds ? 2 : 0) | (t.nontemporal ? 1 : 0);
-  switch (key) {
-    case 0: return launch_k<DT, OP, RW, 2, false, false>(a, w, y, part, st, norm, blocks, t.waves, s);
-    case 1: return launch_k<DT, OP, RW, 2, false, true>(a, w, y, part, st, norm, blocks, t.waves, s);
-    case 2: return launch_k<DT, OP, RW, 2, true, false>(a, w, y, part, st, norm, blocks, t.waves, s);
-    case 3: return launch_k<DT, OP, RW, 2, true, true>(a, w, y, part, st, norm, blocks, t.waves, s);
-    case 4: return launch_k<DT, OP, RW, 4, false, false>(a, w, y, part, st, norm, blocks, t.waves, s);
-    case 5: return launch_k<DT, OP, RW, 4, false, true>(a, w, y, part, st, norm, blocks, t.waves, s);
-    case 6: return launch_k<DT, OP, RW, 4, true, false>(a, w, y, part, st, norm, blocks, t.waves, s);
-    default: return launch_k<DT, OP, RW, 4, true, true>(a, w, y, part, st, norm, blocks, t.waves, s);
-  }
+  return t.unroll == 4 ? launch_wl<DT, OP, RW, 4>(a, w, y, part, st, norm, t, blocks, s)
+                       : launch_wl<DT, OP, RW, 2>(a, w, y, part, st, norm, t, blocks, s);
 }
 
 template <int DT, int OP>

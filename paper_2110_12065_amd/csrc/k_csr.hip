@@ -82,7 +82,6 @@ k_csr_product(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ c
               int64_t n, const float* __restrict__ w, float* __restrict__ y, double* __restrict__ part,
               SolveState* __restrict__ st, float alpha, float c, double inv_n) {
   __shared__ double sh[16];
-  __shared__ int sh_flag;
   if (state_done(st)) return;
   const double base = (METHOD == MAPI_METHOD_MAPI) ? st->ex[0] + st->ex[1]
                                                    : ((double)alpha * inv_n) * st->ex[1] + (double)c * st->ex[0];
@@ -112,15 +111,9 @@ k_csr_product(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ c
       nrm += fabs((double)yi);
     }
   }
+  // one partial of the normaliser per block, summed in block order by the normalisation kernel
   const double bsum = block_sum_f64(nrm, sh);
-  if (threadIdx.x == 0) store_agent(&part[blockIdx.x], bsum);
-  if (arrive_last(&st->cnt_a, &sh_flag)) {
-    const double tot = block_sum_parts(part, gridDim.x, 1, 0, sh);
-    if (threadIdx.x == 0) {
-      st->nu = tot;
-      st->cnt_a = 0;
-    }
-  }
+  if (threadIdx.x == 0) part[blockIdx.x] = bsum;
 }
 
 __global__ void k_fill_f32(float* p, int64_t n, float v) {

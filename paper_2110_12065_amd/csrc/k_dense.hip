@@ -10,15 +10,20 @@ namespace mapi {
 // ---------------------------------------------------------------- normalise + residual
 // mode 0: dense; mode 1: PageRank with the min1 product (also the clamp sums
 // T and Dg of the new iterate); mode 2: PageRank RPI (sum of w, dangling sum).
+// Every block first sums the product kernel's per-block partials pprod[0..nprod)
+// in block order (the same float64 value in every block), so the product kernel
+// needs no grid-wide arrival; norm NORM_L2 takes the square root (RPI, eq. 1).
 template <int MODE>
 __global__ void __launch_bounds__(256)
 k_finalize(const float* __restrict__ y, const float* __restrict__ w_old, float* __restrict__ w_new, int64_t n,
-           SolveState* __restrict__ st, double* __restrict__ part, const uint8_t* __restrict__ dangling, double c,
-           double inv_n) {
+           SolveState* __restrict__ st, const double* __restrict__ pprod, int nprod, int norm,
+           double* __restrict__ part, const uint8_t* __restrict__ dangling, double c, double inv_n) {
   __shared__ double sh[16];
   __shared__ int sh_flag;
   if (state_done(st)) return;
-  const double nu = st->nu;
+  const double tot = block_sum_parts(pprod, nprod, 1, 0, sh);
+  const double nu = (norm == NORM_L2) ? sqrt(tot) : tot;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->nu = nu;
   if (!(nu > 0.0) || !(nu < INFINITY)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       st->status = MAPI_ERR_DEGENERATE;
@@ -113,7 +118,7 @@ DenseTuning dense_default_tuning(const DenseArgs& a, int cu_count, int max_lds_b
   // them per size bucket): the matrix is streamed once per product, so
   // non-temporal loads and 8 waves per block keep the most bytes in flight.
   DenseTuning t;
-  const bool lds_fits = (int64_t)dense_lds_bytes(a.dtype, a.n_cols) + 1024 <= (int64_t)max_lds_bytes;
+  const bool lds_fits = (int64_t)dense_lds_bytes(a.dtype, a.n_cols, 1) + 1024 <= (int64_t)max_lds_bytes;
   t.blocks = 0;
   t.waves = 8;
   t.nontemporal = 1;
@@ -179,19 +184,22 @@ hipError_t launch_copy16(const void* src, void* dst, int64_t n16, int cu_count, 
   return hipGetLastError();
 }
 
+// At most one normalisation block per compute unit: the blocks' arrivals on one
+// counter are serialised, so fewer, longer blocks finish sooner for large n.
 int finalize_blocks(int64_t n) {
   int64_t b = (n + 1023) / 1024;
-  if (b > 1024) b = 1024;
+  if (b > 256) b = 256;
   return (int)(b < 1 ? 1 : b);
 }
 
 hipError_t launch_finalize(int mode, const float* y, const float* w_old, float* w_new, int64_t n, SolveState* st,
-                           double* part, const uint8_t* dangling, double c, double inv_n, hipStream_t s) {
+                           const double* pprod, int nprod, int norm, double* part, const uint8_t* dangling, double c,
+                           double inv_n, hipStream_t s) {
   const int blocks = finalize_blocks(n);
   switch (mode) {
-    case 0: hipLaunchKernelGGL(k_finalize<0>, dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, part, dangling, c, inv_n); break;
-    case 1: hipLaunchKernelGGL(k_finalize<1>, dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, part, dangling, c, inv_n); break;
-    case 2: hipLaunchKernelGGL(k_finalize<2>, dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, part, dangling, c, inv_n); break;
+    case 0: hipLaunchKernelGGL(k_finalize<0>, dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n); break;
+    case 1: hipLaunchKernelGGL(k_finalize<1>, dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n); break;
+    case 2: hipLaunchKernelGGL(k_finalize<2>, dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

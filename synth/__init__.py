@@ -121,11 +121,23 @@ def pca_data(D, N, seed, n_factors=16, noise=0.1, outlier_frac=0.05, laplace_b=1
     return X.astype(np.float32)
 
 
+def laplace_from_uniform(r, b):
+    """Laplace(0, b) draws from uniforms r in [0, 1) (torch tensor) by the inverse CDF
+    x = -b sign(u) log(1 - 2|u|), u = r - 1/2.  |u| is clamped to 1/2 - 2^-25 so that
+    r = 0, which float32 uniform generators do return, gives -b log(2^-24) instead of an
+    infinity; every draw is finite, |x| <= 24 b log 2."""
+    import torch
+    u = r - 0.5
+    a = torch.clamp(torch.abs(u), max=0.5 - 2.0 ** -25)
+    return -b * torch.sign(u) * torch.log1p(-2.0 * a)
+
+
 def pca_data_device(D, N, seed, device, n_factors=16, noise=0.1, outlier_frac=0.05, laplace_b=10.0,
                     decay=0.8, lead=2.0):
     """``pca_data`` drawn with torch's seeded generator on ``device``; returns (X, X_clean)
     as float32 tensors (X_clean: the centred low-rank part U Z).  Same recipe and draw
-    order as ``pca_data``; the Laplace draws are inverse-CDF transforms of uniforms."""
+    order as ``pca_data``; the Laplace draws are inverse-CDF transforms of uniforms
+    (``laplace_from_uniform``)."""
     import torch
     g = torch.Generator(device=device)
     g.manual_seed(int(seed))
@@ -135,9 +147,8 @@ def pca_data_device(D, N, seed, device, n_factors=16, noise=0.1, outlier_frac=0.
     clean = U @ Z
     X = clean + noise * torch.randn((D, N), generator=g, device=device, dtype=torch.float32)
     mask = torch.rand((D, N), generator=g, device=device) < outlier_frac
-    u = torch.rand((D, N), generator=g, device=device, dtype=torch.float32) - 0.5
-    lap = -laplace_b * torch.sign(u) * torch.log1p(-2.0 * torch.abs(u))
-    X = torch.where(mask, lap, X)
+    r = torch.rand((D, N), generator=g, device=device, dtype=torch.float32)
+    X = torch.where(mask, laplace_from_uniform(r, laplace_b), X)
     X -= X.mean(dim=1, keepdim=True)
     clean -= clean.mean(dim=1, keepdim=True)
     return X.contiguous(), clean.contiguous()

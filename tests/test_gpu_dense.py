@@ -232,3 +232,44 @@ def test_full_size_n16384_sampled_rows_and_iterates():
                 ai = oracle.fp8_rows_dequantize(qi, si)[0]
             terms = oracle.term_min1(ai, w0)
             assert abs(y[i] - terms.sum()) <= TOL * np.abs(terms).sum()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_every_launch_shape_gives_the_same_product(dtype):
+    # Each row's sum is formed by one wave in a fixed lane order whatever the launch shape, and
+    # the FP8 sign-word staging (w_in_lds 2) flips signs exactly, so y is bitwise shape-independent.
+    m, n = 301, 2061
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    w = rng.standard_normal(n).astype(np.float32)
+    Ad, rs, Aref = _stored(A, dtype)
+    wd = to_dev(w)
+    ref = oracle.mavp(Aref.astype(np.float64), w.astype(np.float64), "min1")
+    first = None
+    lds_modes = (0, 1, 2) if dtype == "fp8" else (0, 1)
+    for op in ("min1", "dot"):
+        first = None
+        for rw in (1, 2, 4, 8):
+            for waves in (4, 8):
+                for unroll in (2, 4):
+                    for lds in lds_modes:
+                        for nt in (0, 1):
+                            shape = dict(rows_per_wave=rw, waves=waves, blocks_per_cu=1 + (rw & 1), unroll=unroll,
+                                         w_in_lds=lds, nontemporal=nt)
+                            y = torch.full((m,), float("nan"), device="cuda")
+                            mp.mapi_mavp_timed(Ad, wd, shape, op=op, reps=1, row_scale=rs, y=y)
+                            yh = y.cpu().numpy()
+                            if first is None:
+                                first = yh
+                                if op == "min1":
+                                    assert rel_l1(yh, ref) <= TOL
+                            else:
+                                np.testing.assert_array_equal(yh, first, err_msg=f"{op} {shape}")
+
+
+def test_sign_word_staging_rejected_for_other_storage():
+    A = to_dev(np.ones((8, 8), np.float32))
+    w = to_dev(np.ones(8, np.float32))
+    shape = dict(rows_per_wave=1, waves=4, blocks_per_cu=1, unroll=2, w_in_lds=2, nontemporal=0)
+    with pytest.raises(mp.MapiError):
+        mp.mapi_mavp_timed(A, w, shape, reps=1)

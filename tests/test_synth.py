@@ -48,3 +48,19 @@ def test_powerlaw_graph_structure():
 def test_dyadic_values():
     A = synth.dyadic_matrix(10, 20, seed=8)
     assert np.all((A * 8) == np.round(A * 8)) and np.abs(A).max() <= 2
+
+
+def test_laplace_from_uniform_is_finite_and_laplace():
+    import torch
+    # r = 0 is a value float32 uniform generators return; it must not give an infinity
+    r = torch.tensor([0.0, 0.25, 0.5, 0.75, 1.0 - 2.0 ** -24], dtype=torch.float32)
+    x = synth.laplace_from_uniform(r, 10.0)
+    assert torch.isfinite(x).all()
+    assert abs(float(x[0]) - 10.0 * np.log(2.0 ** -24)) < 1e-3   # clamped end: u = -1/2 + 2^-25
+    assert float(x[2]) == 0.0
+    # the inverse CDF: P(X <= x) = 1/2 exp(x / b) for x < 0, so r = 1/4 maps to b log(1/2)
+    assert abs(float(x[1]) - 10.0 * np.log(0.5)) < 1e-5 and abs(float(x[3]) + 10.0 * np.log(0.5)) < 1e-5
+    # moments of a large sample: mean 0, E|X| = b
+    g = torch.Generator().manual_seed(3)
+    s = synth.laplace_from_uniform(torch.rand(200000, generator=g), 2.0).double()
+    assert abs(float(s.mean())) < 0.03 and abs(float(s.abs().mean()) - 2.0) < 0.03
