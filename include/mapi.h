@@ -265,10 +265,14 @@ typedef struct mapi_problem {
  * a result is the same alone and in any mix.  infos: host array of count.
  * The call allocates a device arena for the batch (kept by the context).       */
 mapi_status mapi_solve_batched(mapi_ctx* ctx, int32_t count, const mapi_problem* probs, mapi_info* infos);
-/* Persistent grid: compute units * blocks_per_cu blocks (1..8, default 2).      */
+/* Persistent grid: compute units * blocks_per_cu blocks (1..8, default 4).      */
 mapi_status mapi_batched_config(mapi_ctx* ctx, int32_t blocks_per_cu);
 /* Product tile height (row split) used for dense instances of a storage type and
- * size bucket (ceil(log2 n)); the autotuner sets it from measurements.          */
+ * size bucket (ceil(log2 n)); the autotuner sets it from measurements.  Default:
+ * about 1 MiB of matrix per tile, 4..1024 rows.  Every tile is one work item,
+ * and items cost device-wide fences and a claim on one counter, which the chip
+ * serialises, so small tiles lose throughput.  An instance that fits in one tile
+ * is iterated by a single block without queue round trips.                       */
 mapi_status mapi_batched_rows_set(mapi_ctx* ctx, int32_t dtype, int64_t n, int32_t rows_per_tile);
 mapi_status mapi_batched_rows_get(mapi_ctx* ctx, int32_t dtype, int64_t n, int32_t* rows_per_tile);
 /* Autotuner for the row split: solves `count` generated instances of size n with
@@ -283,7 +287,7 @@ mapi_status mapi_generate_dense(mapi_ctx* ctx, int64_t n, uint64_t seed, float* 
 typedef struct mapi_server mapi_server;
 
 typedef struct mapi_serve_cfg {
-  int32_t blocks_per_cu;     /* persistent grid (0 = 2)                            */
+  int32_t blocks_per_cu;     /* persistent grid (0 = 4)                            */
   int32_t max_slots;         /* concurrently admitted instances (0 = 2048)         */
   double idle_exit_ms;       /* an idle block exits after this long (0 = 20)       */
 } mapi_serve_cfg;

@@ -19,11 +19,13 @@ struct BatchState {
 };
 
 int batch_default_rows(int kind, int dtype, int64_t n) {
-  if (kind == BK_CSR) return (int)std::max<int64_t>(4096, (n + kMaxTiles - 1) / kMaxTiles);
+  if (kind == BK_CSR) return (int)std::max<int64_t>(1024, (n + kMaxTiles - 1) / kMaxTiles);
   const int64_t es = elem_size(dtype);
-  int64_t r = (256 * 1024) / std::max<int64_t>(1, n * es);      // about 256 KiB of matrix per tile
-  r = std::max<int64_t>(2, std::min<int64_t>(r, 256));
-  return (int)((r + 1) / 2 * 2);
+  // About 1 MiB of matrix per tile: every item costs a few device-wide fences and a
+  // claim on one counter, which the whole chip serialises, so items must be large.
+  int64_t r = (1024 * 1024) / std::max<int64_t>(1, n * es);
+  r = std::max<int64_t>(4, std::min<int64_t>(r, kMaxTileRows));
+  return (int)((r + 3) / 4 * 4);
 }
 
 static int log2ceil(int64_t x) {
@@ -374,8 +376,8 @@ mapi_status mapi_autotune_batched(mapi_ctx* c, int32_t dtype, int64_t n, int32_t
   int best = batch_default_rows(BK_DENSE, dtype, n);
   double bms = 1e30;
   mapi_status s = MAPI_OK;
-  for (int rows : {2, 4, 8, 16, 32, 64, 128, 256}) {
-    if (rows > n && rows != 2) continue;
+  for (int rows : {4, 8, 16, 32, 64, 128, 256, 512, 1024}) {
+    if (rows > n && rows != 4) continue;
     c->batch_rows[key] = rows;
     const auto t0 = std::chrono::steady_clock::now();
     s = mapi_solve_batched(c, count, P.data(), nullptr);

@@ -22,6 +22,7 @@ constexpr int kVecTile = 8192;      // elements per INIT / FIN / OUT tile
 constexpr int kGenRows = 32;        // rows per generation tile
 constexpr int kSoloBurst = 16;      // iterations a solo block runs before yielding
 constexpr int kBatchLdsFloats = 8192;   // w staged in LDS up to this many columns
+constexpr int kMaxTileRows = 1024;      // default row-split limit
 
 struct BInst {
   // ---- description (written by the host)

@@ -150,25 +150,29 @@ __device__ bool tile_arrive(BInst* I, uint32_t tiles, int* sh_flag) {
 }
 
 // ---------------------------------------------------------------- row products
+// Rows [r0, r1) of one tile: each wave takes RW rows at a time (4 for float32 and
+// bf16 storage, 2 for FP8, whose decoded vectors need more registers) with two
+// 16-byte loads per row and lane in flight.
 template <int DT, int OP>
 __device__ double dense_rows_t(const BInst* I, const float* wv, int r0, int r1, float* y, bool l2) {
+  constexpr int RW = (DT == MAPI_FP8_E4M3) ? 2 : 4;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
   const unsigned char* A = static_cast<const unsigned char*>(I->A);
   const int64_t ldb = I->ld * Traits<DT>::ESZ;
   double nrm = 0.0;
-  for (int g = r0 + 2 * wave; g < r1; g += 2 * nw) {
-    const unsigned char* rp[2];
-    float sc[2];
+  for (int g = r0 + RW * wave; g < r1; g += RW * nw) {
+    const unsigned char* rp[RW];
+    float sc[RW];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int row = min(g + r, r1 - 1);
+    for (int r = 0; r < RW; ++r) {
+      const int row = min(g + r, r1 - 1);   // padded rows re-read the tile's last row
       rp[r] = A + (int64_t)row * ldb;
       sc[r] = (DT == MAPI_FP8_E4M3) ? I->row_scale[row] : 1.0f;
     }
-    float s[2];
-    rows_product<DT, OP, 2, 2, false>(rp, sc, wv, I->n, lane, s);
+    float s[RW];
+    rows_product<DT, OP, RW, 2, false>(rp, sc, wv, I->n, lane, s);
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < RW; ++r)
       if (lane == 0 && g + r < r1) {
         y[g + r] = s[r];
         nrm += l2 ? (double)s[r] * (double)s[r] : fabs((double)s[r]);
@@ -196,67 +200,133 @@ __device__ double dense_rows(const BInst* I, const float* wv, int r0, int r1, fl
   }
 }
 
-// PageRank rows (eq. 11 split sums, as in the single-solve kernel), 8 lanes per row.
+// PageRank rows (eq. 11 split sums, as in the single-solve kernel): G lanes per
+// row, each lane summing the row's in-links k = sub, sub + G, ... in order, then a
+// fixed butterfly.  Each lane group carries R rows at once, so a lane has R
+// independent index, value and gather loads in flight per step: the persistent
+// kernel runs few waves per SIMD and must hide the gathers' latency itself.
 __device__ double csr_rows(const BInst* I, const float* w, int r0, int r1, float* y) {
-  constexpr int G = 8;
+  constexpr int G = 8, R = 4;
   const bool mapi = I->method == MAPI_METHOD_MAPI;
   const double base = mapi ? I->st.ex[0] + I->st.ex[1]
                            : ((double)I->alpha * I->inv_n) * I->st.ex[1] + (double)I->c * I->st.ex[0];
   const float alpha = I->alpha, c = I->c;
-  const int sub = threadIdx.x % G;
+  const int32_t* __restrict__ row_ptr = I->row_ptr;
+  const int32_t* __restrict__ col = I->col;
+  const float* __restrict__ val = I->val;
+  const int sub = threadIdx.x % G, grp = threadIdx.x / G, ngrp = blockDim.x / G;
   double nrm = 0.0;
-  for (int i = r0 + (int)threadIdx.x / G; i < r1; i += (int)blockDim.x / G) {
-    const int32_t p0 = I->row_ptr[i], p1 = I->row_ptr[i + 1];
-    float acc = 0.0f;
-    for (int32_t p = p0 + sub; p < p1; p += G) {
-      const float wj = w[I->col[p]];
-      const float h = I->val[p];
-      if (mapi) {
-        const float g = fmaf(alpha, h, c);
-        acc += __builtin_amdgcn_fmed3f(wj, -g, g) - __builtin_amdgcn_fmed3f(wj, -c, c);
-      } else {
-        acc = fmaf(h, wj, acc);
+  for (int i0 = r0 + grp * R; i0 < r1; i0 += ngrp * R) {
+    int32_t p0[R], len[R];
+    int32_t maxlen = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool ok = i0 + r < r1;
+      p0[r] = ok ? row_ptr[i0 + r] : 0;
+      len[r] = ok ? row_ptr[i0 + r + 1] - p0[r] : 0;
+      maxlen = max(maxlen, len[r]);
+    }
+    float acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0f;
+    for (int32_t k = sub; k < maxlen; k += G) {
+      int32_t cj[R];
+      float h[R], wj[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool ok = k < len[r];
+        cj[r] = ok ? col[p0[r] + k] : 0;
+        h[r] = ok ? val[p0[r] + k] : 0.0f;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) wj[r] = w[cj[r]];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (k < len[r]) {
+          if (mapi) {
+            const float g = fmaf(alpha, h[r], c);
+            acc[r] += __builtin_amdgcn_fmed3f(wj[r], -g, g) - __builtin_amdgcn_fmed3f(wj[r], -c, c);
+          } else {
+            acc[r] = fmaf(h[r], wj[r], acc[r]);
+          }
+        }
       }
     }
 #pragma unroll
-    for (int off = G / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, G);
-    if (sub == 0) {
-      const float yi = mapi ? (float)(base + (double)acc) : (float)((double)alpha * (double)acc + base);
-      y[i] = yi;
-      nrm += fabs((double)yi);
+    for (int r = 0; r < R; ++r) {
+      float a = acc[r];
+#pragma unroll
+      for (int off = G / 2; off >= 1; off >>= 1) a += __shfl_xor(a, off, G);
+      if (sub == 0 && i0 + r < r1) {
+        const float yi = mapi ? (float)(base + (double)a) : (float)((double)alpha * (double)a + base);
+        y[i0 + r] = yi;
+        nrm += fabs((double)yi);
+      }
     }
   }
   return nrm;
 }
 
+// Stage w in LDS; every thread issues all its loads before its first store, so
+// the staging costs one memory latency rather than one per pass.
 __device__ const float* stage_w(const BInst* I, const float* w, float* lds) {
   if (I->kind == BK_CSR || I->n > kBatchLdsFloats) return w;
+  constexpr int K = kBatchLdsFloats / 4 / kBT;
   const int n = I->n, nv4 = n >> 2;
-  for (int v = threadIdx.x; v < nv4; v += blockDim.x)
-    reinterpret_cast<float4*>(lds)[v] = reinterpret_cast<const float4*>(w)[v];
-  for (int j = (nv4 << 2) + threadIdx.x; j < n; j += blockDim.x) lds[j] = w[j];
+  float4 t[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int v = threadIdx.x + k * kBT;
+    if (v < nv4) t[k] = reinterpret_cast<const float4*>(w)[v];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int v = threadIdx.x + k * kBT;
+    if (v < nv4) reinterpret_cast<float4*>(lds)[v] = t[k];
+  }
+  for (int j = (nv4 << 2) + threadIdx.x; j < n; j += kBT) lds[j] = w[j];
   __syncthreads();
   return lds;
 }
 
-// Normalise rows [r0, r1) of y by nu into w_new; returns the residual and PageRank partials.
+// Normalise rows [r0, r1) of y by nu into w_new; returns the residual and PageRank
+// partials.  Each thread visits i = r0 + tid, r0 + tid + kBT, ... in order, with the
+// loads of four visits issued ahead of their use.
 __device__ void fin_rows(const BInst* I, const float* y, const float* w_old, float* w_new, int r0, int r1, double nu,
                          double* r, double* e0, double* e1) {
+  constexpr int U = 4;
   const double c = (double)I->c;
   const double inv_n = I->inv_n;
-  for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-    const float wn = (float)((double)y[i] / nu);
-    w_new[i] = wn;
-    const double wd = (double)wn;
-    *r += fabs(wd - (double)w_old[i]);
-    if (I->kind == BK_CSR) {
-      if (I->method == MAPI_METHOD_MAPI) {
-        const double tc = fmin(fmax(wd, -c), c);
-        *e0 += tc;
-        if (I->dangling[i]) *e1 += fmin(fmax(wd, -inv_n), inv_n) - tc;
-      } else {
-        *e0 += wd;
-        if (I->dangling[i]) *e1 += wd;
+  const bool csr = I->kind == BK_CSR, mapi = I->method == MAPI_METHOD_MAPI;
+  const uint8_t* dangling = I->dangling;
+  for (int i0 = r0 + (int)threadIdx.x; i0 < r1; i0 += U * kBT) {
+    float yv[U], wo[U];
+    uint8_t dg[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * kBT;
+      const bool ok = i < r1;
+      yv[u] = ok ? y[i] : 0.0f;
+      wo[u] = ok ? w_old[i] : 0.0f;
+      dg[u] = (ok && csr) ? dangling[i] : (uint8_t)0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * kBT;
+      if (i >= r1) break;
+      const float wn = (float)((double)yv[u] / nu);
+      w_new[i] = wn;
+      const double wd = (double)wn;
+      *r += fabs(wd - (double)wo[u]);
+      if (csr) {
+        if (mapi) {
+          const double tc = fmin(fmax(wd, -c), c);
+          *e0 += tc;
+          if (dg[u]) *e1 += fmin(fmax(wd, -inv_n), inv_n) - tc;
+        } else {
+          *e0 += wd;
+          if (dg[u]) *e1 += wd;
+        }
       }
     }
   }
@@ -371,8 +441,17 @@ __device__ bool phase_solo(BInst* I, float* lds, double* sh) {
 
 // Copy rows [r0, r1) of the final iterate to the caller's output.
 __device__ void out_rows(const BInst* I, int r0, int r1) {
+  constexpr int U = 4;
   const float* src = (I->st.iter & 1) ? I->wb1 : I->wb0;
-  for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) I->out[i] = src[i];
+  float* out = I->out;
+  for (int i0 = r0 + (int)threadIdx.x; i0 < r1; i0 += U * kBT) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = (i0 + u * kBT < r1) ? src[i0 + u * kBT] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u * kBT < r1) out[i0 + u * kBT] = v[u];
+  }
   __threadfence_system();
 }
 
@@ -447,7 +526,9 @@ __device__ void run_init(BQueue* q, BInst* I, uint32_t ii, uint32_t tile, BCtl* 
   advance(q, I, ii, ctl, lds, S);
 }
 
-__global__ void __launch_bounds__(kBT) k_persistent(BQueue* q, BInst* insts, BCtl* ctl) {
+// At most 128 VGPRs, so four blocks (16 waves) share a compute unit: the gathers
+// of the PageRank rows need the waves to hide their latency.
+__global__ void __launch_bounds__(kBT, 4) k_persistent(BQueue* q, BInst* insts, BCtl* ctl) {
   __shared__ float4 lds4[kBatchLdsFloats / 4];
   __shared__ Shared S;
   __shared__ unsigned long long sh_item;

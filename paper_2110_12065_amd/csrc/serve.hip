@@ -360,7 +360,7 @@ mapi_status mapi_serve_create(int device, size_t hbm_budget, const mapi_serve_cf
   }
   s->budget = hbm_budget;
   s->max_slots = (cfg && cfg->max_slots > 0) ? cfg->max_slots : 2048;
-  const int bpc = (cfg && cfg->blocks_per_cu > 0) ? cfg->blocks_per_cu : 2;
+  const int bpc = (cfg && cfg->blocks_per_cu > 0) ? cfg->blocks_per_cu : 4;
   s->blocks = s->ctx->cu_count * bpc;
   s->idle_ms = (cfg && cfg->idle_exit_ms > 0) ? cfg->idle_exit_ms : 20.0;
   if (s->max_slots > (int)kMaxInstances) s->max_slots = (int)kMaxInstances;
