@@ -287,7 +287,7 @@ mapi_status mapi_generate_dense(mapi_ctx* ctx, int64_t n, uint64_t seed, float* 
 typedef struct mapi_server mapi_server;
 
 typedef struct mapi_serve_cfg {
-  int32_t blocks_per_cu;     /* persistent grid (0 = 4)                            */
+  int32_t blocks_per_cu;     /* persistent grid (0 = 3: room for admission kernels) */
   int32_t max_slots;         /* concurrently admitted instances (0 = 2048)         */
   double idle_exit_ms;       /* an idle block exits after this long (0 = 20)       */
 } mapi_serve_cfg;

@@ -360,7 +360,10 @@ mapi_status mapi_serve_create(int device, size_t hbm_budget, const mapi_serve_cf
   }
   s->budget = hbm_budget;
   s->max_slots = (cfg && cfg->max_slots > 0) ? cfg->max_slots : 2048;
-  const int bpc = (cfg && cfg->blocks_per_cu > 0) ? cfg->blocks_per_cu : 4;
+  // Three persistent blocks per compute unit leave a quarter of the register file
+  // free, so the admission path's own kernels (CSR validation, fills) run beside
+  // the persistent kernel instead of waiting for it to go idle.
+  const int bpc = (cfg && cfg->blocks_per_cu > 0) ? cfg->blocks_per_cu : 3;
   s->blocks = s->ctx->cu_count * bpc;
   s->idle_ms = (cfg && cfg->idle_exit_ms > 0) ? cfg->idle_exit_ms : 20.0;
   if (s->max_slots > (int)kMaxInstances) s->max_slots = (int)kMaxInstances;
