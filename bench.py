@@ -47,7 +47,7 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("dense_kernel.h", "k_dense_f32.hip", "k_dense_bf16.hip", "k_dense_fp8.hip"):
+    for f in ("common.h", "dense_kernel.h", "k_dense_f32.hip", "k_dense_bf16.hip", "k_dense_fp8.hip"):
         with open(os.path.join(ROOT, "paper_2110_12065_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -135,16 +135,40 @@ def _kernel_dtype(name):
     return {"0": "f32", "1": "bf16", "2": "fp8"}.get(first)
 
 
-def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write):
+def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write, bench_json=None):
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     stats = _read_csvs(stats_dir, "*kernel_stats.csv")
-    lines = ["# Kernel time summary: dense products at n = 16384 and the copy reference", "",
+    lines = ["# Kernel time summary: the benchmark at n = 16384 (dense products, normalisation)", "",
              f"Command: `{cmd_stats}`", "",
+             "Top kernels by total time (the first row is the covariance build by rocBLAS in the set-up; "
+             "the product rows include the autotuner's trial launches of the same shape).", "",
              "| kernel | calls | average (us) | min (us) | max (us) |", "|---|---|---|---|---|"]
-    for r in sorted(stats, key=lambda r: -float(r.get("TotalDurationNs", 0) or 0)):
+    for r in sorted(stats, key=lambda r: -float(r.get("TotalDurationNs", 0) or 0))[:24]:
         nm = r.get("Name", r.get("KernelName", "?"))
         lines.append(f"| `{nm[:110]}` | {r.get('Calls')} | {float(r.get('AverageNs', 0)) / 1e3:.1f} | "
                      f"{float(r.get('MinNs', 0)) / 1e3:.1f} | {float(r.get('MaxNs', 0)) / 1e3:.1f} |")
+    # the timed launches: the last 100 dispatches of each storage type's min1 product (the
+    # benchmark's live event timing covers exactly those)
+    trace = _read_csvs(stats_dir, "*kernel_trace.csv")
+    live = {}
+    if bench_json and os.path.exists(bench_json):
+        with open(bench_json) as f:
+            det = json.loads(f.read().strip().splitlines()[-1]).get("detail", {})
+        live = {dt: det.get(f"mapi_{dt}", {}).get("product_kernel_us") for dt in ("f32", "bf16", "fp8")}
+    if trace:
+        lines += ["", "Timed launches (last 100 dispatches of the MAPI min1 product per storage type) "
+                  "against the benchmark's own HIP-event timing of the same launches:", "",
+                  "| storage | kernel | rocprofv3 average (us) | benchmark events (us) |", "|---|---|---|---|"]
+        for dt, code in (("f32", "0"), ("bf16", "1"), ("fp8", "2")):
+            ds = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), r["Kernel_Name"])
+                        for r in trace if r["Kernel_Name"].startswith(f"void mapi::k_mavp_dense<{code}, 0,"))
+            if not ds:
+                continue
+            last = ds[-100:]
+            avg = sum(x[1] for x in last) / len(last) / 1e3
+            ev = live.get(dt)
+            lines.append(f"| {dt} | `{last[-1][2][:48]}` | {avg:.1f} | {ev:.1f} |" if ev else
+                         f"| {dt} | `{last[-1][2][:48]}` | {avg:.1f} | - |")
     with open(os.path.join(ROOT, "profiles", "mavp_dense_n16384_kernel_stats.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -318,7 +342,7 @@ def bench_pagerank(mp, ctx, torch, n=1 << 22, seed=2022):
     return out
 
 
-def bench_serving(mp, torch, n_req=20000, rate=2000.0, seed=11, budget=64 << 30, plain_sample=400):
+def bench_serving(mp, torch, n_req=20000, rate=2000.0, seed=11, budget=64 << 30, plain_sample=400, n_sat=8000):
     """Poisson arrivals; 70 % dense generated problems (n log-uniform 64..8192, BF16/F32, MAPI/RPI),
     30 % PageRank on power-law graphs with 2^10..2^20 nodes (a resident pool of 11 graphs, one per
     power of two, in pinned host memory), tolerance 1e-6 each; compared with the one-at-a-time
@@ -372,6 +396,21 @@ def bench_serving(mp, torch, n_req=20000, rate=2000.0, seed=11, budget=64 << 30,
            "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "peak_pool_bytes": st["peak_bytes"],
            "budget_bytes": budget, "kernel_launches": st["kernel_launches"],
            "converged": int(sum(1 for x in res if x and x["converged"]))}
+    # capacity: the first n_sat requests of the same mix submitted back to back
+    n_sat = min(n_sat, n_req)
+    log(f"serving: capacity run, {n_sat} requests submitted at once")
+    srv = mp.Server(budget_bytes=budget)
+    tickets = [srv.submit(make(r), np.empty(r[1], np.float32)) for r in reqs[:n_sat]]
+    res_sat = [srv.wait(t, timeout_us=120_000_000) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    out["saturated_requests"] = n_sat
+    out["saturated_completed_ok"] = sum(1 for x in res_sat if x is not None and x["status"] == "OK")
+    out["saturated_solves_s"] = st["solves_per_s"]
+    out["saturated_p50_ms"] = st["p50_ms"]
+    out["saturated_p99_ms"] = st["p99_ms"]
+    out["saturated_kernel_launches"] = st["kernel_launches"]
+    out["saturated_peak_pool_bytes"] = st["peak_bytes"]
     # one-at-a-time plain path on a sample: float32, one solve after another on one stream
     log(f"serving: timing the one-at-a-time path on {plain_sample} requests")
     ctx = mp.Context()
@@ -423,9 +462,10 @@ def main():
                     help="other workloads reported under detail (comma list; empty for none)")
     ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--commands", nargs=3, default=["", "", ""], help="commands that produced the three dirs")
+    ap.add_argument("--bench-json", default=None, help="JSON line printed by the profiled benchmark command")
     args = ap.parse_args()
     if args.summarize:
-        summarize(*args.summarize, *args.commands)
+        summarize(*args.summarize, *args.commands, bench_json=args.bench_json)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
