@@ -374,7 +374,7 @@ def bench_serving(mp, torch, n_req=20000, rate=2000.0, seed=11, budget=64 << 30,
         if kind == "gen":
             return mp.request_generated(n, s, dt, meth, max_iters=1000, tol=1e-6, stall_iters=STALL)
         p = pool[s]
-        return mp.request_csr_host(p["row_ptr"].numpy(), p["col"].numpy(), p["val"].numpy(), 0.85, meth,
+        return mp.request_csr_host(p["row_ptr"], p["col"], p["val"], 0.85, meth,
                                    max_iters=1000, tol=1e-6, stall_iters=STALL)
 
     log(f"serving: {n_req} requests at {rate:.0f}/s")

@@ -287,15 +287,19 @@ mapi_status mapi_generate_dense(mapi_ctx* ctx, int64_t n, uint64_t seed, float* 
 typedef struct mapi_server mapi_server;
 
 typedef struct mapi_serve_cfg {
-  int32_t blocks_per_cu;     /* persistent grid (0 = 3: room for admission kernels) */
+  int32_t blocks_per_cu;     /* persistent grid (0 = 3)                            */
   int32_t max_slots;         /* concurrently admitted instances (0 = 2048)         */
   double idle_exit_ms;       /* an idle block exits after this long (0 = 20)       */
 } mapi_serve_cfg;
 
 /* A request: the problem (w_out ignored) and the host buffer that receives the
- * n-float result; the caller keeps the CSR arrays (host memory for
- * MAPI_PROB_CSR requests: row_ptr, col, val are HOST pointers here) and
- * host_out alive until the request completes.                                   */
+ * n-float result.  For MAPI_PROB_CSR requests row_ptr, col and val are HOST
+ * pointers into PINNED memory (hipHostMalloc or equivalent): the persistent
+ * kernel reads them itself at admission, copies them to the device and checks
+ * them (row_ptr[0] = 0, row_ptr[n] = nnz, non-decreasing, 0 <= col < n); an
+ * invalid request completes with MAPI_ERR_ARG and does not affect others.
+ * Pageable CSR arrays are rejected by mapi_serve_submit with MAPI_ERR_ARG.  The
+ * caller keeps the CSR arrays and host_out alive until the request completes.   */
 typedef struct mapi_request {
   mapi_problem prob;
   float* host_out;
@@ -317,10 +321,14 @@ typedef struct mapi_serve_summary {
 } mapi_serve_summary;
 
 /* Continuous-batching server on `device`: admits requests while a device memory
- * budget of hbm_budget bytes (matrix, iterates, partials) and an instance slot
- * are free; admitted requests join the running persistent kernel through a
- * host-to-device inbox, so work of requests arriving at different times
- * overlaps on the device.  The server owns its memory and threads.              */
+ * budget of hbm_budget bytes (matrix, iterates, partials, CSR copy), an instance
+ * slot and room for the result in a pinned output pool (min(budget, 1 GiB)) are
+ * free; admitted requests join the running persistent kernel through a host
+ * memory inbox, so work of requests arriving at different times overlaps on the
+ * device.  Admission and completion issue no copy command or kernel (the kernel
+ * reads descriptors and CSR arrays from pinned host memory and writes results
+ * there), so they never wait behind the persistent kernel on a shared hardware
+ * queue.  The server owns its memory and threads.                               */
 mapi_status mapi_serve_create(int device, size_t hbm_budget, const mapi_serve_cfg* cfg, mapi_server** out);
 /* Non-blocking: queue a request, returns its ticket.  MAPI_ERR_BUDGET (at once)
  * if its footprint alone exceeds the budget.                                     */

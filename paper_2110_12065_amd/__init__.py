@@ -585,18 +585,34 @@ def request_generated(n, seed, dtype="f32", method="mapi", max_iters=1000, tol=1
     return p
 
 
-def request_csr_host(row_ptr, col, val, alpha=0.85, method="mapi", max_iters=1000, tol=1e-6, stall_iters=0):
-    """A PageRank request whose CSR arrays are host numpy arrays (copied by the server at admission)."""
+def _pinned(a, dtype):
+    """A pinned host torch tensor holding `a`: pinned CPU tensors of the right type are used as
+    they are; anything else (numpy arrays, pageable tensors) is copied into pinned memory."""
     import numpy as np
-    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
-    col = np.ascontiguousarray(col, dtype=np.int32)
-    val = np.ascontiguousarray(val, dtype=np.float32)
+    import torch
+    if isinstance(a, torch.Tensor) and a.device.type == "cpu" and a.is_pinned() and a.dtype == dtype \
+            and a.is_contiguous():
+        return a
+    t = torch.as_tensor(np.ascontiguousarray(a)) if not isinstance(a, torch.Tensor) else a
+    out = torch.empty(t.shape, dtype=dtype, pin_memory=True)
+    out.copy_(t.to(dtype))
+    return out
+
+
+def request_csr_host(row_ptr, col, val, alpha=0.85, method="mapi", max_iters=1000, tol=1e-6, stall_iters=0):
+    """A PageRank request whose CSR arrays live in pinned host memory, read by the persistent
+    kernel at admission.  Pinned CPU torch tensors are used in place; numpy arrays or pageable
+    tensors are first copied into pinned memory (kept alive with the request)."""
+    import torch
+    row_ptr = _pinned(row_ptr, torch.int32)
+    col = _pinned(col, torch.int32)
+    val = _pinned(val, torch.float32)
     p = Problem()
     p.kind = PROB_CSR
     p.method = METHODS[method]
-    n = row_ptr.size - 1
-    p.H = Csr(n, col.size, row_ptr.ctypes.data, col.ctypes.data if col.size else None,
-              val.ctypes.data if val.size else None)
+    n = row_ptr.numel() - 1
+    p.H = Csr(n, col.numel(), row_ptr.data_ptr(), col.data_ptr() if col.numel() else None,
+              val.data_ptr() if val.numel() else None)
     p.alpha = float(alpha)
     p.opts = _opts(max_iters, tol, "min1", False, 0, stall_iters)
     p._keep = (row_ptr, col, val)

@@ -85,6 +85,8 @@ mapi_status describe(mapi_ctx* c, const mapi_problem& p, BInst* I, int64_t* matr
     I->alpha = (float)p.alpha;
     I->inv_n = 1.0 / (double)n;
     I->c = (float)((1.0 - p.alpha) * I->inv_n);
+    I->nnz = p.H.nnz;
+    I->etiles = (int32_t)((p.H.nnz + kEdgeTile - 1) / kEdgeTile);
   } else if (p.kind == MAPI_PROB_GENERATED) {
     if (p.gen_n <= 0 || p.gen_n > 16384) return fail(MAPI_ERR_ARG, "generated size must be in [1, 16384]");
     if (p.gen_dtype != MAPI_F32 && p.gen_dtype != MAPI_BF16) return fail(MAPI_ERR_ARG, "generated storage F32 or BF16");
@@ -106,7 +108,7 @@ mapi_status describe(mapi_ctx* c, const mapi_problem& p, BInst* I, int64_t* matr
   I->ntiles = (int)((n + I->rows_per_tile - 1) / I->rows_per_tile);
   I->vtiles = (int)((n + kVecTile - 1) / kVecTile);
   I->gtiles = I->kind == BK_GEN ? (int)((n + kGenRows - 1) / kGenRows) : 0;
-  if ((uint32_t)std::max(std::max(I->ntiles, I->vtiles), I->gtiles) > kMaxTiles)
+  if ((uint32_t)std::max(std::max(I->ntiles, I->vtiles), std::max(I->gtiles, I->etiles)) > kMaxTiles)
     return fail(MAPI_ERR_UNSUPPORTED, "problem needs more than %u tiles per phase", kMaxTiles);
   I->solo = I->ntiles == 1 ? 1 : 0;
   SolveState& st = I->st;
@@ -157,7 +159,7 @@ uint32_t first_phase_tiles(const BInst& I, int* phase) {
 }
 
 uint32_t max_tiles(const BInst& I) {
-  return (uint32_t)std::max(std::max(I.ntiles, I.vtiles), std::max(I.gtiles, 1));
+  return (uint32_t)std::max(std::max(I.ntiles, I.vtiles), std::max(std::max(I.gtiles, I.etiles), 1));
 }
 
 uint32_t pow2_at_least(uint64_t x) {

@@ -16,9 +16,16 @@
 namespace mapi {
 
 enum BKind { BK_DENSE = 0, BK_CSR = 1, BK_GEN = 2 };
-enum BPhase { PH_GEN = 0, PH_INIT = 1, PH_PROD = 2, PH_FIN = 3, PH_OUT = 4, PH_SKIP = 7 };
+// ADMIT copies a served request's descriptor from host memory to the device;
+// PREPA / PREPB copy and check a served PageRank request's CSR arrays (rows, then
+// links) from pinned host memory and flag its dangling nodes.
+enum BPhase {
+  PH_GEN = 0, PH_INIT = 1, PH_PROD = 2, PH_FIN = 3, PH_OUT = 4,
+  PH_ADMIT = 5, PH_PREPA = 6, PH_PREPB = 7, PH_SKIP = 15
+};
 
-constexpr int kVecTile = 8192;      // elements per INIT / FIN / OUT tile
+constexpr int kVecTile = 8192;      // elements per INIT / FIN / OUT / PREPA tile
+constexpr int kEdgeTile = 65536;    // links per PREPB tile
 constexpr int kGenRows = 32;        // rows per generation tile
 constexpr int kSoloBurst = 16;      // iterations a solo block runs before yielding
 constexpr int kBatchLdsFloats = 8192;   // w staged in LDS up to this many columns
@@ -53,7 +60,15 @@ struct BInst {
   double* part;              // ntiles + 3 * vtiles doubles
   float* out;                // result (device or host-mapped)
   int32_t slot_gen;          // reuse generation of this slot (serving)
-  int32_t pad0;
+  int32_t etiles;            // PREPB tiles
+  // served PageRank request: the caller's pinned host arrays (device-accessible
+  // addresses), copied into row_ptr / col / val by the PREP phases; NULL otherwise
+  const int32_t* src_row_ptr;
+  const int32_t* src_col;
+  const float* src_val;
+  int64_t nnz;
+  uint32_t prep_err;         // PREP checks: 1 row_ptr ends, 2 row_ptr order, 4 column out of range
+  uint32_t pad0;
   // ---- dynamic state
   SolveState st;
   uint32_t arrive;           // tiles finished in the current phase
@@ -94,27 +109,28 @@ struct BCtl {
   const volatile int32_t* quit;          // host-mapped
   // completion ring in host memory
   BDone* done;                           // host-mapped
+  const BInst* inst_stage;               // host-mapped descriptors written at admission (serving)
   unsigned long long done_pos;           // device counter
   uint32_t done_mask;
   uint32_t pad3;
 };
 
-// Work item: instance (20 bits), phase (3 bits), tile (16 bits).  A ring slot holds
+// Work item: instance (20 bits), phase (4 bits), tile (15 bits).  A ring slot holds
 // the item and, in its top 25 bits, the low bits of (position + 1), so a consumer
 // recognises the item of the position it claims from one 64-bit load.
 constexpr int kTagShift = 39;
 constexpr unsigned long long kItemMask = (1ull << kTagShift) - 1;
 constexpr uint32_t kMaxInstances = 1u << 20;
-constexpr uint32_t kMaxTiles = 65535;
+constexpr uint32_t kMaxTiles = 32767;
 __host__ __device__ inline unsigned long long bitem(uint32_t inst, int phase, uint32_t tile) {
-  return (unsigned long long)inst | ((unsigned long long)phase << 20) | ((unsigned long long)tile << 23);
+  return (unsigned long long)inst | ((unsigned long long)phase << 20) | ((unsigned long long)tile << 24);
 }
 __host__ __device__ inline unsigned long long bslot(unsigned long long pos, unsigned long long item) {
   return item | (((pos + 1) & 0x1FFFFFFull) << kTagShift);
 }
 __host__ __device__ inline uint32_t item_inst(unsigned long long v) { return (uint32_t)(v & 0xFFFFFull); }
-__host__ __device__ inline int item_phase(unsigned long long v) { return (int)((v >> 20) & 0x7ull); }
-__host__ __device__ inline uint32_t item_tile(unsigned long long v) { return (uint32_t)((v >> 23) & 0xFFFFull); }
+__host__ __device__ inline int item_phase(unsigned long long v) { return (int)((v >> 20) & 0xFull); }
+__host__ __device__ inline uint32_t item_tile(unsigned long long v) { return (uint32_t)((v >> 24) & 0x7FFFull); }
 
 // SplitMix64 output function (Steele, Lea and Flood, 2014), used as a
 // counter-based generator: value = splitmix64(splitmix64(seed) + counter).

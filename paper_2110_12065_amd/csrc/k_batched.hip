@@ -70,7 +70,7 @@ __device__ void q_push(BQueue* q, uint32_t inst, int phase, uint32_t count, unsi
 }
 
 // Serving: move newly submitted items from the host inbox into the queue (block 0, thread 0).
-__device__ void drain_inbox(BQueue* q, const BInst* insts, BCtl* ctl) {
+__device__ void drain_inbox(BQueue* q, BCtl* ctl) {
   const unsigned long long tail = *ctl->inbox_tail;
   unsigned long long h = ctl->inbox_head;
   if (h == tail) return;
@@ -78,9 +78,8 @@ __device__ void drain_inbox(BQueue* q, const BInst* insts, BCtl* ctl) {
   const unsigned long long base = atomicAdd(&q->tail, tail - h);
   for (unsigned long long k = 0; h < tail; ++h, ++k) {
     const unsigned long long v = ctl->inbox[h & ctl->inbox_mask];
-    const int ph = item_phase(v);
-    if (item_tile(v) == 0 && (ph == PH_GEN || (ph == PH_INIT && insts[item_inst(v)].kind != BK_GEN))) {
-      atomicAdd(&q->live, 1u);   // first item of a newly admitted instance: counted before it is visible
+    if (item_phase(v) == PH_ADMIT) {
+      atomicAdd(&q->live, 1u);   // a newly admitted instance: counted before its item is visible
       __threadfence();
     }
     q_put(q, base + k, v);
@@ -97,7 +96,7 @@ __device__ bool q_take(BQueue* q, const BInst* insts, BCtl* ctl, unsigned long l
   unsigned long long* s = q_slot(q, p);
   const int64_t t0 = now_ticks();
   for (int polls = 0;; ++polls) {
-    if (ctl->mode == 1 && blockIdx.x == 0) drain_inbox(q, insts, ctl);
+    if (ctl->mode == 1 && blockIdx.x == 0) drain_inbox(q, ctl);
     unsigned long long v = slot_load(s);
     if (!slot_is(v, p)) {
       const int64_t now = now_ticks();
@@ -526,6 +525,100 @@ __device__ void run_init(BQueue* q, BInst* I, uint32_t ii, uint32_t tile, BCtl* 
   advance(q, I, ii, ctl, lds, S);
 }
 
+// ---------------------------------------------------------------- admission (serving)
+// A served request reaches the device as one ADMIT item: its descriptor is read
+// from pinned host memory, and a PageRank request's CSR arrays are read from the
+// caller's pinned host memory by the PREP phases, so admission needs no copy
+// command or kernel beside the persistent kernel.
+
+// End an instance without solving it (invalid input found on the device).
+__device__ void reject(BInst* I, uint32_t ii, BQueue* q, BCtl* ctl, int status) {
+  if (threadIdx.x == 0) {
+    I->st.status = status;
+    I->st.done = 1;
+  }
+  retire(I, ii, q, ctl);
+}
+
+// First phase of an admitted instance: CSR checks, generation, or the start vector.
+__device__ void start_instance(BQueue* q, BInst* I, uint32_t ii, BCtl* ctl, float* lds, Shared* S);
+
+__device__ void phase_admit(BQueue* q, BInst* insts, uint32_t ii, BCtl* ctl, float* lds, Shared* S) {
+  BInst* I = insts + ii;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(ctl->inst_stage + ii);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(I);
+  for (int k = threadIdx.x; k < (int)(sizeof(BInst) / 4); k += kBT) dst[k] = src[k];
+  __threadfence_block();
+  __syncthreads();
+  start_instance(q, I, ii, ctl, lds, S);
+}
+
+__device__ void start_instance(BQueue* q, BInst* I, uint32_t ii, BCtl* ctl, float* lds, Shared* S) {
+  if (threadIdx.x == 0) I->t_start = now_ticks();
+  if (I->kind == BK_CSR && I->src_row_ptr) q_push(q, ii, PH_PREPA, (uint32_t)I->vtiles, &S->base);
+  else if (I->kind == BK_GEN) q_push(q, ii, PH_GEN, (uint32_t)I->gtiles, &S->base);
+  else q_push(q, ii, PH_INIT, (uint32_t)I->vtiles, &S->base);
+}
+
+// Rows [r0, r1) of a served CSR request: copy row_ptr (and its last entry), check it,
+// mark every node dangling (PREPB clears the ones that are sources).
+__device__ void phase_prepa(BInst* I, uint32_t tile) {
+  const int n = I->n;
+  const int r0 = tile * kVecTile, r1 = min(n, r0 + kVecTile);
+  const int32_t* src = I->src_row_ptr;
+  int32_t* rp = const_cast<int32_t*>(I->row_ptr);
+  uint8_t* dg = const_cast<uint8_t*>(I->dangling);
+  uint32_t err = 0;
+  for (int i = r0 + threadIdx.x; i < r1; i += kBT) {
+    const int32_t a = src[i], b = src[i + 1];
+    rp[i] = a;
+    dg[i] = 1;
+    if (a > b) err |= 2u;
+    if (i == 0 && a != 0) err |= 1u;
+    if (i == n - 1) {
+      rp[n] = b;
+      if ((int64_t)b != I->nnz) err |= 1u;
+    }
+  }
+  if (err) atomicOr(&I->prep_err, err);
+}
+
+// Links [p0, p1): copy col and val, check the column range, clear the dangling
+// flag of every source (the same byte may be cleared by several threads).
+__device__ void phase_prepb(BInst* I, uint32_t tile) {
+  const int64_t p0 = (int64_t)tile * kEdgeTile, p1 = min(I->nnz, p0 + kEdgeTile);
+  const int n = I->n;
+  int32_t* col = const_cast<int32_t*>(I->col);
+  float* val = const_cast<float*>(I->val);
+  uint8_t* dg = const_cast<uint8_t*>(I->dangling);
+  uint32_t err = 0;
+  constexpr int U = 4;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += U * kBT) {
+    int32_t j[U];
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = p + u * kBT;
+      j[u] = e < p1 ? I->src_col[e] : 0;
+      v[u] = e < p1 ? I->src_val[e] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = p + u * kBT;
+      if (e >= p1) break;
+      col[e] = j[u];
+      val[e] = v[u];
+      if (j[u] < 0 || j[u] >= n) err |= 4u;
+      else dg[j[u]] = 0;
+    }
+  }
+  if (err) atomicOr(&I->prep_err, err);
+}
+
+__device__ __forceinline__ uint32_t prep_error(BInst* I) {
+  return __hip_atomic_load(&I->prep_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // At most 128 VGPRs, so four blocks (16 waves) share a compute unit: the gathers
 // of the PageRank rows need the waves to hide their latency.
 __global__ void __launch_bounds__(kBT, 4) k_persistent(BQueue* q, BInst* insts, BCtl* ctl) {
@@ -555,14 +648,14 @@ __global__ void __launch_bounds__(kBT, 4) k_persistent(BQueue* q, BInst* insts, 
     const int n = I->n;
 
     if (ph == PH_GEN) {
-      if (threadIdx.x == 0 && tile == 0) I->t_start = now_ticks();
+      if (threadIdx.x == 0 && tile == 0 && ctl->mode == 0) I->t_start = now_ticks();
       phase_gen(I, tile);
       if (tile_arrive(I, I->gtiles, &S.flag)) {
         if (I->vtiles == 1) run_init(q, I, ii, 0, ctl, lds, &S);
         else q_push(q, ii, PH_INIT, I->vtiles, &S.base);
       }
     } else if (ph == PH_INIT) {
-      if (threadIdx.x == 0 && tile == 0 && I->kind != BK_GEN) I->t_start = now_ticks();
+      if (threadIdx.x == 0 && tile == 0 && I->kind != BK_GEN && ctl->mode == 0) I->t_start = now_ticks();
       run_init(q, I, ii, tile, ctl, lds, &S);
     } else if (ph == PH_PROD) {
       if (I->solo) {
@@ -627,6 +720,23 @@ __global__ void __launch_bounds__(kBT, 4) k_persistent(BQueue* q, BInst* insts, 
     } else if (ph == PH_OUT) {
       out_rows(I, tile * kVecTile, min(n, (int)(tile + 1) * kVecTile));
       if (tile_arrive(I, I->vtiles, &S.flag)) retire(I, ii, q, ctl);
+    } else if (ph == PH_ADMIT) {
+      phase_admit(q, insts, ii, ctl, lds, &S);
+    } else if (ph == PH_PREPA) {
+      phase_prepa(I, tile);
+      if (tile_arrive(I, I->vtiles, &S.flag)) {
+        if (prep_error(I)) reject(I, ii, q, ctl, MAPI_ERR_ARG);
+        else if (I->nnz > 0) q_push(q, ii, PH_PREPB, (uint32_t)I->etiles, &S.base);
+        else if (I->vtiles == 1) run_init(q, I, ii, 0, ctl, lds, &S);
+        else q_push(q, ii, PH_INIT, (uint32_t)I->vtiles, &S.base);
+      }
+    } else if (ph == PH_PREPB) {
+      phase_prepb(I, tile);
+      if (tile_arrive(I, I->etiles, &S.flag)) {
+        if (prep_error(I)) reject(I, ii, q, ctl, MAPI_ERR_ARG);
+        else if (I->vtiles == 1) run_init(q, I, ii, 0, ctl, lds, &S);
+        else q_push(q, ii, PH_INIT, (uint32_t)I->vtiles, &S.base);
+      }
     }
     __syncthreads();
   }

@@ -1,11 +1,16 @@
 // Serving runtime: continuous batching of MAPI / RPI / PageRank requests on one
-// GPU.  A scheduler thread admits requests while an instance slot and device
-// memory under the budget are free, stages their inputs and writes their first
-// work items into a host-memory inbox that block 0 of the running persistent
-// kernel drains into the device queue; a completion thread reads the kernel's
-// completion records, copies results to the callers' buffers and frees the
-// request's memory.  The kernel is (re)launched from a captured graph whenever
-// admitted work exists and no launch is running.
+// GPU.  A scheduler thread admits requests while an instance slot, device memory
+// under the budget and room for the result in a pinned output pool are free; it
+// writes the request's descriptor into pinned host memory and one ADMIT item into
+// a host-memory inbox that block 0 of the running persistent kernel drains into
+// the device queue.  The kernel itself copies the descriptor, and a PageRank
+// request's CSR arrays from the caller's pinned host memory, and writes the
+// result into the pinned output pool, so admission and completion issue no copy
+// command or kernel: nothing of a request waits behind the long-running kernel
+// on a shared hardware queue.  A completion thread reads the kernel's completion
+// records, copies results to the callers' buffers and frees the request's
+// memory.  The kernel is (re)launched from a captured graph whenever admitted
+// work exists and no launch is running.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -80,9 +85,13 @@ struct Ticket {
   int state = 0;             // 0 queued, 1 admitted, 2 done
   mapi_result res{};
   int slot = -1;
-  size_t off = 0, bytes = 0;
-  float* d_out = nullptr;
+  size_t off = 0, bytes = 0;     // device pool
+  size_t out_off = 0;            // pinned output pool (n floats)
   uint32_t tiles = 0;
+  // served PageRank request: device-accessible addresses of the caller's pinned arrays
+  const int32_t* src_row_ptr = nullptr;
+  const int32_t* src_col = nullptr;
+  const float* src_val = nullptr;
 };
 
 constexpr uint32_t kQueueCap = 1u << 22;
@@ -103,7 +112,12 @@ struct mapi_server {
   BQueue* d_q = nullptr;
   BCtl* d_ctl = nullptr;
   unsigned long long* d_item = nullptr;
-  int32_t* d_err = nullptr;
+  // pinned host: descriptors written at admission, results written by the kernel
+  BInst* h_stage = nullptr;
+  char* out_host = nullptr;
+  char* out_dev = nullptr;   // device-accessible address of out_host
+  size_t out_bytes = 0;
+  Pool out_pool;
   // host-visible (pinned, coherent)
   unsigned long long* inbox = nullptr;
   volatile unsigned long long* inbox_tail = nullptr;
@@ -112,7 +126,7 @@ struct mapi_server {
   BDone* done = nullptr;
   uint32_t done_cap = 0;
   unsigned long long inbox_pos = 0;
-  hipStream_t exec = nullptr, copy = nullptr, out_stream = nullptr;
+  hipStream_t exec = nullptr, copy = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   // bookkeeping
@@ -142,54 +156,55 @@ double ms_since(const mapi_server* s) {
   return std::chrono::duration<double, std::milli>(Clock::now() - s->t0).count();
 }
 
+// Device bytes of a request: its instance buffers plus, for PageRank, the CSR copy.
 size_t request_bytes(const mapi_request& r, const BInst& I, int64_t mbytes) {
-  size_t b = instance_bytes(I, mbytes) + align_up(sizeof(float) * (size_t)I.n);    // + result buffer
+  size_t b = instance_bytes(I, mbytes);
   if (r.prob.kind == MAPI_PROB_CSR)
     b += align_up(sizeof(int32_t) * (size_t)(I.n + 1)) + 2 * align_up(4 * (size_t)r.prob.H.nnz);
   return b;
 }
 
-// Stage one admitted request: copy inputs, write its descriptor, queue its first phase.
+// Device-accessible address of pinned host memory, or NULL when p is not pinned.
+const void* pinned_device_address(const void* p) {
+  if (!p) return nullptr;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (a.type != hipMemoryTypeHost || !a.devicePointer) return nullptr;
+  return a.devicePointer;
+}
+
+// Stage one admitted request: lay out its device buffers, write its descriptor to
+// the pinned staging slot and queue one ADMIT item.  Host memory writes only.
 mapi_status stage(mapi_server* s, Ticket& t, BInst& I, int64_t mbytes) {
   char* base = s->pool_base + t.off;
   char* p = place(&I, base, mbytes);
-  t.d_out = reinterpret_cast<float*>(p);
-  p += align_up(sizeof(float) * (size_t)I.n);
-  I.out = t.d_out;
+  I.out = reinterpret_cast<float*>(s->out_dev + t.out_off);
   const mapi_problem& pr = t.req.prob;
   if (pr.kind == MAPI_PROB_CSR) {
-    int32_t* rp = reinterpret_cast<int32_t*>(p);
+    I.row_ptr = reinterpret_cast<int32_t*>(p);
     p += align_up(sizeof(int32_t) * (size_t)(I.n + 1));
-    int32_t* col = reinterpret_cast<int32_t*>(p);
+    I.col = reinterpret_cast<int32_t*>(p);
     p += align_up(4 * (size_t)pr.H.nnz);
-    float* val = reinterpret_cast<float*>(p);
-    HIP_TRY(hipMemcpyAsync(rp, pr.H.row_ptr, sizeof(int32_t) * (I.n + 1), hipMemcpyHostToDevice, s->copy));
-    if (pr.H.nnz) {
-      HIP_TRY(hipMemcpyAsync(col, pr.H.col, 4 * (size_t)pr.H.nnz, hipMemcpyHostToDevice, s->copy));
-      HIP_TRY(hipMemcpyAsync(val, pr.H.val, 4 * (size_t)pr.H.nnz, hipMemcpyHostToDevice, s->copy));
-    }
-    I.row_ptr = rp;
-    I.col = col;
-    I.val = val;
-    HIP_TRY(hipMemsetAsync(s->d_err, 0, sizeof(int32_t), s->copy));
-    HIP_TRY(launch_csr_prep(rp, col, I.n, pr.H.nnz, const_cast<uint8_t*>(I.dangling), s->d_err, s->copy));
-    int32_t err = 0;
-    HIP_TRY(hipMemcpyAsync(&err, s->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s->copy));
-    HIP_TRY(hipStreamSynchronize(s->copy));
-    if (err) return fail(MAPI_ERR_ARG, "invalid CSR arrays (code %d)", err);
+    I.val = reinterpret_cast<float*>(p);
+    I.src_row_ptr = t.src_row_ptr;
+    I.src_col = t.src_col;
+    I.src_val = t.src_val;
   }
+  I.prep_err = 0;
+  I.arrive = 0;
   I.slot_gen = ++s->slot_gen[t.slot];
-  HIP_TRY(hipMemcpyAsync(s->d_inst + t.slot, &I, sizeof(BInst), hipMemcpyHostToDevice, s->copy));
-  HIP_TRY(hipStreamSynchronize(s->copy));
-  int ph;
-  const uint32_t tiles = first_phase_tiles(I, &ph);
-  while (s->inbox_pos + tiles - *s->inbox_head > kInboxCap) {
+  std::memcpy(&s->h_stage[t.slot], &I, sizeof(BInst));
+  while (s->inbox_pos + 1 - *s->inbox_head > kInboxCap) {
     if (s->stop) return fail(MAPI_ERR_HIP, "server stopping");
     std::this_thread::sleep_for(std::chrono::microseconds(50));
   }
-  for (uint32_t k = 0; k < tiles; ++k) s->inbox[(s->inbox_pos + k) & (kInboxCap - 1)] = bitem((uint32_t)t.slot, ph, k);
+  std::atomic_thread_fence(std::memory_order_seq_cst);     // descriptor before its item
+  s->inbox[s->inbox_pos & (kInboxCap - 1)] = bitem((uint32_t)t.slot, PH_ADMIT, 0);
   std::atomic_thread_fence(std::memory_order_seq_cst);
-  s->inbox_pos += tiles;
+  s->inbox_pos += 1;
   *s->inbox_tail = s->inbox_pos;
   std::atomic_thread_fence(std::memory_order_seq_cst);
   return MAPI_OK;
@@ -236,6 +251,10 @@ void scheduler(mapi_server* s) {
         }
         if (s->free_slots.empty() || s->live_tiles + t->tiles > kQueueCap / 2 || !s->pool.alloc(t->bytes, &t->off))
           break;     // wait for completions to free a slot or memory
+        if (!s->out_pool.alloc(sizeof(float) * (size_t)I.n, &t->out_off)) {
+          s->pool.release(t->off, t->bytes);
+          break;
+        }
         s->queued.pop_front();
         t->slot = s->free_slots.back();
         s->free_slots.pop_back();
@@ -247,6 +266,7 @@ void scheduler(mapi_server* s) {
       std::unique_lock<std::mutex> lk(s->mu);
       if (st != MAPI_OK) {
         s->pool.release(t->off, t->bytes);
+        s->out_pool.release(t->out_off, sizeof(float) * (size_t)I.n);
         s->free_slots.push_back(t->slot);
         s->live -= 1;
         s->live_tiles -= t->tiles;
@@ -296,17 +316,18 @@ void completer(mapi_server* s) {
       }
       const int n = (t->req.prob.kind == MAPI_PROB_CSR) ? (int)t->req.prob.H.n
                     : (t->req.prob.kind == MAPI_PROB_GENERATED ? (int)t->req.prob.gen_n : (int)t->req.prob.A.n_rows);
-      hipError_t e = hipMemcpyAsync(t->req.host_out, t->d_out, sizeof(float) * n, hipMemcpyDeviceToHost, s->out_stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(s->out_stream);
+      // the kernel wrote the result into the pinned output pool (its record follows it)
+      if (rec.status == MAPI_OK) std::memcpy(t->req.host_out, s->out_host + t->out_off, sizeof(float) * (size_t)n);
       std::lock_guard<std::mutex> lk(s->mu);
       t->res.iters = rec.iters;
       t->res.converged = rec.converged;
       t->res.residual = rec.residual;
       t->res.norm = rec.norm;
-      finish_ticket(s, *t, e == hipSuccess ? rec.status : MAPI_ERR_HIP);
+      finish_ticket(s, *t, rec.status);
       s->lat_ms.push_back(t->res.t_done_ms - t->res.t_submit_ms);
       s->last_done = t->res.t_done_ms;
       s->pool.release(t->off, t->bytes);
+      s->out_pool.release(t->out_off, sizeof(float) * (size_t)n);
       s->free_slots.push_back(slot);
       s->live -= 1;
       s->live_tiles -= t->tiles;
@@ -328,11 +349,12 @@ void destroy_resources(mapi_server* s) {
   if (s->graph) (void)hipGraphDestroy(s->graph);
   if (s->exec) (void)hipStreamDestroy(s->exec);
   if (s->copy) (void)hipStreamDestroy(s->copy);
-  if (s->out_stream) (void)hipStreamDestroy(s->out_stream);
   if (s->pool_base) (void)hipFree(s->pool_base);
   if (s->d_inst) (void)hipFree(s->d_inst);
   if (s->inbox) (void)hipHostFree(s->inbox);
   if (s->done) (void)hipHostFree(s->done);
+  if (s->h_stage) (void)hipHostFree(s->h_stage);
+  if (s->out_host) (void)hipHostFree(s->out_host);
   if (s->ctx) mapi_destroy(s->ctx);
 }
 
@@ -361,8 +383,8 @@ mapi_status mapi_serve_create(int device, size_t hbm_budget, const mapi_serve_cf
   s->budget = hbm_budget;
   s->max_slots = (cfg && cfg->max_slots > 0) ? cfg->max_slots : 2048;
   // Three persistent blocks per compute unit leave a quarter of the register file
-  // free, so the admission path's own kernels (CSR validation, fills) run beside
-  // the persistent kernel instead of waiting for it to go idle.
+  // free, so other work on the device (the caller's own kernels) runs beside the
+  // long-lived persistent kernel instead of waiting for it to go idle.
   const int bpc = (cfg && cfg->blocks_per_cu > 0) ? cfg->blocks_per_cu : 3;
   s->blocks = s->ctx->cu_count * bpc;
   s->idle_ms = (cfg && cfg->idle_exit_ms > 0) ? cfg->idle_exit_ms : 20.0;
@@ -382,24 +404,26 @@ mapi_status mapi_serve_create(int device, size_t hbm_budget, const mapi_serve_cf
   const size_t o_q = L.take(sizeof(BQueue));
   const size_t o_ctl = L.take(sizeof(BCtl));
   const size_t o_item = L.take(sizeof(unsigned long long) * kQueueCap);
-  const size_t o_err = L.take(sizeof(int32_t));
   char* dev = nullptr;
   if (hipMalloc(reinterpret_cast<void**>(&dev), L.off) != hipSuccess) return bail(MAPI_ERR_ALLOC, "device control");
   s->d_inst = reinterpret_cast<BInst*>(dev + o_inst);
   s->d_q = reinterpret_cast<BQueue*>(dev + o_q);
   s->d_ctl = reinterpret_cast<BCtl*>(dev + o_ctl);
   s->d_item = reinterpret_cast<unsigned long long*>(dev + o_item);
-  s->d_err = reinterpret_cast<int32_t*>(dev + o_err);
-  // host-visible control: inbox ring, its two positions, quit flag, completion ring
+  // host-visible control: inbox ring, its two positions, quit flag, completion ring,
+  // descriptor staging and the result pool
   s->inbox = static_cast<unsigned long long*>(host_mapped(sizeof(unsigned long long) * (kInboxCap + 32)));
   s->done = static_cast<BDone*>(host_mapped(sizeof(BDone) * s->done_cap));
-  if (!s->inbox || !s->done) return bail(MAPI_ERR_ALLOC, "pinned host memory");
+  s->h_stage = static_cast<BInst*>(host_mapped(sizeof(BInst) * s->max_slots));
+  s->out_bytes = std::min<size_t>(hbm_budget, size_t(1) << 30);
+  s->out_host = static_cast<char*>(host_mapped(s->out_bytes));
+  if (!s->inbox || !s->done || !s->h_stage || !s->out_host) return bail(MAPI_ERR_ALLOC, "pinned host memory");
+  s->out_pool.reset(s->out_bytes);
   s->inbox_tail = s->inbox + kInboxCap;
   s->inbox_head = s->inbox + kInboxCap + 8;
   s->quit = reinterpret_cast<volatile int32_t*>(s->inbox + kInboxCap + 16);
   if (hipStreamCreateWithFlags(&s->exec, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&s->out_stream, hipStreamNonBlocking) != hipSuccess)
+      hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess)
     return bail(MAPI_ERR_HIP, "stream creation");
   BQueue hq{};
   hq.item = s->d_item;
@@ -417,6 +441,10 @@ mapi_status mapi_serve_create(int device, size_t hbm_budget, const mapi_serve_cf
   hc.inbox_mask = kInboxCap - 1;
   if (hipHostGetDevicePointer(&dp, s->done, 0) != hipSuccess) return bail(MAPI_ERR_HIP, "completion mapping");
   hc.done = static_cast<BDone*>(dp);
+  if (hipHostGetDevicePointer(&dp, s->h_stage, 0) != hipSuccess) return bail(MAPI_ERR_HIP, "staging mapping");
+  hc.inst_stage = static_cast<const BInst*>(dp);
+  if (hipHostGetDevicePointer(&dp, s->out_host, 0) != hipSuccess) return bail(MAPI_ERR_HIP, "output mapping");
+  s->out_dev = static_cast<char*>(dp);
   hc.done_mask = s->done_cap - 1;
   if (hipMemsetAsync(s->d_item, 0, sizeof(unsigned long long) * kQueueCap, s->copy) != hipSuccess ||
       hipMemcpyAsync(s->d_q, &hq, sizeof(hq), hipMemcpyHostToDevice, s->copy) != hipSuccess ||
@@ -447,10 +475,23 @@ mapi_status mapi_serve_submit(mapi_server* s, const mapi_request* req, uint64_t*
   mapi_status st = describe(s->ctx, req->prob, &I, &mb);
   if (st != MAPI_OK) return st;
   if (request_bytes(*req, I, mb) > s->budget) return fail(MAPI_ERR_BUDGET, "request needs more than the budget");
+  if (sizeof(float) * (size_t)I.n > s->out_bytes) return fail(MAPI_ERR_BUDGET, "result larger than the output pool");
+  const void* src[3] = {nullptr, nullptr, nullptr};
+  if (req->prob.kind == MAPI_PROB_CSR) {
+    const mapi_csr& H = req->prob.H;
+    src[0] = pinned_device_address(H.row_ptr);
+    src[1] = H.nnz ? pinned_device_address(H.col) : nullptr;
+    src[2] = H.nnz ? pinned_device_address(H.val) : nullptr;
+    if (!src[0] || (H.nnz && (!src[1] || !src[2])))
+      return fail(MAPI_ERR_ARG, "CSR arrays of a served request must be in pinned host memory (hipHostMalloc)");
+  }
   std::lock_guard<std::mutex> lk(s->mu);
   const uint64_t id = s->next_ticket++;
   Ticket& t = s->tickets[id];
   t.req = *req;
+  t.src_row_ptr = static_cast<const int32_t*>(src[0]);
+  t.src_col = static_cast<const int32_t*>(src[1]);
+  t.src_val = static_cast<const float*>(src[2]);
   t.res.t_submit_ms = ms_since(s);
   if (s->first_submit < 0) s->first_submit = t.res.t_submit_ms;
   s->queued.push_back(id);

@@ -112,3 +112,52 @@ def test_serve_invalid_request_fails_alone():
     srv.close()
     assert r_bad["status"] == "ERR_ARG"
     assert r_ok["status"] == "OK" and r_ok["iters"] == 50
+
+
+def test_serve_rejects_pageable_csr_arrays():
+    # the kernel reads a served request's CSR arrays from pinned host memory itself
+    import ctypes as C
+    g = synth.powerlaw_graph(300, seed=4)
+    prob = mp.request_csr_host(g["row_ptr"], g["col"], g["val"], 0.85, "mapi")
+    rp, col, val = (np.ascontiguousarray(g[k]) for k in ("row_ptr", "col", "val"))
+    prob.H = mp.Csr(300, col.size, rp.ctypes.data, col.ctypes.data, val.ctypes.data)   # pageable numpy memory
+    srv = mp.Server(budget_bytes=256 << 20)
+    out = np.zeros(300, np.float32)
+    req = mp.Request(prob, out.ctypes.data)
+    t = C.c_uint64()
+    st = mp.lib().mapi_serve_submit(srv.handle, C.byref(req), C.byref(t))
+    srv.close()
+    assert mp.STATUS.get(st, st) == "ERR_ARG"
+
+
+def test_serve_pagerank_checks_on_device():
+    # row_ptr not ending at nnz, a decreasing row_ptr and an out-of-range column are each
+    # found by the kernel's admission phases; valid requests in the same mix are unaffected
+    g = synth.powerlaw_graph(20000, seed=6)
+    bad = []
+    rp = g["row_ptr"].copy(); rp[-1] -= 1
+    bad.append((rp, g["col"], g["val"]))
+    rp = g["row_ptr"].copy(); rp[100], rp[101] = rp[101], rp[100] - 1
+    bad.append((rp, g["col"], g["val"]))
+    col = g["col"].copy(); col[-1] = -3
+    bad.append((g["row_ptr"], col, g["val"]))
+    srv = mp.Server(budget_bytes=1 << 30)
+    tickets = []
+    for i in range(6):
+        if i % 2:
+            r, c, v = bad[i // 2]
+            tickets.append(("bad", srv.submit(mp.request_csr_host(r, c, v, 0.85, "rpi"), np.zeros(20000, np.float32))))
+        else:
+            out = np.zeros(20000, np.float32)
+            tickets.append(("ok", srv.submit(mp.request_csr_host(g["row_ptr"], g["col"], g["val"], 0.85, "rpi",
+                                                                  max_iters=60, tol=1e-7), out), out))
+    res = [(x[0], srv.wait(x[1], timeout_us=60_000_000)) + tuple(x[2:]) for x in tickets]
+    srv.close()
+    rp_d, col_d, val_d = (torch.from_numpy(g[x]).cuda() for x in ("row_ptr", "col", "val"))
+    w_alone, info = _alone(lambda: mp.problem_csr(rp_d, col_d, val_d, 0.85, "rpi", max_iters=60, tol=1e-7))
+    for r in res:
+        if r[0] == "bad":
+            assert r[1]["status"] == "ERR_ARG"
+        else:
+            assert r[1]["status"] == "OK" and r[1]["iters"] == info["iters"]
+            np.testing.assert_array_equal(r[2], w_alone)
