@@ -273,6 +273,40 @@ def bench_batched(mp, ctx, torch, k=128, seed=5):
     return out
 
 
+def bench_small(mp, ctx, torch, n=256, iters=200, tol=1e-7, seed=SEED, copies=256):
+    """The n=256 covariance (X 256x1024 N(0,1), rows centred, b0 ~ U(-1,1)): 200 iterations or
+    tol 1e-7, MAPI and RPI.  Latency-bound (the matrix is 256 KiB): microseconds per iteration of
+    the plain path, and solves/s of the batched kernel on `copies` instances of the same problem
+    (one block iterates each)."""
+    import synth
+    C = torch.from_numpy(synth.dense_cov(n, 4 * n, seed)).cuda()
+    w0 = torch.from_numpy(synth.start_vector(n, seed + 1)).cuda()
+    out = {"n": n, "max_iters": iters, "tol": tol}
+    for meth in ("mapi", "rpi"):
+        fn = mp.mapi_solve if meth == "mapi" else mp.rpi_solve
+        _, info = fn(C, w0, max_iters=iters, tol=tol, check_every=16, ctx=ctx)
+        reps = 20
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn(C, w0, max_iters=iters, tol=tol, check_every=16, ctx=ctx)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        out[f"{meth}_iters"] = info["iters"]
+        out[f"{meth}_plain_us_per_iter"] = sec / max(info["iters"], 1) * 1e6
+        out[f"{meth}_plain_solves_s"] = 1.0 / sec
+        probs = [mp.problem_dense(C, meth, w0=w0, max_iters=iters, tol=tol) for _ in range(copies)]
+        mp.mapi_solve_batched(probs[:2], ctx=ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mp.mapi_solve_batched(probs, ctx=ctx)
+        torch.cuda.synchronize()
+        out[f"{meth}_batched_solves_s"] = copies / (time.perf_counter() - t0)
+        log(f"small n={n} {meth}: {info['iters']} iterations, {out[f'{meth}_plain_us_per_iter']:.1f} us/iteration, "
+            f"batched {out[f'{meth}_batched_solves_s']:.0f} solves/s")
+    return out
+
+
 def bench_pca(mp, ctx, torch, D=4096, N=65536, k=8, seed=77):
     import synth
     log("PCA: generating X 4096 x 65536 on the GPU")
@@ -458,7 +492,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="bench", choices=["bench", "kernels"])
-    ap.add_argument("--sections", default="batched,pca,pagerank,serving",
+    ap.add_argument("--sections", default="small,batched,pca,pagerank,serving",
                     help="other workloads reported under detail (comma list; empty for none)")
     ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--commands", nargs=3, default=["", "", ""], help="commands that produced the three dirs")
@@ -515,7 +549,8 @@ def main():
     traffic = load_traffic("f32")
 
     sections = [x for x in args.sections.split(",") if x]
-    for name, fn in (("batched", lambda: bench_batched(mp, ctx, torch)), ("pca", lambda: bench_pca(mp, ctx, torch)),
+    for name, fn in (("small", lambda: bench_small(mp, ctx, torch)),
+                     ("batched", lambda: bench_batched(mp, ctx, torch)), ("pca", lambda: bench_pca(mp, ctx, torch)),
                      ("pagerank", lambda: bench_pagerank(mp, ctx, torch)), ("serving", lambda: bench_serving(mp, torch))):
         if name in sections:
             log(f"section {name}")
