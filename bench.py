@@ -307,6 +307,47 @@ def bench_small(mp, ctx, torch, n=256, iters=200, tol=1e-7, seed=SEED, copies=25
     return out
 
 
+def bench_hybrid(mp, ctx, torch, D=16384, seed=31):
+    """The Sec. 3.2 spectrum at D=16384: C = V diag(1, 0.9, ..., 0.9) V^T = 0.9 I + 0.1 v v^T
+    (float32, 1 GiB; top eigenvector v, eigen-gap 0.1) from a random start.  1 - cos^2(w_t, v) after
+    fixed iteration counts for RPI, MAPI and MAPI (5 iterations) -> RPI, as in the paper's
+    comparison figure; every iteration costs one product launch of the same kernel."""
+    import synth
+    v = torch.from_numpy(synth.start_vector(D, seed)).cuda()
+    C = torch.outer(v, v) * 0.1
+    C.diagonal().add_(0.9)
+    w0 = torch.from_numpy(synth.start_vector(D, seed + 1)).cuda()
+    vd = v.double() / torch.linalg.norm(v.double())
+    out = {"D": D, "spectrum": "1, 0.9 (D-1 times)"}
+
+    def gap(w):
+        wd = w.double()
+        c = float(torch.dot(wd, vd) / torch.linalg.norm(wd))
+        return max(0.0, 1.0 - c * c)
+
+    out["rpi"] = {t: gap(mp.rpi_solve(C, w0, max_iters=t, check_every=t, ctx=ctx)[0])
+                  for t in (5, 10, 20, 40, 80, 160, 320)}
+    out["mapi"] = {t: gap(mp.mapi_solve(C, w0, max_iters=t, check_every=t, ctx=ctx)[0]) for t in (1, 2, 3, 5, 10, 20)}
+    out["mapi5_then_rpi"] = {k: gap(mp.mapi_hybrid_solve(C, w0, mapi_iters=5, rpi_iters=k, check_every=8, ctx=ctx)[0])
+                             for k in (0, 5, 10, 20, 40)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mp.rpi_solve(C, w0, max_iters=100, check_every=100, ctx=ctx)
+    torch.cuda.synchronize()
+    out["ms_per_iteration"] = (time.perf_counter() - t0) * 1e3 / 100
+    target = 1e-8
+
+    def first(curve, extra=0):
+        hit = [t for t, g in sorted(curve.items()) if g <= target]
+        return hit[0] + extra if hit else None
+
+    out["iterations_to_1e-8"] = {"rpi": first(out["rpi"]), "mapi": first(out["mapi"]),
+                                 "mapi5_then_rpi": first(out["mapi5_then_rpi"], 5)}
+    log(f"hybrid D={D}: 1-cos2 RPI {out['rpi']}, MAPI {out['mapi']}, MAPI5->RPI {out['mapi5_then_rpi']}")
+    del C
+    return out
+
+
 def bench_pca(mp, ctx, torch, D=4096, N=65536, k=8, seed=77):
     import synth
     log("PCA: generating X 4096 x 65536 on the GPU")
@@ -492,7 +533,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="bench", choices=["bench", "kernels"])
-    ap.add_argument("--sections", default="small,batched,pca,pagerank,serving",
+    ap.add_argument("--sections", default="small,hybrid,batched,pca,pagerank,serving",
                     help="other workloads reported under detail (comma list; empty for none)")
     ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--commands", nargs=3, default=["", "", ""], help="commands that produced the three dirs")
@@ -549,7 +590,7 @@ def main():
     traffic = load_traffic("f32")
 
     sections = [x for x in args.sections.split(",") if x]
-    for name, fn in (("small", lambda: bench_small(mp, ctx, torch)),
+    for name, fn in (("small", lambda: bench_small(mp, ctx, torch)), ("hybrid", lambda: bench_hybrid(mp, ctx, torch)),
                      ("batched", lambda: bench_batched(mp, ctx, torch)), ("pca", lambda: bench_pca(mp, ctx, torch)),
                      ("pagerank", lambda: bench_pagerank(mp, ctx, torch)), ("serving", lambda: bench_serving(mp, torch))):
         if name in sections:

@@ -190,6 +190,17 @@ mapi_status mapi_solve(mapi_ctx* ctx, const mapi_dense* A, const float* w0, floa
 mapi_status rpi_solve(mapi_ctx* ctx, const mapi_dense* A, const float* w0, float* w_out,
                       const mapi_opts* opts, mapi_info* info);
 
+/* MAPI, then RPI from its result (Sec. 3.2: the MAPI iterate keeps the
+ * eigenvector's information and ranks; to drive 1 - cos^2 to the top
+ * eigenvector towards 0, optimise with MAPI first and switch to RPI).  Runs
+ * mapi_solve with first_opts (final_l2 forced on: the hand-over vector has unit
+ * l2 norm, kept in a context buffer), then rpi_solve from that vector with
+ * then_opts into w_out.  info_mapi / info_rpi (optional, host) report each phase;
+ * errors of either phase are returned as by mapi_solve and rpi_solve.          */
+mapi_status mapi_hybrid_solve(mapi_ctx* ctx, const mapi_dense* A, const float* w0, float* w_out,
+                              const mapi_opts* first_opts, const mapi_opts* then_opts, mapi_info* info_mapi,
+                              mapi_info* info_rpi);
+
 /* ---------------------------------------------------------------- storage */
 
 /* Convert a float32 matrix (n_rows x n_cols, leading dimension lda) to reduced

@@ -18,7 +18,7 @@ whose parity is unpinned.
 from .core import (  # noqa: F401
     OracleDegenerate,
     term_min1, term_min2, term_diamond, term_dot, TERMS,
-    vec_product, mavp, mapi, rpi, normalize_l2, ranks,
+    vec_product, mavp, mapi, rpi, hybrid, normalize_l2, ranks,
 )
 from .pca import covariance, mingram, mingram_entry, deflate_projection, pca_topk  # noqa: F401
 from .pagerank import (  # noqa: F401

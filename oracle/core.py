@@ -166,6 +166,17 @@ def rpi(A, b0, T, tol=0.0, norm="l2", final_l2=False):
     return res
 
 
+def hybrid(A, w0, T_mapi, T_rpi, tol_mapi=0.0, tol_rpi=0.0, op="min1", final_l2=False):
+    """MAPI, then RPI started from its result (Sec. 3.2, end of the comparison with
+    stochastic PCA: to drive 1 - cos^2 to the top eigenvector towards zero, optimise
+    with MAPI first and switch to RPI).  The MAPI result is divided by its l2 norm
+    (Algorithm 1, last step) before it seeds eq. (1).  Returns (mapi result, rpi result).
+    """
+    m = mapi(A, w0, T_mapi, tol_mapi, op=op, final_l2=True)
+    r = rpi(A, m.w, T_rpi, tol_rpi, final_l2=final_l2)
+    return m, r
+
+
 def ranks(w):
     """1-based indices of w ordered from its largest entry to its smallest.
 

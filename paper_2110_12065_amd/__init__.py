@@ -95,6 +95,8 @@ _SIGS = {
                                 C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]),
     "mapi_pagerank": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
                                 C.POINTER(Opts), C.POINTER(Info)]),
+    "mapi_hybrid_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts),
+                                    C.POINTER(Opts), C.POINTER(Info), C.POINTER(Info)]),
 }
 
 
@@ -263,6 +265,25 @@ def rpi_solve(A, w0, max_iters=100, tol=0.0, final_l2=False, check_every=0, stal
     """RPI (eq. 1) on a square dense matrix.  Returns (w, info)."""
     return _solve(lib().rpi_solve, A, w0, max_iters, tol, "dot", final_l2, check_every, stall_iters, row_scale,
                   w_out, ctx)
+
+
+def mapi_hybrid_solve(A, w0, mapi_iters=100, mapi_tol=0.0, rpi_iters=100, rpi_tol=0.0, op="min1",
+                      final_l2=False, check_every=0, stall_iters=0, row_scale=None, w_out=None, ctx=None):
+    """MAPI (to mapi_iters / mapi_tol), then RPI from its l2-normalised result (to rpi_iters /
+    rpi_tol).  Returns (w, info_mapi, info_rpi)."""
+    import torch
+    c = _ctx_of(ctx, A)
+    d = _dense(A, row_scale)
+    n = A.shape[0]
+    if w_out is None:
+        w_out = torch.empty(n, dtype=torch.float32, device=A.device)
+    o1 = _opts(mapi_iters, mapi_tol, op, True, check_every, stall_iters)
+    o2 = _opts(rpi_iters, rpi_tol, "dot", final_l2, check_every, stall_iters)
+    i1, i2 = Info(), Info()
+    _check(lib().mapi_hybrid_solve(c.handle, C.byref(d), C.c_void_p(_vec(w0, n, "w0")),
+                                   C.c_void_p(_vec(w_out, n, "w_out")), C.byref(o1), C.byref(o2),
+                                   C.byref(i1), C.byref(i2)))
+    return w_out, i1.as_dict(), i2.as_dict()
 
 
 def mapi_quantize(A, dtype, ctx=None):

@@ -241,6 +241,7 @@ void mapi_destroy(mapi_ctx* c) {
   for (auto e : c->pool) (void)hipEventDestroy(e);
   if (c->ws) (void)hipFree(c->ws);
   if (c->big) (void)hipFree(c->big);
+  if (c->mid) (void)hipFree(c->mid);
   mapi_batch_release(c);
   if (c->st_host) (void)hipHostFree(c->st_host);
   delete c;
@@ -440,6 +441,23 @@ mapi_status rpi_solve(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
   if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
   HIP_TRY(hipSetDevice(c->device));
   return run_dense(c, A, w0, w_out, opts, info, true);
+}
+
+mapi_status mapi_hybrid_solve(mapi_ctx* c, const mapi_dense* A, const float* w0, float* w_out,
+                              const mapi_opts* mapi_o, const mapi_opts* rpi_o, mapi_info* info_mapi,
+                              mapi_info* info_rpi) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  mapi_status s;
+  if ((s = check_dense(A, true)) != MAPI_OK) return s;
+  if ((s = check_opts(mapi_o)) != MAPI_OK) return s;
+  if ((s = check_opts(rpi_o)) != MAPI_OK) return s;
+  HIP_TRY(hipSetDevice(c->device));
+  if ((s = ensure(&c->mid, &c->mid_bytes, sizeof(float) * (size_t)A->n_rows, c)) != MAPI_OK) return s;
+  float* mid = static_cast<float*>(c->mid);
+  mapi_opts o1 = *mapi_o;
+  o1.final_l2 = 1;     // the hand-over vector has unit l2 norm
+  if ((s = run_dense(c, A, w0, mid, &o1, info_mapi, false)) != MAPI_OK) return s;
+  return run_dense(c, A, mid, w_out, rpi_o, info_rpi, true);
 }
 
 mapi_status mapi_quantize(mapi_ctx* c, const float* A, int64_t n_rows, int64_t n_cols, int64_t lda, int32_t dtype,

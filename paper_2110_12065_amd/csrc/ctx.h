@@ -56,6 +56,9 @@ struct mapi_ctx {
   // matrices owned by the PCA driver
   void* big = nullptr;
   size_t big_bytes = 0;
+  // intermediate iterate of the MAPI -> RPI hybrid
+  void* mid = nullptr;
+  size_t mid_bytes = 0;
   // timing
   bool timing = false;
   struct Rec { int kind; hipEvent_t a, b; };

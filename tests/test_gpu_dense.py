@@ -273,3 +273,39 @@ def test_sign_word_staging_rejected_for_other_storage():
     shape = dict(rows_per_wave=1, waves=4, blocks_per_cu=1, unroll=2, w_in_lds=2, nontemporal=0)
     with pytest.raises(mp.MapiError):
         mp.mapi_mavp_timed(A, w, shape, reps=1)
+
+
+def _sec32_matrix(D, seed):
+    # the Sec. 3.2 spectrum: C = V diag(1, 0.9, ..., 0.9) V^T = 0.9 I + 0.1 v v^T, top eigenvector v
+    v = synth.start_vector(D, seed).astype(np.float64)
+    return (0.9 * np.eye(D) + 0.1 * np.outer(v, v)).astype(np.float32), v
+
+
+def test_hybrid_matches_chained_calls_and_oracle():
+    D = 300
+    C, v = _sec32_matrix(D, 21)
+    w0 = synth.start_vector(D, 22)
+    Cd, wd = to_dev(C), to_dev(w0)
+    w, im, ir = mp.mapi_hybrid_solve(Cd, wd, mapi_iters=40, mapi_tol=1e-7, rpi_iters=60, rpi_tol=1e-7)
+    assert im["iters"] >= 1 and ir["iters"] >= 1
+    # the same as mapi_solve (final l2) followed by rpi_solve
+    m1, i1 = mp.mapi_solve(Cd, wd, max_iters=40, tol=1e-7, final_l2=True)
+    r1, i2 = mp.rpi_solve(Cd, m1, max_iters=60, tol=1e-7)
+    assert (i1["iters"], i2["iters"]) == (im["iters"], ir["iters"])
+    np.testing.assert_array_equal(w.cpu().numpy(), r1.cpu().numpy())
+    # parity with the oracle at the GPU's iteration counts
+    m, r = oracle.hybrid(C.astype(np.float64), w0, im["iters"], ir["iters"])
+    e, c = report("hybrid D=300", w.cpu().numpy(), r.w)
+    assert e <= TOL and c > COS
+    cos = abs(float(r.w @ v)) / np.linalg.norm(r.w)
+    assert 1 - cos * cos < 1e-9
+
+
+def test_hybrid_zero_mapi_iterations_is_rpi():
+    D = 257
+    C, _ = _sec32_matrix(D, 23)
+    w0 = synth.start_vector(D, 24)
+    w, im, ir = mp.mapi_hybrid_solve(to_dev(C), to_dev(w0), mapi_iters=0, rpi_iters=30)
+    b, _ = mp.rpi_solve(to_dev(C), to_dev(w0 / np.float32(np.linalg.norm(w0))), max_iters=30)
+    assert im["iters"] == 0 and ir["iters"] == 30
+    np.testing.assert_array_equal(w.cpu().numpy(), b.cpu().numpy())

@@ -213,3 +213,29 @@ def test_printed_vectors_are_l2_normalised():
         w = np.array(item["w"])
         slack = 0.0005 * np.abs(w).sum() * 2 + 1e-3
         assert abs(np.linalg.norm(w) - 1.0) < slack, key
+
+
+def test_hybrid_without_mapi_steps_is_rpi_from_the_start_direction():
+    # zero MAPI iterations hand over w0 / ||w0||_2; eq. (1) is invariant to a positive scale of
+    # its start, so the hybrid is RPI from w0 (the MAPI phase is then the identity)
+    A, Q, d = synth.planted_symmetric(40, [0.3], seed=7)
+    w0 = synth.start_vector(40, 8).astype(np.float64) * 3.7
+    m, r = oracle.hybrid(A, w0, 0, 25)
+    ref = oracle.rpi(A, w0, 25)
+    assert m.iters == 0
+    np.testing.assert_allclose(m.w, w0 / np.linalg.norm(w0), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(r.w, ref.w, rtol=0, atol=1e-12)
+
+
+def test_hybrid_hands_over_the_unit_l2_mapi_iterate_and_reaches_the_eigenvector():
+    A, Q, d = synth.planted_symmetric(64, [0.2], seed=11)
+    A = np.abs(A) + 0.05          # positive entries: min1 iterates keep the sign structure of eq. (1)
+    lam, V = np.linalg.eigh(A.astype(np.float64))
+    u = V[:, -1]
+    w0 = np.abs(synth.start_vector(64, 12)).astype(np.float64)
+    m, r0 = oracle.hybrid(A, w0, 30, 0)
+    assert abs(np.linalg.norm(m.w) - 1.0) < 1e-15 and r0.iters == 0
+    np.testing.assert_allclose(r0.w, m.w, rtol=0, atol=0)
+    m, r = oracle.hybrid(A, w0, 30, 400, tol_rpi=1e-14)
+    cos = abs(float(r.w @ u)) / np.linalg.norm(r.w)
+    assert 1.0 - cos * cos < 1e-14      # float64 resolution of cos near 1
