@@ -25,6 +25,7 @@ from .pagerank import (  # noqa: F401
     dangling_mask, dense_G, pagerank_mavp_dense, pagerank_mavp_csr,
     pagerank_rpi_csr, pagerank,
 )
+from .minibatch import minibatch_mapi  # noqa: F401
 from .quant import (  # noqa: F401
     bf16_decode, bf16_encode, e4m3fn_table, e4m3fn_decode, e4m3fn_encode,
     fp8_rows_quantize, fp8_rows_dequantize, bf16_quantize, bf16_dequantize,
