@@ -348,6 +348,36 @@ def bench_hybrid(mp, ctx, torch, D=16384, seed=31):
     return out
 
 
+def bench_minibatch(mp, ctx, torch, N=10 ** 6, D=10, s=1000, T=100, runs=256, seed=41):
+    """Algorithm 3 on the Sec. 3.2 construction (N = 10^6 samples, D = 10, eigen-gap 0.1):
+    `runs` independent runs (own batches and start vectors), one block each, with and without
+    momentum, min1 (Algorithm 3) and dot (the stochastic power method it modifies).  Reports
+    samples/s, batch-matrix terms/s and the mean 1 - cos^2 of w_T to the top eigenvector."""
+    import synth
+    X, v1 = synth.sec32_data(N, D, seed)
+    Xd = torch.from_numpy(X).cuda()
+    B = torch.from_numpy(synth.minibatch_indices(runs, T, s, N, seed + 1)).cuda()
+    W0 = torch.from_numpy(np.stack([synth.start_vector(D, seed + 2 + r) for r in range(runs)])).cuda()
+    vd = torch.from_numpy(v1).cuda()
+    out = {"N": N, "D": D, "s": s, "T": T, "runs": runs}
+    for op in ("min1", "dot"):
+        for beta in (0.0, 0.2):
+            mp.mapi_minibatch(Xd, B[:2], beta, W0[:2], op=op, ctx=ctx)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            W, _ = mp.mapi_minibatch(Xd, B, beta, W0, op=op, final_l2=True, ctx=ctx)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            cos = (W.double() @ vd).abs()
+            key = f"{op}_beta{beta}"
+            out[key] = {"ms": sec * 1e3, "samples_s": runs * T * s / sec, "terms_s": runs * T * s * D * D / sec,
+                        "mean_one_minus_cos2": float((1 - cos * cos).mean()),
+                        "median_one_minus_cos2": float((1 - cos * cos).median())}
+            log(f"minibatch {key}: {sec * 1e3:.2f} ms, {runs * T * s / sec / 1e9:.2f} G samples/s, "
+                f"median 1-cos2 {out[key]['median_one_minus_cos2']:.2e}")
+    return out
+
+
 def bench_pca(mp, ctx, torch, D=4096, N=65536, k=8, seed=77):
     import synth
     log("PCA: generating X 4096 x 65536 on the GPU")
@@ -533,7 +563,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="bench", choices=["bench", "kernels"])
-    ap.add_argument("--sections", default="small,hybrid,batched,pca,pagerank,serving",
+    ap.add_argument("--sections", default="small,hybrid,minibatch,batched,pca,pagerank,serving",
                     help="other workloads reported under detail (comma list; empty for none)")
     ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--commands", nargs=3, default=["", "", ""], help="commands that produced the three dirs")
@@ -591,6 +621,7 @@ def main():
 
     sections = [x for x in args.sections.split(",") if x]
     for name, fn in (("small", lambda: bench_small(mp, ctx, torch)), ("hybrid", lambda: bench_hybrid(mp, ctx, torch)),
+                     ("minibatch", lambda: bench_minibatch(mp, ctx, torch)),
                      ("batched", lambda: bench_batched(mp, ctx, torch)), ("pca", lambda: bench_pca(mp, ctx, torch)),
                      ("pagerank", lambda: bench_pagerank(mp, ctx, torch)), ("serving", lambda: bench_serving(mp, torch))):
         if name in sections:

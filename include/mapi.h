@@ -121,7 +121,8 @@ typedef enum mapi_kernel_kind {
   MAPI_K_CSR = 3,            /* PageRank product kernel                        */
   MAPI_K_DEFLATE = 4,        /* deflation kernels                              */
   MAPI_K_BATCHED = 5,        /* persistent batched kernel                      */
-  MAPI_K_KINDS = 6
+  MAPI_K_MINIBATCH = 6,      /* mini-batch MAPI with momentum kernel           */
+  MAPI_K_KINDS = 7
 } mapi_kernel_kind;
 mapi_status mapi_timing_enable(mapi_ctx* ctx, int enable);
 mapi_status mapi_timing_get(mapi_ctx* ctx, int kind, double* total_ms, int64_t* launches);
@@ -200,6 +201,27 @@ mapi_status rpi_solve(mapi_ctx* ctx, const mapi_dense* A, const float* w0, float
 mapi_status mapi_hybrid_solve(mapi_ctx* ctx, const mapi_dense* A, const float* w0, float* w_out,
                               const mapi_opts* first_opts, const mapi_opts* then_opts, mapi_info* info_mapi,
                               mapi_info* info_rpi);
+
+/* Mini-batch MAPI with momentum (Algorithm 3, Sec. 3.2), `runs` independent runs
+ * (one GPU block each).  Run r iterates T times: with the batch
+ * B_t = batch_idx[(r T + t) s .. + s) of sample indices,
+ *   A_t = (1/s) sum_{i in B_t} x_i (+) x_i^T          (eq. 5 on the batch)
+ *   w_{t+1} = A_t (+) w_t - beta w_{t-1},  w_{-1} = 0
+ *   nu = ||w_{t+1}||_1;  w_t <- w_t / nu;  w_{t+1} <- w_{t+1} / nu
+ * and writes w_T (divided by its l2 norm when final_l2) to w_out + r D.
+ * op MAPI_OP_MIN1 (Algorithm 3) or MAPI_OP_DOT (the same recurrence with
+ * ordinary products: the stochastic power method with momentum).
+ * X: device float32 N x D, samples as ROWS (Algorithm 3's layout), row pitch
+ * ldx >= D elements.  batch_idx: device int32, runs * T * s entries in [0, N)
+ * (the mini batches are drawn by the caller; NULL allowed when T = 0); an index outside gives
+ * MAPI_ERR_ARG and is never used as an address.  w0 / w_out: device float32,
+ * runs * D.  Batch sums are float64 (stored float32), the product float32, nu
+ * float64.  D <= 64 (MAPI_ERR_UNSUPPORTED beyond).  infos (optional, host, runs
+ * entries): iterations run, last nu, status; a zero or non-finite nu stops that
+ * run with MAPI_ERR_DEGENERATE (also returned).                                  */
+mapi_status mapi_minibatch(mapi_ctx* ctx, const float* X, int64_t N, int64_t D, int64_t ldx, const int32_t* batch_idx,
+                           int32_t s, int32_t T, double beta, int32_t op, int32_t runs, const float* w0, float* w_out,
+                           int32_t final_l2, mapi_info* infos);
 
 /* ---------------------------------------------------------------- storage */
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmapi.so")
 MAPI_F32, MAPI_BF16, MAPI_FP8_E4M3 = 0, 1, 2
 OPS = {"min1": 0, "min2": 1, "diamond": 2, "dot": 3}
 METHODS = {"mapi": 0, "rpi": 1}
-KERNELS = {"mavp": 0, "finalize": 1, "gram": 2, "csr": 3, "deflate": 4, "batched": 5}
+KERNELS = {"mavp": 0, "finalize": 1, "gram": 2, "csr": 3, "deflate": 4, "batched": 5, "minibatch": 6}
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_ALLOC", 3: "ERR_HIP", 4: "ERR_DEGENERATE", 5: "ERR_BUDGET",
           6: "ERR_UNSUPPORTED", 7: "ERR_PENDING", 8: "ERR_TIMEOUT"}
 
@@ -97,6 +97,9 @@ _SIGS = {
                                 C.POINTER(Opts), C.POINTER(Info)]),
     "mapi_hybrid_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts),
                                     C.POINTER(Opts), C.POINTER(Info), C.POINTER(Info)]),
+    "mapi_minibatch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_int32,
+                                 C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                 C.c_void_p]),
 }
 
 
@@ -284,6 +287,29 @@ def mapi_hybrid_solve(A, w0, mapi_iters=100, mapi_tol=0.0, rpi_iters=100, rpi_to
                                    C.c_void_p(_vec(w_out, n, "w_out")), C.byref(o1), C.byref(o2),
                                    C.byref(i1), C.byref(i2)))
     return w_out, i1.as_dict(), i2.as_dict()
+
+
+def mapi_minibatch(X, batches, beta, W0, op="min1", final_l2=False, w_out=None, ctx=None):
+    """Mini-batch MAPI with momentum (Algorithm 3).  X: device float32 N x D, samples as rows;
+    batches: device int32 (runs, T, s) sample indices; W0: device float32 (runs, D).
+    Returns (W (runs, D), infos)."""
+    import torch
+    c = _ctx_of(ctx, X)
+    if X.dim() != 2 or X.dtype != torch.float32 or X.stride(1) != 1:
+        raise ValueError("X must be a float32 N x D tensor with unit column stride")
+    if batches.dim() != 3 or batches.dtype != torch.int32 or not batches.is_contiguous():
+        raise ValueError("batches must be a contiguous int32 tensor of shape (runs, T, s)")
+    runs, T, s = batches.shape
+    N, D = X.shape
+    if tuple(W0.shape) != (runs, D) or W0.dtype != torch.float32 or not W0.is_contiguous():
+        raise ValueError("W0 must be a contiguous float32 tensor of shape (runs, D)")
+    if w_out is None:
+        w_out = torch.empty((runs, D), dtype=torch.float32, device=X.device)
+    infos = (Info * runs)()
+    _check(lib().mapi_minibatch(c.handle, C.c_void_p(X.data_ptr()), int(N), int(D), int(X.stride(0)),
+                                C.c_void_p(batches.data_ptr()), int(s), int(T), float(beta), OPS[op], int(runs),
+                                C.c_void_p(W0.data_ptr()), C.c_void_p(w_out.data_ptr()), int(bool(final_l2)), infos))
+    return w_out, [i.as_dict() for i in infos]
 
 
 def mapi_quantize(A, dtype, ctx=None):

@@ -554,6 +554,53 @@ mapi_status mapi_pca_topk(mapi_ctx* c, const float* X, int64_t D, int64_t N, int
   return MAPI_OK;
 }
 
+mapi_status mapi_minibatch(mapi_ctx* c, const float* X, int64_t N, int64_t D, int64_t ldx, const int32_t* batch_idx,
+                           int32_t s, int32_t T, double beta, int32_t op, int32_t runs, const float* w0, float* w_out,
+                           int32_t final_l2, mapi_info* infos) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  if (!X || (!batch_idx && T > 0) || !w0 || !w_out)
+    return fail(MAPI_ERR_ARG, "X, batch_idx (when T > 0), w0 and w_out must be device pointers");
+  if (N <= 0 || D <= 0 || ldx < D) return fail(MAPI_ERR_ARG, "bad shape");
+  if (D > minibatch_max_d()) return fail(MAPI_ERR_UNSUPPORTED, "D > %d", minibatch_max_d());
+  if (s < 1 || T < 0 || runs < 1) return fail(MAPI_ERR_ARG, "s >= 1, T >= 0 and runs >= 1 are required");
+  if (op != MAPI_OP_MIN1 && op != MAPI_OP_DOT) return fail(MAPI_ERR_ARG, "op must be MAPI_OP_MIN1 or MAPI_OP_DOT");
+  if (!(std::fabs(beta) < INFINITY)) return fail(MAPI_ERR_ARG, "beta must be finite");
+  HIP_TRY(hipSetDevice(c->device));
+  Layout L;
+  const size_t o_run = L.take(sizeof(MbRun) * (size_t)runs);
+  const size_t o_bad = L.take(sizeof(int32_t));
+  mapi_status st;
+  if ((st = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return st;
+  char* base = static_cast<char*>(c->ws);
+  int32_t* bad = reinterpret_cast<int32_t*>(base + o_bad);
+  HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int32_t), c->stream));
+  {
+    Timed tm(c, MAPI_K_MINIBATCH);
+    HIP_TRY(launch_minibatch(X, N, (int)D, ldx, batch_idx, s, T, (float)beta, op, runs, w0, w_out, final_l2,
+                             reinterpret_cast<MbRun*>(base + o_run), bad, c->stream));
+  }
+  std::vector<MbRun> host(runs);
+  int32_t bad_h = 0;
+  HIP_TRY(hipMemcpyAsync(host.data(), base + o_run, sizeof(MbRun) * (size_t)runs, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(&bad_h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  collect_timing(c);
+  if (bad_h) return fail(MAPI_ERR_ARG, "a batch index is outside [0, N)");
+  mapi_status worst = MAPI_OK;
+  for (int r = 0; r < runs; ++r) {
+    if (infos) {
+      infos[r].iters = host[r].iters;
+      infos[r].converged = 0;
+      infos[r].residual = 0.0;
+      infos[r].norm = host[r].nu;
+      infos[r].status = host[r].status;
+    }
+    if (host[r].status != MAPI_OK) worst = (mapi_status)host[r].status;
+  }
+  if (worst != MAPI_OK) return fail(worst, "at least one run stopped on a zero or non-finite normaliser (see infos)");
+  return MAPI_OK;
+}
+
 mapi_status mapi_pagerank(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t method, const float* w0,
                           float* w_out, const mapi_opts* o, mapi_info* info) {
   if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");

@@ -210,4 +210,14 @@ int pr_scalar_blocks(int64_t n);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, int cu_count, hipStream_t s);
 
+// Per-run outcome of the mini-batch kernel.
+struct MbRun {
+  int32_t iters, status;
+  double nu;       // last normaliser
+};
+int minibatch_max_d();
+hipError_t launch_minibatch(const float* X, int64_t N, int D, int64_t ldx, const int32_t* idx, int s, int T, float beta,
+                            int op, int runs, const float* w0, float* w_out, int final_l2, MbRun* run_info,
+                            int32_t* bad_index, hipStream_t st);
+
 }  // namespace mapi

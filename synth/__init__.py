@@ -263,3 +263,37 @@ def generated_dense(n, seed):
     inv = np.float32(1.0 / np.sqrt(float(n)))
     w0 = np.where((_counter(vbase, idx) >> _U64(63)).astype(bool), -inv, inv).astype(np.float32)
     return A.astype(np.float32), w0
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.2 construction (stochastic PCA comparison) and mini-batch indices
+# --------------------------------------------------------------------------
+def sec32_data(N, D, seed, gap=0.1):
+    """X = sqrt(N) U Sigma V^T of shape N x D (samples as rows), float32, with U (N x D) and V
+    (D x D) having orthonormal columns and Sigma = diag(1, sqrt(1-gap), ..., sqrt(1-gap)), so
+    that the covariance X^T X / N of eq. (2) is V diag(1, 1-gap, ...) V^T, with eigen-gap `gap`
+    and top eigenvector V[:, 0] (Sec. 3.2: N = 10^6, D = 10, gap 0.1).  The sqrt(N) puts the
+    samples on a unit scale (entries ~ 1), comparable to an l1-normalised iterate in D = 10:
+    the operator of eq. (3) is only jointly homogeneous, and with entries ~ 1e-3 the product
+    would see only the signs of w.  Returns (X, v1) with v1 float64.
+
+    Draw order: G = rng.standard_normal((N, D)); U from numpy's QR of G (signs fixed by
+    diag R); H = rng.standard_normal((D, D)); V from the QR of H likewise.
+    """
+    rng = _rng(seed)
+    G = rng.standard_normal((N, D))
+    U, R = np.linalg.qr(G)
+    U = U * np.sign(np.diag(R))[None, :]
+    H = rng.standard_normal((D, D))
+    V, R2 = np.linalg.qr(H)
+    V = V * np.sign(np.diag(R2))[None, :]
+    sig = np.full(D, np.sqrt(1.0 - gap))
+    sig[0] = 1.0
+    X = np.sqrt(N) * ((U * sig[None, :]) @ V.T)
+    return X.astype(np.float32), V[:, 0].copy()
+
+
+def minibatch_indices(runs, T, s, N, seed):
+    """I.i.d. uniform sample indices in [0, N) for Algorithm 3's mini batches, int32 of shape
+    (runs, T, s): rng.integers(0, N, size=(runs, T, s))."""
+    return _rng(seed).integers(0, N, size=(runs, T, s)).astype(np.int32)

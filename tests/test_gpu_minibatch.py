@@ -1,0 +1,82 @@
+"""GPU parity of mini-batch MAPI with momentum (Algorithm 3) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import cosine, rel_l1, report, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2110_12065_amd as mp  # noqa: E402
+
+TOL = 1e-5
+COS = 1 - 1e-6
+
+
+def _run(X, batches, beta, W0, op="min1", final_l2=False):
+    Xd = to_dev(X)                 # rows padded to a 16-byte pitch: exercises ldx > D
+    W, infos = mp.mapi_minibatch(Xd, torch.from_numpy(batches).cuda(), beta, torch.from_numpy(W0).cuda(), op=op,
+                                 final_l2=final_l2)
+    return W.cpu().numpy(), infos
+
+
+@pytest.mark.parametrize("D,s,T,beta,op", [(1, 3, 5, 0.0, "min1"), (10, 7, 25, 0.2, "min1"), (37, 130, 9, 0.1, "min1"),
+                                           (64, 40, 6, 0.3, "min1"), (10, 7, 25, 0.2, "dot"), (23, 1, 12, 0.0, "min1"),
+                                           (16, 5, 0, 0.2, "min1")])
+def test_minibatch_matches_oracle(D, s, T, beta, op):
+    print(f"[case] minibatch D={D} s={s} T={T} beta={beta} {op}", flush=True)
+    rng = np.random.default_rng(D * 100 + s)
+    N = 500
+    X = rng.standard_normal((N, D)).astype(np.float32)
+    runs = 3
+    batches = synth.minibatch_indices(runs, T, s, N, seed=D + s)
+    W0 = np.stack([synth.start_vector(D, 50 + r) for r in range(runs)])
+    W, infos = _run(X, batches, beta, W0, op=op, final_l2=(T % 2 == 1))
+    for r in range(runs):
+        assert infos[r]["iters"] == T and infos[r]["status"] == "OK"
+        ref = oracle.minibatch_mapi(X.T.astype(np.float64), batches[r], beta, W0[r].astype(np.float64),
+                                    final_l2=(T % 2 == 1), op=op)
+        if T == 0:
+            np.testing.assert_array_equal(W[r], W0[r])
+            continue
+        e, c = report(f"minibatch run {r}", W[r], ref.w)
+        assert e <= TOL and c > COS
+
+
+def test_minibatch_sec32_full_size_against_oracle():
+    # Sec. 3.2: N = 10^6 samples, D = 10, eigen-gap 0.1; s = 1000, beta = 0.2 (each iteration
+    # touches only its batch, so the oracle runs the full-size problem).  T = 20: the momentum
+    # recurrence amplifies float32-size perturbations of X in the float64 oracle itself from 3e-7
+    # (T = 20) to 3e-5 (T = 40) relative l1, so 1e-5 parity is a meaningful bar up to T ~ 20 here.
+    N, D, s, T = 10 ** 6, 10, 1000, 20
+    X, v1 = synth.sec32_data(N, D, seed=9)
+    batches = synth.minibatch_indices(2, T, s, N, seed=10)
+    W0 = np.stack([synth.start_vector(D, 11 + r) for r in range(2)])
+    W, infos = _run(X, batches, 0.2, W0, final_l2=True)
+    for r in range(2):
+        ref = oracle.minibatch_mapi(X.T.astype(np.float64), batches[r], 0.2, W0[r].astype(np.float64), final_l2=True)
+        e, c = report(f"sec32 run {r}", W[r], ref.w)
+        assert e <= TOL and c > COS
+        gap = 1 - cosine(W[r], v1) ** 2
+        print(f"[sec32] run {r}: 1 - cos^2 to v1 = {gap:.3e}", flush=True)
+        assert gap < 0.5         # near v1, not at it: the pseudo-eigenvector of the noisy batches (Fig. 4)
+
+
+def test_minibatch_errors():
+    X = to_dev(np.ones((20, 4), np.float32))
+    W0 = torch.full((1, 4), 0.25, dtype=torch.float32, device="cuda")
+    bad = torch.tensor([[[0, 20]]], dtype=torch.int32, device="cuda")
+    with pytest.raises(mp.MapiError) as ei:
+        mp.mapi_minibatch(X, bad, 0.0, W0)
+    assert ei.value.status == 1
+    X65 = to_dev(np.ones((20, 65), np.float32))
+    with pytest.raises(mp.MapiError) as ei:
+        mp.mapi_minibatch(X65, torch.zeros((1, 1, 1), dtype=torch.int32, device="cuda"), 0.0,
+                          torch.ones((1, 65), dtype=torch.float32, device="cuda"))
+    assert ei.value.status == 6
+    Z = to_dev(np.zeros((20, 4), np.float32))
+    with pytest.raises(mp.MapiError) as ei:
+        mp.mapi_minibatch(Z, torch.zeros((1, 2, 3), dtype=torch.int32, device="cuda"), 0.0, W0)
+    assert ei.value.status == 4

@@ -64,3 +64,17 @@ def test_laplace_from_uniform_is_finite_and_laplace():
     g = torch.Generator().manual_seed(3)
     s = synth.laplace_from_uniform(torch.rand(200000, generator=g), 2.0).double()
     assert abs(float(s.mean())) < 0.03 and abs(float(s.abs().mean()) - 2.0) < 0.03
+
+
+def test_sec32_data_has_the_stated_spectrum():
+    X, v1 = synth.sec32_data(5000, 10, seed=2)
+    C = X.astype(np.float64).T @ X.astype(np.float64) / 5000
+    lam, V = np.linalg.eigh(C)
+    np.testing.assert_allclose(lam[::-1], [1.0] + [0.9] * 9, atol=1e-5)
+    assert abs(abs(V[:, -1] @ v1) - 1.0) < 1e-9
+
+
+def test_minibatch_indices_range_and_shape():
+    b = synth.minibatch_indices(3, 4, 5, 17, seed=1)
+    assert b.shape == (3, 4, 5) and b.dtype == np.int32
+    assert b.min() >= 0 and b.max() < 17
