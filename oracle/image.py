@@ -1,0 +1,73 @@
+"""Image reconstruction via MAPI (Algorithm 2, Sec. 3.1).
+
+Test infrastructure only (see the package docstring).
+
+Pins (tests/test_oracle_image.py):
+  * min_outer: the diagonal of W (+) W^T is sum_k |W_jk| (the l1 identity of Sec. 2.1),
+    the matrix is symmetric, and for columns of constant modulus c it equals
+    c * sign(W) sign(W)^T (numpy matmul).
+  * image_reconstruct with method "rpi": the two vectors span the top-2 eigenspace of the
+    covariance (numpy.linalg.eigh) and the reconstruction equals the projection of every
+    centred image onto that space plus the mean.
+Parity unpinned: the MAPI vectors and reconstruction beyond those invariants.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .core import F64, term_min1, TERMS, mapi, rpi, normalize_l2
+from .pca import covariance, mingram
+
+
+def min_outer(W, op="min1"):
+    """(W (+) W^T)_jl = sum_k op(W_jk, W_lk): the matrix extension (Sec. 2.1) of W W^T for W of
+    shape P x K (a vector is one column)."""
+    W = np.asarray(W, dtype=F64)
+    if W.ndim == 1:
+        W = W[:, None]
+    term = TERMS[op]
+    M = np.zeros((W.shape[0], W.shape[0]), dtype=F64)
+    for k in range(W.shape[1]):
+        M += term(W[:, k][:, None], W[:, k][None, :])
+    return M
+
+
+def image_reconstruct(V, T, w0, method="mapi", op="min1", tol=0.0):
+    """Algorithm 2 on the P x N matrix V whose columns are the N corrupted images:
+
+      m = mean of the columns; Vc = V - m
+      C = (1/(N-1)) Vc (+) Vc^T             (line 4; the covariance of eq. 2 for RPI)
+      w1 = dominant vector of C             (line 5)
+      w2 = dominant vector of C - (w1 (+) w1^T) C      (line 6; RPI: the projection C - w1 w1^T C)
+      W = [w1 w2];  R = (W (+) W^T) Vc + m  (line 8; RPI: W W^T Vc + m)
+
+    Each vector is the l2-normalised result of T iterations (tolerance tol) of MAPI (eq. 6,
+    product `op`) or RPI (eq. 1) from w0.  Returns (R, W, (result 1, result 2)).
+    """
+    V = np.asarray(V, dtype=F64)
+    N = V.shape[1]
+    m = V.mean(axis=1)
+    Vc = V - m[:, None]
+    mapi_like = method == "mapi"
+    C = mingram(Vc, 1.0 / (N - 1), op) if mapi_like else covariance(Vc, 1.0 / (N - 1))
+
+    def solve(A):
+        if mapi_like:
+            return mapi(A, w0, T, tol, op=op, final_l2=True)
+        return rpi(A, w0, T, tol, final_l2=True)
+
+    r1 = solve(C)
+    w1 = r1.w
+    C2 = C - (min_outer(w1, op) if mapi_like else np.outer(w1, w1)) @ C
+    r2 = solve(C2)
+    W = np.stack([w1, r2.w], axis=1)
+    R = (min_outer(W, op) if mapi_like else W @ W.T) @ Vc + m[:, None]
+    return R, W, (r1, r2)
+
+
+def psnr(x, ref, peak=1.0):
+    """Peak signal-to-noise ratio in dB of x against ref (Table 1)."""
+    x = np.asarray(x, dtype=F64)
+    ref = np.asarray(ref, dtype=F64)
+    mse = float(np.mean((x - ref) ** 2))
+    return float("inf") if mse == 0.0 else 10.0 * np.log10(peak * peak / mse)

@@ -297,3 +297,38 @@ def minibatch_indices(runs, T, s, N, seed):
     """I.i.d. uniform sample indices in [0, N) for Algorithm 3's mini batches, int32 of shape
     (runs, T, s): rng.integers(0, N, size=(runs, T, s))."""
     return _rng(seed).integers(0, N, size=(runs, T, s)).astype(np.int32)
+
+
+# --------------------------------------------------------------------------
+# Occluded images (Sec. 3.1 structure, synthetic content)
+# --------------------------------------------------------------------------
+def occluded_images(D, N, seed, tiles=4, bad_tiles=3):
+    """A synthetic D x D gray-scale image in [0, 1] and N corrupted copies (Sec. 3.1: the image
+    is cut into tiles x tiles tiles and, in each copy, `bad_tiles` tiles drawn at random are
+    replaced by i.i.d. U[0, 1] noise).  The paper's images are not available; the clean image is
+    a smooth pattern: 0.5 + 0.25 sin(2 pi u f1) cos(2 pi v f2) plus three Gaussian blobs, clipped
+    to [0, 1].  Returns (clean float32 (D*D,), V float32 (D*D, N)) with pixels in row-major order.
+
+    Draw order: f1, f2 = rng.uniform(1, 3, 2); blob centres rng.uniform(0, 1, (3, 2)), widths
+    rng.uniform(0.05, 0.2, 3), heights rng.uniform(-0.4, 0.4, 3); then per copy
+    rng.choice(tiles * tiles, bad_tiles, replace=False) and the noise of those tiles in order.
+    """
+    rng = _rng(seed)
+    u, v = np.meshgrid(np.linspace(0.0, 1.0, D), np.linspace(0.0, 1.0, D), indexing="ij")
+    f1, f2 = rng.uniform(1.0, 3.0, 2)
+    img = 0.5 + 0.25 * np.sin(2 * np.pi * u * f1) * np.cos(2 * np.pi * v * f2)
+    cen = rng.uniform(0.0, 1.0, (3, 2))
+    wid = rng.uniform(0.05, 0.2, 3)
+    hgt = rng.uniform(-0.4, 0.4, 3)
+    for b in range(3):
+        img += hgt[b] * np.exp(-((u - cen[b, 0]) ** 2 + (v - cen[b, 1]) ** 2) / (2 * wid[b] ** 2))
+    img = np.clip(img, 0.0, 1.0)
+    t = D // tiles
+    V = np.empty((D * D, N), dtype=np.float32)
+    for i in range(N):
+        x = img.copy()
+        for tt in rng.choice(tiles * tiles, bad_tiles, replace=False):
+            r, c = divmod(int(tt), tiles)
+            x[r * t:(r + 1) * t, c * t:(c + 1) * t] = rng.uniform(0.0, 1.0, (t, t))
+        V[:, i] = x.reshape(-1)
+    return img.reshape(-1).astype(np.float32), V

@@ -1,0 +1,51 @@
+"""Pins of the image-reconstruction oracle (Algorithm 2)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def test_min_outer_identities():
+    rng = np.random.default_rng(1)
+    W = rng.standard_normal((30, 2))
+    M = oracle.min_outer(W)
+    np.testing.assert_array_equal(M, M.T)
+    np.testing.assert_allclose(np.diag(M), np.abs(W).sum(axis=1), rtol=0, atol=1e-15)
+    # columns of constant modulus: min(|a|, |b|) = c, so the extension is c sign(W) sign(W)^T
+    S = np.where(rng.uniform(size=(30, 2)) < 0.5, -1.0, 1.0)
+    Wc = S * np.array([0.3, 0.7])[None, :]
+    np.testing.assert_allclose(oracle.min_outer(Wc), (S * [0.3, 0.7]) @ S.T, rtol=0, atol=1e-15)
+
+
+def test_rpi_reconstruction_is_the_top2_projection():
+    clean, V = synth.occluded_images(16, 10, seed=3)
+    w0 = synth.start_vector(256, 4).astype(np.float64)
+    R, W, (r1, r2) = oracle.image_reconstruct(V, 3000, w0, method="rpi", tol=1e-15)
+    Vd = V.astype(np.float64)
+    m = Vd.mean(axis=1)
+    C = np.cov(Vd)                                    # (1/(N-1)) centred, numpy's definition
+    lam, E = np.linalg.eigh(C)
+    top = E[:, -2:]
+    assert np.linalg.norm(W.T @ W - np.eye(2)) < 1e-6  # RPI vectors are orthonormal here
+    np.testing.assert_allclose(W @ W.T, top @ top.T, rtol=0, atol=1e-6)
+    np.testing.assert_allclose(R, top @ (top.T @ (Vd - m[:, None])) + m[:, None], rtol=0, atol=1e-6)
+
+
+def test_mapi_reconstruction_shapes_and_psnr_is_finite():
+    clean, V = synth.occluded_images(16, 10, seed=5)
+    w0 = synth.start_vector(256, 6).astype(np.float64)
+    R, W, _ = oracle.image_reconstruct(V, 40, w0)
+    assert R.shape == (256, 10) and W.shape == (256, 2)
+    np.testing.assert_allclose(np.linalg.norm(W, axis=0), 1.0, rtol=1e-14)
+    p = [oracle.psnr(R[:, i], clean) for i in range(10)]
+    assert all(np.isfinite(p))
+
+
+def test_occluded_images_structure():
+    clean, V = synth.occluded_images(32, 6, seed=7)
+    assert clean.min() >= 0 and clean.max() <= 1 and V.shape == (1024, 6)
+    for i in range(6):
+        diff = (V[:, i] != clean).reshape(32, 32)
+        bad = [diff[r * 8:(r + 1) * 8, c * 8:(c + 1) * 8].any() for r in range(4) for c in range(4)]
+        assert sum(bad) == 3
