@@ -378,6 +378,38 @@ def bench_minibatch(mp, ctx, torch, N=10 ** 6, D=10, s=1000, T=100, runs=256, se
     return out
 
 
+def bench_image(mp, ctx, torch, D=128, N=10, seed=1):
+    """Algorithm 2 at the Sec. 3.1 sizes: a synthetic 128 x 128 image, N = 10 copies with 3 of 16
+    tiles replaced by U[0,1] noise; MAPI (min1) and RPI, each vector to an l1 change < 1e-6 (stall
+    rule).  Reports the wall time of the whole pipeline (min-covariance of 16384 pixels, two solves,
+    the deflation, the reconstruction) and the mean PSNR of the N reconstructions and of the inputs."""
+    import synth
+    clean, V = synth.occluded_images(D, N, seed)
+    Vd = torch.from_numpy(V).cuda()
+    w0 = torch.from_numpy(synth.start_vector(D * D, seed + 1)).cuda()
+    cl = torch.from_numpy(clean).cuda().double()
+
+    def psnr(x):
+        mse = float(((x.double() - cl) ** 2).mean())
+        return 10.0 * np.log10(1.0 / mse)
+
+    out = {"D": D, "N": N, "pixels": D * D, "inputs_psnr_db": float(np.mean([psnr(Vd[:, i]) for i in range(N)]))}
+    for meth in ("mapi", "rpi"):
+        run = lambda: mp.mapi_image_reconstruct(Vd, w0, meth, max_iters=500, tol=1e-6, check_every=8,
+                                               stall_iters=STALL, ctx=ctx)
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R, W, infos = run()
+        torch.cuda.synchronize()
+        out[f"{meth}_ms"] = (time.perf_counter() - t0) * 1e3
+        out[f"{meth}_iters"] = [i["iters"] for i in infos]
+        out[f"{meth}_psnr_db"] = float(np.mean([psnr(R[:, i]) for i in range(N)]))
+        log(f"image {meth}: {out[f'{meth}_ms']:.1f} ms, iterations {out[f'{meth}_iters']}, "
+            f"PSNR {out[f'{meth}_psnr_db']:.2f} dB (inputs {out['inputs_psnr_db']:.2f} dB)")
+    return out
+
+
 def bench_pca(mp, ctx, torch, D=4096, N=65536, k=8, seed=77):
     import synth
     log("PCA: generating X 4096 x 65536 on the GPU")
@@ -563,7 +595,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="bench", choices=["bench", "kernels"])
-    ap.add_argument("--sections", default="small,hybrid,minibatch,batched,pca,pagerank,serving",
+    ap.add_argument("--sections", default="small,hybrid,minibatch,image,batched,pca,pagerank,serving",
                     help="other workloads reported under detail (comma list; empty for none)")
     ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--commands", nargs=3, default=["", "", ""], help="commands that produced the three dirs")
@@ -621,7 +653,7 @@ def main():
 
     sections = [x for x in args.sections.split(",") if x]
     for name, fn in (("small", lambda: bench_small(mp, ctx, torch)), ("hybrid", lambda: bench_hybrid(mp, ctx, torch)),
-                     ("minibatch", lambda: bench_minibatch(mp, ctx, torch)),
+                     ("minibatch", lambda: bench_minibatch(mp, ctx, torch)), ("image", lambda: bench_image(mp, ctx, torch)),
                      ("batched", lambda: bench_batched(mp, ctx, torch)), ("pca", lambda: bench_pca(mp, ctx, torch)),
                      ("pagerank", lambda: bench_pagerank(mp, ctx, torch)), ("serving", lambda: bench_serving(mp, torch))):
         if name in sections:

@@ -202,6 +202,27 @@ mapi_status mapi_hybrid_solve(mapi_ctx* ctx, const mapi_dense* A, const float* w
                               const mapi_opts* first_opts, const mapi_opts* then_opts, mapi_info* info_mapi,
                               mapi_info* info_rpi);
 
+/* Image reconstruction via MAPI (Algorithm 2, Sec. 3.1) from N corrupted copies
+ * of one image: V (device float32, P x N, row pitch ldv >= N) holds the P pixels
+ * of copy i in column i.  m = mean of the columns; Vc = V - m;
+ *   C  = (1/(N-1)) Vc (+) Vc^T                 (line 4, min1; RPI: Vc Vc^T / (N-1))
+ *   w1 = MAPI on C                              (line 5; RPI: eq. 1)
+ *   w2 = MAPI on C - (w1 (+) w1^T) C            (line 6; RPI: C - w1 w1^T C)
+ *   R  = (W (+) W^T) Vc + m, W = [w1 w2]         (line 8; RPI: W W^T Vc + m)
+ * Both solves start from w0 (device, P, 16-byte aligned) and follow opts
+ * (max_iters, tol, check_every, stall_iters; op must be MAPI_OP_MIN1 for MAPI;
+ * final_l2 is ignored).  MAPI vectors are returned as Algorithm 1 leaves them,
+ * with unit l1 norm -- the unit of the operator (w (+) w = ||w||_1, Sec. 2.1), so
+ * that w (+) w^T acts on w as w w^T does for an l2 unit vector; RPI vectors have
+ * unit l2 norm.  R: device P x N (pitch ldr >= N),
+ * the N reconstructions; W: device P x 2 (w1 at W, w2 at W + P).  info2: host,
+ * 2 entries (optional).  The min-outer deflation is computed exactly in O(P^2)
+ * by prefix sums over C's rows in the order of |w1| (no P^3 product).  2 <= N <=
+ * 16, P <= 32768; the context keeps 2 P^2 floats of workspace.                  */
+mapi_status mapi_image_reconstruct(mapi_ctx* ctx, const float* V, int64_t P, int32_t N, int64_t ldv, int32_t method,
+                                   const float* w0, const mapi_opts* opts, float* R, int64_t ldr, float* W,
+                                   mapi_info* info2);
+
 /* Mini-batch MAPI with momentum (Algorithm 3, Sec. 3.2), `runs` independent runs
  * (one GPU block each).  Run r iterates T times: with the batch
  * B_t = batch_idx[(r T + t) s .. + s) of sample indices,

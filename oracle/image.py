@@ -41,8 +41,12 @@ def image_reconstruct(V, T, w0, method="mapi", op="min1", tol=0.0):
       w2 = dominant vector of C - (w1 (+) w1^T) C      (line 6; RPI: the projection C - w1 w1^T C)
       W = [w1 w2];  R = (W (+) W^T) Vc + m  (line 8; RPI: W W^T Vc + m)
 
-    Each vector is the l2-normalised result of T iterations (tolerance tol) of MAPI (eq. 6,
-    product `op`) or RPI (eq. 1) from w0.  Returns (R, W, (result 1, result 2)).
+    Each vector is the result of T iterations (tolerance tol) from w0 of MAPI (eq. 6, product
+    `op`) as Algorithm 1 returns it -- l1-normalised, without the optional l2 step -- or of RPI
+    (eq. 1), l2-normalised.  The l1 norm is the unit of the operator's geometry (w (+) w =
+    ||w||_1, Sec. 2.1): with ||w||_1 = 1 and entries of similar modulus, (w (+) w^T) w ~ w, as
+    w w^T w = w for a unit l2 vector; with l2-normalised MAPI vectors the extension of W W^T is
+    larger by about sqrt(P).  Returns (R, W, (result 1, result 2)).
     """
     V = np.asarray(V, dtype=F64)
     N = V.shape[1]
@@ -53,7 +57,7 @@ def image_reconstruct(V, T, w0, method="mapi", op="min1", tol=0.0):
 
     def solve(A):
         if mapi_like:
-            return mapi(A, w0, T, tol, op=op, final_l2=True)
+            return mapi(A, w0, T, tol, op=op)
         return rpi(A, w0, T, tol, final_l2=True)
 
     r1 = solve(C)

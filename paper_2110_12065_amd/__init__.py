@@ -97,6 +97,9 @@ _SIGS = {
                                 C.POINTER(Opts), C.POINTER(Info)]),
     "mapi_hybrid_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts),
                                     C.POINTER(Opts), C.POINTER(Info), C.POINTER(Info)]),
+    "mapi_image_reconstruct": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_int32,
+                                         C.c_void_p, C.POINTER(Opts), C.c_void_p, C.c_int64, C.c_void_p,
+                                         C.c_void_p]),
     "mapi_minibatch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_int32,
                                  C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                  C.c_void_p]),
@@ -287,6 +290,24 @@ def mapi_hybrid_solve(A, w0, mapi_iters=100, mapi_tol=0.0, rpi_iters=100, rpi_to
                                    C.c_void_p(_vec(w_out, n, "w_out")), C.byref(o1), C.byref(o2),
                                    C.byref(i1), C.byref(i2)))
     return w_out, i1.as_dict(), i2.as_dict()
+
+
+def mapi_image_reconstruct(V, w0, method="mapi", max_iters=100, tol=0.0, check_every=0, stall_iters=0, ctx=None):
+    """Algorithm 2: V device float32 P x N (column i = corrupted copy i).  Returns (R P x N, W P x 2,
+    infos of the two solves)."""
+    import torch
+    c = _ctx_of(ctx, V)
+    if V.dim() != 2 or V.dtype != torch.float32 or V.stride(1) != 1:
+        raise ValueError("V must be a float32 P x N tensor with unit column stride")
+    P, N = V.shape
+    R = torch.empty((P, N), dtype=torch.float32, device=V.device)
+    W = torch.empty((2, P), dtype=torch.float32, device=V.device)
+    o = _opts(max_iters, tol, "min1", False, check_every, stall_iters)
+    infos = (Info * 2)()
+    _check(lib().mapi_image_reconstruct(c.handle, C.c_void_p(V.data_ptr()), int(P), int(N), int(V.stride(0)),
+                                        METHODS[method], C.c_void_p(_vec(w0, P, "w0")), C.byref(o),
+                                        C.c_void_p(R.data_ptr()), int(N), C.c_void_p(W.data_ptr()), infos))
+    return R, W.t(), [i.as_dict() for i in infos]
 
 
 def mapi_minibatch(X, batches, beta, W0, op="min1", final_l2=False, w_out=None, ctx=None):

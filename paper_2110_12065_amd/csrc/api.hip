@@ -554,6 +554,83 @@ mapi_status mapi_pca_topk(mapi_ctx* c, const float* X, int64_t D, int64_t N, int
   return MAPI_OK;
 }
 
+mapi_status mapi_image_reconstruct(mapi_ctx* c, const float* V, int64_t P, int32_t N, int64_t ldv, int32_t method,
+                                   const float* w0, const mapi_opts* opts, float* R, int64_t ldr, float* W,
+                                   mapi_info* info2) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  if (!V || !w0 || !R || !W) return fail(MAPI_ERR_ARG, "V, w0, R and W must be device pointers");
+  if (P < 1 || N < 2 || ldv < N || ldr < N) return fail(MAPI_ERR_ARG, "need P >= 1, N >= 2, ldv >= N, ldr >= N");
+  if (N > image_max_n()) return fail(MAPI_ERR_UNSUPPORTED, "N > %d images", image_max_n());
+  if (P > 32768) return fail(MAPI_ERR_UNSUPPORTED, "P > 32768 pixels");
+  if (method != MAPI_METHOD_MAPI && method != MAPI_METHOD_RPI) return fail(MAPI_ERR_ARG, "method %d", method);
+  mapi_status s;
+  if ((s = check_opts(opts)) != MAPI_OK) return s;
+  const bool rpi = method == MAPI_METHOD_RPI;
+  if (!rpi && opts->op != MAPI_OP_MIN1) return fail(MAPI_ERR_UNSUPPORTED, "the min-outer deflation is built for min1");
+  if (!aligned16(w0)) return fail(MAPI_ERR_ARG, "w0 must be 16-byte aligned");
+  HIP_TRY(hipSetDevice(c->device));
+  const int64_t ldA = (P + 3) / 4 * 4;     // 16-byte rows for the product kernel
+  const int64_t ldc = (N + 3) / 4 * 4;     // centred images, 16-byte rows for the Gram kernel
+  const int G = (int)std::min<int64_t>(64, P);
+  Layout L;
+  const size_t o_C = L.take(sizeof(float) * P * ldA);
+  const size_t o_C2 = L.take(sizeof(float) * P * ldA);
+  const size_t o_Vc = L.take(sizeof(float) * P * ldc);
+  const size_t o_m = L.take(sizeof(float) * P);
+  const size_t o_perm = L.take(sizeof(int32_t) * P);
+  const size_t o_sums = L.take(sizeof(double) * 2 * (size_t)G * P);
+  const size_t o_P = L.take(sizeof(double) * P);
+  const size_t o_Q = L.take(sizeof(double) * P);
+  const size_t o_qp = L.take(sizeof(double) * P * deflate_qpart_count());
+  const size_t o_pf = L.take(sizeof(float) * P);
+  if ((s = ensure(&c->big, &c->big_bytes, L.off, c)) != MAPI_OK) return s;
+  char* base = static_cast<char*>(c->big);
+  float* C = reinterpret_cast<float*>(base + o_C);
+  float* C2 = reinterpret_cast<float*>(base + o_C2);
+  float* Vc = reinterpret_cast<float*>(base + o_Vc);
+  float* m = reinterpret_cast<float*>(base + o_m);
+  int32_t* perm = reinterpret_cast<int32_t*>(base + o_perm);
+  double* sums = reinterpret_cast<double*>(base + o_sums);
+  double* Pm = reinterpret_cast<double*>(base + o_P);
+  double* Qm = reinterpret_cast<double*>(base + o_Q);
+  double* qpart = reinterpret_cast<double*>(base + o_qp);
+  float* w1 = W;
+  float* w2 = W + P;
+  HIP_TRY(launch_img_center(V, P, N, ldv, Vc, ldc, m, c->stream));
+  {
+    Timed tm(c, MAPI_K_GRAM);
+    HIP_TRY(launch_gram(Vc, P, N, ldc, 1.0 / (double)(N - 1), rpi ? MAPI_OP_DOT : MAPI_OP_MIN1, C, ldA, nullptr,
+                        c->stream));
+  }
+  // MAPI vectors as Algorithm 1 returns them (l1 units: w (+) w = ||w||_1 = 1 makes
+  // w (+) w^T act on w as w w^T does for an l2 unit vector); RPI vectors l2 units
+  mapi_opts o = *opts;
+  o.final_l2 = rpi ? 1 : 0;
+  mapi_dense d1{C, P, P, ldA, MAPI_F32, nullptr};
+  mapi_info i1{}, i2{};
+  s = run_dense(c, &d1, w0, w1, &o, &i1, rpi);
+  if (info2) info2[0] = i1;
+  if (s != MAPI_OK) return s;
+  {
+    Timed tm(c, MAPI_K_DEFLATE);
+    if (rpi) {
+      HIP_TRY(launch_mgs_append(Pm, P, 0, w1, reinterpret_cast<float*>(base + o_pf), c->stream));
+      HIP_TRY(launch_deflate_q(C, P, ldA, Pm, Qm, qpart, c->stream));
+      HIP_TRY(launch_deflate_apply(C, P, ldA, Pm, Qm, 1, C2, ldA, c->stream));
+    } else {
+      HIP_TRY(launch_img_minouter_deflate(C, P, ldA, w1, perm, sums, G, C2, c->stream));
+    }
+  }
+  mapi_dense d2{C2, P, P, ldA, MAPI_F32, nullptr};
+  s = run_dense(c, &d2, w0, w2, &o, &i2, rpi);
+  if (info2) info2[1] = i2;
+  if (s != MAPI_OK) return s;
+  HIP_TRY(launch_img_reconstruct(rpi ? MAPI_OP_DOT : MAPI_OP_MIN1, W, Vc, P, N, ldc, m, R, ldr, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  collect_timing(c);
+  return MAPI_OK;
+}
+
 mapi_status mapi_minibatch(mapi_ctx* c, const float* X, int64_t N, int64_t D, int64_t ldx, const int32_t* batch_idx,
                            int32_t s, int32_t T, double beta, int32_t op, int32_t runs, const float* w0, float* w_out,
                            int32_t final_l2, mapi_info* infos) {

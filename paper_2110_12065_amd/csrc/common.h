@@ -210,6 +210,14 @@ int pr_scalar_blocks(int64_t n);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, int cu_count, hipStream_t s);
 
+int image_max_n();
+hipError_t launch_img_center(const float* V, int64_t P, int N, int64_t ldv, float* Vc, int64_t ldc, float* m,
+                             hipStream_t s);
+hipError_t launch_img_minouter_deflate(const float* C, int64_t P, int64_t ldc, const float* w, int32_t* perm,
+                                       double* sums, int G, float* Cd, hipStream_t s);
+hipError_t launch_img_reconstruct(int op, const float* W, const float* Vc, int64_t P, int N, int64_t ldc,
+                                  const float* m, float* R, int64_t ldr, hipStream_t s);
+
 // Per-run outcome of the mini-batch kernel.
 struct MbRun {
   int32_t iters, status;

@@ -1,0 +1,66 @@
+"""GPU parity of image reconstruction via MAPI (Algorithm 2) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import rel_l1, report, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2110_12065_amd as mp  # noqa: E402
+
+TOL = 1e-5
+COS = 1 - 1e-6
+
+
+@pytest.mark.parametrize("D,method,T", [(16, "mapi", 30), (16, "rpi", 60), (30, "mapi", 25), (48, "mapi", 20),
+                                        (48, "rpi", 40)])
+def test_image_reconstruction_matches_oracle(D, method, T):
+    print(f"[case] image D={D} {method} T={T}", flush=True)
+    P, N = D * D, 10
+    clean, V = synth.occluded_images(D, N, seed=D)
+    w0 = synth.start_vector(P, D + 1)
+    R, W, infos = mp.mapi_image_reconstruct(torch.from_numpy(V).cuda(), to_dev(w0), method, max_iters=T)
+    assert [i["iters"] for i in infos] == [T, T]
+    Rr, Wr, _ = oracle.image_reconstruct(V, T, w0.astype(np.float64), method=method)
+    for k in range(2):
+        e, c = report(f"image {method} D={D} w{k + 1}", W[:, k].cpu().numpy(), Wr[:, k])
+        assert e <= TOL and c > COS
+    e = rel_l1(R.cpu().numpy(), Rr)
+    print(f"[parity] image {method} D={D} R: rel_l1={e:.3e}", flush=True)
+    assert e <= TOL
+    p_gpu = np.mean([oracle.psnr(R[:, i].cpu().numpy(), clean) for i in range(N)])
+    p_ref = np.mean([oracle.psnr(Rr[:, i], clean) for i in range(N)])
+    assert abs(p_gpu - p_ref) < 1e-3
+
+
+def test_image_full_size_runs_and_improves_on_the_inputs():
+    # Sec. 3.1 sizes: 128 x 128 images, N = 10 copies, 3 of 16 tiles replaced by noise
+    D, N = 128, 10
+    clean, V = synth.occluded_images(D, N, seed=1)
+    w0 = synth.start_vector(D * D, 2)
+    for method in ("mapi", "rpi"):
+        R, W, infos = mp.mapi_image_reconstruct(torch.from_numpy(V).cuda(), to_dev(w0), method, max_iters=200,
+                                                tol=1e-6, check_every=8, stall_iters=10)
+        Wn = W.cpu().numpy().astype(np.float64)
+        norms = np.abs(Wn).sum(axis=0) if method == "mapi" else np.linalg.norm(Wn, axis=0)
+        np.testing.assert_allclose(norms, 1.0, rtol=1e-6)
+        p_out = np.mean([oracle.psnr(R[:, i].cpu().numpy(), clean) for i in range(N)])
+        p_in = np.mean([oracle.psnr(V[:, i], clean) for i in range(N)])
+        print(f"[image] {method}: iterations {[i['iters'] for i in infos]}, PSNR inputs {p_in:.2f} dB, "
+              f"reconstructions {p_out:.2f} dB", flush=True)
+        assert np.isfinite(p_out) and p_out > p_in + 3.0
+
+
+def test_image_argument_checks():
+    V = torch.zeros((64, 1), dtype=torch.float32, device="cuda")
+    w0 = torch.full((64,), 0.125, dtype=torch.float32, device="cuda")
+    with pytest.raises(mp.MapiError) as ei:
+        mp.mapi_image_reconstruct(V, w0)            # N = 1: the 1/(N-1) scale is undefined
+    assert ei.value.status == 1
+    V17 = torch.zeros((64, 17), dtype=torch.float32, device="cuda")
+    with pytest.raises(mp.MapiError) as ei:
+        mp.mapi_image_reconstruct(V17, w0)
+    assert ei.value.status == 6

@@ -37,9 +37,17 @@ def test_mapi_reconstruction_shapes_and_psnr_is_finite():
     w0 = synth.start_vector(256, 6).astype(np.float64)
     R, W, _ = oracle.image_reconstruct(V, 40, w0)
     assert R.shape == (256, 10) and W.shape == (256, 2)
-    np.testing.assert_allclose(np.linalg.norm(W, axis=0), 1.0, rtol=1e-14)
+    np.testing.assert_allclose(np.abs(W).sum(axis=0), 1.0, rtol=1e-14)    # Algorithm 1's l1 normalisation
     p = [oracle.psnr(R[:, i], clean) for i in range(10)]
     assert all(np.isfinite(p))
+
+
+def test_min_outer_of_a_flat_l1_unit_vector_reproduces_it():
+    # the reason for l1 units: for |w_j| = 1/P, (w (+) w^T) w = w exactly (w (+) w = ||w||_1 = 1)
+    P = 50
+    s = np.where(np.random.default_rng(2).uniform(size=P) < 0.5, -1.0, 1.0)
+    w = s / P
+    np.testing.assert_allclose(oracle.min_outer(w) @ w, w, rtol=0, atol=1e-16)
 
 
 def test_occluded_images_structure():
