@@ -29,6 +29,6 @@ from .minibatch import minibatch_mapi  # noqa: F401
 from .image import min_outer, image_reconstruct, psnr  # noqa: F401
 from .quant import (  # noqa: F401
     bf16_decode, bf16_encode, e4m3fn_table, e4m3fn_decode, e4m3fn_encode,
-    fp8_rows_quantize, fp8_rows_dequantize, bf16_quantize, bf16_dequantize,
+    fp8_row_scale, fp8_rows_quantize, fp8_rows_dequantize, bf16_quantize, bf16_dequantize,
     E4M3_MAX,
 )

@@ -11,8 +11,11 @@ Formats, written from their definitions:
     3 significand bits; exponent field 0 is subnormal; S.1111.111 is NaN; there
     is no infinity; the largest finite magnitude is 448.  Encoding picks the
     nearest finite value, ties to the even code, and saturates to +-448.
-  * Per-row scaling: s_i = fl32(amax_i / 448) (s_i = 1 for an all-zero row),
-    q_ij = e4m3fn(fl32(A_ij / s_i)), dequantised a'_ij = fl32(s_i * q_ij).
+  * Per-row scaling by a power of two: s_i = 2^k_i with k_i the smallest integer
+    >= -126 such that 448 * 2^k_i >= amax_i (s_i = 1 for an all-zero row), so
+    q_ij = e4m3fn(fl32(A_ij / s_i)) never saturates and the dequantised value
+    a'_ij = fl32(s_i * q_ij) is the exact product (the hardware's scaled e4m3
+    conversion applies exactly such a scale).
 
 Pins (tests/test_oracle_quant.py): known code points of both formats; decode and
 encode against torch's CPU float8_e4m3fn / bfloat16 conversions on in-range
@@ -110,12 +113,25 @@ def e4m3fn_encode(x):
     return code.astype(np.uint8)
 
 
+def fp8_row_scale(amax):
+    """Smallest power of two s = 2^k, k >= -126, with 448 s >= amax (1 when amax is 0).
+
+    With amax = m 2^e, m in [0.5, 1): 448 = 0.875 * 2^9, so k = e - 9 when m <= 0.875
+    and k = e - 8 otherwise -- integer logic on the exact binary exponent.
+    """
+    amax = np.asarray(amax, dtype=np.float32)
+    m, e = np.frexp(amax.astype(np.float64))
+    k = e.astype(np.int64) - 9 + (m > 0.875).astype(np.int64)
+    k = np.maximum(k, -126)
+    s = np.ldexp(np.ones_like(m), k).astype(np.float32)
+    return np.where(amax == 0, np.float32(1.0), s).astype(np.float32)
+
+
 def fp8_rows_quantize(A):
     """Row-scaled e4m3fn storage of a float32 matrix -> (codes uint8, scales float32)."""
     A = np.asarray(A, dtype=np.float32)
     amax = np.max(np.abs(A), axis=1).astype(np.float32)
-    s = (amax / np.float32(E4M3_MAX)).astype(np.float32)
-    s[amax == 0] = np.float32(1.0)
+    s = fp8_row_scale(amax)
     t = (A / s[:, None]).astype(np.float32)
     return e4m3fn_encode(t), s
 

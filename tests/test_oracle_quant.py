@@ -69,11 +69,28 @@ def test_fp8_rows_quantize_definition():
     assert q.dtype == np.uint8 and s.dtype == np.float32
     assert s[5] == 1.0 and (q[5] == 0).all()
     amax = np.abs(A).max(axis=1)
-    np.testing.assert_array_equal(s[amax > 0], (amax / np.float32(448.0)).astype(np.float32)[amax > 0])
+    # scales are powers of two, the smallest with amax / s <= 448 (so amax / s > 224)
+    mant, _ = np.frexp(s.astype(np.float64))
+    assert (mant == 0.5).all()
+    r = amax[amax > 0] / s[amax > 0].astype(np.float64)
+    assert (r <= 448.0).all() and (r > 224.0).all()
     Ad = oracle.fp8_rows_dequantize(q, s)
     # three significand bits: relative error at most 2^-4 above the subnormal range
     big = np.abs(A) >= 2.0 ** -6 * s[:, None]
     rel = np.abs(Ad[big] - A[big]) / np.abs(A[big])
     assert rel.max() <= 2.0 ** -4 * (1 + 1e-6)
-    # the row maximum lands on the top code (or its neighbour after the scale's rounding)
-    assert (np.abs(oracle.e4m3fn_decode(q)).max(axis=1)[amax > 0] >= 416).all()
+    # dequantisation is an exact product by a power of two
+    np.testing.assert_array_equal(Ad.astype(np.float64),
+                                  oracle.e4m3fn_decode(q).astype(np.float64) * s[:, None].astype(np.float64))
+    # the row maximum lands in the top binade of the format
+    assert (np.abs(oracle.e4m3fn_decode(q)).max(axis=1)[amax > 0] >= 224).all()
+
+
+def test_fp8_row_scale_edges():
+    # exact boundaries of the rule 448 * 2^k >= amax
+    a = np.array([448.0, 448.00003, 224.0, 1.0, 3.0e38, 1e-45, 0.0], dtype=np.float32)
+    s = oracle.fp8_row_scale(a)
+    assert s[0] == 1.0 and s[1] == 2.0 and s[2] == 0.5
+    assert s[3] == 2.0 ** -8               # 448 / 512 = 0.875 < 1 <= 448 / 256
+    assert s[4] == 2.0 ** 120              # 3e38 / 2^120 = 225.6
+    assert s[5] == np.float32(2.0 ** -126) and s[6] == 1.0
