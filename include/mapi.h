@@ -61,7 +61,9 @@ typedef enum mapi_op {
 typedef enum mapi_method { MAPI_METHOD_MAPI = 0, MAPI_METHOD_RPI = 1 } mapi_method;
 
 /* Dense matrix descriptor.  row_scale: FP8 only, device float[n_rows];
- * element (i, j) is row_scale[i] * decode(data[i * ld + j]).                   */
+ * element (i, j) is fl32(row_scale[i] * decode(data[i * ld + j])).  Any positive
+ * scale is accepted; rows whose scale is a power of two (as mapi_quantize writes)
+ * use the scaled-conversion decode, others a separate multiply -- same values.  */
 typedef struct mapi_dense {
   const void* data;
   int64_t n_rows, n_cols, ld;
@@ -248,9 +250,11 @@ mapi_status mapi_minibatch(mapi_ctx* ctx, const float* X, int64_t N, int64_t D, 
 
 /* Convert a float32 matrix (n_rows x n_cols, leading dimension lda) to reduced
  * storage: MAPI_BF16 -> uint16 codes, nearest value, ties to even;
- * MAPI_FP8_E4M3 -> uint8 e4m3fn codes with row scale s_i = fl32(amax_i / 448)
- * (1 for an all-zero row), codes = e4m3fn(fl32(A_ij / s_i)) nearest, ties to
- * even, saturating at 448.  out has leading dimension ld_out (elements);
+ * MAPI_FP8_E4M3 -> uint8 e4m3fn codes with row scale s_i the smallest power of
+ * two 2^k (k >= -126) with 448 s_i >= amax_i (1 for an all-zero row), codes =
+ * e4m3fn(fl32(A_ij / s_i)) nearest, ties to even (never saturating).  Power-of-two
+ * scales make the dequantised value an exact product, which the product kernels
+ * apply inside the scaled e4m3 conversion.  out has leading dimension ld_out (elements);
  * row_scale (device float[n_rows]) is written for FP8 and may be NULL for BF16. */
 mapi_status mapi_quantize(mapi_ctx* ctx, const float* A, int64_t n_rows, int64_t n_cols, int64_t lda,
                           int32_t dtype, void* out, int64_t ld_out, float* row_scale);

@@ -22,7 +22,17 @@ template <> struct Traits<MAPI_BF16> { static constexpr int VE = 8; static const
 template <> struct Traits<MAPI_FP8_E4M3> { static constexpr int VE = 16; static constexpr int ESZ = 1; };
 
 // Decode one 16-byte vector of stored elements to float32 (FP8: times the row scale).
-template <int DT>
+// P2 (FP8 rows whose scale is a positive power of two): the gfx950 scaled conversion
+// applies the scale's exponent inside the conversion, which for such scales is the
+// exact product, one instruction per two values instead of a conversion and two
+// multiplies.
+__device__ __forceinline__ bool pow2_scale(float s) {
+  const uint32_t u = __float_as_uint(s);
+  const uint32_t ex = (u >> 23) & 0xFFu;
+  return (u & 0x807FFFFFu) == 0u && ex != 0u && ex != 0xFFu;
+}
+
+template <int DT, bool P2 = false>
 __device__ __forceinline__ void decode_vec(const uint4 raw, float scale, float* out) {
   const uint32_t wd[4] = {raw.x, raw.y, raw.z, raw.w};
   if constexpr (DT == MAPI_F32) {
@@ -33,6 +43,16 @@ __device__ __forceinline__ void decode_vec(const uint4 raw, float scale, float* 
     for (int k = 0; k < 4; ++k) {
       out[2 * k] = __uint_as_float(wd[k] << 16);
       out[2 * k + 1] = __uint_as_float(wd[k] & 0xFFFF0000u);
+    }
+  } else if constexpr (P2) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const auto lo = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8((int)wd[k], scale, false);
+      const auto hi = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8((int)wd[k], scale, true);
+      out[4 * k + 0] = lo[0];
+      out[4 * k + 1] = lo[1];
+      out[4 * k + 2] = hi[0];
+      out[4 * k + 3] = hi[1];
     }
   } else {
 #pragma unroll
@@ -81,7 +101,7 @@ __device__ __forceinline__ uint4 load16(const unsigned char* p) {
 // flips the signs of four stored values before decoding, so each term is
 // op(a * sign(w), |w|) -- the same value as op(a, w) -- without per-element sign
 // work.  wsign: the signed w, used for the ragged tail.
-template <int DT, int OP, int RW, int U, bool NT, bool PF = false>
+template <int DT, int OP, int RW, int U, bool NT, bool PF = false, bool P2 = false>
 __device__ __forceinline__ void rows_product(const unsigned char* const* rp, const float* sc, const float* wv,
                                              int n_cols, int lane, float* out, const uint32_t* smask = nullptr,
                                              const float* wsign = nullptr) {
@@ -117,7 +137,7 @@ __device__ __forceinline__ void rows_product(const unsigned char* const* rp, con
         rr.x ^= m.x; rr.y ^= m.y; rr.z ^= m.z; rr.w ^= m.w;
       }
       float a[VE];
-      decode_vec<DT>(rr, sc[r], a);
+      decode_vec<DT, P2>(rr, sc[r], a);
 #pragma unroll
       for (int e = 0; e < VE; ++e) acc[r][e & 1] = op_acc<OP>(acc[r][e & 1], a[e], wf[e], ws[e]);
     }
@@ -205,7 +225,15 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
       sc[r] = (DT == MAPI_FP8_E4M3) ? rscale[row] : 1.0f;
     }
     float sums[RW];
-    rows_product<DT, OP, RW, U, NT, PF>(rp, sc, wv, n_cols, lane, sums, smask, w);
+    if constexpr (DT == MAPI_FP8_E4M3) {
+      bool p2 = true;
+#pragma unroll
+      for (int r = 0; r < RW; ++r) p2 = p2 && pow2_scale(sc[r]);
+      if (p2) rows_product<DT, OP, RW, U, NT, PF, true>(rp, sc, wv, n_cols, lane, sums, smask, w);
+      else rows_product<DT, OP, RW, U, NT, PF, false>(rp, sc, wv, n_cols, lane, sums, smask, w);
+    } else {
+      rows_product<DT, OP, RW, U, NT, PF>(rp, sc, wv, n_cols, lane, sums, smask, w);
+    }
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
       const float s = sums[r];

@@ -57,7 +57,12 @@ k_quant_fp8_rows(const float* __restrict__ A, int64_t n_rows, int64_t n_cols, in
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = amax;
     __syncthreads();
     amax = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
-    const float s = (amax > 0.0f) ? __fdiv_rn(amax, 448.0f) : 1.0f;
+    // smallest power of two s = 2^k (k >= -126) with 448 s >= amax: with amax = m 2^e,
+    // m in [0.5, 1), and 448 = 0.875 * 2^9, k = e - 9, plus one when m > 0.875
+    int e = 0;
+    const float m = frexpf(amax, &e);
+    const int k = max(e - 9 + (m > 0.875f ? 1 : 0), -126);
+    const float s = (amax > 0.0f) ? ldexpf(1.0f, k) : 1.0f;
     if (threadIdx.x == 0) scale[i] = s;
     for (int64_t j = threadIdx.x; j < n_cols; j += blockDim.x) out[i * ldo + j] = e4m3fn_rne_sat(__fdiv_rn(row[j], s));
   }

@@ -309,3 +309,29 @@ def test_hybrid_zero_mapi_iterations_is_rpi():
     b, _ = mp.rpi_solve(to_dev(C), to_dev(w0 / np.float32(np.linalg.norm(w0))), max_iters=30)
     assert im["iters"] == 0 and ir["iters"] == 30
     np.testing.assert_array_equal(w.cpu().numpy(), b.cpu().numpy())
+
+
+def test_fp8_mixed_power_of_two_and_general_scales():
+    # rows with power-of-two scales take the scaled-conversion decode, others the multiply;
+    # both give fl32(s * decode(q)), in every launch shape (row groups may mix the two kinds)
+    rng = np.random.default_rng(17)
+    m, n = 203, 777
+    q = rng.integers(0, 256, size=(m, n), dtype=np.uint8)
+    q[(q & 0x7F) == 0x7F] = 0                      # no NaN codes
+    s = np.where(np.arange(m) % 3 == 0, np.float32(0.6), np.float32(2.0) ** rng.integers(-8, 8, m)).astype(np.float32)
+    Aref = oracle.fp8_rows_dequantize(q, s)
+    w = rng.standard_normal(n).astype(np.float32)
+    ref = oracle.mavp(Aref.astype(np.float64), w.astype(np.float64), "min1")
+    qd, sd, wd = to_dev(q), to_dev(s), to_dev(w)
+    first = None
+    for rw in (1, 2, 4):
+        shape = dict(rows_per_wave=rw, waves=4, blocks_per_cu=1, unroll=2, w_in_lds=1, nontemporal=0)
+        y = torch.full((m,), float("nan"), device="cuda")
+        mp.mapi_mavp_timed(qd, wd, shape, reps=1, row_scale=sd, y=y)
+        yh = y.cpu().numpy()
+        if first is None:
+            first = yh
+            terms = np.abs(Aref).sum(axis=1)       # bound scale per row
+            assert (np.abs(yh - ref) <= TOL * np.maximum(terms, 1e-30)).all()
+        else:
+            np.testing.assert_array_equal(yh, first)
