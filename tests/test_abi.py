@@ -60,3 +60,11 @@ def test_null_arguments_are_rejected_without_gpu(libpath):
     assert L.mapi_solve(None, None, None, None, None, None) == 1
     assert L.mapi_pagerank(None, None, 0.85, 0, None, None, None, None) == 1
     assert b"NULL" in L.mapi_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stdout
