@@ -146,16 +146,43 @@ __host__ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
 // minus 2^23 (uniform integers), s_n = fl32(sqrt(3) / (2^23 sqrt(n))) (unit-variance
 // entries over sqrt(n): semicircle bulk of radius 2), theta = 6 and sigma_i the top
 // bit of splitmix64(splitmix64(seed ^ 0x5BD1E995) + i) as a sign.  Rounded in float32,
-// product then sum.
-__device__ __forceinline__ float gen_entry(uint64_t base, uint64_t sbase, int i, int j, float s_n, float spike) {
+// product then sum.  `same` is sigma_i == sigma_j.
+__device__ __forceinline__ float gen_value(uint64_t base, int i, int j, float s_n, float spike, bool same) {
 #pragma clang fp contract(off)
   const uint64_t lo = (uint64_t)min(i, j), hi = (uint64_t)max(i, j);
   const uint64_t h = splitmix64(base + ((lo << 32) | hi));
   const float x = (float)((int32_t)(h >> 40) - 8388608);
-  const bool si = (splitmix64(sbase + (uint64_t)i) >> 63) != 0;
-  const bool sj = (splitmix64(sbase + (uint64_t)j) >> 63) != 0;
   const float prod = x * s_n;          // rounded on its own: no fused multiply-add here
-  return prod + ((si == sj) ? spike : -spike);
+  return prod + (same ? spike : -spike);
+}
+__device__ __forceinline__ bool gen_sign(uint64_t sbase, int i) {
+  return (splitmix64(sbase + (uint64_t)i) >> 63) != 0;
+}
+
+// Rows r0 .. r1-1 (r1 - r0 <= 32) of the generated matrix, all n columns, written
+// to A (row pitch ld) as float32 or, with BF16 set, rounded to nearest even
+// bfloat16.  The signs are hashed once each: a row's by one lane of every wave
+// (gathered by a ballot), a column's once per thread before its rows, so an entry
+// costs one hash.  Every thread of the block calls it.
+template <bool BF16>
+__device__ __forceinline__ void gen_rows(void* A, int64_t ld, int n, int r0, int r1, uint64_t base, uint64_t sbase,
+                                         float s_n, float spike) {
+  const int lane = threadIdx.x & 63;
+  const bool mine = lane < r1 - r0 && gen_sign(sbase, r0 + lane);
+  const uint64_t rows = __ballot(mine);
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const bool sj = gen_sign(sbase, j);
+    for (int i = r0; i < r1; ++i) {
+      const float a = gen_value(base, i, j, s_n, spike, ((rows >> (i - r0)) & 1ull) == (uint64_t)sj);
+      if (BF16) {
+        uint32_t u = __float_as_uint(a);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        reinterpret_cast<uint16_t*>(A)[(int64_t)i * ld + j] = (uint16_t)(u >> 16);
+      } else {
+        reinterpret_cast<float*>(A)[(int64_t)i * ld + j] = a;
+      }
+    }
+  }
 }
 
 hipError_t launch_persistent(BQueue* q, BInst* inst, BCtl* ctl, int blocks, hipStream_t s);

@@ -346,19 +346,9 @@ __device__ void phase_gen(BInst* I, uint32_t tile) {
   const int n = I->n;
   const int r0 = tile * kGenRows, r1 = min(n, r0 + kGenRows);
   const uint64_t base = splitmix64(I->seed), sbase = splitmix64(I->seed ^ 0x5BD1E995ull);
-  const float s_n = I->gen_scale, spike = I->gen_spike;
-  for (int i = r0; i < r1; ++i) {
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      const float a = gen_entry(base, sbase, i, j, s_n, spike);
-      if (I->dtype == MAPI_BF16) {
-        uint32_t u = __float_as_uint(a);
-        u += 0x7FFFu + ((u >> 16) & 1u);
-        reinterpret_cast<uint16_t*>(const_cast<void*>(I->A))[(int64_t)i * I->ld + j] = (uint16_t)(u >> 16);
-      } else {
-        reinterpret_cast<float*>(const_cast<void*>(I->A))[(int64_t)i * I->ld + j] = a;
-      }
-    }
-  }
+  void* A = const_cast<void*>(I->A);
+  if (I->dtype == MAPI_BF16) gen_rows<true>(A, I->ld, n, r0, r1, base, sbase, I->gen_scale, I->gen_spike);
+  else gen_rows<false>(A, I->ld, n, r0, r1, base, sbase, I->gen_scale, I->gen_spike);
 }
 
 // Start vector rows; PageRank scalars of w0 into part.
@@ -751,19 +741,29 @@ __global__ void __launch_bounds__(kBT, 4) k_persistent(BQueue* q, BInst* insts, 
 }
 
 // Generated problem written out: A (float32, row pitch ld) and its start vector.
-__global__ void __launch_bounds__(256) k_gen_dense(int n, uint64_t seed, float* A, int64_t ld, float* w0, float s_n,
-                                                 float spike, float inv_sqrt_n) {
+// Each block takes `rows` consecutive rows at a time.
+__global__ void __launch_bounds__(256) k_gen_dense(int n, int rows, uint64_t seed, float* A, int64_t ld, float* w0,
+                                                 float s_n, float spike, float inv_sqrt_n) {
   const uint64_t base = splitmix64(seed), sbase = splitmix64(seed ^ 0x5BD1E995ull);
   const uint64_t vbase = splitmix64(seed ^ 0x1B873593ull);
-  for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    for (int j = threadIdx.x; j < n; j += blockDim.x) A[(int64_t)i * ld + j] = gen_entry(base, sbase, i, j, s_n, spike);
-    if (threadIdx.x == 0 && w0) w0[i] = (splitmix64(vbase + (uint64_t)i) >> 63) ? -inv_sqrt_n : inv_sqrt_n;
+  for (int r0 = blockIdx.x * rows; r0 < n; r0 += gridDim.x * rows) {
+    const int r1 = min(n, r0 + rows);
+    gen_rows<false>(A, ld, n, r0, r1, base, sbase, s_n, spike);
+    if (w0 && threadIdx.x < r1 - r0) {
+      const int i = r0 + threadIdx.x;
+      w0[i] = (splitmix64(vbase + (uint64_t)i) >> 63) ? -inv_sqrt_n : inv_sqrt_n;
+    }
   }
 }
 
 hipError_t launch_gen_dense(int n, uint64_t seed, float* A, int64_t ld, float* w0, hipStream_t s) {
   const GenConsts g = gen_consts(n);
-  hipLaunchKernelGGL(k_gen_dense, dim3(n < 8192 ? n : 8192), dim3(256), 0, s, n, seed, A, ld, w0, g.scale, g.spike, g.w0);
+  // At least ~2048 blocks where n allows, up to 32 rows each (a column sign is
+  // hashed once per block-row group).
+  const int rows = n / 2048 < 1 ? 1 : (n / 2048 > 32 ? 32 : n / 2048);
+  const int64_t groups = ((int64_t)n + rows - 1) / rows;
+  const int grid = (int)(groups < 16384 ? (groups > 0 ? groups : 1) : 16384);
+  hipLaunchKernelGGL(k_gen_dense, dim3(grid), dim3(256), 0, s, n, rows, seed, A, ld, w0, g.scale, g.spike, g.w0);
   return hipGetLastError();
 }
 
