@@ -108,6 +108,7 @@ def run_kernels_mode():
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     mp.mapi_copy_reference(src, dst, reps=5, ctx=ctx)
+    mp.mapi_read_reference(C, reps=5, ctx=ctx)
     for dt, (A, rs) in mats.items():
         for _ in range(5):
             mp.mapi_mavp(A, w0, "min1", row_scale=rs, ctx=ctx)
@@ -127,6 +128,8 @@ def _read_csvs(d, pattern):
 def _kernel_dtype(name):
     if "k_copy16" in name:
         return "copy"
+    if "k_read16" in name:
+        return "read"
     if "k_mavp_dense" not in name:
         return None
     # template argument order: storage type, product, ... (0 = f32, 1 = bf16, 2 = fp8)
@@ -155,6 +158,7 @@ def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write, 
         with open(bench_json) as f:
             det = json.loads(f.read().strip().splitlines()[-1]).get("detail", {})
         live = {dt: det.get(f"mapi_{dt}", {}).get("product_kernel_us") for dt in ("f32", "bf16", "fp8")}
+        live.update({f"read_{dt}": v.get("us") for dt, v in det.get("read_reference", {}).items()})
     if trace:
         lines += ["", "Timed launches (last 100 dispatches of the MAPI min1 product per storage type) "
                   "against the benchmark's own HIP-event timing of the same launches:", "",
@@ -169,6 +173,17 @@ def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write, 
             ev = live.get(dt)
             lines.append(f"| {dt} | `{last[-1][2][:48]}` | {avg:.1f} | {ev:.1f} |" if ev else
                          f"| {dt} | `{last[-1][2][:48]}` | {avg:.1f} | - |")
+        # the read reference: 3 untimed + 10 timed launches per matrix, f32 then bf16 then fp8
+        rd = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+                    for r in trace if "k_read16" in r["Kernel_Name"])
+        if len(rd) >= 39:
+            lines += ["", "Read reference (plain streaming read of the same matrix, `k_read16`), timed launches:", "",
+                      "| matrix | rocprofv3 average (us) | benchmark events (us) |", "|---|---|---|"]
+            for k, dt in enumerate(("f32", "bf16", "fp8")):
+                grp = rd[13 * k + 3:13 * k + 13]
+                avg = sum(x[1] for x in grp) / len(grp) / 1e3
+                ev = live.get(f"read_{dt}")
+                lines.append(f"| {dt} | {avg:.1f} | {ev:.1f} |" if ev else f"| {dt} | {avg:.1f} | - |")
     with open(os.path.join(ROOT, "profiles", "mavp_dense_n16384_kernel_stats.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -651,6 +666,16 @@ def main():
     value = elems / sec / 1e9
     traffic = load_traffic("f32")
 
+    # Attainable read bandwidth on the same matrices: a plain streaming read.
+    reads = {}
+    for dt, (A, _) in mats.items():
+        nbytes = A.numel() * A.element_size()
+        mp.mapi_read_reference(A, reps=3, ctx=ctx)
+        ms = mp.mapi_read_reference(A, reps=10, ctx=ctx)
+        reads[dt] = {"bytes": nbytes, "us": ms * 1e3, "gbs": nbytes / (ms * 1e-3) / 1e9}
+        log(f"read reference {dt}: {ms * 1e3:.1f} us, {reads[dt]['gbs']:.0f} GB/s")
+    detail["read_reference"] = reads
+
     sections = [x for x in args.sections.split(",") if x]
     for name, fn in (("small", lambda: bench_small(mp, ctx, torch)), ("hybrid", lambda: bench_hybrid(mp, ctx, torch)),
                      ("minibatch", lambda: bench_minibatch(mp, ctx, torch)), ("image", lambda: bench_image(mp, ctx, torch)),
@@ -700,7 +725,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_mavp_dense<f32,min1>", "launches_timed": launches,
-                     "algorithmic_bytes_per_launch": product_bytes("f32"), "avg_launch_us": k_ms * 1e3},
+                     "algorithmic_bytes_per_launch": product_bytes("f32"), "avg_launch_us": k_ms * 1e3,
+                     "read_reference_gbs": reads["f32"]["gbs"], "frac_of_read_reference": achieved / reads["f32"]["gbs"]},
         "cpu_baseline": cpu,
         "detail": detail,
     }

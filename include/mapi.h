@@ -174,6 +174,11 @@ mapi_status mapi_mavp_timed(mapi_ctx* ctx, const mapi_dense* A, const float* w, 
  * `bytes` (multiple of 16) from src to dst (device, 16-byte aligned).            */
 mapi_status mapi_copy_reference(mapi_ctx* ctx, const void* src, void* dst, size_t bytes, int32_t reps,
                                 double* avg_ms);
+/* Bandwidth reference: mean time in ms of `reps` plain streaming reads of `bytes`
+ * (multiple of 16) at src (device, 16-byte aligned): non-temporal 16-byte loads,
+ * four per lane in flight, nothing written back.  Uses 256 bytes of the context
+ * workspace.                                                                     */
+mapi_status mapi_read_reference(mapi_ctx* ctx, const void* src, size_t bytes, int32_t reps, double* avg_ms);
 
 /* ---------------------------------------------------------------- solvers */
 

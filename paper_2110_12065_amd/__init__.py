@@ -85,6 +85,7 @@ _SIGS = {
                                   C.POINTER(Tuning), C.c_int32, C.POINTER(C.c_double)]),
     "mapi_copy_reference": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32,
                                       C.POINTER(C.c_double)]),
+    "mapi_read_reference": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.POINTER(C.c_double)]),
     "mapi_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]),
     "rpi_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]),
     "mapi_quantize": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_void_p,
@@ -462,6 +463,16 @@ def mapi_copy_reference(src, dst, reps=5, ctx=None):
     ms = C.c_double()
     _check(lib().mapi_copy_reference(c.handle, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
                                      int(reps), C.byref(ms)))
+    return ms.value
+
+
+def mapi_read_reference(src, reps=5, ctx=None):
+    """Mean ms of a plain streaming read of src (non-temporal 16-byte loads): the
+    attainable-read-bandwidth reference."""
+    c = _ctx_of(ctx, src)
+    nbytes = src.numel() * src.element_size()
+    ms = C.c_double()
+    _check(lib().mapi_read_reference(c.handle, C.c_void_p(src.data_ptr()), nbytes, int(reps), C.byref(ms)))
     return ms.value
 
 

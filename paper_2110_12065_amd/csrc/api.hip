@@ -343,6 +343,30 @@ mapi_status mapi_mavp_timed(mapi_ctx* c, const mapi_dense* A, const float* w, fl
   return time_product(c, da, op, w, y, t, reps, avg_ms);
 }
 
+mapi_status mapi_read_reference(mapi_ctx* c, const void* src, size_t bytes, int32_t reps, double* avg_ms) {
+  if (!c || !src || !avg_ms) return fail(MAPI_ERR_ARG, "NULL argument");
+  if (bytes == 0 || bytes % 16 != 0 || !aligned16(src))
+    return fail(MAPI_ERR_ARG, "bytes must be a non-zero multiple of 16 and src 16-byte aligned");
+  if (reps < 1) return fail(MAPI_ERR_ARG, "reps must be >= 1");
+  HIP_TRY(hipSetDevice(c->device));
+  mapi_status s;
+  if ((s = ensure(&c->ws, &c->ws_bytes, 256, c)) != MAPI_OK) return s;
+  uint32_t* sink = static_cast<uint32_t*>(c->ws);
+  hipEvent_t a = get_event(c), b = get_event(c);
+  if (!a || !b) return fail(MAPI_ERR_HIP, "event creation failed");
+  HIP_TRY(launch_read16(src, (int64_t)(bytes / 16), sink, c->cu_count, c->stream));
+  HIP_TRY(hipEventRecord(a, c->stream));
+  for (int r = 0; r < reps; ++r) HIP_TRY(launch_read16(src, (int64_t)(bytes / 16), sink, c->cu_count, c->stream));
+  HIP_TRY(hipEventRecord(b, c->stream));
+  HIP_TRY(hipEventSynchronize(b));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, a, b));
+  c->pool.push_back(a);
+  c->pool.push_back(b);
+  *avg_ms = ms / reps;
+  return MAPI_OK;
+}
+
 mapi_status mapi_autotune_dense(mapi_ctx* c, const mapi_dense* A, int32_t op, int32_t reps, mapi_tuning* best,
                                 double* best_ms) {
   if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");

@@ -136,8 +136,14 @@ struct DenseTuning {
 
 // LDS bytes of the dense product kernel for a w_in_lds mode: w (mode 1) or |w|
 // plus one sign word per 4 columns (mode 2, FP8 storage).
+// Floats of w staged in LDS: whole 16-byte matrix vectors (VE = 16 / element
+// size columns each), padded to groups of 64 vectors for the chunk-interleaved order.
+__host__ __device__ inline int64_t dense_lds_w_floats(int dtype, int64_t n_cols) {
+  const int64_t ve = dtype == MAPI_FP8_E4M3 ? 16 : (dtype == MAPI_BF16 ? 8 : 4);
+  return (n_cols / ve + 63) / 64 * 64 * ve;
+}
 inline size_t dense_lds_bytes(int dtype, int64_t n_cols, int mode) {
-  const size_t wbytes = (size_t)((n_cols + 3) & ~int64_t(3)) * 4;
+  const size_t wbytes = (size_t)dense_lds_w_floats(dtype, n_cols) * 4;
   if (mode == 0) return 0;
   return (mode == 2 && dtype == MAPI_FP8_E4M3) ? wbytes + (size_t)((n_cols >> 2) + 4) * 4 : wbytes;
 }
@@ -182,6 +188,7 @@ hipError_t launch_mgs_append(double* P, int64_t D, int k, const float* w, float*
 int pr_scalar_blocks(int64_t n);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, int cu_count, hipStream_t s);
+hipError_t launch_read16(const void* src, int64_t n16, uint32_t* sink, int cu_count, hipStream_t s);
 
 int image_max_n();
 hipError_t launch_img_center(const float* V, int64_t P, int N, int64_t ldv, float* Vc, int64_t ldc, float* m,

@@ -21,6 +21,18 @@ template <> struct Traits<MAPI_F32> { static constexpr int VE = 4; static conste
 template <> struct Traits<MAPI_BF16> { static constexpr int VE = 8; static constexpr int ESZ = 2; };
 template <> struct Traits<MAPI_FP8_E4M3> { static constexpr int VE = 16; static constexpr int ESZ = 1; };
 
+// Chunk-interleaved LDS order of w: 16-byte matrix vectors in groups of 64 (one
+// per lane of a wave); within a group, chunk q (the q-th float4 of the vector's
+// VE weights) of the group's l-th vector sits at float4 q * 64 + l.  A wave
+// reading chunk q of 64 consecutive vectors touches one contiguous 1 KiB, and
+// chunk q is a fixed offset from chunk 0.  For float32 the order is the natural
+// one.  Columns past the last whole vector are not staged.
+template <int DT>
+__device__ __forceinline__ int perm_base(int v) {
+  constexpr int Q = Traits<DT>::VE / 4;
+  return (v & ~63) * Q + (v & 63);
+}
+
 // Decode one 16-byte vector of stored elements to float32 (FP8: times the row scale).
 // P2 (FP8 rows whose scale is a positive power of two): the gfx950 scaled conversion
 // applies the scale's exponent inside the conversion, which for such scales is the
@@ -101,7 +113,12 @@ __device__ __forceinline__ uint4 load16(const unsigned char* p) {
 // flips the signs of four stored values before decoding, so each term is
 // op(a * sign(w), |w|) -- the same value as op(a, w) -- without per-element sign
 // work.  wsign: the signed w, used for the ragged tail.
-template <int DT, int OP, int RW, int U, bool NT, bool PF = false, bool P2 = false>
+//
+// PERM: wv is in LDS in chunk-interleaved order (perm_base), so each 16-byte LDS
+// read of a wave covers one contiguous 1 KiB instead of a lane stride of VE * 4
+// bytes, which puts 2 (bf16) or 4 (FP8) lanes of every 8 on the same banks; the
+// ragged tail then reads wsign (w in global memory).
+template <int DT, int OP, int RW, int U, bool NT, bool PF = false, bool P2 = false, bool PERM = false>
 __device__ __forceinline__ void rows_product(const unsigned char* const* rp, const float* sc, const float* wv,
                                              int n_cols, int lane, float* out, const uint32_t* smask = nullptr,
                                              const float* wsign = nullptr) {
@@ -115,10 +132,11 @@ __device__ __forceinline__ void rows_product(const unsigned char* const* rp, con
   auto vec = [&](int vv, const uint4* raws) {
     float wf[VE];
     uint32_t ws[VE];
-    const float4* wp = reinterpret_cast<const float4*>(wv + (int64_t)vv * VE);
+    const float4* wp = PERM ? reinterpret_cast<const float4*>(wv) + perm_base<DT>(vv)
+                            : reinterpret_cast<const float4*>(wv + (int64_t)vv * VE);
 #pragma unroll
     for (int q = 0; q < VE / 4; ++q) {
-      const float4 t = wp[q];
+      const float4 t = PERM ? wp[q * 64] : wp[q];
       wf[4 * q] = t.x; wf[4 * q + 1] = t.y; wf[4 * q + 2] = t.z; wf[4 * q + 3] = t.w;
     }
     uint4 m = make_uint4(0u, 0u, 0u, 0u);
@@ -163,7 +181,7 @@ __device__ __forceinline__ void rows_product(const unsigned char* const* rp, con
   // ragged tail: fewer than VE columns past the last full vector
   const int j = nvec * VE + lane;
   if (j < n_cols) {
-    const float wj = PF ? wsign[j] : wv[j];
+    const float wj = (PF || PERM) ? wsign[j] : wv[j];
     const uint32_t sj = sign_bit(wj);
 #pragma unroll
     for (int r = 0; r < RW; ++r) acc[r][0] = op_acc<OP>(acc[r][0], decode_one<DT>(rp[r], j, sc[r]), wj, sj);
@@ -185,28 +203,26 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
 
   constexpr bool PF = WL == 2 && DT == MAPI_FP8_E4M3;
   constexpr bool WLDS = WL != 0;
+  constexpr int VE = Traits<DT>::VE;
+  const int nvec = n_cols / VE;
   const float* wv = w;
   const uint32_t* smask = nullptr;
-  if constexpr (PF) {
-    // |w| and one sign word per 4 columns
-    const int nw4 = n_cols >> 2;
-    uint32_t* sm = reinterpret_cast<uint32_t*>(w_lds + ((n_cols + 3) & ~3));
-    for (int k = threadIdx.x; k < nw4; k += blockDim.x) {
-      const float4 t = reinterpret_cast<const float4*>(w)[k];
-      reinterpret_cast<float4*>(w_lds)[k] = make_float4(fabsf(t.x), fabsf(t.y), fabsf(t.z), fabsf(t.w));
-      sm[k] = (sign_bit(t.x) >> 24) | (sign_bit(t.y) >> 16) | (sign_bit(t.z) >> 8) | sign_bit(t.w);
+  if constexpr (WLDS) {
+    // whole vectors' w in chunk-interleaved order (|w| with PF, plus one sign word
+    // per 4 columns in natural order after the staged region)
+    const int np4 = nvec * (VE / 4);
+    for (int k = threadIdx.x; k < np4; k += blockDim.x) {
+      float4 t = reinterpret_cast<const float4*>(w)[k];
+      if constexpr (PF) {
+        uint32_t* sm = reinterpret_cast<uint32_t*>(w_lds + dense_lds_w_floats(DT, n_cols));
+        sm[k] = (sign_bit(t.x) >> 24) | (sign_bit(t.y) >> 16) | (sign_bit(t.z) >> 8) | sign_bit(t.w);
+        t = make_float4(fabsf(t.x), fabsf(t.y), fabsf(t.z), fabsf(t.w));
+      }
+      reinterpret_cast<float4*>(w_lds)[perm_base<DT>(k / (VE / 4)) + (k % (VE / 4)) * 64] = t;
     }
-    for (int j = (nw4 << 2) + threadIdx.x; j < n_cols; j += blockDim.x) w_lds[j] = fabsf(w[j]);
     __syncthreads();
     wv = w_lds;
-    smask = sm;
-  } else if constexpr (WLDS) {
-    const int nv4 = n_cols >> 2;
-    for (int v = threadIdx.x; v < nv4; v += blockDim.x)
-      reinterpret_cast<float4*>(w_lds)[v] = reinterpret_cast<const float4*>(w)[v];
-    for (int j = (nv4 << 2) + threadIdx.x; j < n_cols; j += blockDim.x) w_lds[j] = w[j];
-    __syncthreads();
-    wv = w_lds;
+    if constexpr (PF) smask = reinterpret_cast<const uint32_t*>(w_lds + dense_lds_w_floats(DT, n_cols));
   }
 
   const int lane = threadIdx.x & (kWave - 1);
@@ -229,10 +245,10 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
       bool p2 = true;
 #pragma unroll
       for (int r = 0; r < RW; ++r) p2 = p2 && pow2_scale(sc[r]);
-      if (p2) rows_product<DT, OP, RW, U, NT, PF, true>(rp, sc, wv, n_cols, lane, sums, smask, w);
-      else rows_product<DT, OP, RW, U, NT, PF, false>(rp, sc, wv, n_cols, lane, sums, smask, w);
+      if (p2) rows_product<DT, OP, RW, U, NT, PF, true, WLDS>(rp, sc, wv, n_cols, lane, sums, smask, w);
+      else rows_product<DT, OP, RW, U, NT, PF, false, WLDS>(rp, sc, wv, n_cols, lane, sums, smask, w);
     } else {
-      rows_product<DT, OP, RW, U, NT, PF>(rp, sc, wv, n_cols, lane, sums, smask, w);
+      rows_product<DT, OP, RW, U, NT, PF, false, WLDS>(rp, sc, wv, n_cols, lane, sums, smask, w);
     }
 #pragma unroll
     for (int r = 0; r < RW; ++r) {

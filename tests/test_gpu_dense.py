@@ -235,10 +235,12 @@ def test_full_size_n16384_sampled_rows_and_iterates():
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
-def test_every_launch_shape_gives_the_same_product(dtype):
+@pytest.mark.parametrize("m,n", [(301, 2061), (67, 1000)])
+def test_every_launch_shape_gives_the_same_product(dtype, m, n):
     # Each row's sum is formed by one wave in a fixed lane order whatever the launch shape, and
     # the FP8 sign-word staging (w_in_lds 2) flips signs exactly, so y is bitwise shape-independent.
-    m, n = 301, 2061
+    # n = 1000 leaves a partial group of 64 vectors in the LDS order (62 FP8 vectors, 125 bf16)
+    # and a ragged tail; n = 2061 whole FP8 groups with a 13-column tail.
     rng = np.random.default_rng(11)
     A = rng.standard_normal((m, n)).astype(np.float32)
     w = rng.standard_normal(n).astype(np.float32)
@@ -335,3 +337,13 @@ def test_fp8_mixed_power_of_two_and_general_scales():
             assert (np.abs(yh - ref) <= TOL * np.maximum(terms, 1e-30)).all()
         else:
             np.testing.assert_array_equal(yh, first)
+
+
+def test_read_reference_times_and_rejects_bad_sizes():
+    x = torch.ones(1 << 20, dtype=torch.float32, device="cuda")
+    ms = mp.mapi_read_reference(x, reps=3)
+    assert 0.0 < ms < 100.0
+    with pytest.raises(mp.MapiError):
+        mp.mapi_read_reference(x[1:], reps=1)           # 4-byte offset: not 16-byte aligned
+    with pytest.raises(mp.MapiError):
+        mp.mapi_read_reference(x, reps=0)
