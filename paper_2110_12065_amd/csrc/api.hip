@@ -242,6 +242,7 @@ void mapi_destroy(mapi_ctx* c) {
   if (c->ws) (void)hipFree(c->ws);
   if (c->big) (void)hipFree(c->big);
   if (c->mid) (void)hipFree(c->mid);
+  if (c->gws) (void)hipFree(c->gws);
   mapi_batch_release(c);
   if (c->st_host) (void)hipHostFree(c->st_host);
   delete c;
@@ -502,6 +503,17 @@ mapi_status mapi_quantize(mapi_ctx* c, const float* A, int64_t n_rows, int64_t n
   return MAPI_OK;
 }
 
+// Device memory for the Gram build's partial tiles (none for the min forms).
+static mapi_status gram_ws(mapi_ctx* c, int64_t D, int64_t N, int op, double** out) {
+  const size_t need = gram_workspace_bytes(D, N, op);
+  *out = nullptr;
+  if (need == 0) return MAPI_OK;
+  mapi_status s;
+  if ((s = ensure(&c->gws, &c->gws_bytes, need, c)) != MAPI_OK) return s;
+  *out = static_cast<double*>(c->gws);
+  return MAPI_OK;
+}
+
 mapi_status mapi_mingram(mapi_ctx* c, const float* X, int64_t D, int64_t N, int64_t ldx, double scale, int32_t op,
                          float* A_out, int64_t lda) {
   if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
@@ -511,9 +523,12 @@ mapi_status mapi_mingram(mapi_ctx* c, const float* X, int64_t D, int64_t N, int6
   if (!aligned16(X) || ldx % 4 != 0) return fail(MAPI_ERR_ARG, "X base and row pitch must be 16-byte aligned");
   if (op != MAPI_OP_MIN1 && op != MAPI_OP_MIN2 && op != MAPI_OP_DOT) return fail(MAPI_ERR_ARG, "op %d", op);
   HIP_TRY(hipSetDevice(c->device));
+  double* gw = nullptr;
+  mapi_status s;
+  if ((s = gram_ws(c, D, N, op, &gw)) != MAPI_OK) return s;
   {
     Timed tm(c, MAPI_K_GRAM);
-    HIP_TRY(launch_gram(X, D, N, ldx, scale, op, A_out, lda, nullptr, c->stream));
+    HIP_TRY(launch_gram(X, D, N, ldx, scale, op, A_out, lda, gw, c->stream));
   }
   HIP_TRY(hipStreamSynchronize(c->stream));
   collect_timing(c);
@@ -549,9 +564,11 @@ mapi_status mapi_pca_topk(mapi_ctx* c, const float* X, int64_t D, int64_t N, int
   double* qpart = reinterpret_cast<double*>(base + o_qp);
   float* wtmp = reinterpret_cast<float*>(base + o_w);
   const bool rpi = method == MAPI_METHOD_RPI;
+  double* gw = nullptr;
+  if ((s = gram_ws(c, D, N, rpi ? MAPI_OP_DOT : opts->op, &gw)) != MAPI_OK) return s;
   {
     Timed tm(c, MAPI_K_GRAM);
-    HIP_TRY(launch_gram(X, D, N, ldx, scale, rpi ? MAPI_OP_DOT : opts->op, A, ldA, nullptr, c->stream));
+    HIP_TRY(launch_gram(X, D, N, ldx, scale, rpi ? MAPI_OP_DOT : opts->op, A, ldA, gw, c->stream));
   }
   mapi_opts o = *opts;
   o.final_l2 = 0;
@@ -621,9 +638,11 @@ mapi_status mapi_image_reconstruct(mapi_ctx* c, const float* V, int64_t P, int32
   float* w1 = W;
   float* w2 = W + P;
   HIP_TRY(launch_img_center(V, P, N, ldv, Vc, ldc, m, c->stream));
+  double* gw = nullptr;
+  if ((s = gram_ws(c, P, N, rpi ? MAPI_OP_DOT : MAPI_OP_MIN1, &gw)) != MAPI_OK) return s;
   {
     Timed tm(c, MAPI_K_GRAM);
-    HIP_TRY(launch_gram(Vc, P, N, ldc, 1.0 / (double)(N - 1), rpi ? MAPI_OP_DOT : MAPI_OP_MIN1, C, ldA, nullptr,
+    HIP_TRY(launch_gram(Vc, P, N, ldc, 1.0 / (double)(N - 1), rpi ? MAPI_OP_DOT : MAPI_OP_MIN1, C, ldA, gw,
                         c->stream));
   }
   // MAPI vectors as Algorithm 1 returns them (l1 units: w (+) w = ||w||_1 = 1 makes

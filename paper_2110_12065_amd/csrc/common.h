@@ -167,8 +167,11 @@ hipError_t launch_quant_bf16(const float* A, int64_t n_rows, int64_t n_cols, int
 hipError_t launch_quant_fp8(const float* A, int64_t n_rows, int64_t n_cols, int64_t lda, uint8_t* out,
                             int64_t ldo, float* scale, hipStream_t s);
 
+// Gram build (eq. 5 min forms, eq. 2 dot); ws: gram_workspace_bytes(D, N, op) bytes
+// of device memory (float64 partial tiles of the covariance build), or NULL when that is 0.
+size_t gram_workspace_bytes(int64_t D, int64_t N, int op);
 hipError_t launch_gram(const float* X, int64_t D, int64_t N, int64_t ldx, double scale, int op, float* A,
-                       int64_t lda, double* acc64, hipStream_t s);
+                       int64_t lda, double* ws, hipStream_t s);
 
 hipError_t launch_csr_prep(const int32_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz, uint8_t* dangling,
                            int32_t* err, hipStream_t s);

@@ -59,6 +59,9 @@ struct mapi_ctx {
   // intermediate iterate of the MAPI -> RPI hybrid
   void* mid = nullptr;
   size_t mid_bytes = 0;
+  // float64 partial tiles of the covariance build
+  void* gws = nullptr;
+  size_t gws_bytes = 0;
   // timing
   bool timing = false;
   struct Rec { int kind; hipEvent_t a, b; };

@@ -1,14 +1,14 @@
 // Gram build over the rows of a data matrix X (D x N, samples as columns):
 //   A_ij = scale * sum_k op(X_ik, X_jk)
-// op min1/min2: the min-covariance of eq. (5); op dot: the covariance of eq. (2).
+// op min1/min2: the min-covariance of eq. (5); op dot: the covariance of eq. (2),
+// built on the matrix cores (k_gram_mfma below).
 //
-// Upper-triangle 64 x 64 output tiles, one per block of 256 threads, each thread
+// Min forms: upper-triangle 64 x 64 output tiles, one per block of 256 threads, each thread
 // a 4 x 4 register tile.  X is streamed through LDS in slabs of 32 samples
 // (transposed so a thread reads its 4 rows and 4 columns as two 16-byte LDS
 // reads per sample), double-buffered through registers.  Terms are accumulated
 // in float32 within a run of 256 samples and in float64 across runs.  The
-// min forms use one xor, one med3 and one add per term on the vector ALU; the
-// dot form uses one fused multiply-add.
+// min forms use one xor, one med3 and one add per term on the vector ALU.
 #include "common.h"
 
 namespace mapi {
@@ -112,10 +112,28 @@ k_gram(const float* __restrict__ X, int D, int64_t N, int64_t ldx, double scale,
       uint32_t sb[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) sb[q] = sign_bit(b[q]);
+      if constexpr (OP == MAPI_OP_MIN1) {
+        // the op_acc<min1> arithmetic, written as three passes over the 16 terms so
+        // that the independent terms interleave instead of running through one temporary
+        float t[4][4];
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
+        for (int p = 0; p < 4; ++p)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) accf[p][q] = op_acc<OP>(accf[p][q], a[p], b[q], sb[q]);
+          for (int q = 0; q < 4; ++q) t[p][q] = flip_sign(a[p], sb[q]);
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) t[p][q] = __builtin_amdgcn_fmed3f(t[p][q], -fabsf(b[q]), fabsf(b[q]));
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) accf[p][q] += t[p][q];
+      } else {
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) accf[p][q] = op_acc<OP>(accf[p][q], a[p], b[q], sb[q]);
+      }
     }
     if (((sidx + 1) * GKS) % GFLUSH == 0 || sidx + 1 == nslabs) {
 #pragma unroll
@@ -157,9 +175,221 @@ k_gram(const float* __restrict__ X, int D, int64_t N, int64_t ldx, double scale,
   }
 }
 
+// ---------------------------------------------------------------- covariance on the matrix cores
+// The dot form (eq. 2 covariance, the RPI build) is a dense contraction and runs on
+// v_mfma_f32_32x32x2f32; the min forms have no product and stay on the vector ALU.
+//
+// Upper-triangle 128 x 128 output tiles, 512 threads: wave (wr, wc) of 8 owns rows
+// 32 wr .. 32 wr + 31 and columns 64 wc .. 64 wc + 63 of the tile as two 32 x 32
+// accumulators.  For this instruction lane l supplies A[l % 32][l / 32] and
+// B[l / 32][l % 32] and holds C[8 (v / 4) + 4 (l / 32) + v % 4][l % 32] in accumulator
+// register v.  X is staged through LDS in slabs of MKS samples of the tile's 128 + 128
+// rows (each row padded by 4 floats: a pitch of an odd number of 16-byte units puts the
+// 16-byte reads of 16 consecutive rows on distinct banks), double-buffered through
+// registers.  Half h of a wave takes samples (MKS / 2) h .. (MKS / 2) (h + 1) - 1 of a
+// slab, so one 16-byte LDS read feeds four MFMA steps, and the two halves' terms in a
+// step are two samples of the same pair of rows.  Accumulation: float32 within runs of 256 samples (the matrix cores' own
+// adds), float64 across runs.  The sample axis is split into KC chunks when that
+// fills the chip better (KC depends only on D and N, so results do not depend on the
+// device): each block then writes a float64 partial tile and k_gram_reduce sums the
+// chunks in order.  With one chunk the block writes its tile (and the mirror) itself.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int MT = 128;         // tile edge
+constexpr int MKS = 64;         // samples per LDS slab
+constexpr int MROW = MKS + 4;   // staged row pitch (floats): an odd number of 16-byte units
+constexpr int MRUN = 256 / MKS; // slabs per float32 run (256 samples)
+constexpr int MSP = MT + 1;     // pitch of the staged output tile
+constexpr int MLPR = MKS / 4;   // loader threads per staged row (one float4 each)
+constexpr int MLP = 2 * MT * MLPR / 512;   // float4s each of the 512 threads loads per slab
+
+// Tile (i0, j0) of A from S (float, row pitch MSP) and, with mirror, its transpose at (j0, i0).
+__device__ void gram_write_tile(const float* S, int i0, int j0, int D, float* __restrict__ A, int64_t lda, bool mirror) {
+  for (int e = threadIdx.x; e < MT * MT; e += blockDim.x) {
+    const int il = e / MT, jl = e % MT;
+    if (i0 + il < D && j0 + jl < D) A[(int64_t)(i0 + il) * lda + j0 + jl] = S[il * MSP + jl];
+  }
+  if (!mirror) return;
+  for (int e = threadIdx.x; e < MT * MT; e += blockDim.x) {
+    const int jl = e / MT, il = e % MT;
+    if (i0 + il < D && j0 + jl < D) A[(int64_t)(j0 + jl) * lda + i0 + il] = S[il * MSP + jl];
+  }
+}
+
+template <bool SPLIT>
+__global__ void __launch_bounds__(512)
+k_gram_mfma(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t chunk, int tiles, double scale,
+            float* __restrict__ A, int64_t lda, double* __restrict__ part) {
+  __shared__ float4 lds4[2 * 2 * MT * MROW / 4];
+  float* lds = reinterpret_cast<float*>(lds4);
+  const int T = (D + MT - 1) / MT;
+  const int tile = blockIdx.x % tiles;
+  const int cidx = blockIdx.x / tiles;
+  int ti, tj;
+  tile_coords(tile, T, &ti, &tj);
+  const int i0 = ti * MT, j0 = tj * MT;
+  const int64_t kb = (int64_t)cidx * chunk;
+  const int64_t ke = min(N, kb + chunk);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int h = lane >> 5, r = lane & 31;
+
+  // loader: staged row sr = lrow + (512 / MLPR) p is row sr of the I block (sr < 128)
+  // or row sr - 128 of the J block; lk selects one of the slab's MLPR float4s
+  const int lrow = tid / MLPR, lk = (tid % MLPR) * 4;
+  float4 pre[MLP];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int p = 0; p < MLP; ++p) {
+      const int sr = lrow + (512 / MLPR) * p;
+      const int row = sr < MT ? i0 + sr : j0 + sr - MT;
+      const int64_t k = k0 + lk;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (row < D) {
+        const float* src = X + (int64_t)row * ldx + k;
+        if (k + 3 < ke) {
+          v = *reinterpret_cast<const float4*>(src);
+        } else {
+          if (k + 0 < ke) v.x = src[0];
+          if (k + 1 < ke) v.y = src[1];
+          if (k + 2 < ke) v.z = src[2];
+        }
+      }
+      pre[p] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < MLP; ++p)
+      *reinterpret_cast<float4*>(lds + (buf * 2 * MT + lrow + (512 / MLPR) * p) * MROW + lk) = pre[p];
+  };
+
+  f32x16 acc0 = {}, acc1 = {};
+  double d0[16], d1[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) d0[v] = d1[v] = 0.0;
+
+  const int64_t nslabs = (ke - kb + MKS - 1) / MKS;
+  load(kb);
+  store(0);
+  __syncthreads();
+  for (int64_t sl = 0; sl < nslabs; ++sl) {
+    const int buf = (int)(sl & 1);
+    if (sl + 1 < nslabs) load(kb + (sl + 1) * MKS);
+    const float* pa = lds + (buf * 2 * MT + wr * 32 + r) * MROW + (MKS / 2) * h;
+    const float* pb = lds + (buf * 2 * MT + MT + wc * 64 + r) * MROW + (MKS / 2) * h;
+#pragma unroll
+    for (int q = 0; q < MKS / 8; ++q) {
+      const float4 a = *reinterpret_cast<const float4*>(pa + 4 * q);
+      const float4 b0 = *reinterpret_cast<const float4*>(pb + 4 * q);
+      const float4 b1 = *reinterpret_cast<const float4*>(pb + 32 * MROW + 4 * q);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b0.x, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b1.x, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b0.y, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b1.y, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b0.z, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b1.z, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b0.w, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b1.w, acc1, 0, 0, 0);
+    }
+    if ((sl + 1) % MRUN == 0 || sl + 1 == nslabs) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        d0[v] += (double)acc0[v];
+        d1[v] += (double)acc1[v];
+      }
+      acc0 = f32x16{};
+      acc1 = f32x16{};
+    }
+    if (sl + 1 < nslabs) {
+      store(buf ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // accumulator register v of tile t: row 32 wr + 8 (v / 4) + 4 h + v % 4, column 64 wc + 32 t + r
+  if constexpr (SPLIT) {
+    double* out = part + ((int64_t)cidx * tiles + tile) * (MT * MT);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int il = wr * 32 + (v >> 2) * 8 + h * 4 + (v & 3);
+      out[il * MT + wc * 64 + r] = d0[v];
+      out[il * MT + wc * 64 + 32 + r] = d1[v];
+    }
+  } else {
+    __syncthreads();      // the staging buffers are reused for the output tile
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int il = wr * 32 + (v >> 2) * 8 + h * 4 + (v & 3);
+      lds[il * MSP + wc * 64 + r] = (float)(scale * d0[v]);
+      lds[il * MSP + wc * 64 + 32 + r] = (float)(scale * d1[v]);
+    }
+    __syncthreads();
+    gram_write_tile(lds, i0, j0, D, A, lda, ti != tj);
+  }
+}
+
+// Sum of the KC float64 partial tiles in chunk order, scaled and rounded once.
+__global__ void __launch_bounds__(256)
+k_gram_reduce(const double* __restrict__ part, int kc, int tiles, int D, double scale, float* __restrict__ A,
+              int64_t lda) {
+  __shared__ float S[MT * MSP];
+  const int T = (D + MT - 1) / MT;
+  int ti, tj;
+  tile_coords(blockIdx.x, T, &ti, &tj);
+  for (int e = threadIdx.x; e < MT * MT; e += blockDim.x) {
+    double sum = 0.0;
+    for (int c = 0; c < kc; ++c) sum += part[((int64_t)c * tiles + blockIdx.x) * (MT * MT) + e];
+    S[(e / MT) * MSP + e % MT] = (float)(scale * sum);
+  }
+  __syncthreads();
+  gram_write_tile(S, ti * MT, tj * MT, D, A, lda, ti != tj);
+}
+
+// Sample chunks of the covariance build: the KC in 1..8 (at most one per 256-sample
+// run) that minimises rounds of 256 resident blocks per chunk of work.
+struct GramSplit {
+  int64_t tiles, chunk;
+  int kc;
+};
+static GramSplit gram_split(int64_t D, int64_t N) {
+  const int64_t T = (D + MT - 1) / MT, tiles = T * (T + 1) / 2;
+  const int64_t runs = (N + 255) / 256;
+  int best = 1;
+  double best_cost = 1e300;
+  for (int kc = 1; kc <= 8 && kc <= runs; ++kc) {
+    const double cost = (double)((tiles * kc + 255) / 256) / kc;
+    if (cost < best_cost - 1e-12) {
+      best_cost = cost;
+      best = kc;
+    }
+  }
+  const int64_t chunk = (runs + best - 1) / best * 256;
+  return GramSplit{tiles, chunk, (int)((N + chunk - 1) / chunk)};
+}
+
+size_t gram_workspace_bytes(int64_t D, int64_t N, int op) {
+  if (op != MAPI_OP_DOT) return 0;
+  const GramSplit g = gram_split(D, N);
+  return g.kc > 1 ? (size_t)g.kc * (size_t)g.tiles * MT * MT * sizeof(double) : 0;
+}
+
 hipError_t launch_gram(const float* X, int64_t D, int64_t N, int64_t ldx, double scale, int op, float* A, int64_t lda,
-                       double* acc64, hipStream_t s) {
-  (void)acc64;
+                       double* ws, hipStream_t s) {
+  if (op == MAPI_OP_DOT) {
+    const GramSplit g = gram_split(D, N);
+    if (g.kc > 1) {
+      if (!ws) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_gram_mfma<true>, dim3((unsigned)(g.tiles * g.kc)), dim3(512), 0, s, X, (int)D, N, ldx,
+                         g.chunk, (int)g.tiles, scale, A, lda, ws);
+      hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)g.tiles), dim3(256), 0, s, ws, g.kc, (int)g.tiles, (int)D,
+                         scale, A, lda);
+    } else {
+      hipLaunchKernelGGL(k_gram_mfma<false>, dim3((unsigned)g.tiles), dim3(512), 0, s, X, (int)D, N, ldx, g.chunk,
+                         (int)g.tiles, scale, A, lda, nullptr);
+    }
+    return hipGetLastError();
+  }
   const int T = (int)((D + GT - 1) / GT);
   const int blocks = T * (T + 1) / 2;
   switch (op) {
@@ -168,9 +398,6 @@ hipError_t launch_gram(const float* X, int64_t D, int64_t N, int64_t ldx, double
       break;
     case MAPI_OP_MIN2:
       hipLaunchKernelGGL(k_gram<MAPI_OP_MIN2>, dim3(blocks), dim3(256), 0, s, X, (int)D, N, ldx, scale, A, lda);
-      break;
-    case MAPI_OP_DOT:
-      hipLaunchKernelGGL(k_gram<MAPI_OP_DOT>, dim3(blocks), dim3(256), 0, s, X, (int)D, N, ldx, scale, A, lda);
       break;
     default:
       return hipErrorInvalidValue;

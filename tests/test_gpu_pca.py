@@ -15,8 +15,11 @@ TOL = 1e-5
 
 
 @pytest.mark.parametrize("op", ["min1", "min2", "dot"])
-@pytest.mark.parametrize("shape", [(1, 1), (5, 7), (64, 300), (130, 1000), (200, 4099)])
+@pytest.mark.parametrize("shape", [(1, 1), (5, 7), (64, 300), (130, 1000), (200, 4099), (1000, 200)])
 def test_gram_dyadic_bitexact(op, shape):
+    # dot: (5, 7) and (1000, 200) take one sample chunk (36 tiles of 128 at D = 1000, each written
+    # with its mirror by the matrix-core kernel); (64, 300), (130, 1000) and (200, 4099) split the
+    # samples into 2, 4 and 6 chunks summed by the reduction kernel
     D, N = shape
     print(f"[case] gram dyadic {op} {shape}", flush=True)
     X = synth.dyadic_matrix(D, N, seed=D * 13 + N)
@@ -83,6 +86,15 @@ def test_full_size_gram_sampled_entries():
         bound = oracle.mingram_entry(np.abs(X[[i]]), 0, 0, 1.0 / N) if i == j else \
             float(np.sum(np.minimum(np.abs(X[i].astype(np.float64)), np.abs(X[j].astype(np.float64)))) / N)
         assert abs(A[i, j] - ref) <= TOL * bound, (i, j)
+    print("[case] full PCA covariance (matrix cores, 8 sample chunks)", flush=True)
+    del A
+    C = mp.mapi_mingram(Xd, 1.0 / N, "dot").cpu().numpy()
+    np.testing.assert_array_equal(C, C.T)
+    for i, j in pairs:
+        ref = oracle.mingram_entry(X, i, j, 1.0 / N, "dot")
+        bound = float(np.sum(np.abs(X[i].astype(np.float64) * X[j].astype(np.float64))) / N)
+        assert abs(C[i, j] - ref) <= TOL * bound, (i, j)
+    del C
     print("[case] full PCA top-8", flush=True)
     W0 = synth.start_vectors(D, 8, seed=78)
     P, infos = mp.mapi_pca_topk(Xd, 8, to_dev(W0), method="mapi", max_iters=50)
