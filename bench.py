@@ -467,10 +467,20 @@ def bench_pca(mp, ctx, torch, D=4096, N=65536, k=8, seed=77):
     return out
 
 
-def bench_pagerank(mp, ctx, torch, n=1 << 22, seed=2022):
+_GRAPHS = {}
+
+
+def _graph(n, seed):
+    """The power-law graph of the PageRank workload (host CSR), generated once per run."""
     import synth
+    if (n, seed) not in _GRAPHS:
+        _GRAPHS[(n, seed)] = synth.powerlaw_graph(n, seed)
+    return _GRAPHS[(n, seed)]
+
+
+def bench_pagerank(mp, ctx, torch, n=1 << 22, seed=2022):
     log("PageRank: generating the 2^22-node graph on the host")
-    g = synth.powerlaw_graph(n, seed)
+    g = _graph(n, seed)
     rp, col, val = (torch.from_numpy(g[x]).cuda() for x in ("row_ptr", "col", "val"))
     nnz = int(g["col"].size)
     bytes_iter = 8.0 * nnz + 4.0 * (n + 1) + 8.0 * n        # links, row pointers, w once, y once
@@ -496,6 +506,124 @@ def bench_pagerank(mp, ctx, torch, n=1 << 22, seed=2022):
         out[f"{meth}_csr_kernel_us"] = kms * 1e3
         out[f"{meth}_gedges_s"] = nnz / (kms * 1e-3) / 1e9
         out[f"{meth}_csr_kernel_gbs"] = bytes_iter / (kms * 1e-3) / 1e9
+    return out
+
+
+def _cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def oracle_workers():
+    """Worker processes for the row-parallel oracle runs: the usable host CPUs, at most 16."""
+    return max(1, min(16, _cpu_info()["usable_cpus"] or 1))
+
+
+_ORACLE_A = None
+
+
+def _oracle_worker_init(shm_name, shape):
+    # a spawned worker (it never touches the GPU) maps the shared FP64 matrix
+    global _ORACLE_A, _ORACLE_SHM
+    from multiprocessing import shared_memory
+    _ORACLE_SHM = shared_memory.SharedMemory(name=shm_name)
+    _ORACLE_A = np.ndarray(shape, dtype=np.float64, buffer=_ORACLE_SHM.buf)
+
+
+def _oracle_worker_rows(task):
+    import oracle
+    r0, r1, w = task
+    return oracle.mavp(_ORACLE_A[r0:r1], w)
+
+
+def oracle_parallel_iterations(A, w0, seconds, max_iters, workers, rows=256):
+    """MAPI iterations of the unchanged oracle product with its rows split over `workers` spawned
+    processes (the matrix in shared memory, one block of rows per task); returns (iterations,
+    seconds).  The processes are children started with a fresh interpreter."""
+    import multiprocessing as mproc
+    from multiprocessing import shared_memory
+    shm = shared_memory.SharedMemory(create=True, size=A.nbytes)
+    try:
+        As = np.ndarray(A.shape, dtype=np.float64, buffer=shm.buf)
+        As[:] = A
+        blocks = [(r, min(A.shape[0], r + rows)) for r in range(0, A.shape[0], rows)]
+        with mproc.get_context("spawn").Pool(workers, _oracle_worker_init, (shm.name, A.shape)) as pool:
+            pool.map(_oracle_worker_rows, [(0, 1, w0)] * workers)          # start-up, untimed
+            w = np.asarray(w0, dtype=np.float64)
+            its = 0
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < seconds and its < max_iters:
+                y = np.concatenate(pool.map(_oracle_worker_rows, [(a, b, w) for a, b in blocks]))
+                w = y / np.abs(y).sum()
+                its += 1
+            dt = time.perf_counter() - t0
+        del As
+        return its, dt
+    finally:
+        shm.close()
+        shm.unlink()
+
+
+def bench_oracle():
+    """The FP64 CPU oracle, untuned, on bounded samples of each workload, one host thread:
+    per-iteration and per-solve times (extrapolated where the whole workload would take minutes)."""
+    import oracle
+    import synth
+    out = dict(_cpu_info())
+    # n = 256 covariance, 200 MAPI iterations (a whole solve)
+    C = synth.dense_cov(256, 1024, SEED)
+    w0 = synth.start_vector(256, SEED + 1)
+    t0 = time.perf_counter()
+    oracle.mapi(C, w0, 200)
+    s = time.perf_counter() - t0
+    out["small_n256_ms_per_solve"] = s * 1e3
+    out["small_n256_us_per_iter"] = s / 200 * 1e6
+    log(f"oracle n=256: {s * 1e3:.0f} ms per 200-iteration solve")
+    # min-covariance of the PCA workload (4096 x 65536): the build on 64 coordinates, extrapolated
+    D, Nn = 4096, 65536
+    Xs = synth.pca_data(64, Nn, 77)
+    t0 = time.perf_counter()
+    oracle.mingram(Xs, 1.0 / Nn, "min1")
+    s = time.perf_counter() - t0
+    rate = 64 * 64 * Nn / s
+    out["pca_min_gram_terms_s"] = rate
+    out["pca_min_gram_s_extrapolated"] = D * (D + 1) / 2 * Nn / rate
+    out["pca_min_gram_sample"] = "64 x 64 entries over 65536 samples (all ordered pairs)"
+    log(f"oracle min-Gram: {rate / 1e6:.0f} M terms/s, full build ~{out['pca_min_gram_s_extrapolated']:.0f} s")
+    # PageRank at 2^22: one iteration of each product (CSR form)
+    n = 1 << 22
+    g = _graph(n, 2022)
+    dang = oracle.dangling_mask(n, g["col"])
+    w = np.full(n, 1.0 / n)
+    for meth, fn in (("mapi", oracle.pagerank_mavp_csr), ("rpi", oracle.pagerank_rpi_csr)):
+        t0 = time.perf_counter()
+        fn(n, g["row_ptr"], g["col"], g["val"], 0.85, w, dang)
+        out[f"pagerank_{meth}_ms_per_iter"] = (time.perf_counter() - t0) * 1e3
+    log(f"oracle PageRank: MAPI {out['pagerank_mapi_ms_per_iter']:.0f} ms, RPI {out['pagerank_rpi_ms_per_iter']:.0f} ms "
+        f"per iteration")
+    # the generated mix (n log-uniform in [64, 8192]): one float32 MAPI solve (tol 1e-6) at the
+    # geometric middle of each quarter of the range; the mean is the expected time per request
+    ns = [int(round(64 * 128 ** ((k + 0.5) / 4))) for k in range(4)]
+    per = []
+    for k, nk in enumerate(ns):
+        A, w0 = synth.generated_dense(nk, 90000 + k)
+        t0 = time.perf_counter()
+        r = oracle.mapi(A, w0, 1000, tol=1e-6)
+        per.append(time.perf_counter() - t0)
+        out[f"mix_n{nk}_ms_per_solve"] = per[-1] * 1e3
+        out[f"mix_n{nk}_iters"] = r.iters
+    out["mix_solves_s_estimate"] = 1.0 / (sum(per) / len(per))
+    out["mix_sample"] = f"one solve per quarter of log-uniform [64, 8192] (n = {ns}), equal weights"
+    log(f"oracle mix: {out['mix_solves_s_estimate']:.2f} solves/s")
     return out
 
 
@@ -615,7 +743,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="bench", choices=["bench", "kernels"])
-    ap.add_argument("--sections", default="small,hybrid,minibatch,image,batched,pca,pagerank,serving",
+    ap.add_argument("--sections", default="small,hybrid,minibatch,image,batched,pca,pagerank,serving,oracle",
                     help="other workloads reported under detail (comma list; empty for none)")
     ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--commands", nargs=3, default=["", "", ""], help="commands that produced the three dirs")
@@ -685,7 +813,8 @@ def main():
     for name, fn in (("small", lambda: bench_small(mp, ctx, torch)), ("hybrid", lambda: bench_hybrid(mp, ctx, torch)),
                      ("minibatch", lambda: bench_minibatch(mp, ctx, torch)), ("image", lambda: bench_image(mp, ctx, torch)),
                      ("batched", lambda: bench_batched(mp, ctx, torch)), ("pca", lambda: bench_pca(mp, ctx, torch)),
-                     ("pagerank", lambda: bench_pagerank(mp, ctx, torch)), ("serving", lambda: bench_serving(mp, torch))):
+                     ("pagerank", lambda: bench_pagerank(mp, ctx, torch)), ("serving", lambda: bench_serving(mp, torch)),
+                     ("oracle", bench_oracle)):
         if name in sections:
             log(f"section {name}")
             t0 = time.perf_counter()
@@ -709,6 +838,13 @@ def main():
         cpu = {"value": its * float(N) * N / dt_s / 1e9, "unit": "Gelem/s", "cores": 1, "kind": "oracle",
                "sample": f"{its} full MAPI iterations (min1 product + l1 normalisation) of the n=16384 FP64 "
                          f"oracle, numpy, one thread, {dt_s:.1f} s"}
+        # the same oracle product over blocks of rows on all usable host CPUs (at most 16)
+        nw = oracle_workers()
+        its_p, dt_p = oracle_parallel_iterations(Ch, w0.cpu().numpy(), 8.0, 40, nw)
+        detail.setdefault("oracle", {})["headline_rows_parallel"] = {
+            "processes": nw, "iterations": its_p, "seconds": dt_p,
+            "gelem_s": its_p * float(N) * N / dt_p / 1e9, **_cpu_info()}
+        log(f"oracle on {nw} processes: {its_p * float(N) * N / dt_p / 1e9:.2f} Gelem/s")
         del Ch
 
     out = {
