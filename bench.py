@@ -377,7 +377,7 @@ def bench_minibatch(mp, ctx, torch, N=10 ** 6, D=10, s=1000, T=100, runs=256, se
     out = {"N": N, "D": D, "s": s, "T": T, "runs": runs}
     for op in ("min1", "dot"):
         for beta in (0.0, 0.2):
-            mp.mapi_minibatch(Xd, B[:2], beta, W0[:2], op=op, ctx=ctx)
+            mp.mapi_minibatch(Xd, B, beta, W0, op=op, ctx=ctx)          # warm, workspace sized
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             W, _ = mp.mapi_minibatch(Xd, B, beta, W0, op=op, final_l2=True, ctx=ctx)

@@ -689,6 +689,7 @@ mapi_status mapi_minibatch(mapi_ctx* c, const float* X, int64_t N, int64_t D, in
   Layout L;
   const size_t o_run = L.take(sizeof(MbRun) * (size_t)runs);
   const size_t o_bad = L.take(sizeof(int32_t));
+  const size_t o_mb = L.take(minibatch_workspace_bytes((int)D, T, runs));
   mapi_status st;
   if ((st = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return st;
   char* base = static_cast<char*>(c->ws);
@@ -697,7 +698,7 @@ mapi_status mapi_minibatch(mapi_ctx* c, const float* X, int64_t N, int64_t D, in
   {
     Timed tm(c, MAPI_K_MINIBATCH);
     HIP_TRY(launch_minibatch(X, N, (int)D, ldx, batch_idx, s, T, (float)beta, op, runs, w0, w_out, final_l2,
-                             reinterpret_cast<MbRun*>(base + o_run), bad, c->stream));
+                             reinterpret_cast<MbRun*>(base + o_run), bad, base + o_mb, c->stream));
   }
   std::vector<MbRun> host(runs);
   int32_t bad_h = 0;

@@ -207,8 +207,11 @@ struct MbRun {
   double nu;       // last normaliser
 };
 int minibatch_max_d();
+// Device workspace of launch_minibatch: the stored batch matrices of one range of t
+// and a state record per run.
+size_t minibatch_workspace_bytes(int D, int T, int runs);
 hipError_t launch_minibatch(const float* X, int64_t N, int D, int64_t ldx, const int32_t* idx, int s, int T, float beta,
                             int op, int runs, const float* w0, float* w_out, int final_l2, MbRun* run_info,
-                            int32_t* bad_index, hipStream_t st);
+                            int32_t* bad_index, void* ws, hipStream_t st);
 
 }  // namespace mapi

@@ -1,13 +1,17 @@
-// Mini-batch MAPI with momentum (Algorithm 3, Sec. 3.2): one block per run
-// iterates, for t = 0 .. T-1 with the batch B_t of s sample indices,
+// Mini-batch MAPI with momentum (Algorithm 3, Sec. 3.2): every run iterates, for
+// t = 0 .. T-1 with the batch B_t of s sample indices,
 //   A_t     = (1/s) sum_{i in B_t} x_i (+) x_i^T     (eq. 5 on the batch; float64 sums, stored float32)
 //   w_{t+1} = A_t (+) w_t - beta w_{t-1}              (float32 product, w_{-1} = 0)
 //   nu = ||w_{t+1}||_1 (float64);  w_t <- w_t / nu;  w_{t+1} <- w_{t+1} / nu
 // and optionally divides w_T by its l2 norm.  The data matrix is N x D with the
-// samples as rows (Algorithm 3's layout), so a gathered sample is one
-// contiguous row.  D <= kMbMaxD keeps the batch matrix, a chunk of gathered
-// samples and the iterates in LDS; each thread owns at most kMbPairs entries of
-// the batch matrix and sums their terms in sample order.
+// samples as rows (Algorithm 3's layout), so a gathered sample is one contiguous row.
+//
+// A_t depends on the data and the batch only, not on the iterate, so the batch
+// matrices of all runs and of a range of t are built at once (k_mb_batches, one
+// block per (run, t): the gather of s rows and s D^2 terms), and only the D x D
+// recurrence runs in order (k_mb_iterate, one wave per run).  The range of t is
+// sized so that the stored batch matrices stay within kMbBufBytes; the iterates
+// carry over between ranges in a per-run state record.
 #include "common.h"
 
 namespace mapi {
@@ -16,6 +20,14 @@ constexpr int kMbThreads = 256;
 constexpr int kMbMaxD = 64;
 constexpr int kMbPairs = kMbMaxD * kMbMaxD / kMbThreads;   // 16
 constexpr int kMbChunk = 128;                                // samples gathered per LDS pass
+constexpr size_t kMbBufBytes = size_t(256) << 20;           // stored batch matrices per range of t
+
+// Iterate of one run between ranges of t.
+struct MbState {
+  float w[kMbMaxD], wp[kMbMaxD];
+  double nu;
+  int32_t it, status;
+};
 
 template <int OP>
 __device__ __forceinline__ double mb_term(float a, float b) {
@@ -27,88 +39,155 @@ __device__ __forceinline__ double mb_term(float a, float b) {
   }
 }
 
-template <int OP>
+// Batch matrices of t = t0 .. t0 + nt - 1, into Abuf[(run * nt + t - t0) * D^2 + k D + l].
+// With DD = D^2 < 256 pairs the block splits the samples into SL = 256 / DD slices:
+// thread (slice, p) sums the terms of pair p over samples slice, slice + SL, ... of
+// each gathered chunk in order, and the slice partials are added in slice order.
+// With DD >= 256 (WIDE) each thread sums up to kMbPairs pairs over all samples in order.
+template <int OP, bool WIDE>
 __global__ void __launch_bounds__(kMbThreads)
-k_minibatch(const float* __restrict__ X, int64_t N, int D, int64_t ldx, const int32_t* __restrict__ idx, int s, int T,
-            float beta, const float* __restrict__ w0, float* __restrict__ w_out, int final_l2, MbRun* __restrict__ runs,
-            int32_t* __restrict__ bad_index) {
+k_mb_batches(const float* __restrict__ X, int64_t N, int D, int64_t ldx, const int32_t* __restrict__ idx, int s,
+             int T, int t0, int nt, float* __restrict__ Abuf, int32_t* __restrict__ bad_index) {
   __shared__ float xb[kMbChunk * kMbMaxD];
-  __shared__ float A[kMbMaxD * kMbMaxD];
-  __shared__ float w[kMbMaxD], wp[kMbMaxD];
-  __shared__ double sh[16];
-  const int run = blockIdx.x, tid = threadIdx.x;
+  __shared__ double part[kMbThreads];
+  const int tid = threadIdx.x;
+  const int run = blockIdx.x / nt, tl = blockIdx.x - run * nt;
   const int DD = D * D;
-  if (tid < D) {
-    w[tid] = w0[(int64_t)run * D + tid];
-    wp[tid] = 0.0f;
-  }
-  const double inv_s = 1.0 / (double)s;
-  int status = MAPI_OK, it = 0;
-  double nu = 0.0;
-  for (int t = 0; t < T; ++t) {
-    const int32_t* B = idx + ((int64_t)run * T + t) * s;
-    double acc[kMbPairs];
+  constexpr bool wide = WIDE;
+  constexpr int NQ = WIDE ? kMbPairs : 1;
+  const int SL = wide ? 1 : kMbThreads / DD;
+  const int slice = wide ? 0 : tid / DD;
+  const bool active = wide || tid < SL * DD;
+  const int32_t* B = idx + ((int64_t)run * T + t0 + tl) * s;
+  double acc[NQ];
 #pragma unroll
-    for (int q = 0; q < kMbPairs; ++q) acc[q] = 0.0;
-    for (int i0 = 0; i0 < s; i0 += kMbChunk) {
-      const int c = min(kMbChunk, s - i0);
-      __syncthreads();   // the previous chunk's readers are done
-      for (int e = tid; e < c * D; e += kMbThreads) {
-        const int i = e / D, k = e - i * D;
-        int64_t j = B[i0 + i];
-        if (j < 0 || j >= N) {   // never used as an address; reported after the run
-          atomicOr(bad_index, 1);
-          j = 0;
-        }
-        xb[i * D + k] = X[j * ldx + k];
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  for (int i0 = 0; i0 < s; i0 += kMbChunk) {
+    const int c = min(kMbChunk, s - i0);
+    __syncthreads();   // the previous chunk's readers are done
+    for (int e = tid; e < c * D; e += kMbThreads) {
+      const int i = e / D, k = e - i * D;
+      int64_t j = B[i0 + i];
+      if (j < 0 || j >= N) {   // never used as an address; reported after the run
+        atomicOr(bad_index, 1);
+        j = 0;
       }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < kMbPairs; ++q) {
-        const int p = tid + q * kMbThreads;
-        if (p < DD) {
-          const int k = p / D, l = p - k * D;
-          double a = acc[q];
-          for (int i = 0; i < c; ++i) a += mb_term<OP>(xb[i * D + k], xb[i * D + l]);
-          acc[q] = a;
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kMbPairs; ++q) {
-      const int p = tid + q * kMbThreads;
-      if (p < DD) A[p] = (float)(acc[q] * inv_s);
+      xb[i * D + k] = X[j * ldx + k];
     }
     __syncthreads();
-    float wn = 0.0f;
-    double part = 0.0;
-    if (tid < D) {
-      float y = 0.0f;
-      for (int l = 0; l < D; ++l) y = op_acc<OP>(y, A[tid * D + l], w[l], sign_bit(w[l]));
-      wn = fmaf(-beta, wp[tid], y);
-      part = fabs((double)wn);
+    if (!active) continue;
+    if constexpr (WIDE) {
+      // samples outside, this thread's pairs inside: each pair still sums its samples in order
+      int kq[NQ], lq[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int p = min(tid + q * kMbThreads, DD - 1);
+        kq[q] = p / D;
+        lq[q] = p - kq[q] * D;
+      }
+#pragma unroll 2
+      for (int i = 0; i < c; ++i) {
+        const float* xi = xb + i * D;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] += mb_term<OP>(xi[kq[q]], xi[lq[q]]);
+      }
+    } else {
+      const int p = tid - slice * DD;
+      const int k = p / D, l = p - k * D;
+      double a = acc[0];
+      for (int i = slice; i < c; i += SL) a += mb_term<OP>(xb[i * D + k], xb[i * D + l]);
+      acc[0] = a;
     }
-    nu = block_sum_f64(part, sh);
+  }
+  const double inv_s = 1.0 / (double)s;
+  float* out = Abuf + ((int64_t)run * nt + tl) * DD;
+  if constexpr (WIDE) {
+    for (int q = 0; q < NQ; ++q) {
+      const int p = tid + q * kMbThreads;
+      if (p < DD) out[p] = (float)(acc[q] * inv_s);
+    }
+    return;
+  }
+  part[tid] = active ? acc[0] : 0.0;
+  __syncthreads();
+  if (tid < DD) {
+    double sum = 0.0;
+    for (int sl = 0; sl < SL; ++sl) sum += part[sl * DD + tid];
+    out[tid] = (float)(sum * inv_s);
+  }
+}
+
+// Fixed-order butterfly sum over the wave.
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// The recurrence over the stored batch matrices of one range of t; one wave per
+// run, lane l < D holding w_l and w_{t-1, l}.  `first` starts from w0, `last`
+// finishes (optional l2 step, output, run record); otherwise the iterate is kept
+// in the run's state record.
+template <int OP>
+__global__ void __launch_bounds__(kWave)
+k_mb_iterate(const float* __restrict__ Abuf, int D, int nt, float beta, MbState* __restrict__ states, int first,
+             int last, const float* __restrict__ w0, float* __restrict__ w_out, int final_l2,
+             MbRun* __restrict__ runs) {
+  const int run = blockIdx.x, l = threadIdx.x;
+  const bool mine = l < D;
+  MbState* S = states + run;
+  float w = 0.0f, wp = 0.0f;
+  double nu = 0.0;
+  int it = 0, status = MAPI_OK;
+  if (first) {
+    if (mine) w = w0[(int64_t)run * D + l];
+  } else {
+    if (mine) {
+      w = S->w[l];
+      wp = S->wp[l];
+    }
+    nu = S->nu;
+    it = S->it;
+    status = S->status;
+  }
+  const int DD = D * D;
+  for (int tl = 0; tl < nt && status == MAPI_OK; ++tl) {
+    const float* A = Abuf + ((int64_t)run * nt + tl) * DD + (int64_t)l * D;
+    float y = 0.0f;
+    for (int m = 0; m < D; ++m) {
+      const float wm = __shfl(w, m);
+      if (mine) y = op_acc<OP>(y, A[m], wm, sign_bit(wm));
+    }
+    const float wn = mine ? fmaf(-beta, wp, y) : 0.0f;
+    nu = wave_sum_d(mine ? fabs((double)wn) : 0.0);
     if (!(nu > 0.0) || !(nu < INFINITY)) {
       status = MAPI_ERR_DEGENERATE;
       break;
     }
-    if (tid < D) {
-      wp[tid] = (float)((double)w[tid] / nu);
-      w[tid] = (float)((double)wn / nu);
-    }
+    wp = (float)((double)w / nu);
+    w = (float)((double)wn / nu);
     ++it;
-    __syncthreads();
   }
-  __syncthreads();
+  if (!last) {
+    if (mine) {
+      S->w[l] = w;
+      S->wp[l] = wp;
+    }
+    if (l == 0) {
+      S->nu = nu;
+      S->it = it;
+      S->status = status;
+    }
+    return;
+  }
   double scale = 1.0;
   if (final_l2 && status == MAPI_OK) {
-    const double q2 = block_sum_f64(tid < D ? (double)w[tid] * (double)w[tid] : 0.0, sh);
+    const double q2 = wave_sum_d(mine ? (double)w * (double)w : 0.0);
     if (!(q2 > 0.0) || !(q2 < INFINITY)) status = MAPI_ERR_DEGENERATE;
     else scale = 1.0 / sqrt(q2);
   }
-  if (tid < D) w_out[(int64_t)run * D + tid] = (scale == 1.0) ? w[tid] : (float)((double)w[tid] * scale);
-  if (tid == 0) {
+  if (mine) w_out[(int64_t)run * D + l] = (scale == 1.0) ? w : (float)((double)w * scale);
+  if (l == 0) {
     runs[run].iters = it;
     runs[run].status = status;
     runs[run].nu = nu;
@@ -117,18 +196,66 @@ k_minibatch(const float* __restrict__ X, int64_t N, int D, int64_t ldx, const in
 
 int minibatch_max_d() { return kMbMaxD; }
 
+static size_t mb_align(size_t x) { return (x + 255) / 256 * 256; }
+
+// Batches per range of t: as many as keep runs x range x D^2 stored floats within kMbBufBytes.
+static int mb_range(int D, int T, int runs) {
+  const size_t per_t = (size_t)runs * (size_t)D * (size_t)D * sizeof(float);
+  size_t r = kMbBufBytes / (per_t > 0 ? per_t : 1);
+  if (r < 1) r = 1;
+  if (r > (size_t)T) r = (size_t)T;
+  return (int)(r < 1 ? 1 : r);
+}
+
+size_t minibatch_workspace_bytes(int D, int T, int runs) {
+  const size_t buf = (size_t)runs * (size_t)mb_range(D, T, runs) * (size_t)D * (size_t)D * sizeof(float);
+  return mb_align(buf) + (size_t)runs * sizeof(MbState);
+}
+
 hipError_t launch_minibatch(const float* X, int64_t N, int D, int64_t ldx, const int32_t* idx, int s, int T, float beta,
                             int op, int runs, const float* w0, float* w_out, int final_l2, MbRun* ri,
-                            int32_t* bad_index, hipStream_t st) {
-  if (op == MAPI_OP_MIN1)
-    hipLaunchKernelGGL(k_minibatch<MAPI_OP_MIN1>, dim3(runs), dim3(kMbThreads), 0, st, X, N, D, ldx, idx, s, T, beta,
-                       w0, w_out, final_l2, ri, bad_index);
-  else if (op == MAPI_OP_DOT)
-    hipLaunchKernelGGL(k_minibatch<MAPI_OP_DOT>, dim3(runs), dim3(kMbThreads), 0, st, X, N, D, ldx, idx, s, T, beta,
-                       w0, w_out, final_l2, ri, bad_index);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+                            int32_t* bad_index, void* ws, hipStream_t st) {
+  if (op != MAPI_OP_MIN1 && op != MAPI_OP_DOT) return hipErrorInvalidValue;
+  const int R = mb_range(D, T, runs);
+  float* Abuf = static_cast<float*>(ws);
+  MbState* states = reinterpret_cast<MbState*>(static_cast<char*>(ws) +
+                                               mb_align((size_t)runs * (size_t)R * D * D * sizeof(float)));
+  if (T == 0) {
+    if (op == MAPI_OP_MIN1)
+      hipLaunchKernelGGL(k_mb_iterate<MAPI_OP_MIN1>, dim3(runs), dim3(kWave), 0, st, Abuf, D, 0, beta, states, 1, 1,
+                         w0, w_out, final_l2, ri);
+    else
+      hipLaunchKernelGGL(k_mb_iterate<MAPI_OP_DOT>, dim3(runs), dim3(kWave), 0, st, Abuf, D, 0, beta, states, 1, 1, w0,
+                         w_out, final_l2, ri);
+    return hipGetLastError();
+  }
+  for (int t0 = 0; t0 < T; t0 += R) {
+    const int nt = min(R, T - t0);
+    const int first = t0 == 0, last = t0 + nt == T;
+    const unsigned grid = (unsigned)((int64_t)runs * nt);
+    if (op == MAPI_OP_MIN1) {
+      if (D * D >= kMbThreads)
+        hipLaunchKernelGGL((k_mb_batches<MAPI_OP_MIN1, true>), dim3(grid), dim3(kMbThreads), 0, st, X, N, D, ldx, idx,
+                           s, T, t0, nt, Abuf, bad_index);
+      else
+        hipLaunchKernelGGL((k_mb_batches<MAPI_OP_MIN1, false>), dim3(grid), dim3(kMbThreads), 0, st, X, N, D, ldx, idx,
+                           s, T, t0, nt, Abuf, bad_index);
+      hipLaunchKernelGGL(k_mb_iterate<MAPI_OP_MIN1>, dim3(runs), dim3(kWave), 0, st, Abuf, D, nt, beta, states, first,
+                         last, w0, w_out, final_l2, ri);
+    } else {
+      if (D * D >= kMbThreads)
+        hipLaunchKernelGGL((k_mb_batches<MAPI_OP_DOT, true>), dim3(grid), dim3(kMbThreads), 0, st, X, N, D, ldx, idx, s,
+                           T, t0, nt, Abuf, bad_index);
+      else
+        hipLaunchKernelGGL((k_mb_batches<MAPI_OP_DOT, false>), dim3(grid), dim3(kMbThreads), 0, st, X, N, D, ldx, idx,
+                           s, T, t0, nt, Abuf, bad_index);
+      hipLaunchKernelGGL(k_mb_iterate<MAPI_OP_DOT>, dim3(runs), dim3(kWave), 0, st, Abuf, D, nt, beta, states, first,
+                         last, w0, w_out, final_l2, ri);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace mapi

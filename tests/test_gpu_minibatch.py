@@ -64,6 +64,25 @@ def test_minibatch_sec32_full_size_against_oracle():
         assert gap < 0.5         # near v1, not at it: the pseudo-eigenvector of the noisy batches (Fig. 4)
 
 
+def test_minibatch_several_ranges_of_t_match_one_range():
+    # 64 runs x 300 iterations of 64 x 64 batch matrices (315 MB stored) take two ranges of t, one
+    # run alone takes one: the iterate carried between ranges must give bitwise the same result.
+    # (Batches of 16: with single-sample batches A_t (+) w collapses to sign(x)(sign(x) . w) once
+    # |w| << |A|, and the iterate reaches an exactly zero normaliser within a few hundred steps.)
+    D, s, T, N, runs = 64, 16, 300, 200, 64
+    print(f"[case] minibatch ranges D={D} T={T} runs={runs}", flush=True)
+    X = np.random.default_rng(64).standard_normal((N, D)).astype(np.float32)
+    batches = synth.minibatch_indices(runs, T, s, N, seed=5)
+    W0 = np.stack([synth.start_vector(D, 60 + r) for r in range(runs)])
+    W, infos = _run(X, batches, 0.0, W0)
+    W1, _ = _run(X, batches[:1], 0.0, W0[:1])
+    np.testing.assert_array_equal(W[0], W1[0])
+    assert all(i["iters"] == T and i["status"] == "OK" for i in infos)
+    ref = oracle.minibatch_mapi(X.T.astype(np.float64), batches[runs - 1], 0.0, W0[runs - 1].astype(np.float64))
+    e, c = report("minibatch last run", W[runs - 1], ref.w)
+    assert e <= TOL and c > COS
+
+
 def test_minibatch_errors():
     X = to_dev(np.ones((20, 4), np.float32))
     W0 = torch.full((1, 4), 0.25, dtype=torch.float32, device="cuda")
