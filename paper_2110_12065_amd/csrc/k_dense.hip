@@ -13,14 +13,25 @@ namespace mapi {
 // Every block first sums the product kernel's per-block partials pprod[0..nprod)
 // in block order (the same float64 value in every block), so the product kernel
 // needs no grid-wide arrival; norm NORM_L2 takes the square root (RPI, eq. 1).
-template <int MODE>
-__global__ void __launch_bounds__(256)
+template <int MODE, int BS, int PF>
+__global__ void __launch_bounds__(BS)
 k_finalize(const float* __restrict__ y, const float* __restrict__ w_old, float* __restrict__ w_new, int64_t n,
            SolveState* __restrict__ st, const double* __restrict__ pprod, int nprod, int norm,
            double* __restrict__ part, const uint8_t* __restrict__ dangling, double c, double inv_n) {
   __shared__ double sh[16];
   __shared__ int sh_flag;
   if (state_done(st)) return;
+  // The first PF elements' y and w_old do not depend on nu: their loads are issued
+  // before the partials are summed, so the two memory round trips overlap.
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float yp[PF], wp[PF];
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    const int64_t i = i0 + k * stride;
+    yp[k] = i < n ? y[i] : 0.0f;
+    wp[k] = i < n ? w_old[i] : 0.0f;
+  }
   const double tot = block_sum_parts(pprod, nprod, 1, 0, sh);
   const double nu = (norm == NORM_L2) ? sqrt(tot) : tot;
   if (blockIdx.x == 0 && threadIdx.x == 0) st->nu = nu;
@@ -32,12 +43,11 @@ k_finalize(const float* __restrict__ y, const float* __restrict__ w_old, float* 
     return;
   }
   double r = 0.0, e0 = 0.0, e1 = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const float wn = (float)((double)y[i] / nu);
+  auto element = [&](int64_t i, float yi, float wo) {
+    const float wn = (float)((double)yi / nu);
     w_new[i] = wn;
     const double wd = (double)wn;
-    r += fabs(wd - (double)w_old[i]);
+    r += fabs(wd - (double)wo);
     if constexpr (MODE == 1) {
       const double tc = fmin(fmax(wd, -c), c);
       e0 += tc;
@@ -46,11 +56,25 @@ k_finalize(const float* __restrict__ y, const float* __restrict__ w_old, float* 
       e0 += wd;
       if (dangling[i]) e1 += wd;
     }
+  };
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    const int64_t i = i0 + k * stride;
+    if (i < n) element(i, yp[k], wp[k]);
   }
+  for (int64_t i = i0 + PF * stride; i < n; i += stride) element(i, y[i], w_old[i]);
   r = block_sum_f64(r, sh);
   if constexpr (MODE != 0) {
     e0 = block_sum_f64(e0, sh);
     e1 = block_sum_f64(e1, sh);
+  }
+  if (gridDim.x == 1) {   // one block holds every sum: no partials, no arrival
+    if (threadIdx.x == 0) {
+      st->ex[0] = e0;
+      st->ex[1] = e1;
+      state_advance(st, r);
+    }
+    return;
   }
   if (threadIdx.x == 0) {
     store_agent(&part[3 * (size_t)blockIdx.x + 0], r);
@@ -217,7 +241,9 @@ hipError_t launch_read16(const void* src, int64_t n16, uint32_t* sink, int cu_co
 }
 
 // At most one normalisation block per compute unit: the blocks' arrivals on one
-// counter are serialised, so fewer, longer blocks finish sooner for large n.
+// counter are serialised, so fewer, longer blocks finish sooner for large n.  (One
+// block of 1024 threads for n <= 64K, which needs no arrival, measured slower: it
+// cannot start until a whole compute unit is free of the product's last blocks.)
 int finalize_blocks(int64_t n) {
   int64_t b = (n + 1023) / 1024;
   if (b > 256) b = 256;
@@ -229,9 +255,9 @@ hipError_t launch_finalize(int mode, const float* y, const float* w_old, float* 
                            double inv_n, hipStream_t s) {
   const int blocks = finalize_blocks(n);
   switch (mode) {
-    case 0: hipLaunchKernelGGL(k_finalize<0>, dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n); break;
-    case 1: hipLaunchKernelGGL(k_finalize<1>, dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n); break;
-    case 2: hipLaunchKernelGGL(k_finalize<2>, dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n); break;
+    case 0: hipLaunchKernelGGL((k_finalize<0, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n); break;
+    case 1: hipLaunchKernelGGL((k_finalize<1, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n); break;
+    case 2: hipLaunchKernelGGL((k_finalize<2, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
