@@ -53,6 +53,34 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def csr_source_hash():
+    h = hashlib.sha256()
+    for f in ("ops.h", "k_csr.hip"):
+        with open(os.path.join(ROOT, "paper_2110_12065_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+PR_N, PR_SEED = 1 << 22, 2022
+
+
+def csr_bytes(n, nnz):
+    """Algorithmic bytes of one PageRank product: links (col, val) and row pointers once, w and y once."""
+    return 8.0 * nnz + 4.0 * (n + 1) + 8.0 * n
+
+
+def load_csr_traffic():
+    """HBM bytes per launch of the MAPI PageRank product on the 2^22-node graph from committed
+    counter runs, or None (also None once the product's sources changed)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f).get("csr") or {}
+    if t.get("source_sha256_16") != csr_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
 def product_bytes(dtype, n=N):
     """Algorithmic HBM bytes of one dense product launch: the matrix once, w and y once
     (plus the row scales for FP8)."""
@@ -112,6 +140,11 @@ def run_kernels_mode():
     for dt, (A, rs) in mats.items():
         for _ in range(5):
             mp.mapi_mavp(A, w0, "min1", row_scale=rs, ctx=ctx)
+    del src, dst
+    # three MAPI PageRank products on the 2^22-node graph
+    g = _graph(PR_N, PR_SEED)
+    rp, col, val = (torch.from_numpy(g[x]).cuda() for x in ("row_ptr", "col", "val"))
+    mp.mapi_pagerank(rp, col, val, 0.85, "mapi", max_iters=3, check_every=3, ctx=ctx)
     torch.cuda.synchronize()
     log("kernels mode done")
 
@@ -130,6 +163,8 @@ def _kernel_dtype(name):
         return "copy"
     if "k_read16" in name:
         return "read"
+    if "k_csr_product<0," in name:
+        return "csr"
     if "k_mavp_dense" not in name:
         return None
     # template argument order: storage type, product, ... (0 = f32, 1 = bf16, 2 = fp8)
@@ -224,6 +259,17 @@ def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write, 
     if "copy" in fetch:
         md.append(f"| copy reference | {fetch['copy']:.0f} | {write.get('copy', 0):.0f} | "
                   f"{2 * copy_bytes:.4e} | {2 * copy_bytes:.4e} | 1.000 |")
+    if "csr" in fetch and "csr" in write and f_scale is not None and w_scale is not None:
+        nnz = int(_graph(PR_N, PR_SEED)["col"].size)
+        b = fetch["csr"] * 1024.0 * f_scale + write["csr"] * 1024.0 * w_scale
+        alg = csr_bytes(PR_N, nnz)
+        out["csr"] = {"source_sha256_16": csr_source_hash(), "n": PR_N, "nnz": nnz, "fetch_kib": fetch["csr"],
+                      "write_kib": write["csr"], "bytes_per_launch": b, "algorithmic_bytes_per_launch": alg}
+        md += ["", f"PageRank MAPI product (`k_csr_product`, n = 2^22, {nnz} links; algorithmic bytes = 8 per link "
+                   "+ 4 per row pointer + 8 per node for w and y):", "",
+               "| kernel | FETCH KiB | WRITE KiB | scaled HBM-side bytes | algorithmic bytes | ratio |",
+               "|---|---|---|---|---|---|",
+               f"| csr MAPI | {fetch['csr']:.0f} | {write['csr']:.0f} | {b:.4e} | {alg:.4e} | {b / alg:.3f} |"]
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
     with open(os.path.join(ROOT, "profiles", "mavp_dense_n16384_traffic.md"), "w") as f:
@@ -481,6 +527,7 @@ def _graph(n, seed):
 def bench_pagerank(mp, ctx, torch, n=1 << 22, seed=2022):
     log("PageRank: generating the 2^22-node graph on the host")
     g = _graph(n, seed)
+    traffic = load_csr_traffic() if (n, seed) == (PR_N, PR_SEED) else None
     rp, col, val = (torch.from_numpy(g[x]).cuda() for x in ("row_ptr", "col", "val"))
     nnz = int(g["col"].size)
     bytes_iter = 8.0 * nnz + 4.0 * (n + 1) + 8.0 * n        # links, row pointers, w once, y once
@@ -506,6 +553,12 @@ def bench_pagerank(mp, ctx, torch, n=1 << 22, seed=2022):
         out[f"{meth}_csr_kernel_us"] = kms * 1e3
         out[f"{meth}_gedges_s"] = nnz / (kms * 1e-3) / 1e9
         out[f"{meth}_csr_kernel_gbs"] = bytes_iter / (kms * 1e-3) / 1e9
+    # counter bytes of the MAPI product (FETCH_SIZE + WRITE_SIZE, scaled; the gathers of w are
+    # counted as the L2 fills they cause)
+    out["mapi_csr_traffic_bytes"] = traffic
+    if traffic:
+        out["mapi_csr_traffic_ratio"] = traffic / bytes_iter
+        out["mapi_csr_traffic_gbs"] = traffic / (out["mapi_csr_kernel_us"] * 1e-6) / 1e9
     return out
 
 
@@ -830,7 +883,7 @@ def main():
         w = w0.cpu().numpy().astype(np.float64)
         t0 = time.perf_counter()
         its = 0
-        while time.perf_counter() - t0 < 12.0 and its < 40:
+        while its < ITERS:        # one whole step: the result is also the accuracy reference below
             y = oracle.mavp(Ch, w)
             w = y / np.abs(y).sum()
             its += 1
@@ -838,6 +891,17 @@ def main():
         cpu = {"value": its * float(N) * N / dt_s / 1e9, "unit": "Gelem/s", "cores": 1, "kind": "oracle",
                "sample": f"{its} full MAPI iterations (min1 product + l1 normalisation) of the n=16384 FP64 "
                          f"oracle, numpy, one thread, {dt_s:.1f} s"}
+        # each storage mode's 20-iteration GPU iterate against this FP64 oracle on the float32 matrix
+        # (for BF16 / FP8 the error of storing the matrix in 2 or 1 bytes: reported, not bounded)
+        acc = {}
+        for dt in ("f32", "bf16", "fp8"):
+            A, rs = mats[dt]
+            wg, _ = mp.mapi_solve(A, w0, max_iters=ITERS, row_scale=rs, check_every=ITERS, ctx=ctx)
+            g = wg.double().cpu().numpy()
+            acc[dt] = {"rel_l1": float(np.abs(g - w).sum() / np.abs(w).sum()),
+                       "cosine": float(abs(g @ w) / (np.linalg.norm(g) * np.linalg.norm(w)))}
+        detail["accuracy_vs_fp64_oracle"] = acc
+        log("accuracy against the FP64 oracle: " + ", ".join(f"{k} rel-l1 {v['rel_l1']:.2e}" for k, v in acc.items()))
         # the same oracle product over blocks of rows on all usable host CPUs (at most 16)
         nw = oracle_workers()
         its_p, dt_p = oracle_parallel_iterations(Ch, w0.cpu().numpy(), 8.0, 40, nw)
