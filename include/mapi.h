@@ -246,7 +246,9 @@ mapi_status mapi_image_reconstruct(mapi_ctx* ctx, const float* V, int64_t P, int
  * runs * D.  Batch sums are float64 (stored float32), the product float32, nu
  * float64.  D <= 64 (MAPI_ERR_UNSUPPORTED beyond).  infos (optional, host, runs
  * entries): iterations run, last nu, status; a zero or non-finite nu stops that
- * run with MAPI_ERR_DEGENERATE (also returned).                                  */
+ * run with MAPI_ERR_DEGENERATE (also returned).  The batch matrices do not depend
+ * on the iterate and are built ahead for a range of t at a time, stored float32
+ * in context device memory (at most 256 MiB, plus 528 bytes per run).          */
 mapi_status mapi_minibatch(mapi_ctx* ctx, const float* X, int64_t N, int64_t D, int64_t ldx, const int32_t* batch_idx,
                            int32_t s, int32_t T, double beta, int32_t op, int32_t runs, const float* w0, float* w_out,
                            int32_t final_l2, mapi_info* infos);
@@ -268,8 +270,13 @@ mapi_status mapi_quantize(mapi_ctx* ctx, const float* A, int64_t n_rows, int64_t
 
 /* Gram build over the rows of X (D x N, row-major, leading dimension ldx; the N
  * samples are the columns, Sec. 1): A_ij = scale * sum_k op(X_ik, X_jk).
- * op MIN1/MIN2: the min-covariance of eq. (5); op DOT: the covariance of eq. (2).
- * A_out: D x D float32, leading dimension lda; the full matrix is written.       */
+ * op MIN1/MIN2: the min-covariance of eq. (5), on the vector ALU; op DOT: the
+ * covariance of eq. (2), on the matrix cores.  Terms are summed in float32 within
+ * runs of 256 samples and in float64 across runs; A is rounded to float32 once.
+ * A_out: D x D float32, leading dimension lda; the full matrix is written.  The
+ * DOT build may split the samples into up to 8 chunks (a function of D and N
+ * only) whose float64 partial tiles live in context device memory: at most
+ * 8 * T (T + 1) / 2 * 128 KiB, T = ceil(D / 128), kept until mapi_destroy.     */
 mapi_status mapi_mingram(mapi_ctx* ctx, const float* X, int64_t D, int64_t N, int64_t ldx,
                          double scale, int32_t op, float* A_out, int64_t lda);
 
@@ -279,8 +286,8 @@ mapi_status mapi_mingram(mapi_ctx* ctx, const float* X, int64_t D, int64_t N, in
  * Vector i is extracted from (I - P P^T) A, P the l2-normalised earlier vectors,
  * orthonormalised by modified Gram-Schmidt in float64, starting from column i of
  * W0.  W0, P_out: device float, D x k, column-major (column i at offset i*D).
- * info_k: host array of k infos.  If A_ws is non-NULL it must hold D*D floats of
- * device scratch for the built matrix (else the context allocates it).          */
+ * info_k: host array of k infos.  The built and deflated matrices (2 D^2 floats)
+ * and the Gram build's partial tiles (mapi_mingram) are context device memory.  */
 mapi_status mapi_pca_topk(mapi_ctx* ctx, const float* X, int64_t D, int64_t N, int64_t ldx,
                           int32_t k, double scale, int32_t method, const float* W0,
                           float* P_out, const mapi_opts* opts, mapi_info* info_k);
