@@ -156,41 +156,57 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
   const DenseTuning t = tuning_for(c, da);
   const int P = dense_part_count(da, t, c->cu_count);
   const int F = finalize_blocks(n);
+  // A fixed-iteration solve (no tolerance, no stall rule: nothing stops it early)
+  // folds each normalisation into the next product, which forms w from the
+  // previous y and partials while staging it in LDS (FusedPrev); the last
+  // iteration is normalised by the normalisation kernel.  Same arithmetic.
+  const bool fused = o->tol == 0.0 && o->stall_iters <= 0 && t.w_in_lds != 0;
   Layout L;
   const size_t o_st = L.take(sizeof(SolveState));
-  const size_t o_pp = L.take(sizeof(double) * (size_t)P);
+  const size_t o_pp = L.take(sizeof(double) * 2 * (size_t)P);
   const size_t o_part = L.take(sizeof(double) * 3 * (size_t)F);
   const size_t o_w0 = L.take(sizeof(float) * n);
   const size_t o_w1 = L.take(sizeof(float) * n);
-  const size_t o_y = L.take(sizeof(float) * n);
+  const size_t o_y = L.take(sizeof(float) * 2 * n);
   if ((s = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return s;
   char* base = static_cast<char*>(c->ws);
   SolveState* st = reinterpret_cast<SolveState*>(base + o_st);
-  double* pprod = reinterpret_cast<double*>(base + o_pp);
+  double* pp[2] = {reinterpret_cast<double*>(base + o_pp), reinterpret_cast<double*>(base + o_pp) + P};
   double* part = reinterpret_cast<double*>(base + o_part);
   float* wb[2] = {reinterpret_cast<float*>(base + o_w0), reinterpret_cast<float*>(base + o_w1)};
-  float* y = reinterpret_cast<float*>(base + o_y);
+  float* yb[2] = {reinterpret_cast<float*>(base + o_y), reinterpret_cast<float*>(base + o_y) + n};
 
   HIP_TRY(hipMemcpyAsync(wb[0], w0, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(launch_state_init(st, o->max_iters, o->tol, o->stall_iters, c->stream));
   const int check = o->check_every > 0 ? o->check_every : 16;
   const int norm = rpi ? NORM_L2 : NORM_L1;
+  int launched = 0;
   for (int it = 0; it < o->max_iters; ++it) {
-    float* wc = wb[it & 1];
-    float* wn = wb[(it & 1) ^ 1];
+    const int b = fused ? (it & 1) : 0;   // y and partials alternate when a product reads the previous ones
     {
       DenseArgs dl = da;
       TimedLaunch tm(c, MAPI_K_MAVP, &dl);
-      HIP_TRY(launch_mavp_dense(dl, op, wc, y, pprod, st, norm, t, c->cu_count, c->stream));
+      const FusedPrev fp{yb[b ^ 1], pp[b ^ 1], P, wb[it & 1], it};
+      HIP_TRY(launch_mavp_dense(dl, op, wb[it & 1], yb[b], pp[b], st, norm, t, c->cu_count, c->stream,
+                                (fused && it > 0) ? &fp : nullptr));
     }
-    {
+    launched = it + 1;
+    if (!fused) {
       Timed tm(c, MAPI_K_FINALIZE);
-      HIP_TRY(launch_finalize(0, y, wc, wn, n, st, pprod, P, norm, part, nullptr, 0.0, 0.0, c->stream));
+      HIP_TRY(launch_finalize(0, yb[0], wb[it & 1], wb[(it & 1) ^ 1], n, st, pp[0], P, norm, part, nullptr, 0.0, 0.0,
+                              c->stream));
     }
     if ((it + 1) % check == 0 && it + 1 < o->max_iters) {
       if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
       if (c->st_host->done) break;
     }
+  }
+  if (fused && launched > 0) {
+    // the last iteration's normalisation; the iterations before it were counted by none
+    const int it = launched - 1;
+    Timed tm(c, MAPI_K_FINALIZE);
+    HIP_TRY(launch_finalize(0, yb[it & 1], wb[it & 1], wb[(it & 1) ^ 1], n, st, pp[it & 1], P, norm, part, nullptr,
+                            0.0, 0.0, c->stream, it));
   }
   HIP_TRY(launch_finish(wb[0], wb[1], w_out, n, st, o->final_l2, c->stream));
   if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
@@ -386,6 +402,8 @@ mapi_status mapi_autotune_dense(mapi_ctx* c, const mapi_dense* A, int32_t op, in
   HIP_TRY(launch_fill_f32(w, da.n_cols, 1.0f / (float)da.n_cols, c->stream));
   DenseTuning bt = dense_default_tuning(da, c->cu_count, c->max_lds);
   double bms = 1e30;
+  DenseTuning bl = bt;      // fastest shape that stages w in LDS
+  double blms = 1e30;
   for (int rw : {1, 2, 4, 8}) {
     if (rw > 1 && rw > da.n_rows) continue;
     for (int waves : {4, 8})
@@ -403,7 +421,18 @@ mapi_status mapi_autotune_dense(mapi_ctx* c, const mapi_dense* A, int32_t op, in
                 bms = ms;
                 bt = t;
               }
+              if (lds != 0 && ms < blms) {
+                blms = ms;
+                bl = t;
+              }
             }
+  }
+  // Shapes that stage w in LDS let a fixed-iteration solve form each iterate inside
+  // the next product (no normalisation launch, several microseconds an iteration):
+  // they are kept when within 3 % of the fastest product.
+  if (bt.w_in_lds == 0 && blms <= 1.03 * bms) {
+    bt = bl;
+    bms = blms;
   }
   const auto key = bucket(da.dtype, da.n_rows, da.n_cols);
   c->tuned[key] = bt;

@@ -67,6 +67,16 @@ __device__ __forceinline__ double load_agent(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Fixed-order sum of part[0..count) by one wave (lane l takes l, l + 64, ...; then
+// a butterfly): every wave that calls it gets the same bits, whatever the block
+// size, so the normaliser is identical in every kernel that forms it.
+__device__ __forceinline__ double wave_sum_parts(const double* part, int count) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double s = 0.0;
+  for (int i = lane; i < count; i += kWave) s += load_agent(&part[i]);
+  return wave_sum_f64(s);
+}
+
 // Publish this block's partial(s) and report whether it arrived last.  The
 // last block then sees every other block's partials.  Call from all threads.
 __device__ __forceinline__ bool arrive_last(uint32_t* counter, int* sh_flag) {
@@ -142,22 +152,41 @@ __host__ __device__ inline int64_t dense_lds_w_floats(int dtype, int64_t n_cols)
   const int64_t ve = dtype == MAPI_FP8_E4M3 ? 16 : (dtype == MAPI_BF16 ? 8 : 4);
   return (n_cols / ve + 63) / 64 * 64 * ve;
 }
+// The columns past the last whole vector (fewer than 16) follow the staged
+// vectors in kDenseTailFloats floats when the product forms w itself (FusedPrev).
+constexpr int kDenseTailFloats = 16;
 inline size_t dense_lds_bytes(int dtype, int64_t n_cols, int mode) {
-  const size_t wbytes = (size_t)dense_lds_w_floats(dtype, n_cols) * 4;
+  const size_t wbytes = (size_t)(dense_lds_w_floats(dtype, n_cols) + kDenseTailFloats) * 4;
   if (mode == 0) return 0;
   return (mode == 2 && dtype == MAPI_FP8_E4M3) ? wbytes + (size_t)((n_cols >> 2) + 4) * 4 : wbytes;
 }
+
+// Normalisation of the previous iteration folded into a dense product (fixed-
+// iteration solves): the kernel forms nu from the previous product's partials,
+// stages w = y_prev * (1 / nu) in LDS instead of reading w, and writes its share
+// of w to w_new.  A zero or non-finite nu marks the solve degenerate after
+// `iter` - 1 completed iterations.
+struct FusedPrev {
+  const float* y_prev;
+  const double* part_prev;
+  int nparts;
+  float* w_new;
+  int iter;
+};
 // Admissible w_in_lds modes for a storage type.
 inline bool lds_mode_ok(int dtype, int mode) { return mode == 0 || mode == 1 || (mode == 2 && dtype == MAPI_FP8_E4M3); }
 
 hipError_t launch_state_init(SolveState* st, int max_iters, double tol, int stall_iters, hipStream_t s);
 hipError_t launch_mavp_dense(const DenseArgs& a, int op, const float* w, float* y, double* part,
-                             SolveState* st, int norm, const DenseTuning& t, int cu_count, hipStream_t s);
+                             SolveState* st, int norm, const DenseTuning& t, int cu_count, hipStream_t s,
+                             const FusedPrev* fp = nullptr);
 int dense_part_count(const DenseArgs& a, const DenseTuning& t, int cu_count);
 DenseTuning dense_default_tuning(const DenseArgs& a, int cu_count, int max_lds_bytes);
+// set_iter >= 0: the completed-iteration count is set to it before this
+// iteration is counted (the last normalisation of a fused solve).
 hipError_t launch_finalize(int mode, const float* y, const float* w_old, float* w_new, int64_t n,
                            SolveState* st, const double* pprod, int nprod, int norm, double* part,
-                           const uint8_t* dangling, double c, double inv_n, hipStream_t s);
+                           const uint8_t* dangling, double c, double inv_n, hipStream_t s, int set_iter = -1);
 int finalize_blocks(int64_t n);
 hipError_t launch_finish(const float* w0buf, const float* w1buf, float* out, int64_t n, SolveState* st, int final_l2,
                          hipStream_t s);

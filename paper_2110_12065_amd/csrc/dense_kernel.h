@@ -194,7 +194,7 @@ template <int DT, int OP, int RW, int U, int WL, bool NT>
 __global__ void __launch_bounds__(512)
 k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, int n_cols,
              const float* __restrict__ rscale, const float* __restrict__ w, float* __restrict__ y,
-             double* __restrict__ part, SolveState* __restrict__ st, int norm) {
+             double* __restrict__ part, SolveState* __restrict__ st, int norm, FusedPrev fp) {
   extern __shared__ float4 w_lds4[];
   float* w_lds = reinterpret_cast<float*>(w_lds4);
   __shared__ double sh[16];
@@ -206,23 +206,80 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
   constexpr int VE = Traits<DT>::VE;
   const int nvec = n_cols / VE;
   const float* wv = w;
+  const float* wtail = w;   // signed w of the columns past the last whole vector
   const uint32_t* smask = nullptr;
   if constexpr (WLDS) {
-    // whole vectors' w in chunk-interleaved order (|w| with PF, plus one sign word
-    // per 4 columns in natural order after the staged region)
+    // FusedPrev: w = y_prev * (1 / nu), nu from the previous product's partials (the
+    // normalisation kernel's arithmetic); this block also writes its share of w.
+    const bool fused = fp.y_prev != nullptr;
+    constexpr int PQ = 8;   // float4s of y_prev per thread loaded before nu is known
     const int np4 = nvec * (VE / 4);
-    for (int k = threadIdx.x; k < np4; k += blockDim.x) {
-      float4 t = reinterpret_cast<const float4*>(w)[k];
+    const float4* src = reinterpret_cast<const float4*>(fused ? fp.y_prev : w);
+    float4 pre[PQ];
+    // this block's share of the new iterate: elements e0 .. e1-1, the first blockDim
+    // of them also loaded before nu is known
+    const int64_t per = ((int64_t)n_cols + gridDim.x - 1) / gridDim.x;
+    const int64_t e0 = (int64_t)blockIdx.x * per, e1 = min((int64_t)n_cols, e0 + per);
+    float ys = 0.0f;
+    if (fused) {
+#pragma unroll
+      for (int q = 0; q < PQ; ++q) {
+        const int k = threadIdx.x + q * blockDim.x;
+        pre[q] = k < np4 ? src[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      if (e0 + threadIdx.x < e1) ys = fp.y_prev[e0 + threadIdx.x];
+    }
+    double inv = 0.0;
+    if (fused) {
+      const double tot = wave_sum_parts(fp.part_prev, fp.nparts);
+      const double nu = (norm == NORM_L2) ? sqrt(tot) : tot;
+      if (!(nu > 0.0) || !(nu < INFINITY)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          st->nu = nu;
+          st->status = MAPI_ERR_DEGENERATE;
+          st->iter = fp.iter - 1;
+          st->done = 1;
+        }
+        return;
+      }
+      inv = 1.0 / nu;
+      if (e0 + threadIdx.x < e1) fp.w_new[e0 + threadIdx.x] = (float)((double)ys * inv);
+      for (int64_t i = e0 + threadIdx.x + blockDim.x; i < e1; i += blockDim.x)
+        fp.w_new[i] = (float)((double)fp.y_prev[i] * inv);
+    }
+    const int64_t wfl = dense_lds_w_floats(DT, n_cols);
+    // whole vectors' w in chunk-interleaved order (|w| with PF, plus one sign word
+    // per 4 columns in natural order after the staged region and the tail)
+    auto stage = [&](int k, float4 t) {
+      if (fused)
+        t = make_float4((float)((double)t.x * inv), (float)((double)t.y * inv), (float)((double)t.z * inv),
+                        (float)((double)t.w * inv));
       if constexpr (PF) {
-        uint32_t* sm = reinterpret_cast<uint32_t*>(w_lds + dense_lds_w_floats(DT, n_cols));
+        uint32_t* sm = reinterpret_cast<uint32_t*>(w_lds + wfl + kDenseTailFloats);
         sm[k] = (sign_bit(t.x) >> 24) | (sign_bit(t.y) >> 16) | (sign_bit(t.z) >> 8) | sign_bit(t.w);
         t = make_float4(fabsf(t.x), fabsf(t.y), fabsf(t.z), fabsf(t.w));
       }
       reinterpret_cast<float4*>(w_lds)[perm_base<DT>(k / (VE / 4)) + (k % (VE / 4)) * 64] = t;
+    };
+    int k0 = threadIdx.x;
+    if (fused) {
+#pragma unroll
+      for (int q = 0; q < PQ; ++q) {
+        const int k = threadIdx.x + q * blockDim.x;
+        if (k < np4) stage(k, pre[q]);
+      }
+      k0 = threadIdx.x + PQ * blockDim.x;
+    }
+    for (int k = k0; k < np4; k += blockDim.x) stage(k, src[k]);
+    if (fused) {   // the tail cannot be read from w: it is formed here, after the staged vectors
+      float* tl = w_lds + wfl;
+      for (int j = nvec * VE + threadIdx.x; j < n_cols; j += blockDim.x)
+        tl[j - nvec * VE] = (float)((double)fp.y_prev[j] * inv);
+      wtail = tl - nvec * VE;
     }
     __syncthreads();
     wv = w_lds;
-    if constexpr (PF) smask = reinterpret_cast<const uint32_t*>(w_lds + dense_lds_w_floats(DT, n_cols));
+    if constexpr (PF) smask = reinterpret_cast<const uint32_t*>(w_lds + wfl + kDenseTailFloats);
   }
 
   const int lane = threadIdx.x & (kWave - 1);
@@ -245,10 +302,10 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
       bool p2 = true;
 #pragma unroll
       for (int r = 0; r < RW; ++r) p2 = p2 && pow2_scale(sc[r]);
-      if (p2) rows_product<DT, OP, RW, U, NT, PF, true, WLDS>(rp, sc, wv, n_cols, lane, sums, smask, w);
-      else rows_product<DT, OP, RW, U, NT, PF, false, WLDS>(rp, sc, wv, n_cols, lane, sums, smask, w);
+      if (p2) rows_product<DT, OP, RW, U, NT, PF, true, WLDS>(rp, sc, wv, n_cols, lane, sums, smask, wtail);
+      else rows_product<DT, OP, RW, U, NT, PF, false, WLDS>(rp, sc, wv, n_cols, lane, sums, smask, wtail);
     } else {
-      rows_product<DT, OP, RW, U, NT, PF, false, WLDS>(rp, sc, wv, n_cols, lane, sums, smask, w);
+      rows_product<DT, OP, RW, U, NT, PF, false, WLDS>(rp, sc, wv, n_cols, lane, sums, smask, wtail);
     }
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
@@ -270,36 +327,39 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
 
 template <int DT, int OP, int RW, int U, int WL, bool NT>
 static hipError_t launch_k(const DenseArgs& a, const float* w, float* y, double* part, SolveState* st, int norm,
-                           int blocks, int waves, hipStream_t s) {
+                           int blocks, int waves, hipStream_t s, const FusedPrev* fp) {
+  const FusedPrev f = fp ? *fp : FusedPrev{nullptr, nullptr, 0, nullptr, 0};
   const unsigned char* A = static_cast<const unsigned char*>(a.A);
   const int64_t ldb = a.ld * Traits<DT>::ESZ;
   const size_t lds = dense_lds_bytes(DT, a.n_cols, WL);
   if (a.ev_start) {
     hipExtLaunchKernelGGL((k_mavp_dense<DT, OP, RW, U, WL, NT>), dim3(blocks), dim3(waves * kWave), (uint32_t)lds, s,
                           a.ev_start, a.ev_stop, 0u, A, ldb, (int)a.n_rows, (int)a.n_cols, a.row_scale, w, y, part,
-                          st, norm);
+                          st, norm, f);
   } else {
     hipLaunchKernelGGL((k_mavp_dense<DT, OP, RW, U, WL, NT>), dim3(blocks), dim3(waves * kWave), lds, s, A, ldb,
-                       (int)a.n_rows, (int)a.n_cols, a.row_scale, w, y, part, st, norm);
+                       (int)a.n_rows, (int)a.n_cols, a.row_scale, w, y, part, st, norm, f);
   }
   return hipGetLastError();
 }
 
 template <int DT, int OP, int RW, int U, int WL>
 static hipError_t launch_nt(const DenseArgs& a, const float* w, float* y, double* part, SolveState* st, int norm,
-                            const DenseTuning& t, int blocks, hipStream_t s) {
-  return t.nontemporal ? launch_k<DT, OP, RW, U, WL, true>(a, w, y, part, st, norm, blocks, t.waves, s)
-                       : launch_k<DT, OP, RW, U, WL, false>(a, w, y, part, st, norm, blocks, t.waves, s);
+                            const DenseTuning& t, int blocks, hipStream_t s, const FusedPrev* fp) {
+  return t.nontemporal ? launch_k<DT, OP, RW, U, WL, true>(a, w, y, part, st, norm, blocks, t.waves, s, fp)
+                       : launch_k<DT, OP, RW, U, WL, false>(a, w, y, part, st, norm, blocks, t.waves, s, fp);
 }
 
 template <int DT, int OP, int RW, int U>
 static hipError_t launch_wl(const DenseArgs& a, const float* w, float* y, double* part, SolveState* st, int norm,
-                            const DenseTuning& t, int blocks, hipStream_t s) {
+                            const DenseTuning& t, int blocks, hipStream_t s, const FusedPrev* fp) {
   switch (t.w_in_lds) {
-    case 0: return launch_nt<DT, OP, RW, U, 0>(a, w, y, part, st, norm, t, blocks, s);
-    case 1: return launch_nt<DT, OP, RW, U, 1>(a, w, y, part, st, norm, t, blocks, s);
+    case 0:
+      if (fp) return hipErrorInvalidValue;   // forming w needs it staged in LDS
+      return launch_nt<DT, OP, RW, U, 0>(a, w, y, part, st, norm, t, blocks, s, fp);
+    case 1: return launch_nt<DT, OP, RW, U, 1>(a, w, y, part, st, norm, t, blocks, s, fp);
     case 2:
-      if constexpr (DT == MAPI_FP8_E4M3) return launch_nt<DT, OP, RW, U, 2>(a, w, y, part, st, norm, t, blocks, s);
+      if constexpr (DT == MAPI_FP8_E4M3) return launch_nt<DT, OP, RW, U, 2>(a, w, y, part, st, norm, t, blocks, s, fp);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
@@ -307,31 +367,31 @@ static hipError_t launch_wl(const DenseArgs& a, const float* w, float* y, double
 
 template <int DT, int OP, int RW>
 static hipError_t launch_rw(const DenseArgs& a, const float* w, float* y, double* part, SolveState* st, int norm,
-                            const DenseTuning& t, int blocks, hipStream_t s) {
-  return t.unroll == 4 ? launch_wl<DT, OP, RW, 4>(a, w, y, part, st, norm, t, blocks, s)
-                       : launch_wl<DT, OP, RW, 2>(a, w, y, part, st, norm, t, blocks, s);
+                            const DenseTuning& t, int blocks, hipStream_t s, const FusedPrev* fp) {
+  return t.unroll == 4 ? launch_wl<DT, OP, RW, 4>(a, w, y, part, st, norm, t, blocks, s, fp)
+                       : launch_wl<DT, OP, RW, 2>(a, w, y, part, st, norm, t, blocks, s, fp);
 }
 
 template <int DT, int OP>
 static hipError_t launch_op(const DenseArgs& a, const float* w, float* y, double* part, SolveState* st, int norm,
-                            const DenseTuning& t, int blocks, hipStream_t s) {
+                            const DenseTuning& t, int blocks, hipStream_t s, const FusedPrev* fp) {
   switch (t.rows_per_wave) {
-    case 1: return launch_rw<DT, OP, 1>(a, w, y, part, st, norm, t, blocks, s);
-    case 2: return launch_rw<DT, OP, 2>(a, w, y, part, st, norm, t, blocks, s);
-    case 4: return launch_rw<DT, OP, 4>(a, w, y, part, st, norm, t, blocks, s);
-    case 8: return launch_rw<DT, OP, 8>(a, w, y, part, st, norm, t, blocks, s);
+    case 1: return launch_rw<DT, OP, 1>(a, w, y, part, st, norm, t, blocks, s, fp);
+    case 2: return launch_rw<DT, OP, 2>(a, w, y, part, st, norm, t, blocks, s, fp);
+    case 4: return launch_rw<DT, OP, 4>(a, w, y, part, st, norm, t, blocks, s, fp);
+    case 8: return launch_rw<DT, OP, 8>(a, w, y, part, st, norm, t, blocks, s, fp);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int DT>
 static hipError_t launch_dt(const DenseArgs& a, int op, const float* w, float* y, double* part, SolveState* st,
-                            int norm, const DenseTuning& t, int blocks, hipStream_t s) {
+                            int norm, const DenseTuning& t, int blocks, hipStream_t s, const FusedPrev* fp) {
   switch (op) {
-    case MAPI_OP_MIN1: return launch_op<DT, MAPI_OP_MIN1>(a, w, y, part, st, norm, t, blocks, s);
-    case MAPI_OP_MIN2: return launch_op<DT, MAPI_OP_MIN2>(a, w, y, part, st, norm, t, blocks, s);
-    case MAPI_OP_DIAMOND: return launch_op<DT, MAPI_OP_DIAMOND>(a, w, y, part, st, norm, t, blocks, s);
-    case MAPI_OP_DOT: return launch_op<DT, MAPI_OP_DOT>(a, w, y, part, st, norm, t, blocks, s);
+    case MAPI_OP_MIN1: return launch_op<DT, MAPI_OP_MIN1>(a, w, y, part, st, norm, t, blocks, s, fp);
+    case MAPI_OP_MIN2: return launch_op<DT, MAPI_OP_MIN2>(a, w, y, part, st, norm, t, blocks, s, fp);
+    case MAPI_OP_DIAMOND: return launch_op<DT, MAPI_OP_DIAMOND>(a, w, y, part, st, norm, t, blocks, s, fp);
+    case MAPI_OP_DOT: return launch_op<DT, MAPI_OP_DOT>(a, w, y, part, st, norm, t, blocks, s, fp);
     default: return hipErrorInvalidValue;
   }
 }

@@ -17,7 +17,7 @@ template <int MODE, int BS, int PF>
 __global__ void __launch_bounds__(BS)
 k_finalize(const float* __restrict__ y, const float* __restrict__ w_old, float* __restrict__ w_new, int64_t n,
            SolveState* __restrict__ st, const double* __restrict__ pprod, int nprod, int norm,
-           double* __restrict__ part, const uint8_t* __restrict__ dangling, double c, double inv_n) {
+           double* __restrict__ part, const uint8_t* __restrict__ dangling, double c, double inv_n, int set_iter) {
   __shared__ double sh[16];
   __shared__ int sh_flag;
   if (state_done(st)) return;
@@ -32,7 +32,7 @@ k_finalize(const float* __restrict__ y, const float* __restrict__ w_old, float* 
     yp[k] = i < n ? y[i] : 0.0f;
     wp[k] = i < n ? w_old[i] : 0.0f;
   }
-  const double tot = block_sum_parts(pprod, nprod, 1, 0, sh);
+  const double tot = wave_sum_parts(pprod, nprod);
   const double nu = (norm == NORM_L2) ? sqrt(tot) : tot;
   if (blockIdx.x == 0 && threadIdx.x == 0) st->nu = nu;
   if (!(nu > 0.0) || !(nu < INFINITY)) {
@@ -42,9 +42,11 @@ k_finalize(const float* __restrict__ y, const float* __restrict__ w_old, float* 
     }
     return;
   }
+  // w = y * (1 / nu): the same arithmetic as a product that forms w itself (FusedPrev)
+  const double inv = 1.0 / nu;
   double r = 0.0, e0 = 0.0, e1 = 0.0;
   auto element = [&](int64_t i, float yi, float wo) {
-    const float wn = (float)((double)yi / nu);
+    const float wn = (float)((double)yi * inv);
     w_new[i] = wn;
     const double wd = (double)wn;
     r += fabs(wd - (double)wo);
@@ -72,6 +74,7 @@ k_finalize(const float* __restrict__ y, const float* __restrict__ w_old, float* 
     if (threadIdx.x == 0) {
       st->ex[0] = e0;
       st->ex[1] = e1;
+      if (set_iter >= 0) st->iter = set_iter;
       state_advance(st, r);
     }
     return;
@@ -92,6 +95,7 @@ k_finalize(const float* __restrict__ y, const float* __restrict__ w_old, float* 
       st->ex[0] = E0;
       st->ex[1] = E1;
       st->cnt_b = 0;
+      if (set_iter >= 0) st->iter = set_iter;
       state_advance(st, R);
     }
   }
@@ -176,20 +180,20 @@ int dense_part_count(const DenseArgs& a, const DenseTuning& t, int cu_count) {
 }
 
 hipError_t launch_dense_f32(const DenseArgs& a, int op, const float* w, float* y, double* part, SolveState* st,
-                            int norm, const DenseTuning& t, int blocks, hipStream_t s);
+                            int norm, const DenseTuning& t, int blocks, hipStream_t s, const FusedPrev* fp);
 hipError_t launch_dense_bf16(const DenseArgs& a, int op, const float* w, float* y, double* part, SolveState* st,
-                             int norm, const DenseTuning& t, int blocks, hipStream_t s);
+                             int norm, const DenseTuning& t, int blocks, hipStream_t s, const FusedPrev* fp);
 hipError_t launch_dense_fp8(const DenseArgs& a, int op, const float* w, float* y, double* part, SolveState* st,
-                            int norm, const DenseTuning& t, int blocks, hipStream_t s);
+                            int norm, const DenseTuning& t, int blocks, hipStream_t s, const FusedPrev* fp);
 
 hipError_t launch_mavp_dense(const DenseArgs& a, int op, const float* w, float* y, double* part, SolveState* st,
-                             int norm, const DenseTuning& t, int cu_count, hipStream_t s) {
+                             int norm, const DenseTuning& t, int cu_count, hipStream_t s, const FusedPrev* fp) {
   if (t.waves != 4 && t.waves != 8) return hipErrorInvalidValue;
   const int blocks = dense_blocks(a, t, cu_count);
   switch (a.dtype) {
-    case MAPI_F32: return launch_dense_f32(a, op, w, y, part, st, norm, t, blocks, s);
-    case MAPI_BF16: return launch_dense_bf16(a, op, w, y, part, st, norm, t, blocks, s);
-    case MAPI_FP8_E4M3: return launch_dense_fp8(a, op, w, y, part, st, norm, t, blocks, s);
+    case MAPI_F32: return launch_dense_f32(a, op, w, y, part, st, norm, t, blocks, s, fp);
+    case MAPI_BF16: return launch_dense_bf16(a, op, w, y, part, st, norm, t, blocks, s, fp);
+    case MAPI_FP8_E4M3: return launch_dense_fp8(a, op, w, y, part, st, norm, t, blocks, s, fp);
     default: return hipErrorInvalidValue;
   }
 }
@@ -252,12 +256,12 @@ int finalize_blocks(int64_t n) {
 
 hipError_t launch_finalize(int mode, const float* y, const float* w_old, float* w_new, int64_t n, SolveState* st,
                            const double* pprod, int nprod, int norm, double* part, const uint8_t* dangling, double c,
-                           double inv_n, hipStream_t s) {
+                           double inv_n, hipStream_t s, int set_iter) {
   const int blocks = finalize_blocks(n);
   switch (mode) {
-    case 0: hipLaunchKernelGGL((k_finalize<0, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n); break;
-    case 1: hipLaunchKernelGGL((k_finalize<1, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n); break;
-    case 2: hipLaunchKernelGGL((k_finalize<2, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n); break;
+    case 0: hipLaunchKernelGGL((k_finalize<0, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n, set_iter); break;
+    case 1: hipLaunchKernelGGL((k_finalize<1, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n, set_iter); break;
+    case 2: hipLaunchKernelGGL((k_finalize<2, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n, set_iter); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -347,3 +347,41 @@ def test_read_reference_times_and_rejects_bad_sizes():
         mp.mapi_read_reference(x[1:], reps=1)           # 4-byte offset: not 16-byte aligned
     with pytest.raises(mp.MapiError):
         mp.mapi_read_reference(x, reps=0)
+
+
+@pytest.mark.parametrize("n", [517, 1003])
+@pytest.mark.parametrize("meth", ["mapi", "rpi"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_normalisation_in_the_product_matches_the_separate_kernel(dtype, meth, n):
+    # A fixed-iteration solve (tol 0) forms each normaliser and iterate inside the next product;
+    # a tolerance too small to ever stop the solve keeps the normalisation kernel after every
+    # product.  Both use the same arithmetic, so the iterates, norms and residuals are the same
+    # bits.  n = 517 and 1003 leave ragged tails for every storage type.
+    print(f"[case] fused normalisation {dtype} {meth} n={n}", flush=True)
+    A32 = synth.dense_cov(n, 2 * n, seed=n)
+    Ad, rs, Aref = _stored(A32, dtype)
+    w0h = synth.start_vector(n, n + 1)
+    w0 = to_dev(w0h)
+    code = {"f32": mp.MAPI_F32, "bf16": mp.MAPI_BF16, "fp8": mp.MAPI_FP8_E4M3}[dtype]
+    fn = mp.mapi_solve if meth == "mapi" else mp.rpi_solve
+    for lds in ((1, 2) if dtype == "fp8" else (1,)):
+        mp.mapi_tuning_set(code, n, n, dict(rows_per_wave=2, waves=8, blocks_per_cu=2, unroll=2, w_in_lds=lds,
+                                            nontemporal=1))
+        wa, ia = fn(Ad, w0, max_iters=13, row_scale=rs)
+        wb, ib = fn(Ad, w0, max_iters=13, tol=1e-300, row_scale=rs)
+        np.testing.assert_array_equal(wa.cpu().numpy(), wb.cpu().numpy())
+        assert ia["iters"] == ib["iters"] == 13
+        assert ia["norm"] == ib["norm"] and ia["residual"] == ib["residual"]
+    ref = (oracle.mapi if meth == "mapi" else oracle.rpi)(Aref.astype(np.float64), w0h.astype(np.float64), 13)
+    assert rel_l1(wa.cpu().numpy(), ref.w) <= TOL
+
+
+def test_degenerate_normaliser_in_the_product_is_reported():
+    # the zero matrix: the first normaliser is zero whether the product or the kernel forms it
+    n = 96
+    mp.mapi_tuning_set(mp.MAPI_F32, n, n, dict(rows_per_wave=1, waves=4, blocks_per_cu=1, unroll=2, w_in_lds=1,
+                                               nontemporal=0))
+    for tol in (0.0, 1e-300):
+        with pytest.raises(mp.MapiError) as ei:
+            mp.mapi_solve(to_dev(np.zeros((n, n), np.float32)), to_dev(synth.start_vector(n, 1)), max_iters=5, tol=tol)
+        assert ei.value.status == 4 and "after 0 iterations" in str(ei.value)
