@@ -355,6 +355,13 @@ def bench_small(mp, ctx, torch, n=256, iters=200, tol=1e-7, seed=SEED, copies=25
         sec = (time.perf_counter() - t0) / reps
         out[f"{meth}_iters"] = info["iters"]
         out[f"{meth}_plain_us_per_iter"] = sec / max(info["iters"], 1) * 1e6
+        # the FP64 oracle at the same iteration count (rounding only: same matrix, same start)
+        import oracle
+        wg, _ = fn(C, w0, max_iters=info["iters"], check_every=16, ctx=ctx)
+        orc = oracle.mapi if meth == "mapi" else oracle.rpi
+        ref = orc(C.cpu().numpy().astype(np.float64), w0.cpu().numpy().astype(np.float64), info["iters"]).w
+        g = wg.double().cpu().numpy()
+        out[f"{meth}_rel_l1_vs_oracle"] = float(np.abs(g - ref).sum() / np.abs(ref).sum())
         out[f"{meth}_plain_solves_s"] = 1.0 / sec
         probs = [mp.problem_dense(C, meth, w0=w0, max_iters=iters, tol=tol) for _ in range(copies)]
         mp.mapi_solve_batched(probs[:2], ctx=ctx)
@@ -489,6 +496,18 @@ def bench_pca(mp, ctx, torch, D=4096, N=65536, k=8, seed=77):
         s = time.perf_counter() - t0
         out[f"gram_{op}_ms"] = s * 1e3
         out[f"gram_{op}_gterms_s"] = terms / s / 1e9
+        # sampled entries against the FP64 oracle, relative to the sum of |terms| (the bound's scale)
+        import oracle
+        rng = np.random.default_rng(3)
+        pairs = [(0, 0), (D - 1, D - 1), (0, D - 1)] + [tuple(int(v) for v in p) for p in rng.integers(0, D, (5, 2))]
+        Ah = A[[i for i, _ in pairs], [j for _, j in pairs]].double().cpu().numpy()
+        worst = 0.0
+        for (i, j), a in zip(pairs, Ah):
+            xi, xj = X[i].double().cpu().numpy(), X[j].double().cpu().numpy()
+            ref = oracle.mingram_entry(np.stack([xi, xj]), 0, 1, 1.0 / N, op)
+            scale = (np.minimum(np.abs(xi), np.abs(xj)) if op == "min1" else np.abs(xi * xj)).sum() / N
+            worst = max(worst, abs(a - ref) / scale)
+        out[f"gram_{op}_sampled_err_vs_oracle"] = worst
         if op == "min1":
             # xor, med3, add per term against the vector ALU rate (256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz)
             out["gram_min1_valu_frac"] = terms * 3.0 / s / 78.6e12
@@ -553,6 +572,34 @@ def bench_pagerank(mp, ctx, torch, n=1 << 22, seed=2022):
         out[f"{meth}_csr_kernel_us"] = kms * 1e3
         out[f"{meth}_gedges_s"] = nnz / (kms * 1e-3) / 1e9
         out[f"{meth}_csr_kernel_gbs"] = bytes_iter / (kms * 1e-3) / 1e9
+    # the MAPI iterate against the FP64 oracle (CSR form) at the GPU's iteration count: the rank
+    # signal is the deviation from 1/n, so its relative l1 error and the top-100 overlap
+    import oracle
+    wm, im = mp.mapi_pagerank(rp, col, val, 0.85, "mapi", max_iters=300, tol=1e-8, stall_iters=10, check_every=4,
+                              ctx=ctx)
+    ref = oracle.pagerank(n, g["row_ptr"], g["col"], g["val"], 0.85, "mapi", np.full(n, 1.0 / n), im["iters"]).w
+    wg = wm.double().cpu().numpy()
+    dev_g, dev_r = wg - 1.0 / n, ref - 1.0 / n
+    out["mapi_oracle_iters"] = im["iters"]
+    out["mapi_rel_l1_vs_oracle"] = float(np.abs(wg - ref).sum() / np.abs(ref).sum())
+    out["mapi_deviation_rel_l1_vs_oracle"] = float(np.abs(dev_g - dev_r).sum() / np.abs(dev_r).sum())
+    top_g, top_r = np.argsort(-wg, kind="stable")[:100], np.argsort(-ref, kind="stable")[:100]
+    out["mapi_top100_overlap_vs_oracle"] = len(set(top_g.tolist()) & set(top_r.tolist()))
+    # the float64 iterate (mapi_pagerank_f64): time per product and the same comparison
+    mp.mapi_pagerank(rp, col, val, 0.85, "mapi", max_iters=2, f64=True, ctx=ctx)
+    ctx.timing(True)
+    ctx.timing_reset()
+    w64, i64 = mp.mapi_pagerank(rp, col, val, 0.85, "mapi", max_iters=im["iters"], f64=True, ctx=ctx)
+    torch.cuda.synchronize()
+    ms, launches = ctx.timing_get("csr")
+    ctx.timing(False)
+    g64 = w64.cpu().numpy()
+    out["mapi_f64_csr_kernel_us"] = ms / max(launches, 1) * 1e3
+    out["mapi_f64_deviation_rel_l1_vs_oracle"] = float(np.abs((g64 - 1.0 / n) - dev_r).sum() / np.abs(dev_r).sum())
+    out["mapi_f64_top100_overlap_vs_oracle"] = len(set(np.argsort(-g64, kind="stable")[:100].tolist())
+                                                   & set(top_r.tolist()))
+    log(f"PageRank float64 iterate: {out['mapi_f64_csr_kernel_us']:.0f} us per product, top-100 overlap "
+        f"{out['mapi_f64_top100_overlap_vs_oracle']} (float32: {out['mapi_top100_overlap_vs_oracle']})")
     # counter bytes of the MAPI product (FETCH_SIZE + WRITE_SIZE, scaled; the gathers of w are
     # counted as the L2 fills they cause)
     out["mapi_csr_traffic_bytes"] = traffic

@@ -301,6 +301,14 @@ mapi_status mapi_pca_topk(mapi_ctx* ctx, const float* X, int64_t D, int64_t N, i
 mapi_status mapi_pagerank(mapi_ctx* ctx, const mapi_csr* H, double alpha, int32_t method,
                           const float* w0, float* w_out, const mapi_opts* opts, mapi_info* info);
 
+/* The same with a float64 iterate: w0 / w_out are device double[n], every term and
+ * row sum is float64 (the float32 iterate resolves about 6e-8 of w ~ 1/n, while the
+ * ranking signal sits in the deviation from 1/n, of order in-degree / n; ties in
+ * in-degree are broken below that resolution).  Twice the iterate's memory and
+ * gather bytes.                                                                  */
+mapi_status mapi_pagerank_f64(mapi_ctx* ctx, const mapi_csr* H, double alpha, int32_t method,
+                              const double* w0, double* w_out, const mapi_opts* opts, mapi_info* info);
+
 /* ---------------------------------------------------------------- batched */
 
 typedef enum mapi_problem_kind {

@@ -96,6 +96,8 @@ _SIGS = {
                                 C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]),
     "mapi_pagerank": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
                                 C.POINTER(Opts), C.POINTER(Info)]),
+    "mapi_pagerank_f64": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
+                                    C.POINTER(Opts), C.POINTER(Info)]),
     "mapi_hybrid_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts),
                                     C.POINTER(Opts), C.POINTER(Info), C.POINTER(Info)]),
     "mapi_image_reconstruct": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_int32,
@@ -392,9 +394,9 @@ def mapi_pca_topk(X, k, W0, method="mapi", scale=None, max_iters=100, tol=0.0, o
 
 
 def mapi_pagerank(row_ptr, col, val, alpha=0.85, method="mapi", w0=None, max_iters=100, tol=0.0, final_l2=False,
-                  check_every=0, stall_iters=0, w_out=None, ctx=None):
+                  check_every=0, stall_iters=0, w_out=None, f64=False, ctx=None):
     """Power iteration on G = alpha H + (1 - alpha)/n 1 (eq. 11), H in CSR by destination row.
-    Returns (w, info)."""
+    Returns (w, info).  f64: float64 iterate (w0 / w_out float64), mapi_pagerank_f64."""
     import torch
     c = _ctx_of(ctx, row_ptr)
     n = row_ptr.numel() - 1
@@ -405,13 +407,18 @@ def mapi_pagerank(row_ptr, col, val, alpha=0.85, method="mapi", w0=None, max_ite
     if val.numel() != nnz:
         raise ValueError("col and val differ in length")
     H = Csr(n, nnz, row_ptr.data_ptr(), col.data_ptr() if nnz else None, val.data_ptr() if nnz else None)
+    wdt = torch.float64 if f64 else torch.float32
     if w_out is None:
-        w_out = torch.empty(n, dtype=torch.float32, device=row_ptr.device)
+        w_out = torch.empty(n, dtype=wdt, device=row_ptr.device)
+    for t, name in ((w0, "w0"), (w_out, "w_out")):
+        if t is not None and not (t.is_cuda and t.dtype == wdt and t.is_contiguous() and t.numel() == n):
+            raise ValueError(f"{name} must be a contiguous {wdt} device tensor of length {n}")
     o = _opts(max_iters, tol, "min1", final_l2, check_every, stall_iters)
     info = Info()
-    _check(lib().mapi_pagerank(c.handle, C.byref(H), float(alpha), METHODS[method],
-                               C.c_void_p(_vec(w0, n, "w0")) if w0 is not None else None,
-                               C.c_void_p(_vec(w_out, n, "w_out")), C.byref(o), C.byref(info)))
+    fn = lib().mapi_pagerank_f64 if f64 else lib().mapi_pagerank
+    _check(fn(c.handle, C.byref(H), float(alpha), METHODS[method],
+              C.c_void_p(w0.data_ptr()) if w0 is not None else None,
+              C.c_void_p(w_out.data_ptr()), C.byref(o), C.byref(info)))
     return w_out, info.as_dict()
 
 

@@ -218,6 +218,97 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
 
 }  // namespace
 
+namespace {
+
+// PageRank power iteration with a float32 or float64 iterate T (eq. 11 split sums).
+template <typename T>
+mapi_status pagerank_run(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t method, const T* w0, T* w_out,
+                         const mapi_opts* o, mapi_info* info) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  if (!H || !H->row_ptr || !w_out) return fail(MAPI_ERR_ARG, "H, H->row_ptr and w_out are required");
+  if (H->n <= 0 || H->n > INT32_MAX || H->nnz < 0 || H->nnz > INT32_MAX) return fail(MAPI_ERR_ARG, "bad n or nnz");
+  if (H->nnz > 0 && (!H->col || !H->val)) return fail(MAPI_ERR_ARG, "col and val are required when nnz > 0");
+  if (!(alpha > 0.0 && alpha < 1.0)) return fail(MAPI_ERR_ARG, "alpha must be in (0, 1)");
+  if (method != MAPI_METHOD_MAPI && method != MAPI_METHOD_RPI) return fail(MAPI_ERR_ARG, "method %d", method);
+  mapi_status s;
+  if ((s = check_opts(o)) != MAPI_OK) return s;
+  HIP_TRY(hipSetDevice(c->device));
+  const int64_t n = H->n;
+  const int F = finalize_blocks(n);
+  const int PP = csr_part_count(n);
+  const int P = std::max(3 * F, 2 * pr_scalar_blocks(n));
+  Layout L;
+  const size_t o_st = L.take(sizeof(SolveState));
+  const size_t o_pp = L.take(sizeof(double) * PP);
+  const size_t o_part = L.take(sizeof(double) * P);
+  const size_t o_w0 = L.take(sizeof(T) * n);
+  const size_t o_w1 = L.take(sizeof(T) * n);
+  const size_t o_y = L.take(sizeof(T) * n);
+  const size_t o_d = L.take(n);
+  const size_t o_err = L.take(sizeof(int32_t));
+  if ((s = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return s;
+  char* base = static_cast<char*>(c->ws);
+  SolveState* st = reinterpret_cast<SolveState*>(base + o_st);
+  double* pprod = reinterpret_cast<double*>(base + o_pp);
+  double* part = reinterpret_cast<double*>(base + o_part);
+  T* wb[2] = {reinterpret_cast<T*>(base + o_w0), reinterpret_cast<T*>(base + o_w1)};
+  T* y = reinterpret_cast<T*>(base + o_y);
+  uint8_t* dangling = reinterpret_cast<uint8_t*>(base + o_d);
+  int32_t* err = reinterpret_cast<int32_t*>(base + o_err);
+
+  HIP_TRY(hipMemsetAsync(err, 0, sizeof(int32_t), c->stream));
+  HIP_TRY(launch_csr_prep(H->row_ptr, H->col, n, H->nnz, dangling, err, c->stream));
+  int32_t err_h = 0;
+  HIP_TRY(hipMemcpyAsync(&err_h, err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (err_h) return fail(MAPI_ERR_ARG, "invalid CSR arrays (code %d)", err_h);
+
+  const double inv_n = 1.0 / (double)n;
+  const double cc = (1.0 - alpha) * inv_n;
+  if (w0) {
+    HIP_TRY(hipMemcpyAsync(wb[0], w0, sizeof(T) * n, hipMemcpyDeviceToDevice, c->stream));
+  } else if constexpr (sizeof(T) == 4) {
+    HIP_TRY(launch_fill_f32(wb[0], n, (float)inv_n, c->stream));
+  } else {
+    HIP_TRY(launch_fill_f64(wb[0], n, inv_n, c->stream));
+  }
+  HIP_TRY(launch_state_init(st, o->max_iters, o->tol, o->stall_iters, c->stream));
+  HIP_TRY(launch_pr_scalars<T>(method, wb[0], n, dangling, cc, inv_n, st, part, c->stream));
+  const int check = o->check_every > 0 ? o->check_every : 16;
+  const int mode = method == MAPI_METHOD_MAPI ? 1 : 2;
+  for (int it = 0; it < o->max_iters; ++it) {
+    T* wc = wb[it & 1];
+    T* wn = wb[(it & 1) ^ 1];
+    {
+      Timed tm(c, MAPI_K_CSR);
+      HIP_TRY(launch_csr_product<T>(method, H->row_ptr, H->col, H->val, n, wc, y, pprod, st, alpha, cc, inv_n,
+                                    c->stream));
+    }
+    {
+      Timed tm(c, MAPI_K_FINALIZE);
+      if constexpr (sizeof(T) == 4)
+        HIP_TRY(launch_finalize(mode, y, wc, wn, n, st, pprod, PP, NORM_L1, part, dangling, cc, inv_n, c->stream));
+      else
+        HIP_TRY(launch_finalize_f64(mode, y, wc, wn, n, st, pprod, PP, part, dangling, cc, inv_n, c->stream));
+    }
+    if ((it + 1) % check == 0 && it + 1 < o->max_iters) {
+      if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
+      if (c->st_host->done) break;
+    }
+  }
+  if constexpr (sizeof(T) == 4)
+    HIP_TRY(launch_finish(wb[0], wb[1], w_out, n, st, o->final_l2, c->stream));
+  else
+    HIP_TRY(launch_finish_f64(wb[0], wb[1], w_out, n, st, o->final_l2, c->stream));
+  if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
+  fill_info(info, *c->st_host);
+  if (c->st_host->status == MAPI_ERR_DEGENERATE)
+    return fail(MAPI_ERR_DEGENERATE, "normaliser was zero or not finite after %d iterations", c->st_host->iter);
+  return MAPI_OK;
+}
+
+}  // namespace
+
 // ====================================================================== C-ABI
 extern "C" {
 
@@ -753,79 +844,12 @@ mapi_status mapi_minibatch(mapi_ctx* c, const float* X, int64_t N, int64_t D, in
 
 mapi_status mapi_pagerank(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t method, const float* w0,
                           float* w_out, const mapi_opts* o, mapi_info* info) {
-  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
-  if (!H || !H->row_ptr || !w_out) return fail(MAPI_ERR_ARG, "H, H->row_ptr and w_out are required");
-  if (H->n <= 0 || H->n > INT32_MAX || H->nnz < 0 || H->nnz > INT32_MAX) return fail(MAPI_ERR_ARG, "bad n or nnz");
-  if (H->nnz > 0 && (!H->col || !H->val)) return fail(MAPI_ERR_ARG, "col and val are required when nnz > 0");
-  if (!(alpha > 0.0 && alpha < 1.0)) return fail(MAPI_ERR_ARG, "alpha must be in (0, 1)");
-  if (method != MAPI_METHOD_MAPI && method != MAPI_METHOD_RPI) return fail(MAPI_ERR_ARG, "method %d", method);
-  mapi_status s;
-  if ((s = check_opts(o)) != MAPI_OK) return s;
-  HIP_TRY(hipSetDevice(c->device));
-  const int64_t n = H->n;
-  const int F = finalize_blocks(n);
-  const int PP = csr_part_count(n);
-  const int P = std::max(3 * F, 2 * pr_scalar_blocks(n));
-  Layout L;
-  const size_t o_st = L.take(sizeof(SolveState));
-  const size_t o_pp = L.take(sizeof(double) * PP);
-  const size_t o_part = L.take(sizeof(double) * P);
-  const size_t o_w0 = L.take(sizeof(float) * n);
-  const size_t o_w1 = L.take(sizeof(float) * n);
-  const size_t o_y = L.take(sizeof(float) * n);
-  const size_t o_d = L.take(n);
-  const size_t o_err = L.take(sizeof(int32_t));
-  if ((s = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return s;
-  char* base = static_cast<char*>(c->ws);
-  SolveState* st = reinterpret_cast<SolveState*>(base + o_st);
-  double* pprod = reinterpret_cast<double*>(base + o_pp);
-  double* part = reinterpret_cast<double*>(base + o_part);
-  float* wb[2] = {reinterpret_cast<float*>(base + o_w0), reinterpret_cast<float*>(base + o_w1)};
-  float* y = reinterpret_cast<float*>(base + o_y);
-  uint8_t* dangling = reinterpret_cast<uint8_t*>(base + o_d);
-  int32_t* err = reinterpret_cast<int32_t*>(base + o_err);
+  return pagerank_run<float>(c, H, alpha, method, w0, w_out, o, info);
+}
 
-  HIP_TRY(hipMemsetAsync(err, 0, sizeof(int32_t), c->stream));
-  HIP_TRY(launch_csr_prep(H->row_ptr, H->col, n, H->nnz, dangling, err, c->stream));
-  int32_t err_h = 0;
-  HIP_TRY(hipMemcpyAsync(&err_h, err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  if (err_h) return fail(MAPI_ERR_ARG, "invalid CSR arrays (code %d)", err_h);
-
-  const double inv_n = 1.0 / (double)n;
-  const double cc = (1.0 - alpha) * inv_n;
-  if (w0) {
-    HIP_TRY(hipMemcpyAsync(wb[0], w0, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
-  } else {
-    HIP_TRY(launch_fill_f32(wb[0], n, (float)inv_n, c->stream));
-  }
-  HIP_TRY(launch_state_init(st, o->max_iters, o->tol, o->stall_iters, c->stream));
-  HIP_TRY(launch_pr_scalars(method, wb[0], n, dangling, cc, inv_n, st, part, c->stream));
-  const int check = o->check_every > 0 ? o->check_every : 16;
-  const int mode = method == MAPI_METHOD_MAPI ? 1 : 2;
-  for (int it = 0; it < o->max_iters; ++it) {
-    float* wc = wb[it & 1];
-    float* wn = wb[(it & 1) ^ 1];
-    {
-      Timed tm(c, MAPI_K_CSR);
-      HIP_TRY(launch_csr_product(method, H->row_ptr, H->col, H->val, n, wc, y, pprod, st, (float)alpha, (float)cc,
-                                 inv_n, c->stream));
-    }
-    {
-      Timed tm(c, MAPI_K_FINALIZE);
-      HIP_TRY(launch_finalize(mode, y, wc, wn, n, st, pprod, PP, NORM_L1, part, dangling, cc, inv_n, c->stream));
-    }
-    if ((it + 1) % check == 0 && it + 1 < o->max_iters) {
-      if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
-      if (c->st_host->done) break;
-    }
-  }
-  HIP_TRY(launch_finish(wb[0], wb[1], w_out, n, st, o->final_l2, c->stream));
-  if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
-  fill_info(info, *c->st_host);
-  if (c->st_host->status == MAPI_ERR_DEGENERATE)
-    return fail(MAPI_ERR_DEGENERATE, "normaliser was zero or not finite after %d iterations", c->st_host->iter);
-  return MAPI_OK;
+mapi_status mapi_pagerank_f64(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t method, const double* w0,
+                              double* w_out, const mapi_opts* o, mapi_info* info) {
+  return pagerank_run<double>(c, H, alpha, method, w0, w_out, o, info);
 }
 
 }  // extern "C"

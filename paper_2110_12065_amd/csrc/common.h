@@ -187,9 +187,15 @@ DenseTuning dense_default_tuning(const DenseArgs& a, int cu_count, int max_lds_b
 hipError_t launch_finalize(int mode, const float* y, const float* w_old, float* w_new, int64_t n,
                            SolveState* st, const double* pprod, int nprod, int norm, double* part,
                            const uint8_t* dangling, double c, double inv_n, hipStream_t s, int set_iter = -1);
+// The same for a float64 iterate (PageRank modes 1 and 2).
+hipError_t launch_finalize_f64(int mode, const double* y, const double* w_old, double* w_new, int64_t n,
+                               SolveState* st, const double* pprod, int nprod, double* part, const uint8_t* dangling,
+                               double c, double inv_n, hipStream_t s);
 int finalize_blocks(int64_t n);
 hipError_t launch_finish(const float* w0buf, const float* w1buf, float* out, int64_t n, SolveState* st, int final_l2,
                          hipStream_t s);
+hipError_t launch_finish_f64(const double* w0buf, const double* w1buf, double* out, int64_t n, SolveState* st,
+                             int final_l2, hipStream_t s);
 
 hipError_t launch_quant_bf16(const float* A, int64_t n_rows, int64_t n_cols, int64_t lda, uint16_t* out,
                              int64_t ldo, hipStream_t s);
@@ -204,11 +210,14 @@ hipError_t launch_gram(const float* X, int64_t D, int64_t N, int64_t ldx, double
 
 hipError_t launch_csr_prep(const int32_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz, uint8_t* dangling,
                            int32_t* err, hipStream_t s);
-hipError_t launch_pr_scalars(int method, const float* w, int64_t n, const uint8_t* dangling, double c,
-                             double inv_n, SolveState* st, double* part, hipStream_t s);
+// PageRank kernels for a float32 or float64 iterate T (instantiated for both).
+template <typename T>
+hipError_t launch_pr_scalars(int method, const T* w, int64_t n, const uint8_t* dangling, double c, double inv_n,
+                             SolveState* st, double* part, hipStream_t s);
+template <typename T>
 hipError_t launch_csr_product(int method, const int32_t* row_ptr, const int32_t* col, const float* val, int64_t n,
-                              const float* w, float* y, double* part, SolveState* st, float alpha, float c,
-                              double inv_n, hipStream_t s);
+                              const T* w, T* y, double* part, SolveState* st, double alpha, double c, double inv_n,
+                              hipStream_t s);
 int csr_part_count(int64_t n);
 
 hipError_t launch_deflate_q(const float* A, int64_t D, int64_t lda, const double* p, double* q, double* qpart,
@@ -219,6 +228,7 @@ hipError_t launch_deflate_apply(const float* A, int64_t D, int64_t lda, const do
 hipError_t launch_mgs_append(double* P, int64_t D, int k, const float* w, float* p_out, hipStream_t s);
 int pr_scalar_blocks(int64_t n);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, int cu_count, hipStream_t s);
 hipError_t launch_read16(const void* src, int64_t n16, uint32_t* sink, int cu_count, hipStream_t s);
 

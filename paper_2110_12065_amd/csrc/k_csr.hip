@@ -42,9 +42,9 @@ __global__ void k_csr_check(const int32_t* __restrict__ row_ptr, const int32_t* 
 }
 
 // T/Dg (MAPI) or sum/dangling-sum (RPI) of an iterate, into st->ex.
-template <int METHOD>
+template <int METHOD, typename T>
 __global__ void __launch_bounds__(256)
-k_pr_scalars(const float* __restrict__ w, int64_t n, const uint8_t* __restrict__ dangling, double c, double inv_n,
+k_pr_scalars(const T* __restrict__ w, int64_t n, const uint8_t* __restrict__ dangling, double c, double inv_n,
              SolveState* __restrict__ st, double* __restrict__ part) {
   __shared__ double sh[16];
   __shared__ int sh_flag;
@@ -80,15 +80,19 @@ k_pr_scalars(const float* __restrict__ w, int64_t n, const uint8_t* __restrict__
 // G lanes per row, each summing the row's in-links k = sub, sub + G, ... in order,
 // then a fixed butterfly; each lane group carries R consecutive rows at once, so a
 // lane keeps R independent index / value / gather chains in flight.
-template <int METHOD, int G, int R>
+// T: the iterate's type.  float: float32 terms and row sums (the clamps on v_med3_f32);
+// double: every term and sum in float64 (the FP64-iterate option).
+template <int METHOD, int G, int R, typename T>
 __global__ void __launch_bounds__(256)
 k_csr_product(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const float* __restrict__ val,
-              int64_t n, const float* __restrict__ w, float* __restrict__ y, double* __restrict__ part,
-              SolveState* __restrict__ st, float alpha, float c, double inv_n) {
+              int64_t n, const T* __restrict__ w, T* __restrict__ y, double* __restrict__ part,
+              SolveState* __restrict__ st, double alpha, double c, double inv_n) {
   __shared__ double sh[16];
   if (state_done(st)) return;
-  const double base = (METHOD == MAPI_METHOD_MAPI) ? st->ex[0] + st->ex[1]
-                                                   : ((double)alpha * inv_n) * st->ex[1] + (double)c * st->ex[0];
+  // the float32 iterate uses alpha and c rounded to float32 (as the batched kernel does)
+  const double ad = sizeof(T) == 4 ? (double)(float)alpha : alpha;
+  const double cd = sizeof(T) == 4 ? (double)(float)c : c;
+  const double base = (METHOD == MAPI_METHOD_MAPI) ? st->ex[0] + st->ex[1] : (ad * inv_n) * st->ex[1] + cd * st->ex[0];
   const int sub = threadIdx.x % G;
   const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int64_t ng = ((int64_t)gridDim.x * blockDim.x) / G;
@@ -103,12 +107,14 @@ k_csr_product(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ c
       len[r] = ok ? row_ptr[i0 + r + 1] - p0[r] : 0;
       maxlen = max(maxlen, len[r]);
     }
-    float acc[R];
+    const float af = (float)ad, cf = (float)cd;
+    T acc[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = 0.0f;
+    for (int r = 0; r < R; ++r) acc[r] = T(0);
     for (int32_t k = sub; k < maxlen; k += G) {
       int32_t cj[R];
-      float h[R], wj[R];
+      float h[R];
+      T wj[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const bool ok = k < len[r];
@@ -121,22 +127,26 @@ k_csr_product(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ c
       for (int r = 0; r < R; ++r) {
         if (k < len[r]) {
           if constexpr (METHOD == MAPI_METHOD_MAPI) {
-            const float g = fmaf(alpha, h[r], c);
-            acc[r] += __builtin_amdgcn_fmed3f(wj[r], -g, g) - __builtin_amdgcn_fmed3f(wj[r], -c, c);
+            if constexpr (sizeof(T) == 4) {
+              const float g = fmaf(af, h[r], cf);
+              acc[r] += __builtin_amdgcn_fmed3f(wj[r], -g, g) - __builtin_amdgcn_fmed3f(wj[r], -cf, cf);
+            } else {
+              const double g = ad * (double)h[r] + cd;
+              acc[r] += fmin(fmax(wj[r], -g), g) - fmin(fmax(wj[r], -cd), cd);
+            }
           } else {
-            acc[r] = fmaf(h[r], wj[r], acc[r]);
+            acc[r] = fma((T)h[r], wj[r], acc[r]);
           }
         }
       }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      float a = acc[r];
+      T a = acc[r];
 #pragma unroll
       for (int off = G / 2; off >= 1; off >>= 1) a += __shfl_xor(a, off, G);
       if (sub == 0 && i0 + r < n) {
-        const float yi = (METHOD == MAPI_METHOD_MAPI) ? (float)(base + (double)a)
-                                                      : (float)((double)alpha * (double)a + base);
+        const T yi = (METHOD == MAPI_METHOD_MAPI) ? (T)(base + (double)a) : (T)(ad * (double)a + base);
         y[i0 + r] = yi;
         nrm += fabs((double)yi);
       }
@@ -162,6 +172,15 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_csr_prep(const int32_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz, uint8_t* dangling,
                            int32_t* err, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, dangling, n, (uint8_t)1);
@@ -172,15 +191,22 @@ hipError_t launch_csr_prep(const int32_t* row_ptr, const int32_t* col, int64_t n
 
 int pr_scalar_blocks(int64_t n) { return grid_for(n, 1024, 1024); }
 
-hipError_t launch_pr_scalars(int method, const float* w, int64_t n, const uint8_t* dangling, double c, double inv_n,
+template <typename T>
+hipError_t launch_pr_scalars(int method, const T* w, int64_t n, const uint8_t* dangling, double c, double inv_n,
                              SolveState* st, double* part, hipStream_t s) {
   const int b = pr_scalar_blocks(n);
   if (method == MAPI_METHOD_MAPI)
-    hipLaunchKernelGGL(k_pr_scalars<MAPI_METHOD_MAPI>, dim3(b), dim3(256), 0, s, w, n, dangling, c, inv_n, st, part);
+    hipLaunchKernelGGL((k_pr_scalars<MAPI_METHOD_MAPI, T>), dim3(b), dim3(256), 0, s, w, n, dangling, c, inv_n, st,
+                       part);
   else
-    hipLaunchKernelGGL(k_pr_scalars<MAPI_METHOD_RPI>, dim3(b), dim3(256), 0, s, w, n, dangling, c, inv_n, st, part);
+    hipLaunchKernelGGL((k_pr_scalars<MAPI_METHOD_RPI, T>), dim3(b), dim3(256), 0, s, w, n, dangling, c, inv_n, st,
+                       part);
   return hipGetLastError();
 }
+template hipError_t launch_pr_scalars<float>(int, const float*, int64_t, const uint8_t*, double, double, SolveState*,
+                                             double*, hipStream_t);
+template hipError_t launch_pr_scalars<double>(int, const double*, int64_t, const uint8_t*, double, double,
+                                              SolveState*, double*, hipStream_t);
 
 constexpr int kCsrGroup = 8;   // lanes per row
 constexpr int kCsrRows = 1;    // rows per lane group at once (the kernel runs at full occupancy: more rows per
@@ -188,17 +214,24 @@ constexpr int kCsrRows = 1;    // rows per lane group at once (the kernel runs a
 
 int csr_part_count(int64_t n) { return grid_for(n, 256 / kCsrGroup * kCsrRows, 4096); }
 
+template <typename T>
 hipError_t launch_csr_product(int method, const int32_t* row_ptr, const int32_t* col, const float* val, int64_t n,
-                              const float* w, float* y, double* part, SolveState* st, float alpha, float c,
-                              double inv_n, hipStream_t s) {
+                              const T* w, T* y, double* part, SolveState* st, double alpha, double c, double inv_n,
+                              hipStream_t s) {
   const int b = csr_part_count(n);
   if (method == MAPI_METHOD_MAPI)
-    hipLaunchKernelGGL((k_csr_product<MAPI_METHOD_MAPI, kCsrGroup, kCsrRows>), dim3(b), dim3(256), 0, s, row_ptr, col, val, n, w,
-                       y, part, st, alpha, c, inv_n);
+    hipLaunchKernelGGL((k_csr_product<MAPI_METHOD_MAPI, kCsrGroup, kCsrRows, T>), dim3(b), dim3(256), 0, s, row_ptr,
+                       col, val, n, w, y, part, st, alpha, c, inv_n);
   else
-    hipLaunchKernelGGL((k_csr_product<MAPI_METHOD_RPI, kCsrGroup, kCsrRows>), dim3(b), dim3(256), 0, s, row_ptr, col, val, n, w,
-                       y, part, st, alpha, c, inv_n);
+    hipLaunchKernelGGL((k_csr_product<MAPI_METHOD_RPI, kCsrGroup, kCsrRows, T>), dim3(b), dim3(256), 0, s, row_ptr,
+                       col, val, n, w, y, part, st, alpha, c, inv_n);
   return hipGetLastError();
 }
+template hipError_t launch_csr_product<float>(int, const int32_t*, const int32_t*, const float*, int64_t,
+                                              const float*, float*, double*, SolveState*, double, double, double,
+                                              hipStream_t);
+template hipError_t launch_csr_product<double>(int, const int32_t*, const int32_t*, const float*, int64_t,
+                                               const double*, double*, double*, SolveState*, double, double, double,
+                                               hipStream_t);
 
 }  // namespace mapi

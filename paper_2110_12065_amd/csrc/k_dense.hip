@@ -13,9 +13,9 @@ namespace mapi {
 // Every block first sums the product kernel's per-block partials pprod[0..nprod)
 // in block order (the same float64 value in every block), so the product kernel
 // needs no grid-wide arrival; norm NORM_L2 takes the square root (RPI, eq. 1).
-template <int MODE, int BS, int PF>
+template <int MODE, int BS, int PF, typename T = float>
 __global__ void __launch_bounds__(BS)
-k_finalize(const float* __restrict__ y, const float* __restrict__ w_old, float* __restrict__ w_new, int64_t n,
+k_finalize(const T* __restrict__ y, const T* __restrict__ w_old, T* __restrict__ w_new, int64_t n,
            SolveState* __restrict__ st, const double* __restrict__ pprod, int nprod, int norm,
            double* __restrict__ part, const uint8_t* __restrict__ dangling, double c, double inv_n, int set_iter) {
   __shared__ double sh[16];
@@ -25,12 +25,12 @@ k_finalize(const float* __restrict__ y, const float* __restrict__ w_old, float* 
   // before the partials are summed, so the two memory round trips overlap.
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  float yp[PF], wp[PF];
+  T yp[PF], wp[PF];
 #pragma unroll
   for (int k = 0; k < PF; ++k) {
     const int64_t i = i0 + k * stride;
-    yp[k] = i < n ? y[i] : 0.0f;
-    wp[k] = i < n ? w_old[i] : 0.0f;
+    yp[k] = i < n ? y[i] : T(0);
+    wp[k] = i < n ? w_old[i] : T(0);
   }
   const double tot = wave_sum_parts(pprod, nprod);
   const double nu = (norm == NORM_L2) ? sqrt(tot) : tot;
@@ -45,8 +45,8 @@ k_finalize(const float* __restrict__ y, const float* __restrict__ w_old, float* 
   // w = y * (1 / nu): the same arithmetic as a product that forms w itself (FusedPrev)
   const double inv = 1.0 / nu;
   double r = 0.0, e0 = 0.0, e1 = 0.0;
-  auto element = [&](int64_t i, float yi, float wo) {
-    const float wn = (float)((double)yi * inv);
+  auto element = [&](int64_t i, T yi, T wo) {
+    const T wn = (T)((double)yi * inv);
     w_new[i] = wn;
     const double wd = (double)wn;
     r += fabs(wd - (double)wo);
@@ -116,11 +116,12 @@ __global__ void k_state_init(SolveState* st, int max_iters, double tol, int stal
 // Copy the final iterate (buffer chosen by the parity of the completed
 // iteration count) to `out`, optionally divided by its l2 norm (Algorithm 1,
 // last step).  One block; the norm is a fixed-order float64 sum.
+template <typename T>
 __global__ void __launch_bounds__(1024)
-k_finish(const float* __restrict__ w0buf, const float* __restrict__ w1buf, float* __restrict__ out, int64_t n,
+k_finish(const T* __restrict__ w0buf, const T* __restrict__ w1buf, T* __restrict__ out, int64_t n,
          SolveState* __restrict__ st, int final_l2) {
   __shared__ double sh[16];
-  const float* src = (st->iter & 1) ? w1buf : w0buf;
+  const T* src = (st->iter & 1) ? w1buf : w0buf;
   double scale = 1.0;
   if (final_l2) {
     double s = 0.0;
@@ -132,7 +133,7 @@ k_finish(const float* __restrict__ w0buf, const float* __restrict__ w1buf, float
     }
     scale = 1.0 / sqrt(s);
   }
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) out[i] = final_l2 ? (float)((double)src[i] * scale) : src[i];
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) out[i] = final_l2 ? (T)((double)src[i] * scale) : src[i];
 }
 
 // ---------------------------------------------------------------- launchers
@@ -269,7 +270,25 @@ hipError_t launch_finalize(int mode, const float* y, const float* w_old, float* 
 
 hipError_t launch_finish(const float* w0buf, const float* w1buf, float* out, int64_t n, SolveState* st, int final_l2,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, w0buf, w1buf, out, n, st, final_l2);
+  hipLaunchKernelGGL(k_finish<float>, dim3(1), dim3(1024), 0, s, w0buf, w1buf, out, n, st, final_l2);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_f64(const double* w0buf, const double* w1buf, double* out, int64_t n, SolveState* st,
+                             int final_l2, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish<double>, dim3(1), dim3(1024), 0, s, w0buf, w1buf, out, n, st, final_l2);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_f64(int mode, const double* y, const double* w_old, double* w_new, int64_t n,
+                               SolveState* st, const double* pprod, int nprod, double* part, const uint8_t* dangling,
+                               double c, double inv_n, hipStream_t s) {
+  const int blocks = finalize_blocks(n);
+  switch (mode) {
+    case 1: hipLaunchKernelGGL((k_finalize<1, 256, 4, double>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, NORM_L1, part, dangling, c, inv_n, -1); break;
+    case 2: hipLaunchKernelGGL((k_finalize<2, 256, 4, double>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, NORM_L1, part, dangling, c, inv_n, -1); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -114,3 +114,45 @@ def test_full_size_2pow22_nodes_three_iterations():
         e, _ = report(f"pagerank {method} n=2^22 T=3", wg, ref.w)
         assert e <= TOL
         report(f"pagerank {method} n=2^22 T=3 deviation from 1/n", wg - 1 / n, ref.w - 1 / n)
+
+
+@pytest.mark.parametrize("method", ["mapi", "rpi"])
+def test_float64_iterate_matches_dense_oracle_and_the_deviation(method):
+    # the FP64-iterate option: on 4096 nodes the iterate and its deviation from 1/n (the ranking
+    # signal) match the dense brute-force FP64 oracle to summation order
+    n, T = 4096, 12
+    g = synth.powerlaw_graph(n, seed=9)
+    rp, col, val = _dev(g)
+    w, info = mp.mapi_pagerank(rp, col, val, 0.85, method, max_iters=T, f64=True)
+    assert w.dtype == torch.float64 and info["iters"] == T
+    ref = oracle.pagerank(n, g["row_ptr"], g["col"], g["val"], 0.85, method, synth.uniform_start(n), T, form="dense")
+    wg = w.cpu().numpy()
+    assert rel_l1(wg, ref.w) <= 1e-12
+    assert rel_l1(wg - 1 / n, ref.w - 1 / n) <= 1e-9
+    # a float64 start vector is used as given
+    w0 = torch.from_numpy(np.full(n, 1.0 / n)).cuda()
+    w2, _ = mp.mapi_pagerank(rp, col, val, 0.85, method, w0=w0, max_iters=T, f64=True)
+    np.testing.assert_array_equal(w2.cpu().numpy(), wg)
+
+
+def test_float64_iterate_ranks_the_2pow22_graph():
+    # n = 2^22, three MAPI iterations: the float64 iterate's top 100 is the oracle's (ties in the
+    # oracle's scores at the cut would allow either order; the test checks there are none)
+    n = 1 << 22
+    print("[case] float64 pagerank generate", flush=True)
+    g = synth.powerlaw_graph(n, seed=2022)
+    rp, col, val = _dev(g)
+    w, info = mp.mapi_pagerank(rp, col, val, 0.85, "mapi", max_iters=3, f64=True)
+    ref = oracle.pagerank(n, g["row_ptr"], g["col"], g["val"], 0.85, "mapi", synth.uniform_start(n), 3)
+    wg = w.cpu().numpy()
+    assert rel_l1(wg - 1 / n, ref.w - 1 / n) <= 1e-9
+    order = np.argsort(-ref.w, kind="stable")
+    assert ref.w[order[99]] - ref.w[order[100]] > 1e-12 * ref.w[order[99]]
+    assert set(np.argsort(-wg, kind="stable")[:100].tolist()) == set(order[:100].tolist())
+
+
+def test_float64_iterate_rejects_float32_vectors():
+    g = synth.powerlaw_graph(256, seed=3)
+    rp, col, val = _dev(g)
+    with pytest.raises(ValueError):
+        mp.mapi_pagerank(rp, col, val, 0.85, "mapi", w0=torch.full((256,), 1 / 256, device="cuda"), f64=True)
