@@ -385,3 +385,31 @@ def test_degenerate_normaliser_in_the_product_is_reported():
         with pytest.raises(mp.MapiError) as ei:
             mp.mapi_solve(to_dev(np.zeros((n, n), np.float32)), to_dev(synth.start_vector(n, 1)), max_iters=5, tol=tol)
         assert ei.value.status == 4 and "after 0 iterations" in str(ei.value)
+
+
+@pytest.mark.parametrize("n", [1, 3, 17, 64])
+@pytest.mark.parametrize("T", [1, 2, 3])
+def test_normalisation_in_the_product_edge_cases(n, T):
+    # tiny sizes (one vector or only a ragged tail), one and two iterations (no product that
+    # forms the iterate, or exactly one), final l2 and an output that aliases the start vector:
+    # the fixed-iteration solve with w staged in LDS (the product forms the iterate) equals the one
+    # with w read from global memory (normalisation kernel after every product; same row sums).
+    # (A tolerance cannot force the second path here: at n = 1 the iterate is exactly +-1 after one
+    # step, so any positive tolerance stops the solve on a zero residual.)
+    print(f"[case] fused normalisation edge n={n} T={T}", flush=True)
+    rng = np.random.default_rng(n * 10 + T)
+    A = to_dev((rng.standard_normal((n, n)) + 3.0).astype(np.float32))
+    w0h = rng.uniform(0.5, 1.0, n).astype(np.float32)
+    shape = dict(rows_per_wave=1, waves=4, blocks_per_cu=1, unroll=2, nontemporal=0)
+    for final_l2 in (False, True):
+        res = []
+        for lds in (1, 0):
+            mp.mapi_tuning_set(mp.MAPI_F32, n, n, dict(shape, w_in_lds=lds))
+            res.append(mp.mapi_solve(A, to_dev(w0h), max_iters=T, final_l2=final_l2))
+        (wa, ia), (wb, ib) = res
+        np.testing.assert_array_equal(wa.cpu().numpy(), wb.cpu().numpy())
+        assert ia["iters"] == ib["iters"] == T and ia["norm"] == ib["norm"] and ia["residual"] == ib["residual"]
+        mp.mapi_tuning_set(mp.MAPI_F32, n, n, dict(shape, w_in_lds=1))
+        alias = to_dev(w0h)
+        wc, _ = mp.mapi_solve(A, alias, max_iters=T, final_l2=final_l2, w_out=alias)
+        np.testing.assert_array_equal(wc.cpu().numpy(), wa.cpu().numpy())
