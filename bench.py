@@ -528,6 +528,13 @@ def bench_pca(mp, ctx, torch, D=4096, N=65536, k=8, seed=77):
         out[f"pca_{meth}_converged"] = int(sum(i["converged"] for i in infos))
         recon = P @ (P.t() @ clean)
         out[f"pca_{meth}_reconstruction_error"] = float(torch.linalg.norm(clean - recon) / cn)
+        # where the time goes: a second run with the kernel timers (events around each launch)
+        ctx.timing(True)
+        ctx.timing_reset()
+        mp.mapi_pca_topk(X, k, W0, method=meth, max_iters=1000, tol=1e-6, check_every=8, ctx=ctx)
+        torch.cuda.synchronize()
+        out[f"pca_{meth}_kernel_ms"] = {kind: ctx.timing_get(kind)[0] for kind in ("gram", "mavp", "finalize", "deflate")}
+        ctx.timing(False)
     del X, clean
     return out
 
