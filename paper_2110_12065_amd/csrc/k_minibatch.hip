@@ -19,7 +19,8 @@ namespace mapi {
 constexpr int kMbThreads = 256;
 constexpr int kMbMaxD = 64;
 constexpr int kMbPairs = kMbMaxD * kMbMaxD / kMbThreads;   // 16
-constexpr int kMbChunk = 128;                                // samples gathered per LDS pass
+constexpr int kMbLdsFloats = 128 * kMbMaxD;                  // gathered samples' LDS buffer (32 KiB)
+constexpr int kMbMaxChunk = 1024;                            // samples per gather pass at most
 constexpr size_t kMbBufBytes = size_t(256) << 20;           // stored batch matrices per range of t
 
 // Iterate of one run between ranges of t.
@@ -42,13 +43,15 @@ __device__ __forceinline__ double mb_term(float a, float b) {
 // Batch matrices of t = t0 .. t0 + nt - 1, into Abuf[(run * nt + t - t0) * D^2 + k D + l].
 // With DD = D^2 < 256 pairs the block splits the samples into SL = 256 / DD slices:
 // thread (slice, p) sums the terms of pair p over samples slice, slice + SL, ... of
-// each gathered chunk in order, and the slice partials are added in slice order.
+// each gathered chunk (in four interleaved chains, added in a fixed order), and the
+// slice partials are added in slice order.
 // With DD >= 256 (WIDE) each thread sums up to kMbPairs pairs over all samples in order.
 template <int OP, bool WIDE>
 __global__ void __launch_bounds__(kMbThreads)
 k_mb_batches(const float* __restrict__ X, int64_t N, int D, int64_t ldx, const int32_t* __restrict__ idx, int s,
              int T, int t0, int nt, float* __restrict__ Abuf, int32_t* __restrict__ bad_index) {
-  __shared__ float xb[kMbChunk * kMbMaxD];
+  __shared__ float xb[kMbLdsFloats];
+  __shared__ int32_t jb[kMbMaxChunk];
   __shared__ double part[kMbThreads];
   const int tid = threadIdx.x;
   const int run = blockIdx.x / nt, tl = blockIdx.x - run * nt;
@@ -62,17 +65,25 @@ k_mb_batches(const float* __restrict__ X, int64_t N, int D, int64_t ldx, const i
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  for (int i0 = 0; i0 < s; i0 += kMbChunk) {
-    const int c = min(kMbChunk, s - i0);
+  // samples per gather: as many as the buffer holds (819 at D = 10), at most kMbMaxChunk
+  const int chunk = min(kMbMaxChunk, kMbLdsFloats / D);
+  for (int i0 = 0; i0 < s; i0 += chunk) {
+    const int c = min(chunk, s - i0);
     __syncthreads();   // the previous chunk's readers are done
+    // the chunk's sample indices first (one coalesced pass; an index outside [0, N) is
+    // reported after the run and never used as an address), then the rows with
+    // independent loads, several in flight per thread
+    for (int i = tid; i < c; i += kMbThreads) {
+      const int32_t j = B[i0 + i];
+      const bool ok = j >= 0 && (int64_t)j < N;
+      if (!ok) atomicOr(bad_index, 1);
+      jb[i] = ok ? j : 0;
+    }
+    __syncthreads();
+#pragma unroll 4
     for (int e = tid; e < c * D; e += kMbThreads) {
       const int i = e / D, k = e - i * D;
-      int64_t j = B[i0 + i];
-      if (j < 0 || j >= N) {   // never used as an address; reported after the run
-        atomicOr(bad_index, 1);
-        j = 0;
-      }
-      xb[i * D + k] = X[j * ldx + k];
+      xb[e] = X[(int64_t)jb[i] * ldx + k];
     }
     __syncthreads();
     if (!active) continue;
@@ -92,11 +103,20 @@ k_mb_batches(const float* __restrict__ X, int64_t N, int D, int64_t ldx, const i
         for (int q = 0; q < NQ; ++q) acc[q] += mb_term<OP>(xi[kq[q]], xi[lq[q]]);
       }
     } else {
+      // four independent float64 chains (samples slice + SL (4 m + r) into chain r), added
+      // in a fixed order: the adds do not wait on each other
       const int p = tid - slice * DD;
       const int k = p / D, l = p - k * D;
-      double a = acc[0];
-      for (int i = slice; i < c; i += SL) a += mb_term<OP>(xb[i * D + k], xb[i * D + l]);
-      acc[0] = a;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int i = slice;
+      for (; i + 3 * SL < c; i += 4 * SL) {
+        a0 += mb_term<OP>(xb[i * D + k], xb[i * D + l]);
+        a1 += mb_term<OP>(xb[(i + SL) * D + k], xb[(i + SL) * D + l]);
+        a2 += mb_term<OP>(xb[(i + 2 * SL) * D + k], xb[(i + 2 * SL) * D + l]);
+        a3 += mb_term<OP>(xb[(i + 3 * SL) * D + k], xb[(i + 3 * SL) * D + l]);
+      }
+      for (; i < c; i += SL) a0 += mb_term<OP>(xb[i * D + k], xb[i * D + l]);
+      acc[0] += (a0 + a1) + (a2 + a3);
     }
   }
   const double inv_s = 1.0 / (double)s;
