@@ -274,9 +274,10 @@ mapi_status mapi_quantize(mapi_ctx* ctx, const float* A, int64_t n_rows, int64_t
  * covariance of eq. (2), on the matrix cores.  Terms are summed in float32 within
  * runs of 256 samples and in float64 across runs; A is rounded to float32 once.
  * A_out: D x D float32, leading dimension lda; the full matrix is written.  The
- * DOT build may split the samples into up to 8 chunks (a function of D and N
- * only) whose float64 partial tiles live in context device memory: at most
- * 8 * T (T + 1) / 2 * 128 KiB, T = ceil(D / 128), kept until mapi_destroy.     */
+ * build may split the samples into up to 8 (DOT) or 16 (MIN1, MIN2) chunks (a
+ * function of D, N and op only) whose float64 partial tiles live in context
+ * device memory: at most 16 * T (T + 1) / 2 * 128 KiB, T = ceil(D / 128)
+ * (1.1 GB at D = 4096), kept until mapi_destroy.                               */
 mapi_status mapi_mingram(mapi_ctx* ctx, const float* X, int64_t D, int64_t N, int64_t ldx,
                          double scale, int32_t op, float* A_out, int64_t lda);
 

@@ -623,7 +623,7 @@ mapi_status mapi_quantize(mapi_ctx* c, const float* A, int64_t n_rows, int64_t n
   return MAPI_OK;
 }
 
-// Device memory for the Gram build's partial tiles (none for the min forms).
+// Device memory for the Gram build's float64 partial tiles (none when it runs in one chunk).
 static mapi_status gram_ws(mapi_ctx* c, int64_t D, int64_t N, int op, double** out) {
   const size_t need = gram_workspace_bytes(D, N, op);
   *out = nullptr;

@@ -1,22 +1,20 @@
 // Gram build over the rows of a data matrix X (D x N, samples as columns):
 //   A_ij = scale * sum_k op(X_ik, X_jk)
-// op min1/min2: the min-covariance of eq. (5); op dot: the covariance of eq. (2),
-// built on the matrix cores (k_gram_mfma below).
+// op min1/min2: the min-covariance of eq. (5), on the vector ALU (k_gram_min); op dot:
+// the covariance of eq. (2), on the matrix cores (k_gram_mfma).
 //
-// Min forms: upper-triangle 64 x 64 output tiles, one per block of 256 threads, each thread
-// a 4 x 4 register tile.  X is streamed through LDS in slabs of 32 samples
-// (transposed so a thread reads its 4 rows and 4 columns as two 16-byte LDS
-// reads per sample), double-buffered through registers.  Terms are accumulated
-// in float32 within a run of 256 samples and in float64 across runs.  The
-// min forms use one xor, one med3 and one add per term on the vector ALU.
+// Both builds cover the upper triangle in 128 x 128 output tiles and order their
+// blocks by sample chunk first, so that the blocks resident at one time read the
+// same chunk of X while it is held in the last-level cache.  Terms are summed in
+// float32 within runs of 256 samples and in float64 across runs.  With several
+// chunks each block writes a float64 partial tile and k_gram_reduce sums the chunks
+// in order; with one chunk the block writes its tile (and the mirror) itself.  The
+// chunk count depends only on D and N, so results do not depend on the device.
 #include "common.h"
 
 namespace mapi {
 
-constexpr int GT = 64;          // tile edge
-constexpr int GKS = 32;         // samples per LDS slab
-constexpr int GPAD = 4;         // LDS row padding (floats)
-constexpr int GFLUSH = 256;     // samples per float32 run
+constexpr int MT = 128;          // tile edge
 
 __device__ __forceinline__ void tile_coords(int b, int T, int* ti, int* tj) {
   int i = 0;
@@ -28,114 +26,130 @@ __device__ __forceinline__ void tile_coords(int b, int T, int* ti, int* tj) {
   *tj = i + b;
 }
 
-template <int OP>
-__global__ void __launch_bounds__(256)
-k_gram(const float* __restrict__ X, int D, int64_t N, int64_t ldx, double scale, float* __restrict__ A, int64_t lda) {
-  __shared__ float4 lds4[2 * 2 * GKS * (GT + GPAD) / 4];
+// ---------------------------------------------------------------- min forms on the vector ALU
+// 1024 threads, each a 4 x 4 register tile of the 128 x 128 output tile: rows 4 ty .. 4 ty + 3,
+// columns 4 tx .. 4 tx + 3 (tx = tid % 32, ty = tid / 32), so that per sample a wave reads
+// two broadcast 16-byte row operands and 512 contiguous bytes of column operands from LDS.
+// X is staged through LDS in slabs of NKS samples, transposed (sample-major: the tile's
+// 128 I rows then its 128 J rows, pitch NP floats), double-buffered through registers;
+// the next sample's operands are read before the current sample's terms.
+// min1 term: with g = |b|, med3(a, -g, g) carries min(|a|, |b|) with the sign of a, and
+// sign(b) is applied by a fused multiply-add with s = +-1 (s carries the sign bit of b):
+// the product is exact, so the term and the sum equal those of a sign-bit flip and an
+// add, in one instruction; s is formed once per column and sample.
+// min2 term: med3(a ^ signbit(b), 0, |b|) and an add, as in the product kernels.
+constexpr int NTH = 1024;                    // threads per block
+constexpr int NKS = 32;                      // samples per slab
+constexpr int NP = 2 * MT + 4;               // staged pitch (floats); 16-byte aligned
+constexpr int NRUN = 256 / NKS;              // slabs per float32 run
+constexpr int NLPR = NKS / 4;                // loader threads per staged row (one float4 each)
+constexpr int NLP = 2 * MT * NLPR / NTH;     // float4s each thread loads per slab
+
+template <int OP, bool SPLIT>
+__global__ void __launch_bounds__(NTH)
+k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t chunk, int tiles, double scale,
+           float* __restrict__ A, int64_t lda, double* __restrict__ part) {
+  __shared__ float4 lds4[2 * NKS * NP / 4];
   float* lds = reinterpret_cast<float*>(lds4);
-  const int T = (D + GT - 1) / GT;
+  const int T = (D + MT - 1) / MT;
+  const int tile = blockIdx.x % tiles;
+  const int cidx = blockIdx.x / tiles;
   int ti, tj;
-  tile_coords(blockIdx.x, T, &ti, &tj);
-  const int i0 = ti * GT, j0 = tj * GT;
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  tile_coords(tile, T, &ti, &tj);
+  const int i0 = ti * MT, j0 = tj * MT;
+  const int64_t kb = (int64_t)cidx * chunk;
+  const int64_t ke = min(N, kb + chunk);
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
 
-  // loader mapping: 8 threads per row, 4 consecutive samples each; 2 passes of 32 rows
-  const int lrow = tid >> 3, lk = (tid & 7) * 4;
-
-  auto slab = [&](int buf, int m) -> float* { return lds + (buf * 2 + m) * GKS * (GT + GPAD); };
-
-  float4 pre[2][2];   // [matrix][pass]
-  auto load_slab = [&](int64_t k0) {
+  // loader: staged row sr = lrow + (NTH / NLPR) p is row sr of the I block (sr < 128)
+  // or row sr - 128 of the J block; lk selects one of the slab's NLPR float4s
+  const int lrow = tid / NLPR, lk = (tid % NLPR) * 4;
+  float4 pre[NLP];
+  auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      const int base = m ? j0 : i0;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int r = base + lrow + 32 * h;
-        const int64_t k = k0 + lk;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (r < D) {
-          const float* src = X + (int64_t)r * ldx + k;
-          if (k + 3 < N) {
-            v = *reinterpret_cast<const float4*>(src);
-          } else {
-            if (k + 0 < N) v.x = src[0];
-            if (k + 1 < N) v.y = src[1];
-            if (k + 2 < N) v.z = src[2];
-          }
+    for (int p = 0; p < NLP; ++p) {
+      const int sr = lrow + (NTH / NLPR) * p;
+      const int row = sr < MT ? i0 + sr : j0 + sr - MT;
+      const int64_t k = k0 + lk;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (row < D) {
+        const float* src = X + (int64_t)row * ldx + k;
+        if (k + 3 < ke) {
+          v = *reinterpret_cast<const float4*>(src);
+        } else {
+          if (k + 0 < ke) v.x = src[0];
+          if (k + 1 < ke) v.y = src[1];
+          if (k + 2 < ke) v.z = src[2];
         }
-        pre[m][h] = v;
       }
+      pre[p] = v;
     }
   };
-  auto store_slab = [&](int buf) {
+  auto store = [&](int buf) {
+    float* s = lds + buf * NKS * NP;
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      float* s = slab(buf, m);
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int r = lrow + 32 * h;
-        s[(lk + 0) * (GT + GPAD) + r] = pre[m][h].x;
-        s[(lk + 1) * (GT + GPAD) + r] = pre[m][h].y;
-        s[(lk + 2) * (GT + GPAD) + r] = pre[m][h].z;
-        s[(lk + 3) * (GT + GPAD) + r] = pre[m][h].w;
-      }
+    for (int p = 0; p < NLP; ++p) {
+      const int sr = lrow + (NTH / NLPR) * p;
+      s[(lk + 0) * NP + sr] = pre[p].x;
+      s[(lk + 1) * NP + sr] = pre[p].y;
+      s[(lk + 2) * NP + sr] = pre[p].z;
+      s[(lk + 3) * NP + sr] = pre[p].w;
     }
   };
 
   float accf[4][4];
   double acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      accf[a][b] = 0.0f;
-      acc[a][b] = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      accf[p][q] = 0.0f;
+      acc[p][q] = 0.0;
     }
 
-  const int64_t nslabs = (N + GKS - 1) / GKS;
-  load_slab(0);
-  store_slab(0);
+  const int64_t nslabs = (ke - kb + NKS - 1) / NKS;
+  load(kb);
+  store(0);
   __syncthreads();
-  for (int64_t sidx = 0; sidx < nslabs; ++sidx) {
-    const int buf = (int)(sidx & 1);
-    if (sidx + 1 < nslabs) load_slab((sidx + 1) * GKS);
-    const float* si = slab(buf, 0);
-    const float* sj = slab(buf, 1);
-#pragma unroll 8
-    for (int k = 0; k < GKS; ++k) {
-      const float4 av = *reinterpret_cast<const float4*>(si + k * (GT + GPAD) + ty * 4);
-      const float4 bv = *reinterpret_cast<const float4*>(sj + k * (GT + GPAD) + tx * 4);
-      const float a[4] = {av.x, av.y, av.z, av.w};
-      const float b[4] = {bv.x, bv.y, bv.z, bv.w};
-      uint32_t sb[4];
+  for (int64_t sl = 0; sl < nslabs; ++sl) {
+    const int buf = (int)(sl & 1);
+    if (sl + 1 < nslabs) load(kb + (sl + 1) * NKS);
+    const float* s = lds + buf * NKS * NP;
+    float4 a = *reinterpret_cast<const float4*>(s + ty * 4);
+    float4 b = *reinterpret_cast<const float4*>(s + MT + tx * 4);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sb[q] = sign_bit(b[q]);
+    for (int k = 0; k < NKS; ++k) {
+      float4 an, bn;
+      if (k + 1 < NKS) {
+        an = *reinterpret_cast<const float4*>(s + (k + 1) * NP + ty * 4);
+        bn = *reinterpret_cast<const float4*>(s + (k + 1) * NP + MT + tx * 4);
+      }
+      const float av[4] = {a.x, a.y, a.z, a.w};
+      const float bv[4] = {b.x, b.y, b.z, b.w};
       if constexpr (OP == MAPI_OP_MIN1) {
-        // the op_acc<min1> arithmetic, written as three passes over the 16 terms so
-        // that the independent terms interleave instead of running through one temporary
-        float t[4][4];
+        float sg[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sg[q] = __uint_as_float(sign_bit(bv[q]) | 0x3f800000u);
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) t[p][q] = flip_sign(a[p], sb[q]);
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) t[p][q] = __builtin_amdgcn_fmed3f(t[p][q], -fabsf(b[q]), fabsf(b[q]));
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) accf[p][q] += t[p][q];
+          for (int q = 0; q < 4; ++q)
+            accf[p][q] = fmaf(__builtin_amdgcn_fmed3f(av[p], -fabsf(bv[q]), fabsf(bv[q])), sg[q], accf[p][q]);
       } else {
+        uint32_t sb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sb[q] = sign_bit(bv[q]);
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) accf[p][q] = op_acc<OP>(accf[p][q], a[p], b[q], sb[q]);
+          for (int q = 0; q < 4; ++q) accf[p][q] = op_acc<OP>(accf[p][q], av[p], bv[q], sb[q]);
+      }
+      if (k + 1 < NKS) {
+        a = an;
+        b = bn;
       }
     }
-    if (((sidx + 1) * GKS) % GFLUSH == 0 || sidx + 1 == nslabs) {
+    if ((sl + 1) % NRUN == 0 || sl + 1 == nslabs) {
 #pragma unroll
       for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -144,32 +158,39 @@ k_gram(const float* __restrict__ X, int D, int64_t N, int64_t ldx, double scale,
           accf[p][q] = 0.0f;
         }
     }
-    if (sidx + 1 < nslabs) {
-      store_slab(buf ^ 1);
+    if (sl + 1 < nslabs) {
+      store(buf ^ 1);
       __syncthreads();
     }
   }
 
-  // epilogue: tile (i, j) and, off the diagonal, its mirror (j, i)
+  if constexpr (SPLIT) {
+    double* out = part + ((int64_t)cidx * tiles + tile) * (MT * MT);
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const int i = i0 + ty * 4 + p;
-    if (i >= D) continue;
+    for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = j0 + tx * 4 + q;
-      if (j < D) A[(int64_t)i * lda + j] = (float)(scale * acc[p][q]);
+      for (int q = 0; q < 4; ++q) out[(ty * 4 + p) * MT + tx * 4 + q] = acc[p][q];
+  } else {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int i = i0 + ty * 4 + p;
+      if (i >= D) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + tx * 4 + q;
+        if (j < D) A[(int64_t)i * lda + j] = (float)(scale * acc[p][q]);
+      }
     }
-  }
-  if (ti != tj) {
+    if (ti != tj) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = j0 + tx * 4 + q;
-      if (j >= D) continue;
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + tx * 4 + q;
+        if (j >= D) continue;
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const int i = i0 + ty * 4 + p;
-        if (i < D) A[(int64_t)j * lda + i] = (float)(scale * acc[p][q]);
+        for (int p = 0; p < 4; ++p) {
+          const int i = i0 + ty * 4 + p;
+          if (i < D) A[(int64_t)j * lda + i] = (float)(scale * acc[p][q]);
+        }
       }
     }
   }
@@ -188,14 +209,10 @@ k_gram(const float* __restrict__ X, int D, int64_t N, int64_t ldx, double scale,
 // 16-byte reads of 16 consecutive rows on distinct banks), double-buffered through
 // registers.  Half h of a wave takes samples (MKS / 2) h .. (MKS / 2) (h + 1) - 1 of a
 // slab, so one 16-byte LDS read feeds four MFMA steps, and the two halves' terms in a
-// step are two samples of the same pair of rows.  Accumulation: float32 within runs of 256 samples (the matrix cores' own
-// adds), float64 across runs.  The sample axis is split into KC chunks when that
-// fills the chip better (KC depends only on D and N, so results do not depend on the
-// device): each block then writes a float64 partial tile and k_gram_reduce sums the
-// chunks in order.  With one chunk the block writes its tile (and the mirror) itself.
+// step are two samples of the same pair of rows.  The float32 runs are the matrix
+// cores' own adds.
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int MT = 128;         // tile edge
 constexpr int MKS = 64;         // samples per LDS slab
 constexpr int MROW = MKS + 4;   // staged row pitch (floats): an odd number of 16-byte units
 constexpr int MRUN = 256 / MKS; // slabs per float32 run (256 samples)
@@ -346,19 +363,21 @@ k_gram_reduce(const double* __restrict__ part, int kc, int tiles, int D, double 
   gram_write_tile(S, ti * MT, tj * MT, D, A, lda, ti != tj);
 }
 
-// Sample chunks of the covariance build: the KC in 1..8 (at most one per 256-sample
-// run) that minimises rounds of 256 resident blocks per chunk of work.
+// Sample chunks of a Gram build: the KC in 1..kc_max (at most one per 256-sample run)
+// that minimises rounds of `resident` blocks per chunk of work.  resident is the
+// block count one launch keeps on the chip (a constant per kernel, not read from the
+// device, so that the chunking and with it the result depend only on D and N).
 struct GramSplit {
   int64_t tiles, chunk;
   int kc;
 };
-static GramSplit gram_split(int64_t D, int64_t N) {
+static GramSplit gram_split(int64_t D, int64_t N, int64_t resident, int kc_max) {
   const int64_t T = (D + MT - 1) / MT, tiles = T * (T + 1) / 2;
   const int64_t runs = (N + 255) / 256;
   int best = 1;
   double best_cost = 1e300;
-  for (int kc = 1; kc <= 8 && kc <= runs; ++kc) {
-    const double cost = (double)((tiles * kc + 255) / 256) / kc;
+  for (int kc = 1; kc <= kc_max && kc <= runs; ++kc) {
+    const double cost = (double)((tiles * kc + resident - 1) / resident) / kc;
     if (cost < best_cost - 1e-12) {
       best_cost = cost;
       best = kc;
@@ -367,41 +386,47 @@ static GramSplit gram_split(int64_t D, int64_t N) {
   const int64_t chunk = (runs + best - 1) / best * 256;
   return GramSplit{tiles, chunk, (int)((N + chunk - 1) / chunk)};
 }
+// one block per CU for both builds
+static GramSplit gram_split_op(int64_t D, int64_t N, int op) {
+  return op == MAPI_OP_DOT ? gram_split(D, N, 256, 8) : gram_split(D, N, 256, 16);
+}
 
 size_t gram_workspace_bytes(int64_t D, int64_t N, int op) {
-  if (op != MAPI_OP_DOT) return 0;
-  const GramSplit g = gram_split(D, N);
+  const GramSplit g = gram_split_op(D, N, op);
   return g.kc > 1 ? (size_t)g.kc * (size_t)g.tiles * MT * MT * sizeof(double) : 0;
+}
+
+template <int OP>
+static void launch_gram_min(const GramSplit& g, const float* X, int64_t D, int64_t N, int64_t ldx, double scale,
+                            float* A, int64_t lda, double* ws, hipStream_t s) {
+  if (g.kc > 1)
+    hipLaunchKernelGGL((k_gram_min<OP, true>), dim3((unsigned)(g.tiles * g.kc)), dim3(NTH), 0, s, X, (int)D, N, ldx,
+                       g.chunk, (int)g.tiles, scale, A, lda, ws);
+  else
+    hipLaunchKernelGGL((k_gram_min<OP, false>), dim3((unsigned)g.tiles), dim3(NTH), 0, s, X, (int)D, N, ldx, g.chunk,
+                       (int)g.tiles, scale, A, lda, nullptr);
 }
 
 hipError_t launch_gram(const float* X, int64_t D, int64_t N, int64_t ldx, double scale, int op, float* A, int64_t lda,
                        double* ws, hipStream_t s) {
+  if (op != MAPI_OP_DOT && op != MAPI_OP_MIN1 && op != MAPI_OP_MIN2) return hipErrorInvalidValue;
+  const GramSplit g = gram_split_op(D, N, op);
+  if (g.kc > 1 && !ws) return hipErrorInvalidValue;
   if (op == MAPI_OP_DOT) {
-    const GramSplit g = gram_split(D, N);
-    if (g.kc > 1) {
-      if (!ws) return hipErrorInvalidValue;
+    if (g.kc > 1)
       hipLaunchKernelGGL(k_gram_mfma<true>, dim3((unsigned)(g.tiles * g.kc)), dim3(512), 0, s, X, (int)D, N, ldx,
                          g.chunk, (int)g.tiles, scale, A, lda, ws);
-      hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)g.tiles), dim3(256), 0, s, ws, g.kc, (int)g.tiles, (int)D,
-                         scale, A, lda);
-    } else {
+    else
       hipLaunchKernelGGL(k_gram_mfma<false>, dim3((unsigned)g.tiles), dim3(512), 0, s, X, (int)D, N, ldx, g.chunk,
                          (int)g.tiles, scale, A, lda, nullptr);
-    }
-    return hipGetLastError();
+  } else if (op == MAPI_OP_MIN1) {
+    launch_gram_min<MAPI_OP_MIN1>(g, X, D, N, ldx, scale, A, lda, ws, s);
+  } else {
+    launch_gram_min<MAPI_OP_MIN2>(g, X, D, N, ldx, scale, A, lda, ws, s);
   }
-  const int T = (int)((D + GT - 1) / GT);
-  const int blocks = T * (T + 1) / 2;
-  switch (op) {
-    case MAPI_OP_MIN1:
-      hipLaunchKernelGGL(k_gram<MAPI_OP_MIN1>, dim3(blocks), dim3(256), 0, s, X, (int)D, N, ldx, scale, A, lda);
-      break;
-    case MAPI_OP_MIN2:
-      hipLaunchKernelGGL(k_gram<MAPI_OP_MIN2>, dim3(blocks), dim3(256), 0, s, X, (int)D, N, ldx, scale, A, lda);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
+  if (g.kc > 1)
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)g.tiles), dim3(256), 0, s, ws, g.kc, (int)g.tiles, (int)D, scale,
+                       A, lda);
   return hipGetLastError();
 }
 

@@ -17,9 +17,9 @@ TOL = 1e-5
 @pytest.mark.parametrize("op", ["min1", "min2", "dot"])
 @pytest.mark.parametrize("shape", [(1, 1), (5, 7), (64, 300), (130, 1000), (200, 4099), (1000, 200)])
 def test_gram_dyadic_bitexact(op, shape):
-    # dot: (5, 7) and (1000, 200) take one sample chunk (36 tiles of 128 at D = 1000, each written
-    # with its mirror by the matrix-core kernel); (64, 300), (130, 1000) and (200, 4099) split the
-    # samples into 2, 4 and 6 chunks summed by the reduction kernel
+    # (5, 7) and (1000, 200) take one sample chunk (36 tiles of 128 at D = 1000, each written with
+    # its mirror by the build kernel); (64, 300), (130, 1000) and (200, 4099) split the samples into
+    # 2, 4 and 6 (dot) or 9 (min forms) chunks summed by the reduction kernel
     D, N = shape
     print(f"[case] gram dyadic {op} {shape}", flush=True)
     X = synth.dyadic_matrix(D, N, seed=D * 13 + N)
