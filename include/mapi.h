@@ -117,7 +117,7 @@ const char* mapi_version(void);
  * HIP events on the context stream; mapi_timing_get returns the summed
  * duration in milliseconds and the number of launches since the last reset.  */
 typedef enum mapi_kernel_kind {
-  MAPI_K_MAVP = 0,           /* dense product kernel (MAPI and RPI)            */
+  MAPI_K_MAVP = 0,           /* dense product kernel (MAPI and RPI); a one-block solve counts once */
   MAPI_K_FINALIZE = 1,       /* normalisation + residual kernel                */
   MAPI_K_GRAM = 2,           /* min-covariance / covariance build              */
   MAPI_K_CSR = 3,            /* PageRank product kernel                        */
@@ -164,7 +164,10 @@ typedef struct mapi_tuning {
  * best / best_ms (optional, host) receive the choice and its mean time.        */
 mapi_status mapi_autotune_dense(mapi_ctx* ctx, const mapi_dense* A, int32_t op, int32_t reps,
                                 mapi_tuning* best, double* best_ms);
-/* Read or overwrite the table entry used for a (dtype, n_rows, n_cols) bucket. */
+/* Read or overwrite the table entry used for a (dtype, n_rows, n_cols) bucket.
+ * A bucket written by mapi_tuning_set is pinned: its solves always use the
+ * per-iteration product and normalisation kernels with that shape, also where
+ * the one-block solve (mapi_solve) would apply.                                  */
 mapi_status mapi_tuning_get(mapi_ctx* ctx, int32_t dtype, int64_t n_rows, int64_t n_cols, mapi_tuning* out);
 mapi_status mapi_tuning_set(mapi_ctx* ctx, int32_t dtype, int64_t n_rows, int64_t n_cols, const mapi_tuning* t);
 /* Mean time in ms of `reps` products y = A (+) w with an explicit launch shape. */
@@ -188,7 +191,13 @@ mapi_status mapi_read_reference(mapi_ctx* ctx, const void* src, size_t bytes, in
  * used exactly as given (the product is not homogeneous in w alone).  The
  * normaliser and the residual are accumulated in float64, the iterate is
  * float32.  w_out (device float[n]) may alias w0.  MAPI_ERR_DEGENERATE if a
- * normaliser is zero or not finite; info->iters then counts completed steps.  */
+ * normaliser is zero or not finite; info->iters then counts completed steps.
+ * A float32 system with n <= 256 and op MIN1 or MIN2 (rpi_solve: any such
+ * system) is solved by one launch of one block that holds A in registers and
+ * runs every iteration, normalisation and stop test inside the kernel, unless
+ * its bucket is pinned (mapi_tuning_set); larger systems, other storage types
+ * and the diamond product launch a product and a normalisation per iteration.
+ * The two paths differ only in the order of the row and norm sums.              */
 mapi_status mapi_solve(mapi_ctx* ctx, const mapi_dense* A, const float* w0, float* w_out,
                        const mapi_opts* opts, mapi_info* info);
 

@@ -152,6 +152,23 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
   if (op < MAPI_OP_MIN1 || op > MAPI_OP_DOT || (!rpi && op == MAPI_OP_DOT))
     return fail(MAPI_ERR_ARG, "op %d is not a MAPI product", o->op);
   const int64_t n = A->n_rows;
+  const int norm = rpi ? NORM_L2 : NORM_L1;
+  if (A->dtype == MAPI_F32 && small_solve_fits(n, op) && !c->pinned.count(bucket(A->dtype, n, A->n_cols))) {
+    // the whole solve in one launch: latency, not bandwidth, bounds this size
+    if ((s = ensure(&c->ws, &c->ws_bytes, sizeof(SolveState), c)) != MAPI_OK) return s;
+    SolveState* st = static_cast<SolveState*>(c->ws);
+    HIP_TRY(launch_state_init(st, o->max_iters, o->tol, o->stall_iters, c->stream));
+    {
+      Timed tm(c, MAPI_K_MAVP);
+      HIP_TRY(launch_solve_small(op, static_cast<const float*>(A->data), A->ld, n, w0, w_out, st, norm, o->final_l2,
+                                 c->stream));
+    }
+    if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
+    fill_info(info, *c->st_host);
+    if (c->st_host->status == MAPI_ERR_DEGENERATE)
+      return fail(MAPI_ERR_DEGENERATE, "normaliser was zero or not finite after %d iterations", c->st_host->iter);
+    return MAPI_OK;
+  }
   const DenseArgs da = dense_args(A);
   const DenseTuning t = tuning_for(c, da);
   const int P = dense_part_count(da, t, c->cu_count);
@@ -179,7 +196,6 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
   HIP_TRY(hipMemcpyAsync(wb[0], w0, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(launch_state_init(st, o->max_iters, o->tol, o->stall_iters, c->stream));
   const int check = o->check_every > 0 ? o->check_every : 16;
-  const int norm = rpi ? NORM_L2 : NORM_L1;
   int launched = 0;
   for (int it = 0; it < o->max_iters; ++it) {
     const int b = fused ? (it & 1) : 0;   // y and partials alternate when a product reads the previous ones
@@ -549,6 +565,7 @@ mapi_status mapi_tuning_set(mapi_ctx* c, int32_t dtype, int64_t n_rows, int64_t 
   if ((s = to_dense_tuning(tu, &t)) != MAPI_OK) return s;
   if (!lds_mode_ok(dtype, t.w_in_lds)) return fail(MAPI_ERR_ARG, "w_in_lds 2 needs FP8 storage");
   c->tuned[bucket(dtype, n_rows, n_cols)] = t;
+  c->pinned.insert(bucket(dtype, n_rows, n_cols));
   return MAPI_OK;
 }
 

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <map>
+#include <set>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -71,6 +72,9 @@ struct mapi_ctx {
   int64_t t_n[MAPI_K_KINDS] = {};
   // autotuned launch shapes of the dense product per (dtype, log2 rows, log2 cols)
   std::map<std::tuple<int, int, int>, mapi::DenseTuning> tuned;
+  // buckets whose shape the caller set (mapi_tuning_set): their solves always take the
+  // multi-kernel path, also where the one-block solve would apply
+  std::set<std::tuple<int, int, int>> pinned;
   // persistent batched solver: arena and launch settings
   mapi::BatchState* batch = nullptr;
   hipStream_t side = nullptr;        // stream the batched graph is captured on

@@ -1,0 +1,192 @@
+// Whole power iteration of a small dense float32 system in one block (Algorithm 1
+// for MAPI, eq. 1 for RPI, n <= 256).  At this size a solve is bound by launch and
+// synchronisation latency, not by memory: one launch per iteration pair costs more
+// than the iteration's arithmetic.  Here the matrix is read once into registers and
+// every iteration runs inside the kernel: the product, the float64 normaliser, the
+// residual ||w_t - w_{t-1}||_1 and the stop rule, with the same arithmetic per
+// element as the multi-kernel path (w = fl32(y * (1 / nu)), float64 sums of |y| or
+// y^2 and of the residual); only the order of the float32 row sums and the float64
+// sums differs.
+#include "common.h"
+
+namespace mapi {
+
+constexpr int kSmallN = 256;                    // largest n
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallRows = kSmallN / (kSmallThreads / kWave);   // rows per wave (16)
+
+// Reduce-scatter of 16 row partials over the wave.  The partials of rows j and j + 8 are
+// formed together and halved at once (lane offset 32: each lane keeps the row its bit 5
+// selects and adds the partner's partial of that row), so no more than a pair is live;
+// offsets 16, 8 and 4 halve the rest in the same way, and offsets 2 and 1 complete the
+// sums.  Lane l ends with the full sum of row l >> 2.  Fixed order.
+template <typename RowPartial>
+__device__ __forceinline__ float wave_rows16(RowPartial part, int lane) {
+  float v[8];
+  const bool hi5 = (lane & 32) != 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float lo = part(j), hi = part(j + 8);
+    v[j] = (hi5 ? hi : lo) + __shfl_xor(hi5 ? lo : hi, 32, kWave);
+  }
+#pragma unroll
+  for (int half = 4, off = 16; half >= 1; half >>= 1, off >>= 1) {
+    const bool h = (lane & off) != 0;
+#pragma unroll
+    for (int j = 0; j < half; ++j) {
+      const float keep = h ? v[j + half] : v[j];
+      const float send = h ? v[j] : v[j + half];
+      v[j] = keep + __shfl_xor(send, off, kWave);
+    }
+  }
+  float s = v[0];
+  s += __shfl_xor(s, 2, kWave);
+  s += __shfl_xor(s, 1, kWave);
+  return s;
+}
+
+template <int OP>
+__global__ void __launch_bounds__(kSmallThreads)
+k_solve_small(const float* __restrict__ A, int64_t ld, int n, const float* __restrict__ w0, float* __restrict__ out,
+              SolveState* __restrict__ st, int norm, int final_l2) {
+  __shared__ __align__(16) float wl[2][kSmallN];
+  __shared__ float yl[kSmallN];
+  __shared__ int sh_done, sh_iter;
+  __shared__ SolveState ss;   // the stop rule's state, advanced by thread 0
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+
+  // rows kSmallRows * wave + r and columns 4 lane + e of A, zero outside n x n
+  float a[kSmallRows][4];
+#pragma unroll
+  for (int r = 0; r < kSmallRows; ++r) {
+    const int row = kSmallRows * wave + r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int col = 4 * lane + e;
+      a[r][e] = (row < n && col < n) ? A[(int64_t)row * ld + col] : 0.0f;
+    }
+  }
+  for (int i = tid; i < kSmallN; i += kSmallThreads) {
+    wl[0][i] = i < n ? w0[i] : 0.0f;
+    wl[1][i] = 0.0f;
+  }
+  if (tid == 0) {
+    ss = *st;
+    sh_done = ss.done;
+    sh_iter = ss.iter;
+  }
+  __syncthreads();
+
+  while (!sh_done) {
+    const int it = sh_iter;
+    const float* w = wl[it & 1];
+    const float4 wv4 = *reinterpret_cast<const float4*>(w + 4 * lane);
+    const float wv[4] = {wv4.x, wv4.y, wv4.z, wv4.w};
+    uint32_t ws[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ws[e] = sign_bit(wv[e]);
+    const float yrow = wave_rows16(
+        [&](int r) {
+          float t = 0.0f;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) t = op_acc<OP>(t, a[r][e], wv[e], ws[e]);
+          return t;
+        },
+        lane);
+    const int row = kSmallRows * wave + (lane >> 2);
+    if ((lane & 3) == 0 && row < n) yl[row] = yrow;
+    __syncthreads();
+    if (wave == 0) {
+      // element i = lane + 64 q of y, w_{t-1} and the new iterate
+      float yv[4], wo[4];
+      double sq = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = lane + kWave * q;
+        yv[q] = i < n ? yl[i] : 0.0f;
+        wo[q] = w[i];
+        sq += (norm == NORM_L2) ? (double)yv[q] * (double)yv[q] : fabs((double)yv[q]);
+      }
+      const double tot = wave_sum_f64(sq);
+      const double nu = (norm == NORM_L2) ? sqrt(tot) : tot;
+      if (!(nu > 0.0) || !(nu < INFINITY)) {
+        if (lane == 0) {
+          ss.nu = nu;
+          ss.status = MAPI_ERR_DEGENERATE;
+          ss.done = 1;
+          sh_done = 1;
+        }
+      } else {
+        const double inv = 1.0 / nu;
+        double r = 0.0;
+        float* wn = wl[(it & 1) ^ 1];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = lane + kWave * q;
+          const float v = (float)((double)yv[q] * inv);
+          if (i < n) {
+            wn[i] = v;
+            r += fabs((double)v - (double)wo[q]);
+          }
+        }
+        r = wave_sum_f64(r);
+        if (lane == 0) {
+          ss.nu = nu;
+          state_advance(&ss, r);
+          sh_done = ss.done;
+          sh_iter = ss.iter;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // the final iterate, optionally divided by its l2 norm (Algorithm 1, last step)
+  const float* wf = wl[sh_iter & 1];
+  __shared__ double sh[kSmallThreads / kWave];
+  double scale = 1.0;
+  bool write = true;
+  if (final_l2) {
+    const double v = tid < n ? (double)wf[tid] : 0.0;
+    const double l2 = block_sum_f64(v * v, sh);
+    if (!(l2 > 0.0) || !(l2 < INFINITY)) {
+      write = false;
+      if (tid == 0) ss.status = MAPI_ERR_DEGENERATE;
+    } else {
+      scale = 1.0 / sqrt(l2);
+    }
+  }
+  if (write && tid < n) out[tid] = final_l2 ? (float)((double)wf[tid] * scale) : wf[tid];
+  __syncthreads();
+  if (tid == 0) *st = ss;
+}
+
+// the min forms and the ordinary product (the diamond form of eq. 7 keeps the multi-kernel path)
+bool small_solve_fits(int64_t n, int op) {
+  return n >= 1 && n <= kSmallN && (op == MAPI_OP_MIN1 || op == MAPI_OP_MIN2 || op == MAPI_OP_DOT);
+}
+
+hipError_t launch_solve_small(int op, const float* A, int64_t ld, int64_t n, const float* w0, float* out,
+                              SolveState* st, int norm, int final_l2, hipStream_t s) {
+  if (!small_solve_fits(n, op)) return hipErrorInvalidValue;
+  const int ni = (int)n;
+  switch (op) {
+    case MAPI_OP_MIN1:
+      hipLaunchKernelGGL(k_solve_small<MAPI_OP_MIN1>, dim3(1), dim3(kSmallThreads), 0, s, A, ld, ni, w0, out, st, norm,
+                         final_l2);
+      break;
+    case MAPI_OP_MIN2:
+      hipLaunchKernelGGL(k_solve_small<MAPI_OP_MIN2>, dim3(1), dim3(kSmallThreads), 0, s, A, ld, ni, w0, out, st, norm,
+                         final_l2);
+      break;
+    case MAPI_OP_DOT:
+      hipLaunchKernelGGL(k_solve_small<MAPI_OP_DOT>, dim3(1), dim3(kSmallThreads), 0, s, A, ld, ni, w0, out, st, norm,
+                         final_l2);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mapi

@@ -187,14 +187,16 @@ def test_reduced_storage_solve_matches_oracle_on_stored_matrix(dtype):
 
 
 def test_timing_counts_product_launches():
-    C = synth.dense_cov(256, 512, seed=5)
-    ctx = mp.default_context()
-    ctx.timing(True)
-    ctx.timing_reset()
-    mp.mapi_solve(to_dev(C), to_dev(synth.start_vector(256, 6)), max_iters=9)
-    ms, n = ctx.timing_get("mavp")
-    ctx.timing(False)
-    assert n == 9 and ms > 0
+    # n = 300: one product launch per iteration; n = 256 (float32): the whole solve is one launch
+    ctx = mp.Context()
+    for n, launches in ((300, 9), (256, 1)):
+        C = synth.dense_cov(n, 512, seed=5)
+        ctx.timing(True)
+        ctx.timing_reset()
+        mp.mapi_solve(to_dev(C), to_dev(synth.start_vector(n, 6)), max_iters=9, ctx=ctx)
+        ms, count = ctx.timing_get("mavp")
+        ctx.timing(False)
+        assert count == launches and ms > 0, n
 
 
 def test_full_size_n16384_sampled_rows_and_iterates():
