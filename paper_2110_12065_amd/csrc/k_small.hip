@@ -15,11 +15,41 @@ constexpr int kSmallN = 256;                    // largest n
 constexpr int kSmallThreads = 1024;
 constexpr int kSmallRows = kSmallN / (kSmallThreads / kWave);   // rows per wave (16)
 
-// Reduce-scatter of 16 row partials over the wave.  The partials of rows j and j + 8 are
-// formed together and halved at once (lane offset 32: each lane keeps the row its bit 5
-// selects and adds the partner's partial of that row), so no more than a pair is live;
-// offsets 16, 8 and 4 halve the rest in the same way, and offsets 2 and 1 complete the
-// sums.  Lane l ends with the full sum of row l >> 2.  Fixed order.
+// Cross-lane moves within rows of 16 lanes (DPP, no LDS round trip): quad_perm xor 1
+// and xor 2, row_half_mirror (lane i of each 8 from lane 7 - i) and row_mirror (lane i
+// of each 16 from lane 15 - i).
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the wave, the same bits in every lane (each step adds the same two values on
+// both sides of a pair): quads, 8s and 16s by DPP, then lane offsets 16 and 32.
+__device__ __forceinline__ double wave_total_f64(double v) {
+  v += dpp_f64<kDppXor1>(v);
+  v += dpp_f64<kDppXor2>(v);
+  v += dpp_f64<kDppHalfMirror>(v);
+  v += dpp_f64<kDppMirror>(v);
+  v += __shfl_xor(v, 16, kWave);
+  v += __shfl_xor(v, 32, kWave);
+  return v;
+}
+
+// Reduce-scatter of 16 row partials over the wave.  Each halving step pairs every lane
+// with a partner that differs in the step's lane bit and agrees in the bits halved
+// before: bit 5 (lane offset 32) and bit 4 (offset 16) by lane shuffles, bit 3 by
+// row_mirror, bit 2 by row_half_mirror.  A lane keeps the half of its partials that
+// its bit selects and adds the partner's partials of that half.  The partials of rows
+// j and j + 8 are formed together and halved at once, so no more than a pair is live.
+// After the halvings the quad's four lanes are summed (xor 1, xor 2): lane l ends with
+// the full sum of row l >> 2.  Fixed order.
 template <typename RowPartial>
 __device__ __forceinline__ float wave_rows16(RowPartial part, int lane) {
   float v[8];
@@ -29,19 +59,16 @@ __device__ __forceinline__ float wave_rows16(RowPartial part, int lane) {
     const float lo = part(j), hi = part(j + 8);
     v[j] = (hi5 ? hi : lo) + __shfl_xor(hi5 ? lo : hi, 32, kWave);
   }
+  const bool h4 = (lane & 16) != 0;
 #pragma unroll
-  for (int half = 4, off = 16; half >= 1; half >>= 1, off >>= 1) {
-    const bool h = (lane & off) != 0;
+  for (int j = 0; j < 4; ++j) v[j] = (h4 ? v[j + 4] : v[j]) + __shfl_xor(h4 ? v[j] : v[j + 4], 16, kWave);
+  const bool h3 = (lane & 8) != 0;
 #pragma unroll
-    for (int j = 0; j < half; ++j) {
-      const float keep = h ? v[j + half] : v[j];
-      const float send = h ? v[j] : v[j + half];
-      v[j] = keep + __shfl_xor(send, off, kWave);
-    }
-  }
-  float s = v[0];
-  s += __shfl_xor(s, 2, kWave);
-  s += __shfl_xor(s, 1, kWave);
+  for (int j = 0; j < 2; ++j) v[j] = (h3 ? v[j + 2] : v[j]) + dpp_f32<kDppMirror>(h3 ? v[j] : v[j + 2]);
+  const bool h2 = (lane & 4) != 0;
+  float s = (h2 ? v[1] : v[0]) + dpp_f32<kDppHalfMirror>(h2 ? v[0] : v[1]);
+  s += dpp_f32<kDppXor1>(s);
+  s += dpp_f32<kDppXor2>(s);
   return s;
 }
 
@@ -107,7 +134,7 @@ k_solve_small(const float* __restrict__ A, int64_t ld, int n, const float* __res
         wo[q] = w[i];
         sq += (norm == NORM_L2) ? (double)yv[q] * (double)yv[q] : fabs((double)yv[q]);
       }
-      const double tot = wave_sum_f64(sq);
+      const double tot = wave_total_f64(sq);
       const double nu = (norm == NORM_L2) ? sqrt(tot) : tot;
       if (!(nu > 0.0) || !(nu < INFINITY)) {
         if (lane == 0) {
@@ -129,7 +156,7 @@ k_solve_small(const float* __restrict__ A, int64_t ld, int n, const float* __res
             r += fabs((double)v - (double)wo[q]);
           }
         }
-        r = wave_sum_f64(r);
+        r = wave_total_f64(r);
         if (lane == 0) {
           ss.nu = nu;
           state_advance(&ss, r);
