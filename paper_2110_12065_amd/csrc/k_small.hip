@@ -30,22 +30,44 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// v(lane) + v(lane ^ B) for B = 16 or 32 by a lane swap of v with itself (both words).
+template <int B>
+__device__ __forceinline__ double swap_pair_sum(double v) {
+  const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+  const auto a = B == 32 ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                         : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = B == 32 ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                         : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+
 // Sum over the wave, the same bits in every lane (each step adds the same two values on
-// both sides of a pair): quads, 8s and 16s by DPP, then lane offsets 16 and 32.
+// both sides of a pair): quads, 8s and 16s by DPP, then lane bits 4 and 5 by lane swaps.
 __device__ __forceinline__ double wave_total_f64(double v) {
   v += dpp_f64<kDppXor1>(v);
   v += dpp_f64<kDppXor2>(v);
   v += dpp_f64<kDppHalfMirror>(v);
   v += dpp_f64<kDppMirror>(v);
-  v += __shfl_xor(v, 16, kWave);
-  v += __shfl_xor(v, 32, kWave);
+  v = swap_pair_sum<16>(v);
+  v = swap_pair_sum<32>(v);
   return v;
+}
+
+// One halving step at lane bit 5 (B = 32) or 4 (B = 16) by a lane swap between two
+// registers: v_permlane32_swap exchanges lanes 32..63 of `lo` with lanes 0..31 of `hi`,
+// v_permlane16_swap the odd 16-lane rows of `lo` with the even rows of `hi`.  Afterwards
+// a lane whose bit B is clear holds its own `lo` and its partner's `lo`, a lane whose bit
+// is set its partner's `hi` and its own `hi`: the sum is the halved partial.
+template <int B>
+__device__ __forceinline__ float swap_halve(float lo, float hi) {
+  const auto r = B == 32 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false)
+                         : __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
 // Reduce-scatter of 16 row partials over the wave.  Each halving step pairs every lane
 // with a partner that differs in the step's lane bit and agrees in the bits halved
-// before: bit 5 (lane offset 32) and bit 4 (offset 16) by lane shuffles, bit 3 by
-// row_mirror, bit 2 by row_half_mirror.  A lane keeps the half of its partials that
+// before: bits 5 and 4 by lane swaps, bit 3 by row_mirror, bit 2 by row_half_mirror.  A lane keeps the half of its partials that
 // its bit selects and adds the partner's partials of that half.  The partials of rows
 // j and j + 8 are formed together and halved at once, so no more than a pair is live.
 // After the halvings the quad's four lanes are summed (xor 1, xor 2): lane l ends with
@@ -53,15 +75,10 @@ __device__ __forceinline__ double wave_total_f64(double v) {
 template <typename RowPartial>
 __device__ __forceinline__ float wave_rows16(RowPartial part, int lane) {
   float v[8];
-  const bool hi5 = (lane & 32) != 0;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const float lo = part(j), hi = part(j + 8);
-    v[j] = (hi5 ? hi : lo) + __shfl_xor(hi5 ? lo : hi, 32, kWave);
-  }
-  const bool h4 = (lane & 16) != 0;
+  for (int j = 0; j < 8; ++j) v[j] = swap_halve<32>(part(j), part(j + 8));
 #pragma unroll
-  for (int j = 0; j < 4; ++j) v[j] = (h4 ? v[j + 4] : v[j]) + __shfl_xor(h4 ? v[j] : v[j + 4], 16, kWave);
+  for (int j = 0; j < 4; ++j) v[j] = swap_halve<16>(v[j], v[j + 4]);
   const bool h3 = (lane & 8) != 0;
 #pragma unroll
   for (int j = 0; j < 2; ++j) v[j] = (h3 ? v[j + 2] : v[j]) + dpp_f32<kDppMirror>(h3 ? v[j] : v[j + 2]);
