@@ -173,6 +173,71 @@ def _kernel_dtype(name):
     return {"0": "f32", "1": "bf16", "2": "fp8"}.get(first)
 
 
+SECTION_KERNELS = ("k_gram_min", "k_gram_reduce", "k_gram_mfma", "k_solve_small", "k_mb_batches", "k_mb_iterate",
+                   "k_deflate", "k_mgs_append", "k_mavp_dense", "k_finalize")
+SECTIONS_PROFILE = "pca4096x65536_n256_minibatch_kernel_stats.md"
+
+
+def summarize_sections(stats_dir, cmd, bench_json=None):
+    """profiles/ summary of the kernels of the PCA (4096 x 65536), n = 256 and mini-batch sections
+    from a rocprofv3 --kernel-trace --stats run, beside the benchmark's own host timings."""
+    stats = _read_csvs(stats_dir, "*kernel_stats.csv")
+    det = {}
+    if bench_json and os.path.exists(bench_json):
+        with open(bench_json) as f:
+            det = json.loads(f.read().strip().splitlines()[-1]).get("detail", {})
+    lines = ["# Kernel time summary: PCA 4096 x 65536 (min-covariance and covariance builds, top-8 "
+             "solves), the n = 256 solve, mini-batch MAPI (Alg. 3)", "", f"Command: `{cmd}`", "",
+             "Kernels of these sections by total time (the product and normalisation rows include the "
+             "headline benchmark's launches, which every run makes first):", "",
+             "| kernel | calls | average (us) | min (us) | max (us) |", "|---|---|---|---|---|"]
+    keep = [r for r in stats if any(k in r.get("Name", r.get("KernelName", "")) for k in SECTION_KERNELS)]
+    by = {}
+    for r in sorted(keep, key=lambda r: -float(r.get("TotalDurationNs", 0) or 0))[:24]:
+        nm = r.get("Name", r.get("KernelName", "?"))
+        lines.append(f"| `{nm[:110]}` | {r.get('Calls')} | {float(r.get('AverageNs', 0)) / 1e3:.1f} | "
+                     f"{float(r.get('MinNs', 0)) / 1e3:.1f} | {float(r.get('MaxNs', 0)) / 1e3:.1f} |")
+    for r in keep:
+        nm = r.get("Name", r.get("KernelName", ""))
+        for k in SECTION_KERNELS:
+            if k in nm:
+                tot, calls = by.get(k, (0.0, 0))
+                by[k] = (tot + float(r.get("TotalDurationNs", 0) or 0), calls + int(r.get("Calls", 0) or 0))
+    pca, small = det.get("pca", {}), det.get("small", {})
+    lines += ["", "Against the benchmark's host timings (same run):", "",
+              "| quantity | rocprofv3 | benchmark |", "|---|---|---|"]
+    if "k_gram_min" in by:
+        t, c = by["k_gram_min"]
+        tr, cr = by.get("k_gram_reduce", (0.0, 0))
+        lines.append(f"| min1 build at 4096 x 65536: `k_gram_min` (+ `k_gram_reduce`) per build | "
+                     f"{t / max(c, 1) / 1e6:.2f} ms (+ {tr / max(cr, 1) / 1e6:.2f} ms, shared with the other builds) | "
+                     f"{pca.get('gram_min1_ms', float('nan')):.2f} ms per `mapi_mingram` call |")
+    if "k_gram_mfma" in by:
+        t, c = by["k_gram_mfma"]
+        lines.append(f"| covariance build on the matrix cores, per launch | {t / max(c, 1) / 1e6:.2f} ms | "
+                     f"{pca.get('gram_dot_ms', float('nan')):.2f} ms per call |")
+    # the one-block solve per product: template argument 0 = min1 (MAPI), 3 = ordinary product (RPI)
+    for meth, tag in (("mapi", "k_solve_small<0>"), ("rpi", "k_solve_small<3>")):
+        rows = [r for r in keep if tag in r.get("Name", r.get("KernelName", ""))]
+        if not rows:
+            continue
+        t = sum(float(r.get("TotalDurationNs", 0) or 0) for r in rows)
+        c = sum(int(r.get("Calls", 0) or 0) for r in rows)
+        it = small.get(f"{meth}_iters") or 200
+        lines.append(f"| n = 256 one-block solve ({meth.upper()}, {it} iterations), per launch | "
+                     f"{t / max(c, 1) / 1e3:.1f} us ({t / max(c, 1) / 1e3 / it:.2f} us per iteration) | "
+                     f"{small.get(f'{meth}_plain_us_per_iter', float('nan')):.2f} us per iteration (host clock, "
+                     f"launch and state read-back included) |")
+    for k in ("k_mb_batches", "k_mb_iterate"):
+        if k in by:
+            t, c = by[k]
+            lines.append(f"| `{k}` per launch | {t / max(c, 1) / 1e3:.1f} us | |")
+    out = os.path.join(ROOT, "profiles", SECTIONS_PROFILE)
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    log(f"wrote {out}")
+
+
 def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write, bench_json=None):
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     stats = _read_csvs(stats_dir, "*kernel_stats.csv")
@@ -860,9 +925,14 @@ def main():
     ap.add_argument("--sections", default="small,hybrid,minibatch,image,batched,pca,pagerank,serving,oracle",
                     help="other workloads reported under detail (comma list; empty for none)")
     ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-sections", metavar="STATS_DIR",
+                    help="write the kernel summary of the pca, small and minibatch sections (first --commands entry)")
     ap.add_argument("--commands", nargs=3, default=["", "", ""], help="commands that produced the three dirs")
     ap.add_argument("--bench-json", default=None, help="JSON line printed by the profiled benchmark command")
     args = ap.parse_args()
+    if args.summarize_sections:
+        summarize_sections(args.summarize_sections, args.commands[0], bench_json=args.bench_json)
+        return
     if args.summarize:
         summarize(*args.summarize, *args.commands, bench_json=args.bench_json)
         return
