@@ -21,6 +21,8 @@ constexpr int kMbMaxD = 64;
 constexpr int kMbPairs = kMbMaxD * kMbMaxD / kMbThreads;   // 16
 constexpr int kMbLdsFloats = 128 * kMbMaxD;                  // gathered samples' LDS buffer (32 KiB)
 constexpr int kMbMaxChunk = 1024;                            // samples per gather pass at most
+constexpr int kMbIdx = kMbMaxChunk / kMbThreads;             // sample indices per thread and pass
+constexpr int kMbGather = kMbLdsFloats / kMbThreads;         // gathered floats per thread and pass
 constexpr size_t kMbBufBytes = size_t(256) << 20;           // stored batch matrices per range of t
 
 // Iterate of one run between ranges of t.
@@ -57,6 +59,7 @@ k_mb_batches(const float* __restrict__ X, int64_t N, int D, int64_t ldx, const i
   const int run = blockIdx.x / nt, tl = blockIdx.x - run * nt;
   const int DD = D * D;
   constexpr bool wide = WIDE;
+  constexpr int GB = WIDE ? 8 : 16;   // gather loads in flight per thread (keeps the occupancy of the sums)
   constexpr int NQ = WIDE ? kMbPairs : 1;
   const int SL = wide ? 1 : kMbThreads / DD;
   const int slice = wide ? 0 : tid / DD;
@@ -70,20 +73,54 @@ k_mb_batches(const float* __restrict__ X, int64_t N, int D, int64_t ldx, const i
   for (int i0 = 0; i0 < s; i0 += chunk) {
     const int c = min(chunk, s - i0);
     __syncthreads();   // the previous chunk's readers are done
-    // the chunk's sample indices first (one coalesced pass; an index outside [0, N) is
-    // reported after the run and never used as an address), then the rows with
-    // independent loads, several in flight per thread
-    for (int i = tid; i < c; i += kMbThreads) {
-      const int32_t j = B[i0 + i];
-      const bool ok = j >= 0 && (int64_t)j < N;
-      if (!ok) atomicOr(bad_index, 1);
-      jb[i] = ok ? j : 0;
+    // the chunk's sample indices first (an index outside [0, N) is reported after the
+    // run and never used as an address), then the rows: each thread issues all of its
+    // index loads (at most kMbIdx) before it checks the first, and its row loads in
+    // passes of GB before it stores the first (at most kMbGather floats per chunk), so a
+    // chunk costs one memory round trip for the indices and one or two for the rows
+    int32_t jv[kMbIdx];
+#pragma unroll
+    for (int q = 0; q < kMbIdx; ++q) {
+      const int i = tid + q * kMbThreads;
+      jv[q] = i < c ? B[i0 + i] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kMbIdx; ++q) {
+      const int i = tid + q * kMbThreads;
+      if (i < c) {
+        const int32_t j = jv[q];
+        const bool ok = j >= 0 && (int64_t)j < N;
+        if (!ok) atomicOr(bad_index, 1);
+        jb[i] = ok ? j : 0;
+      }
     }
     __syncthreads();
-#pragma unroll 4
-    for (int e = tid; e < c * D; e += kMbThreads) {
-      const int i = e / D, k = e - i * D;
-      xb[e] = X[(int64_t)jb[i] * ldx + k];
+    // element e = tid + kMbThreads q of the chunk is coordinate k of sample i (e = i D + k),
+    // advanced by kMbThreads = qd D + rd per step; i is clamped to the chunk, so every
+    // address is that of a checked sample row
+    {
+      const int n_e = c * D, qd = kMbThreads / D, rd = kMbThreads - qd * D;
+      int i = tid / D, k = tid - (tid / D) * D;
+#pragma unroll 1
+      for (int q0 = 0; q0 < kMbGather && tid + q0 * kMbThreads < n_e; q0 += GB) {
+        float gv[GB];
+#pragma unroll
+        for (int q = 0; q < GB; ++q) {
+          const int e = tid + (q0 + q) * kMbThreads;
+          gv[q] = e < n_e ? X[(int64_t)jb[min(i, c - 1)] * ldx + k] : 0.0f;
+          i += qd;
+          k += rd;
+          if (k >= D) {
+            k -= D;
+            ++i;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < GB; ++q) {
+          const int e = tid + (q0 + q) * kMbThreads;
+          if (e < n_e) xb[e] = gv[q];
+        }
+      }
     }
     __syncthreads();
     if (!active) continue;
