@@ -126,14 +126,25 @@ k_solve_small(const float* __restrict__ A, int64_t ld, int n, const float* __res
     const float* w = wl[it & 1];
     const float4 wv4 = *reinterpret_cast<const float4*>(w + 4 * lane);
     const float wv[4] = {wv4.x, wv4.y, wv4.z, wv4.w};
+    // min1 term as med3(a, -|w|, |w|) times s = +-1 (the sign bit of w) in one FMA: the
+    // product is exact, so the term and the sum equal those of a sign flip and an add
     uint32_t ws[4];
+    float sg[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) ws[e] = sign_bit(wv[e]);
+    for (int e = 0; e < 4; ++e) {
+      ws[e] = sign_bit(wv[e]);
+      sg[e] = __uint_as_float(ws[e] | 0x3f800000u);
+    }
     const float yrow = wave_rows16(
         [&](int r) {
           float t = 0.0f;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) t = op_acc<OP>(t, a[r][e], wv[e], ws[e]);
+          for (int e = 0; e < 4; ++e) {
+            if constexpr (OP == MAPI_OP_MIN1)
+              t = fmaf(__builtin_amdgcn_fmed3f(a[r][e], -fabsf(wv[e]), fabsf(wv[e])), sg[e], t);
+            else
+              t = op_acc<OP>(t, a[r][e], wv[e], ws[e]);
+          }
           return t;
         },
         lane);
