@@ -28,6 +28,22 @@ def test_gram_dyadic_bitexact(op, shape):
     np.testing.assert_array_equal(A, ref)
 
 
+@pytest.mark.parametrize("op", ["min1", "min2", "dot"])
+def test_gram_padded_rows_match_contiguous(op):
+    # X as a view of a buffer with row pitch 1008 > N = 1001 whose padding holds NaN: a read
+    # past sample N would poison the result; the sums must equal the contiguous build's bits
+    D, N, ld = 200, 1001, 1008
+    X = synth.pca_data(D, N, seed=9)
+    buf = torch.full((D, ld), float("nan"), dtype=torch.float32, device="cuda")
+    buf[:, :N] = to_dev(X)
+    Xp = buf[:, :N]
+    assert Xp.stride(0) == ld and not Xp.is_contiguous()
+    A = mp.mapi_mingram(Xp, 1.0 / N, op).cpu().numpy()
+    B = mp.mapi_mingram(to_dev(X), 1.0 / N, op).cpu().numpy()
+    assert np.isfinite(A).all()
+    np.testing.assert_array_equal(A, B)
+
+
 @pytest.mark.parametrize("op", ["min1", "dot"])
 def test_gram_random_within_bound(op):
     D, N = 256, 4096
