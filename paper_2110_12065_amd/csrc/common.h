@@ -46,6 +46,44 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   return v;
 }
 
+// Cross-lane moves within rows of 16 lanes (DPP, no LDS round trip): quad_perm xor 1
+// and xor 2, row_half_mirror (lane i of each 8 from lane 7 - i) and row_mirror (lane i
+// of each 16 from lane 15 - i).
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// v(lane) + v(lane ^ B) for B = 16 or 32 by a lane swap of v with itself (both words).
+template <int B>
+__device__ __forceinline__ double swap_pair_sum(double v) {
+  const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+  const auto a = B == 32 ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                         : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = B == 32 ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                         : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+
+// Sum over the wave, the same bits in every lane (each step adds the same two values on
+// both sides of a pair): quads, 8s and 16s by DPP, then lane bits 4 and 5 by lane swaps.
+__device__ __forceinline__ double wave_total_f64(double v) {
+  v += dpp_f64<kDppXor1>(v);
+  v += dpp_f64<kDppXor2>(v);
+  v += dpp_f64<kDppHalfMirror>(v);
+  v += dpp_f64<kDppMirror>(v);
+  v = swap_pair_sum<16>(v);
+  v = swap_pair_sum<32>(v);
+  return v;
+}
+
 // Fixed-order block sum of one double per thread (blockDim.x <= 1024).  Result
 // valid in every thread.  `sh` holds at least blockDim.x / 64 doubles.
 __device__ __forceinline__ double block_sum_f64(double v, double* sh) {

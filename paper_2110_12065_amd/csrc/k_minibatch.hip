@@ -174,12 +174,6 @@ k_mb_batches(const float* __restrict__ X, int64_t N, int D, int64_t ldx, const i
   }
 }
 
-// Fixed-order butterfly sum over the wave.
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
 
 // The recurrence over the stored batch matrices of one range of t; one wave per
 // run, lane l < D holding w_l and w_{t-1, l}.  `first` starts from w0, `last`
@@ -216,7 +210,7 @@ k_mb_iterate(const float* __restrict__ Abuf, int D, int nt, float beta, MbState*
       if (mine) y = op_acc<OP>(y, A[m], wm, sign_bit(wm));
     }
     const float wn = mine ? fmaf(-beta, wp, y) : 0.0f;
-    nu = wave_sum_d(mine ? fabs((double)wn) : 0.0);
+    nu = wave_total_f64(mine ? fabs((double)wn) : 0.0);
     if (!(nu > 0.0) || !(nu < INFINITY)) {
       status = MAPI_ERR_DEGENERATE;
       break;
@@ -239,7 +233,7 @@ k_mb_iterate(const float* __restrict__ Abuf, int D, int nt, float beta, MbState*
   }
   double scale = 1.0;
   if (final_l2 && status == MAPI_OK) {
-    const double q2 = wave_sum_d(mine ? (double)w * (double)w : 0.0);
+    const double q2 = wave_total_f64(mine ? (double)w * (double)w : 0.0);
     if (!(q2 > 0.0) || !(q2 < INFINITY)) status = MAPI_ERR_DEGENERATE;
     else scale = 1.0 / sqrt(q2);
   }
