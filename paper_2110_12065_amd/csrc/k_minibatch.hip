@@ -23,6 +23,8 @@ constexpr int kMbLdsFloats = 128 * kMbMaxD;                  // gathered samples
 constexpr int kMbMaxChunk = 1024;                            // samples per gather pass at most
 constexpr int kMbIdx = kMbMaxChunk / kMbThreads;             // sample indices per thread and pass
 constexpr int kMbGather = kMbLdsFloats / kMbThreads;         // gathered floats per thread and pass
+constexpr int kMbIterLds = 16384;                            // staged batch-matrix floats of the recurrence (64 KiB)
+constexpr int kMbIterBatch = 16;                             // staging loads in flight per lane
 constexpr size_t kMbBufBytes = size_t(256) << 20;           // stored batch matrices per range of t
 
 // Iterate of one run between ranges of t.
@@ -201,23 +203,48 @@ k_mb_iterate(const float* __restrict__ Abuf, int D, int nt, float beta, MbState*
     it = S->it;
     status = S->status;
   }
+  // the run's batch matrices of this range are contiguous: they are copied into LDS a
+  // stage of ns steps at a time with every load of a lane issued before its first store,
+  // so the steps read A without a memory round trip each
+  __shared__ __align__(16) float As[kMbIterLds];
   const int DD = D * D;
-  for (int tl = 0; tl < nt && status == MAPI_OK; ++tl) {
-    const float* A = Abuf + ((int64_t)run * nt + tl) * DD + (int64_t)l * D;
-    float y = 0.0f;
-    for (int m = 0; m < D; ++m) {
-      const float wm = __shfl(w, m);
-      if (mine) y = op_acc<OP>(y, A[m], wm, sign_bit(wm));
+  const int ns = kMbIterLds / DD;   // >= 4: DD <= 4096
+  for (int t0 = 0; t0 < nt && status == MAPI_OK; t0 += ns) {
+    const int cnt = min(ns, nt - t0);
+    const float* src = Abuf + ((int64_t)run * nt + t0) * DD;
+    const int nf = cnt * DD;
+    for (int e0 = 0; e0 < nf; e0 += kMbIterBatch * kWave) {
+      float v[kMbIterBatch];
+#pragma unroll
+      for (int q = 0; q < kMbIterBatch; ++q) {
+        const int e = e0 + q * kWave + l;
+        v[q] = e < nf ? src[e] : 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < kMbIterBatch; ++q) {
+        const int e = e0 + q * kWave + l;
+        if (e < nf) As[e] = v[q];
+      }
     }
-    const float wn = mine ? fmaf(-beta, wp, y) : 0.0f;
-    nu = wave_total_f64(mine ? fabs((double)wn) : 0.0);
-    if (!(nu > 0.0) || !(nu < INFINITY)) {
-      status = MAPI_ERR_DEGENERATE;
-      break;
+    __syncthreads();
+    for (int tl = 0; tl < cnt; ++tl) {
+      const float* A = As + tl * DD + l * D;
+      float y = 0.0f;
+      for (int m = 0; m < D; ++m) {
+        const float wm = __shfl(w, m);
+        if (mine) y = op_acc<OP>(y, A[m], wm, sign_bit(wm));
+      }
+      const float wn = mine ? fmaf(-beta, wp, y) : 0.0f;
+      nu = wave_total_f64(mine ? fabs((double)wn) : 0.0);
+      if (!(nu > 0.0) || !(nu < INFINITY)) {
+        status = MAPI_ERR_DEGENERATE;
+        break;
+      }
+      wp = (float)((double)w / nu);
+      w = (float)((double)wn / nu);
+      ++it;
     }
-    wp = (float)((double)w / nu);
-    w = (float)((double)wn / nu);
-    ++it;
+    __syncthreads();   // the stage is read before the next one overwrites it
   }
   if (!last) {
     if (mine) {
