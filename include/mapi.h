@@ -252,7 +252,9 @@ mapi_status mapi_image_reconstruct(mapi_ctx* ctx, const float* V, int64_t P, int
  * ldx >= D elements.  batch_idx: device int32, runs * T * s entries in [0, N)
  * (the mini batches are drawn by the caller; NULL allowed when T = 0); an index outside gives
  * MAPI_ERR_ARG and is never used as an address.  w0 / w_out: device float32,
- * runs * D.  Batch sums are float64 (stored float32), the product float32, nu
+ * runs * D.  Batch sums are float64 (min1 with D * D < 256: runs of 16 exact
+ * float32 terms per chain summed in float32, the runs in float64), stored
+ * float32; the product float32, nu
  * float64.  D <= 64 (MAPI_ERR_UNSUPPORTED beyond).  infos (optional, host, runs
  * entries): iterations run, last nu, status; a zero or non-finite nu stops that
  * run with MAPI_ERR_DEGENERATE (also returned).  The batch matrices do not depend

@@ -23,6 +23,7 @@ constexpr int kMbLdsFloats = 128 * kMbMaxD;                  // gathered samples
 constexpr int kMbMaxChunk = 1024;                            // samples per gather pass at most
 constexpr int kMbIdx = kMbMaxChunk / kMbThreads;             // sample indices per thread and pass
 constexpr int kMbGather = kMbLdsFloats / kMbThreads;         // gathered floats per thread and pass
+constexpr int kMbRun = 16;                                   // min1 terms per float32 run of a chain (narrow batches)
 constexpr int kMbIterLds = 16384;                            // staged batch-matrix floats of the recurrence (64 KiB)
 constexpr int kMbIterBatch = 16;                             // staging loads in flight per lane
 constexpr size_t kMbBufBytes = size_t(256) << 20;           // stored batch matrices per range of t
@@ -148,11 +149,36 @@ k_mb_batches(const float* __restrict__ X, int64_t N, int D, int64_t ldx, const i
       const int k = p / D, l = p - k * D;
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       int i = slice;
-      for (; i + 3 * SL < c; i += 4 * SL) {
-        a0 += mb_term<OP>(xb[i * D + k], xb[i * D + l]);
-        a1 += mb_term<OP>(xb[(i + SL) * D + k], xb[(i + SL) * D + l]);
-        a2 += mb_term<OP>(xb[(i + 2 * SL) * D + k], xb[(i + 2 * SL) * D + l]);
-        a3 += mb_term<OP>(xb[(i + 3 * SL) * D + k], xb[(i + 3 * SL) * D + l]);
+      if constexpr (OP == MAPI_OP_MIN1) {
+        // min1 terms are exact in float32: each chain sums runs of kMbRun terms in float32
+        // and adds the runs in float64
+        float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f, f3 = 0.0f;
+        int run_len = 0;
+        for (; i + 3 * SL < c; i += 4 * SL) {
+          f0 += (float)mb_term<OP>(xb[i * D + k], xb[i * D + l]);
+          f1 += (float)mb_term<OP>(xb[(i + SL) * D + k], xb[(i + SL) * D + l]);
+          f2 += (float)mb_term<OP>(xb[(i + 2 * SL) * D + k], xb[(i + 2 * SL) * D + l]);
+          f3 += (float)mb_term<OP>(xb[(i + 3 * SL) * D + k], xb[(i + 3 * SL) * D + l]);
+          if (++run_len == kMbRun) {
+            a0 += f0;
+            a1 += f1;
+            a2 += f2;
+            a3 += f3;
+            f0 = f1 = f2 = f3 = 0.0f;
+            run_len = 0;
+          }
+        }
+        a0 += f0;
+        a1 += f1;
+        a2 += f2;
+        a3 += f3;
+      } else {
+        for (; i + 3 * SL < c; i += 4 * SL) {
+          a0 += mb_term<OP>(xb[i * D + k], xb[i * D + l]);
+          a1 += mb_term<OP>(xb[(i + SL) * D + k], xb[(i + SL) * D + l]);
+          a2 += mb_term<OP>(xb[(i + 2 * SL) * D + k], xb[(i + 2 * SL) * D + l]);
+          a3 += mb_term<OP>(xb[(i + 3 * SL) * D + k], xb[(i + 3 * SL) * D + l]);
+        }
       }
       for (; i < c; i += SL) a0 += mb_term<OP>(xb[i * D + k], xb[i * D + l]);
       acc[0] += (a0 + a1) + (a2 + a3);
