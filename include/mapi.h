@@ -192,8 +192,8 @@ mapi_status mapi_read_reference(mapi_ctx* ctx, const void* src, size_t bytes, in
  * normaliser and the residual are accumulated in float64, the iterate is
  * float32.  w_out (device float[n]) may alias w0.  MAPI_ERR_DEGENERATE if a
  * normaliser is zero or not finite; info->iters then counts completed steps.
- * A float32 system with n <= 256 and op MIN1 or MIN2 (rpi_solve: any such
- * system) is solved by one launch of one block that holds A in registers and
+ * A float32 system with n <= 256, op MIN1 or MIN2 (rpi_solve: any such system)
+ * and max_iters <= 65536 is solved by one launch of one block that holds A in registers and
  * runs every iteration, normalisation and stop test inside the kernel, unless
  * its bucket is pinned (mapi_tuning_set); larger systems, other storage types
  * and the diamond product launch a product and a normalisation per iteration.

@@ -153,8 +153,10 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
     return fail(MAPI_ERR_ARG, "op %d is not a MAPI product", o->op);
   const int64_t n = A->n_rows;
   const int norm = rpi ? NORM_L2 : NORM_L1;
-  if (A->dtype == MAPI_F32 && small_solve_fits(n, op) && !c->pinned.count(bucket(A->dtype, n, A->n_cols))) {
-    // the whole solve in one launch: latency, not bandwidth, bounds this size
+  if (A->dtype == MAPI_F32 && small_solve_fits(n, op) && o->max_iters <= kSmallMaxIters &&
+      !c->pinned.count(bucket(A->dtype, n, A->n_cols))) {
+    // the whole solve in one launch: latency, not bandwidth, bounds this size (at most
+    // kSmallMaxIters iterations, a fraction of a second, stay inside one kernel)
     if ((s = ensure(&c->ws, &c->ws_bytes, sizeof(SolveState), c)) != MAPI_OK) return s;
     SolveState* st = static_cast<SolveState*>(c->ws);
     HIP_TRY(launch_state_init(st, o->max_iters, o->tol, o->stall_iters, c->stream));

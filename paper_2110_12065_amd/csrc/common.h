@@ -233,6 +233,7 @@ int finalize_blocks(int64_t n);
 // Whole solve of a small dense float32 system in one block (n <= 256): the state must
 // be initialised; writes the final iterate (optional l2 step) to out and the state.
 bool small_solve_fits(int64_t n, int op);
+constexpr int kSmallMaxIters = 1 << 16;   // longer solves launch per iteration
 hipError_t launch_solve_small(int op, const float* A, int64_t ld, int64_t n, const float* w0, float* out,
                               SolveState* st, int norm, int final_l2, hipStream_t s);
 hipError_t launch_finish(const float* w0buf, const float* w1buf, float* out, int64_t n, SolveState* st, int final_l2,

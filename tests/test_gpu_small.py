@@ -119,3 +119,19 @@ def test_repeat_is_bitwise_deterministic():
     b, ib = mp.mapi_solve(to_dev(C), to_dev(w0), max_iters=200, ctx=one)
     np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
     assert ia == ib
+
+
+def test_long_solves_launch_per_iteration():
+    # more than 65536 allowed iterations: the solve launches a product per iteration, so no
+    # single kernel runs for long; a tolerance ends it early
+    A, _, _ = synth.planted_symmetric(64, [0.4], seed=51)
+    w0 = synth.start_vector(64, 52)
+    ctx = mp.Context()
+    ctx.timing(True)
+    ctx.timing_reset()
+    w, info = mp.mapi_solve(to_dev(A), to_dev(w0), max_iters=100000, tol=1e-6, ctx=ctx)
+    _, launches = ctx.timing_get("mavp")
+    ctx.timing(False)
+    assert info["converged"] and launches >= info["iters"] > 1
+    ref = oracle.mapi(A.astype(np.float64), w0, info["iters"])
+    assert rel_l1(w.cpu().numpy(), ref.w) <= TOL
