@@ -26,6 +26,21 @@ __device__ __forceinline__ void tile_coords(int b, int T, int* ti, int* tj) {
   *tj = i + b;
 }
 
+constexpr int MSP = MT + 1;      // pitch of a tile staged in LDS for its write-out
+
+// Tile (i0, j0) of A from S (float, row pitch MSP) and, with mirror, its transpose at (j0, i0).
+__device__ void gram_write_tile(const float* S, int i0, int j0, int D, float* __restrict__ A, int64_t lda, bool mirror) {
+  for (int e = threadIdx.x; e < MT * MT; e += blockDim.x) {
+    const int il = e / MT, jl = e % MT;
+    if (i0 + il < D && j0 + jl < D) A[(int64_t)(i0 + il) * lda + j0 + jl] = S[il * MSP + jl];
+  }
+  if (!mirror) return;
+  for (int e = threadIdx.x; e < MT * MT; e += blockDim.x) {
+    const int jl = e / MT, il = e % MT;
+    if (i0 + il < D && j0 + jl < D) A[(int64_t)(j0 + jl) * lda + i0 + il] = S[il * MSP + jl];
+  }
+}
+
 // ---------------------------------------------------------------- min forms on the vector ALU
 // 1024 threads, each a 4 x 4 register tile of the 128 x 128 output tile: rows 4 ty .. 4 ty + 3,
 // columns 4 tx .. 4 tx + 3 (tx = tid % 32, ty = tid / 32), so that per sample a wave reads
@@ -171,28 +186,16 @@ k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t c
 #pragma unroll
       for (int q = 0; q < 4; ++q) out[(ty * 4 + p) * MT + tx * 4 + q] = acc[p][q];
   } else {
+    // the tile is staged in the (now free) slab buffers so that it and its mirror are
+    // written along rows
+    static_assert(MT * MSP <= 2 * NKS * NP, "staged tile fits the slab buffers");
+    __syncthreads();
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int i = i0 + ty * 4 + p;
-      if (i >= D) continue;
+    for (int p = 0; p < 4; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = j0 + tx * 4 + q;
-        if (j < D) A[(int64_t)i * lda + j] = (float)(scale * acc[p][q]);
-      }
-    }
-    if (ti != tj) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = j0 + tx * 4 + q;
-        if (j >= D) continue;
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          const int i = i0 + ty * 4 + p;
-          if (i < D) A[(int64_t)j * lda + i] = (float)(scale * acc[p][q]);
-        }
-      }
-    }
+      for (int q = 0; q < 4; ++q) lds[(ty * 4 + p) * MSP + tx * 4 + q] = (float)(scale * acc[p][q]);
+    __syncthreads();
+    gram_write_tile(lds, i0, j0, D, A, lda, ti != tj);
   }
 }
 
@@ -216,22 +219,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int MKS = 64;         // samples per LDS slab
 constexpr int MROW = MKS + 4;   // staged row pitch (floats): an odd number of 16-byte units
 constexpr int MRUN = 256 / MKS; // slabs per float32 run (256 samples)
-constexpr int MSP = MT + 1;     // pitch of the staged output tile
 constexpr int MLPR = MKS / 4;   // loader threads per staged row (one float4 each)
 constexpr int MLP = 2 * MT * MLPR / 512;   // float4s each of the 512 threads loads per slab
-
-// Tile (i0, j0) of A from S (float, row pitch MSP) and, with mirror, its transpose at (j0, i0).
-__device__ void gram_write_tile(const float* S, int i0, int j0, int D, float* __restrict__ A, int64_t lda, bool mirror) {
-  for (int e = threadIdx.x; e < MT * MT; e += blockDim.x) {
-    const int il = e / MT, jl = e % MT;
-    if (i0 + il < D && j0 + jl < D) A[(int64_t)(i0 + il) * lda + j0 + jl] = S[il * MSP + jl];
-  }
-  if (!mirror) return;
-  for (int e = threadIdx.x; e < MT * MT; e += blockDim.x) {
-    const int jl = e / MT, il = e % MT;
-    if (i0 + il < D && j0 + jl < D) A[(int64_t)(j0 + jl) * lda + i0 + il] = S[il * MSP + jl];
-  }
-}
 
 template <bool SPLIT>
 __global__ void __launch_bounds__(512)
