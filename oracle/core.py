@@ -15,6 +15,11 @@ Pins (tests/test_oracle_core.py):
     in one step; Proposition 1's closed form with the diamond operator of
     eq. (7), reached exactly at the second iteration.
   * rpi: the dominant eigenvector of numpy.linalg.eigh on planted-gap matrices.
+  * mavp, mapi, rpi (l1 form): exact rational brute force (fractions.Fraction) on
+    dyadic systems with n <= 8 for up to 5 iterations -- the product exactly, and the
+    iterates, the l1 normalisers and the l1 residual sequence ||w_t - w_{t-1}||_1 to
+    float64 rounding (tests/test_oracle_bruteforce.py), including the stop iteration
+    for a tolerance between two exact residuals.
   * ranks: the rank lists the paper prints for its own vectors (Sec. 3.2 and
     Sec. 3.3), stored under tests/golden/.
 Parity unpinned: MAPI's fixed point on general matrices (no closed form exists;

@@ -6,10 +6,17 @@ Pins (tests/test_oracle_image.py):
   * min_outer: the diagonal of W (+) W^T is sum_k |W_jk| (the l1 identity of Sec. 2.1),
     the matrix is symmetric, and for columns of constant modulus c it equals
     c * sign(W) sign(W)^T (numpy matmul).
+  * minouter_deflate and minouter_reconstruct (Alg. 2, deflation and reconstruction steps):
+    for vectors of constant modulus, where w (+) w^T = c s s^T, they equal the numpy
+    expressions C - c s (s^T C) and sum_k c_k s_k (s_k^T Vc) + m -- which fixes the side
+    the min-outer product multiplies from (a transposed product fails).
+  * image_reconstruct with method "mapi": its vectors are oracle.mapi on the eq. (5)
+    min-covariance with the 1/(N-1) scale and on the deflated matrix, and R is the
+    reconstruction step applied to them (checked by composing the pinned steps).
   * image_reconstruct with method "rpi": the two vectors span the top-2 eigenspace of the
     covariance (numpy.linalg.eigh) and the reconstruction equals the projection of every
     centred image onto that space plus the mean.
-Parity unpinned: the MAPI vectors and reconstruction beyond those invariants.
+Parity unpinned: none beyond the MAPI fixed point (see core).
 """
 from __future__ import annotations
 
@@ -30,6 +37,20 @@ def min_outer(W, op="min1"):
     for k in range(W.shape[1]):
         M += term(W[:, k][:, None], W[:, k][None, :])
     return M
+
+
+def minouter_deflate(C, w, op="min1"):
+    """Alg. 2, deflation step: C - (w (+) w^T) C, the min-outer product of the first vector
+    multiplying C from the left."""
+    C = np.asarray(C, dtype=F64)
+    return C - min_outer(w, op) @ C
+
+
+def minouter_reconstruct(W, Vc, m, op="min1"):
+    """Alg. 2, reconstruction step: (W (+) W^T) Vc + m, the min-outer product of the vectors
+    (columns of W) applied to the centred images (columns of Vc), plus the mean image m."""
+    Vc = np.asarray(Vc, dtype=F64)
+    return min_outer(W, op) @ Vc + np.asarray(m, dtype=F64)[:, None]
 
 
 def image_reconstruct(V, T, w0, method="mapi", op="min1", tol=0.0):
@@ -62,10 +83,10 @@ def image_reconstruct(V, T, w0, method="mapi", op="min1", tol=0.0):
 
     r1 = solve(C)
     w1 = r1.w
-    C2 = C - (min_outer(w1, op) if mapi_like else np.outer(w1, w1)) @ C
+    C2 = minouter_deflate(C, w1, op) if mapi_like else C - np.outer(w1, w1) @ C
     r2 = solve(C2)
     W = np.stack([w1, r2.w], axis=1)
-    R = (min_outer(W, op) if mapi_like else W @ W.T) @ Vc + m[:, None]
+    R = minouter_reconstruct(W, Vc, m, op) if mapi_like else W @ W.T @ Vc + m[:, None]
     return R, W, (r1, r2)
 
 

@@ -57,3 +57,54 @@ def test_occluded_images_structure():
         diff = (V[:, i] != clean).reshape(32, 32)
         bad = [diff[r * 8:(r + 1) * 8, c * 8:(c + 1) * 8].any() for r in range(4) for c in range(4)]
         assert sum(bad) == 3
+
+
+def _flat(rng, P, c):
+    s = np.where(rng.uniform(size=P) < 0.5, -1.0, 1.0)
+    return s, c * s
+
+
+def test_minouter_deflation_multiplies_from_the_left():
+    # Alg. 2 deflation: for w = c s (constant modulus), w (+) w^T = c s s^T, so the step is
+    # C - c s (s^T C); the right-hand product C - C (c s s^T) differs for a generic C
+    rng = np.random.default_rng(11)
+    P = 40
+    X = rng.standard_normal((P, 7))
+    C = oracle.mingram(X, 1.0 / 6)
+    s, w = _flat(rng, P, 1.0 / P)
+    got = oracle.minouter_deflate(C, w)
+    want = C - (1.0 / P) * np.outer(s, s @ C)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-14)
+    wrong = C - (1.0 / P) * np.outer(C @ s, s)
+    assert np.max(np.abs(wrong - want)) > 1e-3
+
+
+def test_minouter_reconstruction_of_flat_vectors():
+    # Alg. 2 reconstruction: with W = [c1 s1, c2 s2], W (+) W^T = c1 s1 s1^T + c2 s2 s2^T
+    rng = np.random.default_rng(12)
+    P, N = 36, 5
+    s1, w1 = _flat(rng, P, 1.0 / P)
+    s2, w2 = _flat(rng, P, 0.5 / P)
+    Vc = rng.standard_normal((P, N))
+    m = rng.uniform(size=P)
+    R = oracle.minouter_reconstruct(np.stack([w1, w2], axis=1), Vc, m)
+    want = (1.0 / P) * np.outer(s1, s1 @ Vc) + (0.5 / P) * np.outer(s2, s2 @ Vc) + m[:, None]
+    np.testing.assert_allclose(R, want, rtol=0, atol=1e-14)
+    # a single column is not the same as the pair (the sum over the columns of W is taken)
+    R1 = oracle.minouter_reconstruct(w1[:, None], Vc, m)
+    assert np.max(np.abs(R1 - want)) > 1e-3
+
+
+def test_mapi_reconstruction_is_the_composition_of_the_pinned_steps():
+    clean, V = synth.occluded_images(16, 10, seed=5)
+    w0 = synth.start_vector(256, 6).astype(np.float64)
+    R, W, (r1, r2) = oracle.image_reconstruct(V, 25, w0)
+    Vd = V.astype(np.float64)
+    m = Vd.mean(axis=1)
+    Vc = Vd - m[:, None]
+    C = oracle.mingram(Vc, 1.0 / 9)                       # eq. (5) with Alg. 2's 1/(N-1)
+    a1 = oracle.mapi(C, w0, 25)
+    np.testing.assert_array_equal(W[:, 0], a1.w)
+    a2 = oracle.mapi(oracle.minouter_deflate(C, a1.w), w0, 25)
+    np.testing.assert_array_equal(W[:, 1], a2.w)
+    np.testing.assert_array_equal(R, oracle.minouter_reconstruct(np.stack([a1.w, a2.w], axis=1), Vc, m))
