@@ -2,9 +2,13 @@
 
 Workload (headline): dense symmetric covariance n = 16384, C = X X^T / 32768 with
 X i.i.d. N(0, 1) rows centred (synthetic, seeded), stored in float32.  One step
-is one MAPI solve of ITERS iterations (fixed count: products, float64 l1
-normalisation and residual every iteration).  `value` is the product throughput
-in Gelem/s (n^2 min-terms per iteration).  The same line carries RPI and the
+is one MAPI solve of ITERS iterations (tolerance 0, so all ITERS run): every
+iteration forms the min1 product, its float64 l1 normaliser, the float32 iterate
+and the float64 residual ||w_t - w_{t-1}||_1, and advances the stop rule.  The
+iterate and residual of iteration t are formed inside product t + 1 and the
+stop rule for t is advanced by product t + 2 (or by the last normalisation
+kernel), one launch per iteration.  `value` is the product throughput in Gelem/s
+(n^2 min-terms per iteration).  The same line carries RPI and the
 BF16 / FP8 storage modes under "detail", the roofline of the dense product
 kernel, and the FP64 CPU oracle timed on a bounded sample of the same work.
 

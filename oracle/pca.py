@@ -74,7 +74,8 @@ def pca_topk(X, k, W0, method="mapi", T=100, tol=0.0, scale=None, op="min1", A=N
     method "rpi":  power iteration of eq. (1) on the covariance of eq. (2).
     Vector i is extracted from (I - P P^T) A where P holds the i-1 earlier vectors
     (Sec. 1), started from column i of W0 (D x k).  Returns (P, [IterResult]).
-    ``A`` may pass a prebuilt matrix of the right kind to skip the build.
+    ``A`` may pass a prebuilt matrix of the right kind to skip the build.  ``T`` is
+    one iteration limit for every vector or a sequence of k limits, one per vector.
     """
     X = np.asarray(X, dtype=F64)
     D, N = X.shape
@@ -84,13 +85,14 @@ def pca_topk(X, k, W0, method="mapi", T=100, tol=0.0, scale=None, op="min1", A=N
         A = mingram(X, scale, op) if method == "mapi" else covariance(X, scale)
     W0 = np.asarray(W0, dtype=F64)
     P = np.zeros((D, 0), dtype=F64)
+    Ts = [int(T)] * k if np.isscalar(T) else [int(t) for t in T]
     results = []
     for i in range(k):
         Ai = deflate_projection(A, P)
         if method == "mapi":
-            r = mapi(Ai, W0[:, i], T, tol, op=op)
+            r = mapi(Ai, W0[:, i], Ts[i], tol, op=op)
         else:
-            r = rpi(Ai, W0[:, i], T, tol, norm="l2")
+            r = rpi(Ai, W0[:, i], Ts[i], tol, norm="l2")
         results.append(r)
         P = _mgs_append(P, r.w)
     return P, results

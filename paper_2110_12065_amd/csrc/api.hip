@@ -175,25 +175,29 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
   const DenseTuning t = tuning_for(c, da);
   const int P = dense_part_count(da, t, c->cu_count);
   const int F = finalize_blocks(n);
-  // A fixed-iteration solve (no tolerance, no stall rule: nothing stops it early)
-  // folds each normalisation into the next product, which forms w from the
-  // previous y and partials while staging it in LDS (FusedPrev); the last
-  // iteration is normalised by the normalisation kernel.  Same arithmetic.
-  const bool fused = o->tol == 0.0 && o->stall_iters <= 0 && t.w_in_lds != 0;
+  // With w staged in LDS, each product forms its own iterate from the previous y and
+  // partials (FusedPrev), adds its share of the residual ||w_t - w_{t-1}||_1 to a
+  // per-block partial, and advances the stop rule for the previous iteration: one
+  // launch per iteration, the stop decision one launch late.  The last iteration is
+  // normalised by the normalisation kernel.  Same arithmetic as the kernel pair.
+  const bool fused = t.w_in_lds != 0;
   Layout L;
   const size_t o_st = L.take(sizeof(SolveState));
   const size_t o_pp = L.take(sizeof(double) * 2 * (size_t)P);
+  const size_t o_rp = L.take(sizeof(double) * 2 * (size_t)P);
   const size_t o_part = L.take(sizeof(double) * 3 * (size_t)F);
   const size_t o_w0 = L.take(sizeof(float) * n);
   const size_t o_w1 = L.take(sizeof(float) * n);
-  const size_t o_y = L.take(sizeof(float) * 2 * n);
+  const size_t o_y0 = L.take(sizeof(float) * n);
+  const size_t o_y1 = L.take(sizeof(float) * n);
   if ((s = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return s;
   char* base = static_cast<char*>(c->ws);
   SolveState* st = reinterpret_cast<SolveState*>(base + o_st);
   double* pp[2] = {reinterpret_cast<double*>(base + o_pp), reinterpret_cast<double*>(base + o_pp) + P};
+  double* rp[2] = {reinterpret_cast<double*>(base + o_rp), reinterpret_cast<double*>(base + o_rp) + P};
   double* part = reinterpret_cast<double*>(base + o_part);
   float* wb[2] = {reinterpret_cast<float*>(base + o_w0), reinterpret_cast<float*>(base + o_w1)};
-  float* yb[2] = {reinterpret_cast<float*>(base + o_y), reinterpret_cast<float*>(base + o_y) + n};
+  float* yb[2] = {reinterpret_cast<float*>(base + o_y0), reinterpret_cast<float*>(base + o_y1)};
 
   HIP_TRY(hipMemcpyAsync(wb[0], w0, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(launch_state_init(st, o->max_iters, o->tol, o->stall_iters, c->stream));
@@ -204,7 +208,8 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
     {
       DenseArgs dl = da;
       TimedLaunch tm(c, MAPI_K_MAVP, &dl);
-      const FusedPrev fp{yb[b ^ 1], pp[b ^ 1], P, wb[it & 1], it};
+      const FusedPrev fp{yb[b ^ 1], pp[b ^ 1], P, wb[it & 1], it, wb[(it & 1) ^ 1], it >= 2 ? rp[b ^ 1] : nullptr,
+                         rp[b]};
       HIP_TRY(launch_mavp_dense(dl, op, wb[it & 1], yb[b], pp[b], st, norm, t, c->cu_count, c->stream,
                                 (fused && it > 0) ? &fp : nullptr));
     }
@@ -220,11 +225,12 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
     }
   }
   if (fused && launched > 0) {
-    // the last iteration's normalisation; the iterations before it were counted by none
+    // the last iteration's normalisation, after the stop rule for the one before it
+    // (whose residual the last product formed)
     const int it = launched - 1;
     Timed tm(c, MAPI_K_FINALIZE);
     HIP_TRY(launch_finalize(0, yb[it & 1], wb[it & 1], wb[(it & 1) ^ 1], n, st, pp[it & 1], P, norm, part, nullptr,
-                            0.0, 0.0, c->stream, it));
+                            0.0, 0.0, c->stream, it >= 1 ? rp[it & 1] : nullptr, P));
   }
   HIP_TRY(launch_finish(wb[0], wb[1], w_out, n, st, o->final_l2, c->stream));
   if ((s = sync_and_state(c, st)) != MAPI_OK) return s;

@@ -199,17 +199,25 @@ inline size_t dense_lds_bytes(int dtype, int64_t n_cols, int mode) {
   return (mode == 2 && dtype == MAPI_FP8_E4M3) ? wbytes + (size_t)((n_cols >> 2) + 4) * 4 : wbytes;
 }
 
-// Normalisation of the previous iteration folded into a dense product (fixed-
-// iteration solves): the kernel forms nu from the previous product's partials,
-// stages w = y_prev * (1 / nu) in LDS instead of reading w, and writes its share
-// of w to w_new.  A zero or non-finite nu marks the solve degenerate after
-// `iter` - 1 completed iterations.
+// Normalisation and convergence check of the previous iteration folded into a
+// dense product.  Launch t (t >= 1) forms nu_t from the previous product's
+// partials, stages w_t = y_t * (1 / nu_t) in LDS instead of reading w, writes its
+// share of w_t to w_new and adds |w_t - w_{t-1}| over that share (w_old) into a
+// float64 residual partial (rpart_out, one per block).  The residual of iteration
+// t is therefore known only to the next launch, which sums rpart_prev in a fixed
+// order and advances the stop rule for iteration t - 1 before anything else: the
+// stop decision lags one launch, and a solve that converges at iteration t has
+// computed one product past it.  A zero or non-finite nu marks the solve
+// degenerate after `iter` - 1 completed iterations.
 struct FusedPrev {
   const float* y_prev;
   const double* part_prev;
   int nparts;
   float* w_new;
   int iter;
+  const float* w_old;          // w_{t-1}
+  const double* rpart_prev;    // residual partials of iteration t - 1 (NULL for t = 1)
+  double* rpart_out;           // residual partials of iteration t
 };
 // Admissible w_in_lds modes for a storage type.
 inline bool lds_mode_ok(int dtype, int mode) { return mode == 0 || mode == 1 || (mode == 2 && dtype == MAPI_FP8_E4M3); }
@@ -220,11 +228,13 @@ hipError_t launch_mavp_dense(const DenseArgs& a, int op, const float* w, float* 
                              const FusedPrev* fp = nullptr);
 int dense_part_count(const DenseArgs& a, const DenseTuning& t, int cu_count);
 DenseTuning dense_default_tuning(const DenseArgs& a, int cu_count, int max_lds_bytes);
-// set_iter >= 0: the completed-iteration count is set to it before this
-// iteration is counted (the last normalisation of a fused solve).
+// rprev (dense only): residual partials of the previous iteration, written by a
+// product that formed that iterate (FusedPrev); they are summed and the stop rule
+// advanced for that iteration before this one is formed.
 hipError_t launch_finalize(int mode, const float* y, const float* w_old, float* w_new, int64_t n,
                            SolveState* st, const double* pprod, int nprod, int norm, double* part,
-                           const uint8_t* dangling, double c, double inv_n, hipStream_t s, int set_iter = -1);
+                           const uint8_t* dangling, double c, double inv_n, hipStream_t s,
+                           const double* rprev = nullptr, int nrprev = 0);
 // The same for a float64 iterate (PageRank modes 1 and 2).
 hipError_t launch_finalize_f64(int mode, const double* y, const double* w_old, double* w_new, int64_t n,
                                SolveState* st, const double* pprod, int nprod, double* part, const uint8_t* dangling,

@@ -208,9 +208,11 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
   const float* wv = w;
   const float* wtail = w;   // signed w of the columns past the last whole vector
   const uint32_t* smask = nullptr;
+  double racc = 0.0;        // FusedPrev: this thread's part of ||w_t - w_{t-1}||_1
   if constexpr (WLDS) {
     // FusedPrev: w = y_prev * (1 / nu), nu from the previous product's partials (the
-    // normalisation kernel's arithmetic); this block also writes its share of w.
+    // normalisation kernel's arithmetic); this block also writes its share of w and
+    // the residual partial of that share.
     const bool fused = fp.y_prev != nullptr;
     constexpr int PQ = 8;   // float4s of y_prev per thread loaded before nu is known
     const int np4 = nvec * (VE / 4);
@@ -220,22 +222,38 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
     // of them also loaded before nu is known
     const int64_t per = ((int64_t)n_cols + gridDim.x - 1) / gridDim.x;
     const int64_t e0 = (int64_t)blockIdx.x * per, e1 = min((int64_t)n_cols, e0 + per);
-    float ys = 0.0f;
+    float ys = 0.0f, wo = 0.0f;
     if (fused) {
 #pragma unroll
       for (int q = 0; q < PQ; ++q) {
         const int k = threadIdx.x + q * blockDim.x;
         pre[q] = k < np4 ? src[k] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
-      if (e0 + threadIdx.x < e1) ys = fp.y_prev[e0 + threadIdx.x];
+      if (e0 + threadIdx.x < e1) {
+        ys = fp.y_prev[e0 + threadIdx.x];
+        wo = fp.w_old[e0 + threadIdx.x];
+      }
     }
     double inv = 0.0;
     if (fused) {
+      if (fp.rpart_prev != nullptr) {
+        // the stop rule for iteration t - 1, whose residual partials the previous
+        // launch wrote: every block sums them in the same order and takes the same
+        // tolerance decision; block 0 advances the state (the stall rule, which
+        // depends on earlier iterations, is decided there alone: a block that
+        // carries on only forms w_t, which the result w_{t-1} does not share a
+        // buffer with, and the next launch sees the solve done)
+        const double rprev = wave_sum_parts(fp.rpart_prev, fp.nparts);
+        if (blockIdx.x == 0 && threadIdx.x == 0) state_advance(st, rprev);
+        if (rprev < st->tol) return;
+      }
       const double tot = wave_sum_parts(fp.part_prev, fp.nparts);
       const double nu = (norm == NORM_L2) ? sqrt(tot) : tot;
+      // block 0's thread 0 records nu_t unless it has just stopped the solve (stall rule)
+      const bool owner = blockIdx.x == 0 && threadIdx.x == 0 && !state_done(st);
+      if (owner) st->nu = nu;
       if (!(nu > 0.0) || !(nu < INFINITY)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-          st->nu = nu;
+        if (owner) {
           st->status = MAPI_ERR_DEGENERATE;
           st->iter = fp.iter - 1;
           st->done = 1;
@@ -243,9 +261,16 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
         return;
       }
       inv = 1.0 / nu;
-      if (e0 + threadIdx.x < e1) fp.w_new[e0 + threadIdx.x] = (float)((double)ys * inv);
-      for (int64_t i = e0 + threadIdx.x + blockDim.x; i < e1; i += blockDim.x)
-        fp.w_new[i] = (float)((double)fp.y_prev[i] * inv);
+      if (e0 + threadIdx.x < e1) {
+        const float wn = (float)((double)ys * inv);
+        fp.w_new[e0 + threadIdx.x] = wn;
+        racc = fabs((double)wn - (double)wo);
+      }
+      for (int64_t i = e0 + threadIdx.x + blockDim.x; i < e1; i += blockDim.x) {
+        const float wn = (float)((double)fp.y_prev[i] * inv);
+        fp.w_new[i] = wn;
+        racc += fabs((double)wn - (double)fp.w_old[i]);
+      }
     }
     const int64_t wfl = dense_lds_w_floats(DT, n_cols);
     // whole vectors' w in chunk-interleaved order (|w| with PF, plus one sign word
@@ -323,12 +348,16 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
   if (part == nullptr || norm == NORM_NONE) return;
   const double bsum = block_sum_f64(nrm, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = bsum;
+  if (WLDS && fp.rpart_out != nullptr) {
+    const double rsum = block_sum_f64(racc, sh);
+    if (threadIdx.x == 0) fp.rpart_out[blockIdx.x] = rsum;
+  }
 }
 
 template <int DT, int OP, int RW, int U, int WL, bool NT>
 static hipError_t launch_k(const DenseArgs& a, const float* w, float* y, double* part, SolveState* st, int norm,
                            int blocks, int waves, hipStream_t s, const FusedPrev* fp) {
-  const FusedPrev f = fp ? *fp : FusedPrev{nullptr, nullptr, 0, nullptr, 0};
+  const FusedPrev f = fp ? *fp : FusedPrev{nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr, nullptr};
   const unsigned char* A = static_cast<const unsigned char*>(a.A);
   const int64_t ldb = a.ld * Traits<DT>::ESZ;
   const size_t lds = dense_lds_bytes(DT, a.n_cols, WL);

@@ -17,7 +17,8 @@ template <int MODE, int BS, int PF, typename T = float>
 __global__ void __launch_bounds__(BS)
 k_finalize(const T* __restrict__ y, const T* __restrict__ w_old, T* __restrict__ w_new, int64_t n,
            SolveState* __restrict__ st, const double* __restrict__ pprod, int nprod, int norm,
-           double* __restrict__ part, const uint8_t* __restrict__ dangling, double c, double inv_n, int set_iter) {
+           double* __restrict__ part, const uint8_t* __restrict__ dangling, double c, double inv_n,
+           const double* __restrict__ rprev, int nrprev) {
   __shared__ double sh[16];
   __shared__ int sh_flag;
   if (state_done(st)) return;
@@ -32,11 +33,22 @@ k_finalize(const T* __restrict__ y, const T* __restrict__ w_old, T* __restrict__
     yp[k] = i < n ? y[i] : T(0);
     wp[k] = i < n ? w_old[i] : T(0);
   }
+  if (rprev != nullptr) {
+    // the previous iteration's residual (its iterate was formed inside a product):
+    // the same fixed-order sum and tolerance decision in every block; block 0
+    // advances the stop rule for it
+    const double r0 = wave_sum_parts(rprev, nrprev);
+    if (blockIdx.x == 0 && threadIdx.x == 0) state_advance(st, r0);
+    if (r0 < st->tol) return;
+  }
   const double tot = wave_sum_parts(pprod, nprod);
   const double nu = (norm == NORM_L2) ? sqrt(tot) : tot;
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->nu = nu;
+  // block 0's thread 0 alone writes the state; it skips this iteration if it has just
+  // stopped the solve on the stall rule
+  const bool owner = blockIdx.x == 0 && threadIdx.x == 0 && !state_done(st);
+  if (owner) st->nu = nu;
   if (!(nu > 0.0) || !(nu < INFINITY)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (owner) {
       st->status = MAPI_ERR_DEGENERATE;
       st->done = 1;
     }
@@ -70,12 +82,13 @@ k_finalize(const T* __restrict__ y, const T* __restrict__ w_old, T* __restrict__
     e0 = block_sum_f64(e0, sh);
     e1 = block_sum_f64(e1, sh);
   }
+  // (a stall stop of the previous iteration, taken by block 0 above, leaves the state
+  // done: this iteration is then not counted)
   if (gridDim.x == 1) {   // one block holds every sum: no partials, no arrival
     if (threadIdx.x == 0) {
       st->ex[0] = e0;
       st->ex[1] = e1;
-      if (set_iter >= 0) st->iter = set_iter;
-      state_advance(st, r);
+      if (!state_done(st)) state_advance(st, r);
     }
     return;
   }
@@ -95,8 +108,7 @@ k_finalize(const T* __restrict__ y, const T* __restrict__ w_old, T* __restrict__
       st->ex[0] = E0;
       st->ex[1] = E1;
       st->cnt_b = 0;
-      if (set_iter >= 0) st->iter = set_iter;
-      state_advance(st, R);
+      if (!state_done(st)) state_advance(st, R);
     }
   }
 }
@@ -257,12 +269,13 @@ int finalize_blocks(int64_t n) {
 
 hipError_t launch_finalize(int mode, const float* y, const float* w_old, float* w_new, int64_t n, SolveState* st,
                            const double* pprod, int nprod, int norm, double* part, const uint8_t* dangling, double c,
-                           double inv_n, hipStream_t s, int set_iter) {
+                           double inv_n, hipStream_t s, const double* rprev, int nrprev) {
   const int blocks = finalize_blocks(n);
+  if (mode != 0 && rprev != nullptr) return hipErrorInvalidValue;
   switch (mode) {
-    case 0: hipLaunchKernelGGL((k_finalize<0, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n, set_iter); break;
-    case 1: hipLaunchKernelGGL((k_finalize<1, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n, set_iter); break;
-    case 2: hipLaunchKernelGGL((k_finalize<2, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n, set_iter); break;
+    case 0: hipLaunchKernelGGL((k_finalize<0, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n, rprev, nrprev); break;
+    case 1: hipLaunchKernelGGL((k_finalize<1, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n, rprev, nrprev); break;
+    case 2: hipLaunchKernelGGL((k_finalize<2, 256, 4>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, norm, part, dangling, c, inv_n, rprev, nrprev); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -285,8 +298,8 @@ hipError_t launch_finalize_f64(int mode, const double* y, const double* w_old, d
                                double c, double inv_n, hipStream_t s) {
   const int blocks = finalize_blocks(n);
   switch (mode) {
-    case 1: hipLaunchKernelGGL((k_finalize<1, 256, 4, double>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, NORM_L1, part, dangling, c, inv_n, -1); break;
-    case 2: hipLaunchKernelGGL((k_finalize<2, 256, 4, double>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, NORM_L1, part, dangling, c, inv_n, -1); break;
+    case 1: hipLaunchKernelGGL((k_finalize<1, 256, 4, double>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, NORM_L1, part, dangling, c, inv_n, nullptr, 0); break;
+    case 2: hipLaunchKernelGGL((k_finalize<2, 256, 4, double>), dim3(blocks), dim3(256), 0, s, y, w_old, w_new, n, st, pprod, nprod, NORM_L1, part, dangling, c, inv_n, nullptr, 0); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

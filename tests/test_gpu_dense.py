@@ -351,31 +351,93 @@ def test_read_reference_times_and_rejects_bad_sizes():
         mp.mapi_read_reference(x, reps=0)
 
 
+def _pair_shapes(dtype):
+    """Launch shapes that differ only in the staging of w: with w in LDS each product forms its
+    own iterate and residual partials and advances the stop rule one launch late; with w read
+    from global memory a normalisation kernel follows every product.  Same grid, so the same
+    normaliser partials and the same bits of every iterate."""
+    base = dict(rows_per_wave=2, waves=8, blocks_per_cu=2, unroll=2, nontemporal=1)
+    fused = [dict(base, w_in_lds=l) for l in ((1, 2) if dtype == "fp8" else (1,))]
+    return fused, dict(base, w_in_lds=0)
+
+
 @pytest.mark.parametrize("n", [517, 1003])
 @pytest.mark.parametrize("meth", ["mapi", "rpi"])
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
-def test_normalisation_in_the_product_matches_the_separate_kernel(dtype, meth, n):
-    # A fixed-iteration solve (tol 0) forms each normaliser and iterate inside the next product;
-    # a tolerance too small to ever stop the solve keeps the normalisation kernel after every
-    # product.  Both use the same arithmetic, so the iterates, norms and residuals are the same
-    # bits.  n = 517 and 1003 leave ragged tails for every storage type.
-    print(f"[case] fused normalisation {dtype} {meth} n={n}", flush=True)
-    A32 = synth.dense_cov(n, 2 * n, seed=n)
+def test_stop_rule_in_the_product_matches_the_kernel_pair(dtype, meth, n):
+    # fixed iteration counts and tolerance stops: iterates, normalisers and iteration counts are
+    # the same bits on both paths; a residual that stopped the solve was summed inside the next
+    # product on one path and by the normalisation kernel on the other (float64, another order).
+    # n = 517 and 1003 leave ragged tails for every storage type.
+    print(f"[case] stop rule in the product {dtype} {meth} n={n}", flush=True)
+    A32, _, _ = synth.planted_symmetric(n, [0.4], seed=n)
     Ad, rs, Aref = _stored(A32, dtype)
     w0h = synth.start_vector(n, n + 1)
     w0 = to_dev(w0h)
     code = {"f32": mp.MAPI_F32, "bf16": mp.MAPI_BF16, "fp8": mp.MAPI_FP8_E4M3}[dtype]
     fn = mp.mapi_solve if meth == "mapi" else mp.rpi_solve
-    for lds in ((1, 2) if dtype == "fp8" else (1,)):
-        mp.mapi_tuning_set(code, n, n, dict(rows_per_wave=2, waves=8, blocks_per_cu=2, unroll=2, w_in_lds=lds,
-                                            nontemporal=1))
-        wa, ia = fn(Ad, w0, max_iters=13, row_scale=rs)
-        wb, ib = fn(Ad, w0, max_iters=13, tol=1e-300, row_scale=rs)
-        np.testing.assert_array_equal(wa.cpu().numpy(), wb.cpu().numpy())
-        assert ia["iters"] == ib["iters"] == 13
-        assert ia["norm"] == ib["norm"] and ia["residual"] == ib["residual"]
-    ref = (oracle.mapi if meth == "mapi" else oracle.rpi)(Aref.astype(np.float64), w0h.astype(np.float64), 13)
-    assert rel_l1(wa.cpu().numpy(), ref.w) <= TOL
+    fused, pair = _pair_shapes(dtype)
+    for T, tol in ((13, 0.0), (500, 1e-5)):
+        mp.mapi_tuning_set(code, n, n, pair)
+        wb, ib = fn(Ad, w0, max_iters=T, tol=tol, check_every=5, row_scale=rs)
+        for shape in fused:
+            mp.mapi_tuning_set(code, n, n, shape)
+            wa, ia = fn(Ad, w0, max_iters=T, tol=tol, check_every=5, row_scale=rs)
+            np.testing.assert_array_equal(wa.cpu().numpy(), wb.cpu().numpy())
+            assert ia["iters"] == ib["iters"] and ia["converged"] == ib["converged"], (ia, ib)
+            assert ia["norm"] == ib["norm"]
+            assert ia["residual"] == pytest.approx(ib["residual"], rel=1e-12, abs=0)
+        if tol == 0.0:
+            assert ia["iters"] == T and ia["residual"] == ib["residual"]
+        else:
+            assert ia["converged"] and ia["residual"] < tol and ia["iters"] < T
+        t = ia["iters"]
+        ref = (oracle.mapi if meth == "mapi" else oracle.rpi)(Aref.astype(np.float64), w0h.astype(np.float64), t)
+        e = rel_l1(wa.cpu().numpy(), ref.w)
+        assert e <= TOL
+        # |r_gpu - r_oracle| <= ||w_t err||_1 + ||w_{t-1} err||_1 (triangle inequality); the
+        # iterate error measured at t, with a factor 4 for the previous iterate and slack
+        bound = 4 * e * np.abs(ref.w).sum() + 1e-3 * ref.residuals[-1] + 1e-9
+        assert abs(ia["residual"] - ref.residuals[-1]) <= bound
+        if tol > 0.0:
+            stop = (oracle.mapi if meth == "mapi" else oracle.rpi)(Aref.astype(np.float64), w0h.astype(np.float64),
+                                                                    T, tol=tol)
+            assert abs(stop.iters - t) <= 2
+
+
+@pytest.mark.parametrize("n", [512, 1024, 4096])
+@pytest.mark.parametrize("meth", ["mapi", "rpi"])
+def test_stop_rule_in_the_product_exact_residuals(meth, n):
+    # A constant positive matrix and a positive start: the first iterate is the constant vector
+    # (1/n for MAPI, 1/sqrt(n) for RPI, exact for these n) and every later residual is exactly
+    # 0.  So the stop iteration of each rule is known exactly: a zero tolerance never converges;
+    # tol 1e-300 stops at iteration 2; the stall rule with k = 3 stops at 2 + 3 = 5 (iteration 2
+    # sets the smallest residual, 0, and three iterations do not beat it).  The lagged decision
+    # is taken by the next product (T > t + 1), by the last normalisation (T = t + 1) or not at
+    # all (T <= t).
+    print(f"[case] exact stop rule {meth} n={n}", flush=True)
+    A = to_dev(np.full((n, n), 0.7, np.float32))
+    w0h = np.random.default_rng(n).uniform(0.1, 1.0, n).astype(np.float32)
+    w0 = to_dev(w0h)
+    fn = mp.mapi_solve if meth == "mapi" else mp.rpi_solve
+    const = 1.0 / n if meth == "mapi" else 1.0 / np.sqrt(n)
+    fused, pair = _pair_shapes("f32")
+    cases = [  # T, tol, stall -> iters, converged
+        (7, 0.0, 0, 7, False), (9, 1e-300, 0, 2, True), (2, 1e-300, 0, 2, True), (3, 1e-300, 0, 2, True),
+        (1, 1e-300, 0, 1, False), (12, 0.0, 3, 5, False), (5, 0.0, 3, 5, False), (6, 0.0, 3, 5, False),
+        (4, 0.0, 3, 4, False)]
+    for shape in fused + [pair]:
+        mp.mapi_tuning_set(mp.MAPI_F32, n, n, shape)
+        for T, tol, stall, iters, conv in cases:
+            w, info = fn(A, w0, max_iters=T, tol=tol, stall_iters=stall, check_every=1 + T % 3)
+            assert info["iters"] == iters and info["converged"] == conv, (shape, T, tol, stall, info)
+            if iters >= 2:
+                assert info["residual"] == 0.0
+                np.testing.assert_array_equal(w.cpu().numpy(), np.full(n, const, np.float32))
+            ref = (oracle.mapi if meth == "mapi" else oracle.rpi)(np.full((n, n), np.float32(0.7), np.float64),
+                                                                    w0h.astype(np.float64), iters)
+            assert rel_l1(w.cpu().numpy(), ref.w) <= TOL
+            assert info["norm"] == pytest.approx(ref.norms[-1], rel=1e-6)
 
 
 def test_degenerate_normaliser_in_the_product_is_reported():

@@ -117,3 +117,30 @@ def test_full_size_gram_sampled_entries():
     P = P.cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(P.T @ P, np.eye(8), atol=1e-6)
     assert all(i["iters"] == 50 for i in infos)
+
+
+@pytest.mark.parametrize("method", ["mapi", "rpi"])
+def test_full_size_pca_top8_matches_oracle_on_the_gpu_built_matrix(method):
+    # the PCA workload (D = 4096, N = 65536, top 8, device-generated data) with a tolerance of
+    # 1e-6 and at most 30 iterations per vector; the FP64 oracle runs the deflation chain on the
+    # same matrix (the GPU build, promoted) for each vector's GPU iteration count
+    D, N, k = 4096, 65536, 8
+    print(f"[case] full PCA top-8 {method}: generate", flush=True)
+    X, _ = synth.pca_data_device(D, N, seed=77, device="cuda")
+    op = "min1" if method == "mapi" else "dot"
+    A = mp.mapi_mingram(X, 1.0 / N, op).cpu().numpy().astype(np.float64)
+    W0 = synth.start_vectors(D, k, seed=78)
+    print(f"[case] full PCA top-8 {method}: GPU", flush=True)
+    P, infos = mp.mapi_pca_topk(X, k, to_dev(W0), method=method, max_iters=30, tol=1e-6, check_every=4)
+    del X
+    P = P.cpu().numpy().astype(np.float64)
+    counts = [i["iters"] for i in infos]
+    print(f"[case] full PCA top-8 {method}: oracle at iterations {counts}", flush=True)
+    Pr, res = oracle.pca_topk(np.zeros((D, 1), np.float32), k, W0, method=method, T=counts, A=A)
+    for i in range(k):
+        assert res[i].iters == counts[i]
+        e, c = report(f"full pca {method} vector {i} ({counts[i]} iterations)", P[:, i], Pr[:, i])
+        assert e <= TOL and c > 1 - 1e-6
+        if infos[i]["converged"]:
+            assert res[i].residuals[-1] < 2e-6       # the oracle's residual at the GPU's stop
+    np.testing.assert_allclose(P.T @ P, np.eye(k), atol=1e-6)
