@@ -59,7 +59,7 @@ def kernel_source_hash():
 
 def csr_source_hash():
     h = hashlib.sha256()
-    for f in ("ops.h", "k_csr.hip"):
+    for f in ("ops.h", "k_csr.hip", "k_csr_split.hip"):
         with open(os.path.join(ROOT, "paper_2110_12065_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -145,10 +145,14 @@ def run_kernels_mode():
         for _ in range(5):
             mp.mapi_mavp(A, w0, "min1", row_scale=rs, ctx=ctx)
     del src, dst
-    # three MAPI PageRank products on the 2^22-node graph
+    # three MAPI PageRank products on the 2^22-node graph: the column-split product (the default
+    # at this size), then the plain CSR product
     g = _graph(PR_N, PR_SEED)
     rp, col, val = (torch.from_numpy(g[x]).cuda() for x in ("row_ptr", "col", "val"))
     mp.mapi_pagerank(rp, col, val, 0.85, "mapi", max_iters=3, check_every=3, ctx=ctx)
+    plain = mp.Context()
+    mp.mapi_pagerank_split_config(0, ctx=plain)
+    mp.mapi_pagerank(rp, col, val, 0.85, "mapi", max_iters=3, check_every=3, ctx=plain)
     torch.cuda.synchronize()
     log("kernels mode done")
 
@@ -168,7 +172,11 @@ def _kernel_dtype(name):
     if "k_read16" in name:
         return "read"
     if "k_csr_product<0," in name:
-        return "csr"
+        return "csr_plain"
+    if "k_csr_split_product<0," in name:
+        return "csr_split"
+    if "k_csr_split_combine<0," in name:
+        return "csr_combine"
     if "k_mavp_dense" not in name:
         return None
     # template argument order: storage type, product, ... (0 = f32, 1 = bf16, 2 = fp8)
@@ -328,17 +336,27 @@ def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write, 
     if "copy" in fetch:
         md.append(f"| copy reference | {fetch['copy']:.0f} | {write.get('copy', 0):.0f} | "
                   f"{2 * copy_bytes:.4e} | {2 * copy_bytes:.4e} | 1.000 |")
-    if "csr" in fetch and "csr" in write and f_scale is not None and w_scale is not None:
+    parts = ("csr_split", "csr_combine")
+    if all(k in fetch and k in write for k in parts) and f_scale is not None and w_scale is not None:
         nnz = int(_graph(PR_N, PR_SEED)["col"].size)
-        b = fetch["csr"] * 1024.0 * f_scale + write["csr"] * 1024.0 * w_scale
         alg = csr_bytes(PR_N, nnz)
-        out["csr"] = {"source_sha256_16": csr_source_hash(), "n": PR_N, "nnz": nnz, "fetch_kib": fetch["csr"],
-                      "write_kib": write["csr"], "bytes_per_launch": b, "algorithmic_bytes_per_launch": alg}
-        md += ["", f"PageRank MAPI product (`k_csr_product`, n = 2^22, {nnz} links; algorithmic bytes = 8 per link "
-                   "+ 4 per row pointer + 8 per node for w and y):", "",
+        per = {k: fetch[k] * 1024.0 * f_scale + write[k] * 1024.0 * w_scale for k in parts + ("csr_plain",)
+               if k in fetch and k in write}
+        b = per["csr_split"] + per["csr_combine"]
+        out["csr"] = {"source_sha256_16": csr_source_hash(), "n": PR_N, "nnz": nnz,
+                      "fetch_kib": {k: fetch[k] for k in per}, "write_kib": {k: write[k] for k in per},
+                      "bytes_per_launch": b, "bytes_per_kernel": per, "algorithmic_bytes_per_launch": alg}
+        md += ["", f"PageRank MAPI product at n = 2^22 ({nnz} links; algorithmic bytes = 8 per link + 4 per row "
+                   "pointer + 8 per node for w and y). One product is the column-split kernel plus its combine "
+                   "kernel (the default at this size); the plain CSR product is measured beside it:", "",
                "| kernel | FETCH KiB | WRITE KiB | scaled HBM-side bytes | algorithmic bytes | ratio |",
-               "|---|---|---|---|---|---|",
-               f"| csr MAPI | {fetch['csr']:.0f} | {write['csr']:.0f} | {b:.4e} | {alg:.4e} | {b / alg:.3f} |"]
+               "|---|---|---|---|---|---|"]
+        names = {"csr_split": "`k_csr_split_product`", "csr_combine": "`k_csr_split_combine`",
+                 "csr_plain": "`k_csr_product` (plain)"}
+        for k, v in per.items():
+            md.append(f"| {names[k]} | {fetch[k]:.0f} | {write[k]:.0f} | {v:.4e} | "
+                      f"{alg if k != 'csr_combine' else 0:.4e} | {v / alg:.3f} |")
+        md.append(f"| split product + combine | | | {b:.4e} | {alg:.4e} | {b / alg:.3f} |")
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
     with open(os.path.join(ROOT, "profiles", "mavp_dense_n16384_traffic.md"), "w") as f:
@@ -517,8 +535,8 @@ def bench_minibatch(mp, ctx, torch, N=10 ** 6, D=10, s=1000, T=100, runs=256, se
 
 def bench_image(mp, ctx, torch, D=128, N=10, seed=1):
     """Algorithm 2 at the Sec. 3.1 sizes: a synthetic 128 x 128 image, N = 10 copies with 3 of 16
-    tiles replaced by U[0,1] noise; MAPI (min1) and RPI, each vector to an l1 change < 1e-6 (stall
-    rule).  Reports the wall time of the whole pipeline (min-covariance of 16384 pixels, two solves,
+    tiles replaced by U[0,1] noise; MAPI with the min1 product (eq. 3), MAPI with the min2 product
+    (eq. 4; Table 1's min2-PI column) and RPI, each vector to an l1 change < 1e-6 (stall rule).  Reports the wall time of the whole pipeline (min-covariance of 16384 pixels, two solves,
     the deflation, the reconstruction) and the mean PSNR of the N reconstructions and of the inputs."""
     import synth
     clean, V = synth.occluded_images(D, N, seed)
@@ -531,19 +549,19 @@ def bench_image(mp, ctx, torch, D=128, N=10, seed=1):
         return 10.0 * np.log10(1.0 / mse)
 
     out = {"D": D, "N": N, "pixels": D * D, "inputs_psnr_db": float(np.mean([psnr(Vd[:, i]) for i in range(N)]))}
-    for meth in ("mapi", "rpi"):
+    for tag, meth, op in (("mapi", "mapi", "min1"), ("mapi_min2", "mapi", "min2"), ("rpi", "rpi", "min1")):
         run = lambda: mp.mapi_image_reconstruct(Vd, w0, meth, max_iters=500, tol=1e-6, check_every=8,
-                                               stall_iters=STALL, ctx=ctx)
+                                               stall_iters=STALL, op=op, ctx=ctx)
         run()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         R, W, infos = run()
         torch.cuda.synchronize()
-        out[f"{meth}_ms"] = (time.perf_counter() - t0) * 1e3
-        out[f"{meth}_iters"] = [i["iters"] for i in infos]
-        out[f"{meth}_psnr_db"] = float(np.mean([psnr(R[:, i]) for i in range(N)]))
-        log(f"image {meth}: {out[f'{meth}_ms']:.1f} ms, iterations {out[f'{meth}_iters']}, "
-            f"PSNR {out[f'{meth}_psnr_db']:.2f} dB (inputs {out['inputs_psnr_db']:.2f} dB)")
+        out[f"{tag}_ms"] = (time.perf_counter() - t0) * 1e3
+        out[f"{tag}_iters"] = [i["iters"] for i in infos]
+        out[f"{tag}_psnr_db"] = float(np.mean([psnr(R[:, i]) for i in range(N)]))
+        log(f"image {tag}: {out[f'{tag}_ms']:.1f} ms, iterations {out[f'{tag}_iters']}, "
+            f"PSNR {out[f'{tag}_psnr_db']:.2f} dB (inputs {out['inputs_psnr_db']:.2f} dB)")
     return out
 
 
@@ -683,6 +701,42 @@ def bench_pagerank(mp, ctx, torch, n=1 << 22, seed=2022):
                                                    & set(top_r.tolist()))
     log(f"PageRank float64 iterate: {out['mapi_f64_csr_kernel_us']:.0f} us per product, top-100 overlap "
         f"{out['mapi_f64_top100_overlap_vs_oracle']} (float32: {out['mapi_top100_overlap_vs_oracle']})")
+    # the plain CSR product on the same graph (no column split), per product
+    plain = mp.Context()
+    mp.mapi_pagerank_split_config(0, ctx=plain)
+    for meth in ("mapi", "rpi"):
+        mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=2, ctx=plain)
+        plain.timing(True)
+        plain.timing_reset()
+        mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=10, ctx=plain)
+        ms, launches = plain.timing_get("csr")
+        plain.timing(False)
+        out[f"{meth}_plain_csr_kernel_us"] = ms / max(launches, 1) * 1e3
+    log(f"PageRank products: split {out['mapi_csr_kernel_us']:.0f} us (MAPI) / {out['rpi_csr_kernel_us']:.0f} us "
+        f"(RPI), plain {out['mapi_plain_csr_kernel_us']:.0f} / {out['rpi_plain_csr_kernel_us']:.0f} us")
+    plain.close()
+    # Sec. 3.3's comparison at the 1e-8 stop, with the float64 iterate (the float32 iterate's
+    # floor, about 5e-8 in l1 at this n, stops RPI short of it): iterations and time to an l1
+    # change below 1e-8, MAPI against RPI
+    for meth in ("mapi", "rpi"):
+        mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=2, f64=True, ctx=ctx)
+        ctx.timing(True)
+        ctx.timing_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, inf = mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=500, tol=1e-8, check_every=4, f64=True,
+                                  ctx=ctx)
+        torch.cuda.synchronize()
+        s = time.perf_counter() - t0
+        ms, launches = ctx.timing_get("csr")
+        ctx.timing(False)
+        out[f"{meth}_f64_to_1e-8_iters"] = inf["iters"]
+        out[f"{meth}_f64_to_1e-8_converged"] = inf["converged"]
+        out[f"{meth}_f64_to_1e-8_residual"] = inf["residual"]
+        out[f"{meth}_f64_to_1e-8_ms"] = s * 1e3
+        out[f"{meth}_f64_csr_kernel_us_1e-8_run"] = ms / max(launches, 1) * 1e3
+        log(f"PageRank float64 {meth} to 1e-8: {inf['iters']} iterations, converged {inf['converged']}, "
+            f"{s * 1e3:.1f} ms")
     # counter bytes of the MAPI product (FETCH_SIZE + WRITE_SIZE, scaled; the gathers of w are
     # counted as the L2 fills they cause)
     out["mapi_csr_traffic_bytes"] = traffic
@@ -810,11 +864,11 @@ def bench_oracle():
     return out
 
 
-def bench_serving(mp, torch, n_req=20000, rate=2000.0, seed=11, budget=64 << 30, plain_sample=400, n_sat=8000):
+def bench_serving(mp, torch, n_req=20000, rate=2000.0, seed=11, budget=64 << 30, n_sat=8000):
     """Poisson arrivals; 70 % dense generated problems (n log-uniform 64..8192, BF16/F32, MAPI/RPI),
     30 % PageRank on power-law graphs with 2^10..2^20 nodes (a resident pool of 11 graphs, one per
     power of two, in pinned host memory), tolerance 1e-6 each; compared with the one-at-a-time
-    plain path (FIFO, float32) whose latencies are simulated from measured service times."""
+    plain path (FIFO, float32) run on the same arrivals."""
     import synth
     rng = np.random.default_rng(seed)
     log("serving: building the graph pool")
@@ -879,15 +933,17 @@ def bench_serving(mp, torch, n_req=20000, rate=2000.0, seed=11, budget=64 << 30,
     out["saturated_p99_ms"] = st["p99_ms"]
     out["saturated_kernel_launches"] = st["kernel_launches"]
     out["saturated_peak_pool_bytes"] = st["peak_bytes"]
-    # one-at-a-time plain path on a sample: float32, one solve after another on one stream
-    log(f"serving: timing the one-at-a-time path on {plain_sample} requests")
+    # the one-at-a-time plain path on the same arrival process: float32, FIFO, one solve after
+    # another on one stream, each request started at its arrival time or when the previous one
+    # is done; latency from arrival to the result in host memory
+    log(f"serving: one-at-a-time path on the same {n_req} arrivals")
     ctx = mp.Context()
-    idx = rng.choice(n_req, size=min(plain_sample, n_req), replace=False)
-    service = []
-    for i in idx:
-        kind, n, dt, meth, s = reqs[i]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+    lat = np.empty(n_req)
+    t_start = time.perf_counter()
+    for i, (kind, n, dt, meth, s) in enumerate(reqs):
+        wait = arrivals[i] - (time.perf_counter() - t_start)
+        if wait > 0:
+            time.sleep(wait)
         if kind == "gen":
             A, w0 = mp.mapi_generate_dense(n, s, ctx=ctx)
             fn = mp.mapi_solve if meth == "mapi" else mp.rpi_solve
@@ -898,23 +954,14 @@ def bench_serving(mp, torch, n_req=20000, rate=2000.0, seed=11, budget=64 << 30,
             w, _ = mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=1000, tol=1e-6, check_every=4,
                                     stall_iters=STALL, ctx=ctx)
         w.cpu()
-        service.append(time.perf_counter() - t0)
-        if len(service) % 100 == 0:
-            log(f"serving: one-at-a-time {len(service)} done")
+        lat[i] = (time.perf_counter() - t_start) - arrivals[i]
+        if i % 2000 == 0:
+            log(f"serving: one-at-a-time {i} done")
+    total = time.perf_counter() - t_start
     ctx.close()
-    service = np.array(service)
-    # FIFO single server fed by the same arrival process, service times drawn from the sample
-    draws = service[rng.integers(0, service.size, n_req)]
-    free = 0.0
-    lat = np.empty(n_req)
-    for i in range(n_req):
-        start = max(arrivals[i], free)
-        free = start + draws[i]
-        lat[i] = free - arrivals[i]
-    out["plain_f32_solves_s"] = 1.0 / float(service.mean())
-    out["plain_f32_p50_ms_simulated"] = float(np.percentile(lat, 50) * 1e3)
-    out["plain_f32_p99_ms_simulated"] = float(np.percentile(lat, 99) * 1e3)
-    out["plain_sample"] = int(service.size)
+    out["plain_f32_solves_s"] = n_req / (total - float(arrivals[0]))
+    out["plain_f32_p50_ms"] = float(np.percentile(lat, 50) * 1e3)
+    out["plain_f32_p99_ms"] = float(np.percentile(lat, 99) * 1e3)
     return out
 
 

@@ -18,9 +18,13 @@
  *  - Errors are returned as mapi_status; mapi_last_error() gives a message for
  *    the calling thread.  No C++ exception crosses this boundary.  Not reaching
  *    the tolerance is not an error: it is reported as converged = 0.
- *  - The context allocates its own device workspace (iteration buffers, partial
- *    sums) on first use and keeps it until mapi_destroy.  One context must not
- *    be used from two threads at once.
+ *  - Device workspace (iteration buffers, partial sums, built matrices): by
+ *    default the context allocates it on first use and keeps it until
+ *    mapi_destroy.  A caller that owns its device memory (a torch tensor, say)
+ *    gives the context one region with mapi_set_workspace, sized by
+ *    mapi_workspace_size; every call then takes its buffers from that region
+ *    and allocates no device memory (mapi_serve_* excepted: a server owns its
+ *    pool).  One context must not be used from two threads at once.
  */
 #ifndef MAPI_H
 #define MAPI_H
@@ -112,6 +116,45 @@ mapi_status mapi_set_stream(mapi_ctx* ctx, void* hip_stream);
 const char* mapi_last_error(void);
 /* Library version string. */
 const char* mapi_version(void);
+
+/* ---------------------------------------------------------------- workspace */
+
+/* What a call keeps in device memory besides the caller's inputs and outputs,
+ * sized by mapi_workspace_size(ctx, kind, n, nnz, &bytes); n and nnz per kind: */
+typedef enum mapi_ws_kind {
+  MAPI_WS_SOLVE = 0,         /* mapi_solve, rpi_solve: n = matrix order            */
+  MAPI_WS_HYBRID = 1,        /* mapi_hybrid_solve: n = matrix order                */
+  MAPI_WS_PAGERANK = 2,      /* mapi_pagerank: n = nodes, nnz = links              */
+  MAPI_WS_PAGERANK_F64 = 3,  /* mapi_pagerank_f64: n = nodes, nnz = links          */
+  MAPI_WS_PRODUCT = 4,       /* mapi_mavp, mapi_mavp_timed, mapi_autotune_dense,
+                                mapi_read_reference: n = rows, nnz = columns      */
+  MAPI_WS_MINGRAM = 5,       /* mapi_mingram: n = D, nnz = N samples               */
+  MAPI_WS_PCA = 6,           /* mapi_pca_topk with k = 1: n = D, nnz = N samples;
+                                each further vector adds MAPI_WS_PCA_VECTOR        */
+  MAPI_WS_PCA_VECTOR = 7,    /* bytes per principal vector: n = D                  */
+  MAPI_WS_IMAGE = 8,         /* mapi_image_reconstruct: n = P pixels, nnz = N images */
+  MAPI_WS_MINIBATCH = 9,     /* mapi_minibatch as the context would run it: n = D,
+                                nnz = runs (batch matrices of up to 256 MiB)      */
+  MAPI_WS_MINIBATCH_MIN = 10 /* mapi_minibatch's least workspace (batch matrices of
+                                one step of t per launch): n = D, nnz = runs      */
+} mapi_ws_kind;
+
+/* Bytes of caller workspace that any call of `kind` at that size needs (an upper
+ * bound over launch shapes and products).  Host-only arithmetic, no device work;
+ * MAPI_ERR_ARG for an unknown kind or sizes out of range.  Sizes depend on the
+ * context's device (its compute-unit count).                                    */
+mapi_status mapi_workspace_size(const mapi_ctx* ctx, int32_t kind, int64_t n, int64_t nnz, size_t* bytes);
+
+/* Give the context a device region (on its device, 256-byte aligned, owned by the
+ * caller and kept alive and unused by others while set) for all its calls: they
+ * carve their buffers from its start and allocate no device memory.  A call that
+ * needs more than `bytes` fails with MAPI_ERR_ARG before any device work
+ * (mapi_minibatch builds fewer steps of batch matrices per launch to fit, down to
+ * MAPI_WS_MINIBATCH_MIN).  Calls are blocking, so one region serves them in turn;
+ * its contents are not kept between calls.  dev_ptr NULL (bytes 0) returns to
+ * context-owned memory.  Synchronises the context stream and frees the device
+ * memory the context had allocated for itself.                                  */
+mapi_status mapi_set_workspace(mapi_ctx* ctx, void* dev_ptr, size_t bytes);
 
 /* Kernel timing: when enabled, every launch of the kind below is bracketed by
  * HIP events on the context stream; mapi_timing_get returns the summed
@@ -220,21 +263,23 @@ mapi_status mapi_hybrid_solve(mapi_ctx* ctx, const mapi_dense* A, const float* w
 
 /* Image reconstruction via MAPI (Algorithm 2, Sec. 3.1) from N corrupted copies
  * of one image: V (device float32, P x N, row pitch ldv >= N) holds the P pixels
- * of copy i in column i.  m = mean of the columns; Vc = V - m;
- *   C  = (1/(N-1)) Vc (+) Vc^T                 (line 4, min1; RPI: Vc Vc^T / (N-1))
+ * of copy i in column i.  m = mean of the columns; Vc = V - m; (+) is opts->op,
+ * min1 (eq. 3) or min2 (eq. 4, Table 1's min2-PI), in every step:
+ *   C  = (1/(N-1)) Vc (+) Vc^T                 (line 4; RPI: Vc Vc^T / (N-1))
  *   w1 = MAPI on C                              (line 5; RPI: eq. 1)
  *   w2 = MAPI on C - (w1 (+) w1^T) C            (line 6; RPI: C - w1 w1^T C)
  *   R  = (W (+) W^T) Vc + m, W = [w1 w2]         (line 8; RPI: W W^T Vc + m)
  * Both solves start from w0 (device, P, 16-byte aligned) and follow opts
- * (max_iters, tol, check_every, stall_iters; op must be MAPI_OP_MIN1 for MAPI;
- * final_l2 is ignored).  MAPI vectors are returned as Algorithm 1 leaves them,
+ * (max_iters, tol, check_every, stall_iters; op MAPI_OP_MIN1 or MAPI_OP_MIN2 for
+ * MAPI, else MAPI_ERR_UNSUPPORTED; final_l2 is ignored).  MAPI vectors are returned as Algorithm 1 leaves them,
  * with unit l1 norm -- the unit of the operator (w (+) w = ||w||_1, Sec. 2.1), so
  * that w (+) w^T acts on w as w w^T does for an l2 unit vector; RPI vectors have
  * unit l2 norm.  R: device P x N (pitch ldr >= N),
  * the N reconstructions; W: device P x 2 (w1 at W, w2 at W + P).  info2: host,
  * 2 entries (optional).  The min-outer deflation is computed exactly in O(P^2)
- * by prefix sums over C's rows in the order of |w1| (no P^3 product).  2 <= N <=
- * 16, P <= 32768; the context keeps 2 P^2 floats of workspace.                  */
+ * by prefix sums over C's rows in the order of |w1| (no P^3 product; for min2
+ * kept separately over the rows of each sign of w1).  2 <= N <=
+ * 16, P <= 32768; about 2 P^2 floats of workspace (MAPI_WS_IMAGE).              */
 mapi_status mapi_image_reconstruct(mapi_ctx* ctx, const float* V, int64_t P, int32_t N, int64_t ldv, int32_t method,
                                    const float* w0, const mapi_opts* opts, float* R, int64_t ldr, float* W,
                                    mapi_info* info2);
@@ -259,7 +304,7 @@ mapi_status mapi_image_reconstruct(mapi_ctx* ctx, const float* V, int64_t P, int
  * entries): iterations run, last nu, status; a zero or non-finite nu stops that
  * run with MAPI_ERR_DEGENERATE (also returned).  The batch matrices do not depend
  * on the iterate and are built ahead for a range of t at a time, stored float32
- * in context device memory (at most 256 MiB, plus 528 bytes per run).          */
+ * in workspace (at most 256 MiB, plus 528 bytes per run; MAPI_WS_MINIBATCH).   */
 mapi_status mapi_minibatch(mapi_ctx* ctx, const float* X, int64_t N, int64_t D, int64_t ldx, const int32_t* batch_idx,
                            int32_t s, int32_t T, double beta, int32_t op, int32_t runs, const float* w0, float* w_out,
                            int32_t final_l2, mapi_info* infos);
@@ -286,9 +331,9 @@ mapi_status mapi_quantize(mapi_ctx* ctx, const float* A, int64_t n_rows, int64_t
  * runs of 256 samples and in float64 across runs; A is rounded to float32 once.
  * A_out: D x D float32, leading dimension lda; the full matrix is written.  The
  * build may split the samples into up to 8 (DOT) or 16 (MIN1, MIN2) chunks (a
- * function of D, N and op only) whose float64 partial tiles live in context
- * device memory: at most 16 * T (T + 1) / 2 * 128 KiB, T = ceil(D / 128)
- * (1.1 GB at D = 4096), kept until mapi_destroy.                               */
+ * function of D, N and op only) whose float64 partial tiles live in workspace
+ * (MAPI_WS_MINGRAM): at most 16 * T (T + 1) / 2 * 128 KiB, T = ceil(D / 128)
+ * (1.1 GB at D = 4096).                                                         */
 mapi_status mapi_mingram(mapi_ctx* ctx, const float* X, int64_t D, int64_t N, int64_t ldx,
                          double scale, int32_t op, float* A_out, int64_t lda);
 
@@ -298,8 +343,9 @@ mapi_status mapi_mingram(mapi_ctx* ctx, const float* X, int64_t D, int64_t N, in
  * Vector i is extracted from (I - P P^T) A, P the l2-normalised earlier vectors,
  * orthonormalised by modified Gram-Schmidt in float64, starting from column i of
  * W0.  W0, P_out: device float, D x k, column-major (column i at offset i*D).
- * info_k: host array of k infos.  The built and deflated matrices (2 D^2 floats)
- * and the Gram build's partial tiles (mapi_mingram) are context device memory.  */
+ * info_k: host array of k infos.  The built and deflated matrices (2 D^2 floats),
+ * the Gram build's partial tiles (mapi_mingram) and the float64 basis are
+ * workspace (MAPI_WS_PCA + (k - 1) MAPI_WS_PCA_VECTOR).                         */
 mapi_status mapi_pca_topk(mapi_ctx* ctx, const float* X, int64_t D, int64_t N, int64_t ldx,
                           int32_t k, double scale, int32_t method, const float* W0,
                           float* P_out, const mapi_opts* opts, mapi_info* info_k);
@@ -312,6 +358,16 @@ mapi_status mapi_pca_topk(mapi_ctx* ctx, const float* X, int64_t D, int64_t N, i
  * normaliser.  alpha in (0, 1).  w0: device float[n], or NULL for 1/n.         */
 mapi_status mapi_pagerank(mapi_ctx* ctx, const mapi_csr* H, double alpha, int32_t method,
                           const float* w0, float* w_out, const mapi_opts* opts, mapi_info* info);
+
+/* Layout of the PageRank product.  A graph with at least min_n nodes (default 2^20,
+ * whose iterate outgrows one XCD's L2) is copied once per solve into 8 column blocks
+ * of ceil(n / 8) sources, each block's links of every row contiguous (about 8 bytes
+ * per link plus 9 bytes per node per block of workspace, counted by MAPI_WS_PAGERANK);
+ * each product then gathers every block's iterate slice on one XCD, where it stays in
+ * L2, and adds the 8 per-block row sums in block order.  Smaller graphs, graphs with a
+ * row holding 255 or more links in one block, and min_n <= 0 use the plain CSR
+ * product.  The two differ only in the order of the float32 (float64) row sums.      */
+mapi_status mapi_pagerank_split_config(mapi_ctx* ctx, int64_t min_n);
 
 /* The same with a float64 iterate: w0 / w_out are device double[n], every term and
  * row sum is float64 (the float32 iterate resolves about 6e-8 of w ~ 1/n, while the
@@ -353,8 +409,14 @@ typedef struct mapi_problem {
  * kernel launched from a captured hipGraph; each instance's arithmetic (tile
  * shapes, reduction order) depends only on its own kind, storage and size, so
  * a result is the same alone and in any mix.  infos: host array of count.
- * The call allocates a device arena for the batch (kept by the context).       */
+ * The batch's device arena (instances, work queue, iterates, partials, generated
+ * matrices) comes from the caller's workspace when one is set, else the context
+ * allocates it and keeps it.                                                     */
 mapi_status mapi_solve_batched(mapi_ctx* ctx, int32_t count, const mapi_problem* probs, mapi_info* infos);
+/* Bytes of that arena for this list of problems (host arithmetic only; the
+ * problems are checked as mapi_solve_batched checks them).                        */
+mapi_status mapi_solve_batched_workspace_size(mapi_ctx* ctx, int32_t count, const mapi_problem* probs,
+                                              size_t* bytes);
 /* Persistent grid: compute units * blocks_per_cu blocks (1..8, default 4).      */
 mapi_status mapi_batched_config(mapi_ctx* ctx, int32_t blocks_per_cu);
 /* Product tile height (row split) used for dense instances of a storage type and

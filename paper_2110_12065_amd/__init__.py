@@ -21,6 +21,8 @@ MAPI_F32, MAPI_BF16, MAPI_FP8_E4M3 = 0, 1, 2
 OPS = {"min1": 0, "min2": 1, "diamond": 2, "dot": 3}
 METHODS = {"mapi": 0, "rpi": 1}
 KERNELS = {"mavp": 0, "finalize": 1, "gram": 2, "csr": 3, "deflate": 4, "batched": 5, "minibatch": 6}
+WORKSPACE = {"solve": 0, "hybrid": 1, "pagerank": 2, "pagerank_f64": 3, "product": 4, "mingram": 5, "pca": 6,
+             "pca_vector": 7, "image": 8, "minibatch": 9, "minibatch_min": 10}
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_ALLOC", 3: "ERR_HIP", 4: "ERR_DEGENERATE", 5: "ERR_BUDGET",
           6: "ERR_UNSUPPORTED", 7: "ERR_PENDING", 8: "ERR_TIMEOUT"}
 
@@ -73,6 +75,8 @@ _SIGS = {
     "mapi_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mapi_last_error": (C.c_char_p, []),
     "mapi_version": (C.c_char_p, []),
+    "mapi_workspace_size": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
+    "mapi_set_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "mapi_timing_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "mapi_timing_get": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "mapi_timing_reset": (C.c_int, [C.c_void_p]),
@@ -98,6 +102,7 @@ _SIGS = {
                                 C.POINTER(Opts), C.POINTER(Info)]),
     "mapi_pagerank_f64": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
                                     C.POINTER(Opts), C.POINTER(Info)]),
+    "mapi_pagerank_split_config": (C.c_int, [C.c_void_p, C.c_int64]),
     "mapi_hybrid_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts),
                                     C.POINTER(Opts), C.POINTER(Info), C.POINTER(Info)]),
     "mapi_image_reconstruct": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_int32,
@@ -144,6 +149,25 @@ class Context:
         h = C.c_void_p()
         _check(lib().mapi_create(self.device, C.c_void_p(self._stream), C.byref(h)))
         self.handle = h
+
+    # caller-owned device workspace --------------------------------------------
+    def workspace_size(self, kind, n, nnz=0):
+        """Bytes of workspace a call of `kind` (a WORKSPACE key) needs at size (n, nnz)."""
+        b = C.c_size_t()
+        _check(lib().mapi_workspace_size(self.handle, WORKSPACE[kind], int(n), int(nnz), C.byref(b)))
+        return b.value
+
+    def set_workspace(self, buf):
+        """Make every call of this context take its device buffers from `buf` (a device
+        tensor, kept alive here); None returns to context-owned memory."""
+        if buf is None:
+            _check(lib().mapi_set_workspace(self.handle, None, 0))
+            self._ws = None
+            return
+        if not buf.is_cuda or not buf.is_contiguous():
+            raise ValueError("the workspace must be a contiguous device tensor")
+        _check(lib().mapi_set_workspace(self.handle, C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+        self._ws = buf
 
     def sync_stream(self):
         import torch
@@ -295,9 +319,10 @@ def mapi_hybrid_solve(A, w0, mapi_iters=100, mapi_tol=0.0, rpi_iters=100, rpi_to
     return w_out, i1.as_dict(), i2.as_dict()
 
 
-def mapi_image_reconstruct(V, w0, method="mapi", max_iters=100, tol=0.0, check_every=0, stall_iters=0, ctx=None):
-    """Algorithm 2: V device float32 P x N (column i = corrupted copy i).  Returns (R P x N, W P x 2,
-    infos of the two solves)."""
+def mapi_image_reconstruct(V, w0, method="mapi", max_iters=100, tol=0.0, check_every=0, stall_iters=0, op="min1",
+                           ctx=None):
+    """Algorithm 2: V device float32 P x N (column i = corrupted copy i); op "min1" (eq. 3) or
+    "min2" (eq. 4) for MAPI.  Returns (R P x N, W P x 2, infos of the two solves)."""
     import torch
     c = _ctx_of(ctx, V)
     if V.dim() != 2 or V.dtype != torch.float32 or V.stride(1) != 1:
@@ -305,7 +330,7 @@ def mapi_image_reconstruct(V, w0, method="mapi", max_iters=100, tol=0.0, check_e
     P, N = V.shape
     R = torch.empty((P, N), dtype=torch.float32, device=V.device)
     W = torch.empty((2, P), dtype=torch.float32, device=V.device)
-    o = _opts(max_iters, tol, "min1", False, check_every, stall_iters)
+    o = _opts(max_iters, tol, op, False, check_every, stall_iters)
     infos = (Info * 2)()
     _check(lib().mapi_image_reconstruct(c.handle, C.c_void_p(V.data_ptr()), int(P), int(N), int(V.stride(0)),
                                         METHODS[method], C.c_void_p(_vec(w0, P, "w0")), C.byref(o),
@@ -422,6 +447,12 @@ def mapi_pagerank(row_ptr, col, val, alpha=0.85, method="mapi", w0=None, max_ite
     return w_out, info.as_dict()
 
 
+def mapi_pagerank_split_config(min_n, ctx=None):
+    """PageRank graphs with at least min_n nodes use the column-split product (min_n <= 0: never)."""
+    c = ctx if ctx is not None else default_context()
+    _check(lib().mapi_pagerank_split_config(c.handle, int(min_n)))
+
+
 # ------------------------------------------------------------------ launch shapes
 def mapi_autotune_dense(A, op="min1", reps=3, row_scale=None, ctx=None):
     """Time every launch shape of the dense product on A and keep the fastest for A's size bucket.
@@ -494,6 +525,8 @@ PROB_DENSE, PROB_CSR, PROB_GENERATED = 0, 1, 2
 
 _SIGS.update({
     "mapi_solve_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Problem), C.POINTER(Info)]),
+    "mapi_solve_batched_workspace_size": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Problem),
+                                                    C.POINTER(C.c_size_t)]),
     "mapi_batched_config": (C.c_int, [C.c_void_p, C.c_int32]),
     "mapi_batched_rows_set": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int32]),
     "mapi_batched_rows_get": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_int32)]),
@@ -575,6 +608,16 @@ def mapi_solve_batched(problems, ctx=None):
     if st not in (0, 4):
         _check(st)
     return res
+
+
+def mapi_solve_batched_workspace_size(problems, ctx=None):
+    """Bytes of the device arena mapi_solve_batched needs for this list of problems."""
+    c = ctx if ctx is not None else default_context()
+    k = len(problems)
+    arr = (Problem * k)(*problems)
+    b = C.c_size_t()
+    _check(lib().mapi_solve_batched_workspace_size(c.handle, k, arr, C.byref(b)))
+    return b.value
 
 
 def mapi_batched_config(blocks_per_cu, ctx=None):

@@ -1,5 +1,6 @@
 // C-ABI of libmapi: argument checks, device workspace, iteration drivers and
 // kernel timing.  Declarations and contracts are in include/mapi.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -141,9 +142,60 @@ void fill_info(mapi_info* info, const SolveState& s) {
   info->status = s.status;
 }
 
-// Power iteration on a dense square matrix: MAPI (op, l1) or RPI (dot, l2).
-mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* w_out, const mapi_opts* o,
-                      mapi_info* info, bool rpi) {
+}  // namespace
+
+namespace mapi {
+
+// Upper bound of the dense product kernel's block (partial) count for n rows: blocks
+// of at least 4 waves of at least one row each, at most 16 blocks per compute unit.
+int dense_part_bound(int64_t n, int cu_count) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + 3) / 4, (int64_t)cu_count * 16));
+}
+
+// Buffers of one dense solve, carved from one device region: the solve state, two sets
+// of product and residual partials, the normalisation partials, two iterates and two
+// products (a product that forms the previous iterate reads the other set).
+struct DenseBufs {
+  SolveState* st;
+  double* pp[2];
+  double* rp[2];
+  double* part;
+  float* wb[2];
+  float* yb[2];
+};
+
+// Bytes of that region for an n x n system (the layout does not depend on the launch
+// shape); with `base`, the buffers' addresses.
+size_t dense_layout(int64_t n, int cu_count, char* base, DenseBufs* b) {
+  const int P = dense_part_bound(n, cu_count);
+  const int F = finalize_blocks(n);
+  Layout L;
+  const size_t o_st = L.take(sizeof(SolveState));
+  const size_t o_pp = L.take(sizeof(double) * 2 * (size_t)P);
+  const size_t o_rp = L.take(sizeof(double) * 2 * (size_t)P);
+  const size_t o_part = L.take(sizeof(double) * 3 * (size_t)F);
+  const size_t o_w0 = L.take(sizeof(float) * n);
+  const size_t o_w1 = L.take(sizeof(float) * n);
+  const size_t o_y0 = L.take(sizeof(float) * n);
+  const size_t o_y1 = L.take(sizeof(float) * n);
+  if (base && b) {
+    b->st = reinterpret_cast<SolveState*>(base + o_st);
+    b->pp[0] = reinterpret_cast<double*>(base + o_pp);
+    b->pp[1] = b->pp[0] + P;
+    b->rp[0] = reinterpret_cast<double*>(base + o_rp);
+    b->rp[1] = b->rp[0] + P;
+    b->part = reinterpret_cast<double*>(base + o_part);
+    b->wb[0] = reinterpret_cast<float*>(base + o_w0);
+    b->wb[1] = reinterpret_cast<float*>(base + o_w1);
+    b->yb[0] = reinterpret_cast<float*>(base + o_y0);
+    b->yb[1] = reinterpret_cast<float*>(base + o_y1);
+  }
+  return L.off;
+}
+
+size_t dense_ws_bytes(int64_t n, int cu_count) { return dense_layout(n, cu_count, nullptr, nullptr); }
+
+mapi_status check_solve_args(const mapi_dense* A, const float* w0, const float* w_out, const mapi_opts* o, bool rpi) {
   mapi_status s;
   if ((s = check_dense(A, true)) != MAPI_OK) return s;
   if ((s = check_opts(o)) != MAPI_OK) return s;
@@ -151,14 +203,24 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
   const int op = rpi ? MAPI_OP_DOT : o->op;
   if (op < MAPI_OP_MIN1 || op > MAPI_OP_DOT || (!rpi && op == MAPI_OP_DOT))
     return fail(MAPI_ERR_ARG, "op %d is not a MAPI product", o->op);
+  return MAPI_OK;
+}
+
+// Power iteration on a dense square matrix: MAPI (op, l1) or RPI (dot, l2).  Arguments
+// checked by check_solve_args; ws: device region of dense_ws_bytes(n) bytes.
+mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* w_out, const mapi_opts* o,
+                      mapi_info* info, bool rpi, char* ws) {
+  mapi_status s;
+  const int op = rpi ? MAPI_OP_DOT : o->op;
   const int64_t n = A->n_rows;
   const int norm = rpi ? NORM_L2 : NORM_L1;
+  DenseBufs B;
+  dense_layout(n, c->cu_count, ws, &B);
+  SolveState* st = B.st;
   if (A->dtype == MAPI_F32 && small_solve_fits(n, op) && o->max_iters <= kSmallMaxIters &&
       !c->pinned.count(bucket(A->dtype, n, A->n_cols))) {
     // the whole solve in one launch: latency, not bandwidth, bounds this size (at most
     // kSmallMaxIters iterations, a fraction of a second, stay inside one kernel)
-    if ((s = ensure(&c->ws, &c->ws_bytes, sizeof(SolveState), c)) != MAPI_OK) return s;
-    SolveState* st = static_cast<SolveState*>(c->ws);
     HIP_TRY(launch_state_init(st, o->max_iters, o->tol, o->stall_iters, c->stream));
     {
       Timed tm(c, MAPI_K_MAVP);
@@ -174,30 +236,18 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
   const DenseArgs da = dense_args(A);
   const DenseTuning t = tuning_for(c, da);
   const int P = dense_part_count(da, t, c->cu_count);
-  const int F = finalize_blocks(n);
+  if (P > dense_part_bound(n, c->cu_count)) return fail(MAPI_ERR_ARG, "launch shape exceeds the partial bound");
   // With w staged in LDS, each product forms its own iterate from the previous y and
   // partials (FusedPrev), adds its share of the residual ||w_t - w_{t-1}||_1 to a
   // per-block partial, and advances the stop rule for the previous iteration: one
   // launch per iteration, the stop decision one launch late.  The last iteration is
   // normalised by the normalisation kernel.  Same arithmetic as the kernel pair.
   const bool fused = t.w_in_lds != 0;
-  Layout L;
-  const size_t o_st = L.take(sizeof(SolveState));
-  const size_t o_pp = L.take(sizeof(double) * 2 * (size_t)P);
-  const size_t o_rp = L.take(sizeof(double) * 2 * (size_t)P);
-  const size_t o_part = L.take(sizeof(double) * 3 * (size_t)F);
-  const size_t o_w0 = L.take(sizeof(float) * n);
-  const size_t o_w1 = L.take(sizeof(float) * n);
-  const size_t o_y0 = L.take(sizeof(float) * n);
-  const size_t o_y1 = L.take(sizeof(float) * n);
-  if ((s = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return s;
-  char* base = static_cast<char*>(c->ws);
-  SolveState* st = reinterpret_cast<SolveState*>(base + o_st);
-  double* pp[2] = {reinterpret_cast<double*>(base + o_pp), reinterpret_cast<double*>(base + o_pp) + P};
-  double* rp[2] = {reinterpret_cast<double*>(base + o_rp), reinterpret_cast<double*>(base + o_rp) + P};
-  double* part = reinterpret_cast<double*>(base + o_part);
-  float* wb[2] = {reinterpret_cast<float*>(base + o_w0), reinterpret_cast<float*>(base + o_w1)};
-  float* yb[2] = {reinterpret_cast<float*>(base + o_y0), reinterpret_cast<float*>(base + o_y1)};
+  double* const* pp = B.pp;
+  double* const* rp = B.rp;
+  double* part = B.part;
+  float* const* wb = B.wb;
+  float* const* yb = B.yb;
 
   HIP_TRY(hipMemcpyAsync(wb[0], w0, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(launch_state_init(st, o->max_iters, o->tol, o->stall_iters, c->stream));
@@ -240,7 +290,124 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
   return MAPI_OK;
 }
 
-}  // namespace
+size_t hybrid_ws_bytes(int64_t n, int cu_count) {
+  return align_up(sizeof(float) * (size_t)n) + dense_ws_bytes(n, cu_count);
+}
+
+// Largest float64 partial-tile store of the Gram build over the products it runs with.
+size_t gram_ws_max(int64_t D, int64_t N) {
+  return std::max(gram_workspace_bytes(D, N, MAPI_OP_MIN1), gram_workspace_bytes(D, N, MAPI_OP_DOT));
+}
+
+// Region of mapi_pca_topk: the built and deflated matrices, the deflation partials, the
+// current vector, the Gram build's partial tiles and a dense solve's buffers, then the
+// float64 basis P and its products Q = A P (D x k each) last, so that the size grows by
+// exactly 16 D bytes per vector.
+struct PcaLayout {
+  int64_t ldA;
+  size_t o_A, o_Ai, o_qp, o_w, o_g, o_d, o_PQ, total;
+};
+PcaLayout pca_layout(int64_t D, int64_t k, size_t gram_bytes, int cu_count) {
+  PcaLayout p;
+  p.ldA = (D + 3) / 4 * 4;
+  Layout L;
+  p.o_A = L.take(sizeof(float) * D * p.ldA);
+  p.o_Ai = L.take(sizeof(float) * D * p.ldA);
+  p.o_qp = L.take(sizeof(double) * D * deflate_qpart_count());
+  p.o_w = L.take(sizeof(float) * D);
+  p.o_g = L.take(gram_bytes);
+  p.o_d = L.take(dense_ws_bytes(D, cu_count));
+  p.o_PQ = L.off;
+  p.total = p.o_PQ + 2 * sizeof(double) * (size_t)D * (size_t)k;
+  return p;
+}
+
+// Region of mapi_image_reconstruct (P pixels, N images).
+struct ImageLayout {
+  int64_t ldA, ldc;
+  int G;
+  size_t o_C, o_C2, o_Vc, o_m, o_perm, o_sums, o_P, o_Q, o_qp, o_pf, o_g, o_d, total;
+};
+ImageLayout image_layout(int64_t P, int64_t N, size_t gram_bytes, int cu_count) {
+  ImageLayout l;
+  l.ldA = (P + 3) / 4 * 4;     // 16-byte rows for the product kernel
+  l.ldc = (N + 3) / 4 * 4;     // centred images, 16-byte rows for the Gram kernel
+  l.G = (int)std::min<int64_t>(64, P);
+  Layout L;
+  l.o_C = L.take(sizeof(float) * P * l.ldA);
+  l.o_C2 = L.take(sizeof(float) * P * l.ldA);
+  l.o_Vc = L.take(sizeof(float) * P * l.ldc);
+  l.o_m = L.take(sizeof(float) * P);
+  l.o_perm = L.take(sizeof(int32_t) * P);
+  l.o_sums = L.take(sizeof(double) * image_defl_sums_per_column() * (size_t)l.G * P);
+  l.o_P = L.take(sizeof(double) * P);
+  l.o_Q = L.take(sizeof(double) * P);
+  l.o_qp = L.take(sizeof(double) * P * deflate_qpart_count());
+  l.o_pf = L.take(sizeof(float) * P);
+  l.o_g = L.take(gram_bytes);
+  l.o_d = L.take(dense_ws_bytes(P, cu_count));
+  l.total = L.off;
+  return l;
+}
+
+// Whether a PageRank solve on n nodes with nnz links uses the column-split product.
+bool pagerank_split(const mapi_ctx* c, int64_t n, int64_t nnz) {
+  return c->csr_split_min_n > 0 && n >= c->csr_split_min_n && nnz > 0;
+}
+
+// Region of a PageRank solve with iterate type of `es` bytes, then the column-split
+// copy of the link matrix when the solve uses it.
+struct PrLayout {
+  int PP, P;
+  size_t o_st, o_pp, o_part, o_w0, o_w1, o_y, o_d, o_err, o_split, total;
+};
+PrLayout pagerank_layout(int64_t n, int64_t nnz, size_t es, bool split) {
+  PrLayout l;
+  const int F = finalize_blocks(n);
+  l.PP = std::max(csr_part_count(n), split_combine_blocks(n));
+  l.P = std::max(3 * F, 2 * pr_scalar_blocks(n));
+  Layout L;
+  l.o_st = L.take(sizeof(SolveState));
+  l.o_pp = L.take(sizeof(double) * l.PP);
+  l.o_part = L.take(sizeof(double) * l.P);
+  l.o_w0 = L.take(es * n);
+  l.o_w1 = L.take(es * n);
+  l.o_y = L.take(es * n);
+  l.o_d = L.take(n);
+  l.o_err = L.take(sizeof(int32_t));
+  l.o_split = L.take(split ? split_csr_bytes(n, nnz, es) : 0);
+  l.total = L.off;
+  return l;
+}
+
+// Region of mapi_minibatch: per-run records, the index-error flag, then the batch
+// matrices of `range` steps of t and the runs' states.
+size_t minibatch_bytes(int D, int range, int runs) {
+  Layout L;
+  L.take(sizeof(MbRun) * (size_t)runs);
+  L.take(sizeof(int32_t));
+  return L.off + minibatch_workspace_bytes(D, range, runs);
+}
+
+// Scratch of the single-product calls (mapi_mavp's aligned copy of w, the autotuner's
+// w and y, mapi_read_reference's sink).
+size_t product_ws_bytes(int64_t n_rows, int64_t n_cols) {
+  return align_up(sizeof(float) * (size_t)n_cols) + align_up(sizeof(float) * (size_t)n_rows);
+}
+
+// mapi_solve / rpi_solve: checks, then the solve in the context's (or the caller's) workspace.
+mapi_status solve_entry(mapi_ctx* c, const mapi_dense* A, const float* w0, float* w_out, const mapi_opts* o,
+                        mapi_info* info, bool rpi) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  mapi_status s;
+  if ((s = check_solve_args(A, w0, w_out, o, rpi)) != MAPI_OK) return s;
+  HIP_TRY(hipSetDevice(c->device));
+  char* ws = nullptr;
+  if ((s = acquire(c, &c->ws, &c->ws_bytes, dense_ws_bytes(A->n_rows, c->cu_count), &ws)) != MAPI_OK) return s;
+  return run_dense(c, A, w0, w_out, o, info, rpi, ws);
+}
+
+}  // namespace mapi
 
 namespace {
 
@@ -258,27 +425,17 @@ mapi_status pagerank_run(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t m
   if ((s = check_opts(o)) != MAPI_OK) return s;
   HIP_TRY(hipSetDevice(c->device));
   const int64_t n = H->n;
-  const int F = finalize_blocks(n);
-  const int PP = csr_part_count(n);
-  const int P = std::max(3 * F, 2 * pr_scalar_blocks(n));
-  Layout L;
-  const size_t o_st = L.take(sizeof(SolveState));
-  const size_t o_pp = L.take(sizeof(double) * PP);
-  const size_t o_part = L.take(sizeof(double) * P);
-  const size_t o_w0 = L.take(sizeof(T) * n);
-  const size_t o_w1 = L.take(sizeof(T) * n);
-  const size_t o_y = L.take(sizeof(T) * n);
-  const size_t o_d = L.take(n);
-  const size_t o_err = L.take(sizeof(int32_t));
-  if ((s = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return s;
-  char* base = static_cast<char*>(c->ws);
-  SolveState* st = reinterpret_cast<SolveState*>(base + o_st);
-  double* pprod = reinterpret_cast<double*>(base + o_pp);
-  double* part = reinterpret_cast<double*>(base + o_part);
-  T* wb[2] = {reinterpret_cast<T*>(base + o_w0), reinterpret_cast<T*>(base + o_w1)};
-  T* y = reinterpret_cast<T*>(base + o_y);
-  uint8_t* dangling = reinterpret_cast<uint8_t*>(base + o_d);
-  int32_t* err = reinterpret_cast<int32_t*>(base + o_err);
+  bool split = pagerank_split(c, n, H->nnz);
+  const PrLayout l = pagerank_layout(n, H->nnz, sizeof(T), split);
+  char* base = nullptr;
+  if ((s = acquire(c, &c->ws, &c->ws_bytes, l.total, &base)) != MAPI_OK) return s;
+  SolveState* st = reinterpret_cast<SolveState*>(base + l.o_st);
+  double* pprod = reinterpret_cast<double*>(base + l.o_pp);
+  double* part = reinterpret_cast<double*>(base + l.o_part);
+  T* wb[2] = {reinterpret_cast<T*>(base + l.o_w0), reinterpret_cast<T*>(base + l.o_w1)};
+  T* y = reinterpret_cast<T*>(base + l.o_y);
+  uint8_t* dangling = reinterpret_cast<uint8_t*>(base + l.o_d);
+  int32_t* err = reinterpret_cast<int32_t*>(base + l.o_err);
 
   HIP_TRY(hipMemsetAsync(err, 0, sizeof(int32_t), c->stream));
   HIP_TRY(launch_csr_prep(H->row_ptr, H->col, n, H->nnz, dangling, err, c->stream));
@@ -286,6 +443,20 @@ mapi_status pagerank_run(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t m
   HIP_TRY(hipMemcpyAsync(&err_h, err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (err_h) return fail(MAPI_ERR_ARG, "invalid CSR arrays (code %d)", err_h);
+  // the column-split copy of the validated matrix, unless a row has too many links in
+  // one block for its layout (then the plain product runs)
+  SplitCsr sp;
+  if (split) {
+    sp = split_csr_place(base + l.o_split, n, H->nnz, sizeof(T));
+    HIP_TRY(hipMemsetAsync(sp.flags, 0, sizeof(int32_t), c->stream));
+    HIP_TRY(launch_split_count(H->row_ptr, H->col, sp, c->stream));
+    int32_t flags_h = 0;
+    HIP_TRY(hipMemcpyAsync(&flags_h, sp.flags, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (flags_h) split = false;
+    else HIP_TRY(launch_split_fill(H->row_ptr, H->col, H->val, sp, c->stream));
+  }
+  const int PP = split ? split_combine_blocks(n) : csr_part_count(n);
 
   const double inv_n = 1.0 / (double)n;
   const double cc = (1.0 - alpha) * inv_n;
@@ -305,8 +476,11 @@ mapi_status pagerank_run(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t m
     T* wn = wb[(it & 1) ^ 1];
     {
       Timed tm(c, MAPI_K_CSR);
-      HIP_TRY(launch_csr_product<T>(method, H->row_ptr, H->col, H->val, n, wc, y, pprod, st, alpha, cc, inv_n,
-                                    c->stream));
+      if (split)
+        HIP_TRY(launch_csr_split_product<T>(method, sp, wc, y, pprod, st, alpha, cc, inv_n, c->stream));
+      else
+        HIP_TRY(launch_csr_product<T>(method, H->row_ptr, H->col, H->val, n, wc, y, pprod, st, alpha, cc, inv_n,
+                                      c->stream));
     }
     {
       Timed tm(c, MAPI_K_FINALIZE);
@@ -387,6 +561,80 @@ mapi_status mapi_set_stream(mapi_ctx* c, void* hip_stream) {
   return MAPI_OK;
 }
 
+mapi_status mapi_workspace_size(const mapi_ctx* c, int32_t kind, int64_t n, int64_t nnz, size_t* bytes) {
+  if (!c || !bytes) return fail(MAPI_ERR_ARG, "ctx and bytes are required");
+  *bytes = 0;
+  if (n <= 0 || n > INT32_MAX) return fail(MAPI_ERR_ARG, "n must be in [1, 2^31)");
+  const int cu = c->cu_count;
+  switch (kind) {
+    case MAPI_WS_SOLVE: *bytes = dense_ws_bytes(n, cu); break;
+    case MAPI_WS_HYBRID: *bytes = hybrid_ws_bytes(n, cu); break;
+    case MAPI_WS_PAGERANK:
+    case MAPI_WS_PAGERANK_F64:
+      if (nnz < 0 || nnz > INT32_MAX) return fail(MAPI_ERR_ARG, "nnz (the link count) must be in [0, 2^31)");
+      *bytes = pagerank_layout(n, nnz, kind == MAPI_WS_PAGERANK ? sizeof(float) : sizeof(double),
+                               pagerank_split(c, n, nnz)).total;
+      break;
+    case MAPI_WS_PRODUCT:
+      if (nnz <= 0) return fail(MAPI_ERR_ARG, "nnz (the column count) must be positive");
+      *bytes = product_ws_bytes(n, nnz);
+      break;
+    case MAPI_WS_MINGRAM:
+      if (nnz <= 0) return fail(MAPI_ERR_ARG, "nnz (the sample count N) must be positive");
+      *bytes = gram_ws_max(n, nnz);
+      break;
+    case MAPI_WS_PCA:
+      if (nnz <= 0) return fail(MAPI_ERR_ARG, "nnz (the sample count N) must be positive");
+      *bytes = pca_layout(n, 1, gram_ws_max(n, nnz), cu).total;
+      break;
+    case MAPI_WS_PCA_VECTOR: *bytes = 2 * sizeof(double) * (size_t)n; break;
+    case MAPI_WS_IMAGE:
+      if (nnz < 2) return fail(MAPI_ERR_ARG, "nnz (the image count N) must be at least 2");
+      *bytes = image_layout(n, nnz, gram_ws_max(n, nnz), cu).total;
+      break;
+    case MAPI_WS_MINIBATCH:
+      if (nnz <= 0 || nnz > INT32_MAX) return fail(MAPI_ERR_ARG, "nnz (the run count) must be positive");
+      if (n > minibatch_max_d()) return fail(MAPI_ERR_UNSUPPORTED, "D > %d", minibatch_max_d());
+      *bytes = minibatch_bytes((int)n, minibatch_range((int)n, INT32_MAX, (int)nnz), (int)nnz);
+      break;
+    case MAPI_WS_MINIBATCH_MIN:
+      if (nnz <= 0 || nnz > INT32_MAX) return fail(MAPI_ERR_ARG, "nnz (the run count) must be positive");
+      if (n > minibatch_max_d()) return fail(MAPI_ERR_UNSUPPORTED, "D > %d", minibatch_max_d());
+      *bytes = minibatch_bytes((int)n, 1, (int)nnz);
+      break;
+    default: return fail(MAPI_ERR_ARG, "unknown workspace kind %d", kind);
+  }
+  *bytes = align_up(*bytes);
+  return MAPI_OK;
+}
+
+mapi_status mapi_set_workspace(mapi_ctx* c, void* dev_ptr, size_t bytes) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  if (dev_ptr && (reinterpret_cast<uintptr_t>(dev_ptr) & 255u) != 0)
+    return fail(MAPI_ERR_ARG, "the workspace must be 256-byte aligned");
+  if (dev_ptr && bytes == 0) return fail(MAPI_ERR_ARG, "a workspace needs a non-zero size");
+  HIP_TRY(hipSetDevice(c->device));
+  // the previous workspace (the caller's or the context's own) may still be read by
+  // enqueued work; the context's own buffers are given back
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->side) HIP_TRY(hipStreamSynchronize(c->side));
+  for (auto* own : {&c->ws, &c->big, &c->mid, &c->gws}) {
+    if (*own) HIP_TRY(hipFree(*own));
+    *own = nullptr;
+  }
+  c->ws_bytes = c->big_bytes = c->mid_bytes = c->gws_bytes = 0;
+  mapi_batch_free_arena(c);
+  c->user_ws = static_cast<char*>(dev_ptr);
+  c->user_ws_bytes = dev_ptr ? bytes : 0;
+  return MAPI_OK;
+}
+
+mapi_status mapi_pagerank_split_config(mapi_ctx* c, int64_t min_n) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  c->csr_split_min_n = min_n > 0 ? min_n : 0;
+  return MAPI_OK;
+}
+
 mapi_status mapi_timing_enable(mapi_ctx* c, int enable) {
   if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
   c->timing = enable != 0;
@@ -426,9 +674,10 @@ mapi_status mapi_mavp(mapi_ctx* c, const mapi_dense* A, const float* w, float* y
   const DenseTuning t = tuning_for(c, da);
   const float* wv = w;
   if (!aligned16(w)) {
-    if ((s = ensure(&c->ws, &c->ws_bytes, sizeof(float) * (size_t)A->n_cols, c)) != MAPI_OK) return s;
-    HIP_TRY(hipMemcpyAsync(c->ws, w, sizeof(float) * A->n_cols, hipMemcpyDeviceToDevice, c->stream));
-    wv = static_cast<const float*>(c->ws);
+    char* base = nullptr;
+    if ((s = acquire(c, &c->ws, &c->ws_bytes, sizeof(float) * (size_t)A->n_cols, &base)) != MAPI_OK) return s;
+    HIP_TRY(hipMemcpyAsync(base, w, sizeof(float) * A->n_cols, hipMemcpyDeviceToDevice, c->stream));
+    wv = reinterpret_cast<const float*>(base);
   }
   {
     DenseArgs dl = da;
@@ -482,8 +731,9 @@ mapi_status mapi_read_reference(mapi_ctx* c, const void* src, size_t bytes, int3
   if (reps < 1) return fail(MAPI_ERR_ARG, "reps must be >= 1");
   HIP_TRY(hipSetDevice(c->device));
   mapi_status s;
-  if ((s = ensure(&c->ws, &c->ws_bytes, 256, c)) != MAPI_OK) return s;
-  uint32_t* sink = static_cast<uint32_t*>(c->ws);
+  char* base = nullptr;
+  if ((s = acquire(c, &c->ws, &c->ws_bytes, 256, &base)) != MAPI_OK) return s;
+  uint32_t* sink = reinterpret_cast<uint32_t*>(base);
   hipEvent_t a = get_event(c), b = get_event(c);
   if (!a || !b) return fail(MAPI_ERR_HIP, "event creation failed");
   HIP_TRY(launch_read16(src, (int64_t)(bytes / 16), sink, c->cu_count, c->stream));
@@ -508,12 +758,10 @@ mapi_status mapi_autotune_dense(mapi_ctx* c, const mapi_dense* A, int32_t op, in
   if (reps < 1) reps = 3;
   HIP_TRY(hipSetDevice(c->device));
   const DenseArgs da = dense_args(A);
-  Layout L;
-  const size_t o_w = L.take(sizeof(float) * da.n_cols);
-  const size_t o_y = L.take(sizeof(float) * da.n_rows);
-  if ((s = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return s;
-  float* w = reinterpret_cast<float*>(static_cast<char*>(c->ws) + o_w);
-  float* y = reinterpret_cast<float*>(static_cast<char*>(c->ws) + o_y);
+  char* base = nullptr;
+  if ((s = acquire(c, &c->ws, &c->ws_bytes, product_ws_bytes(da.n_rows, da.n_cols), &base)) != MAPI_OK) return s;
+  float* w = reinterpret_cast<float*>(base);
+  float* y = reinterpret_cast<float*>(base + align_up(sizeof(float) * (size_t)da.n_cols));
   HIP_TRY(launch_fill_f32(w, da.n_cols, 1.0f / (float)da.n_cols, c->stream));
   DenseTuning bt = dense_default_tuning(da, c->cu_count, c->max_lds);
   double bms = 1e30;
@@ -601,16 +849,12 @@ mapi_status mapi_copy_reference(mapi_ctx* c, const void* src, void* dst, size_t 
 
 mapi_status mapi_solve(mapi_ctx* c, const mapi_dense* A, const float* w0, float* w_out, const mapi_opts* opts,
                        mapi_info* info) {
-  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
-  HIP_TRY(hipSetDevice(c->device));
-  return run_dense(c, A, w0, w_out, opts, info, false);
+  return solve_entry(c, A, w0, w_out, opts, info, false);
 }
 
 mapi_status rpi_solve(mapi_ctx* c, const mapi_dense* A, const float* w0, float* w_out, const mapi_opts* opts,
                       mapi_info* info) {
-  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
-  HIP_TRY(hipSetDevice(c->device));
-  return run_dense(c, A, w0, w_out, opts, info, true);
+  return solve_entry(c, A, w0, w_out, opts, info, true);
 }
 
 mapi_status mapi_hybrid_solve(mapi_ctx* c, const mapi_dense* A, const float* w0, float* w_out,
@@ -618,16 +862,17 @@ mapi_status mapi_hybrid_solve(mapi_ctx* c, const mapi_dense* A, const float* w0,
                               mapi_info* info_rpi) {
   if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
   mapi_status s;
-  if ((s = check_dense(A, true)) != MAPI_OK) return s;
-  if ((s = check_opts(mapi_o)) != MAPI_OK) return s;
+  if ((s = check_solve_args(A, w0, w_out, mapi_o, false)) != MAPI_OK) return s;
   if ((s = check_opts(rpi_o)) != MAPI_OK) return s;
   HIP_TRY(hipSetDevice(c->device));
-  if ((s = ensure(&c->mid, &c->mid_bytes, sizeof(float) * (size_t)A->n_rows, c)) != MAPI_OK) return s;
-  float* mid = static_cast<float*>(c->mid);
+  char* base = nullptr;
+  if ((s = acquire(c, &c->mid, &c->mid_bytes, hybrid_ws_bytes(A->n_rows, c->cu_count), &base)) != MAPI_OK) return s;
+  float* mid = reinterpret_cast<float*>(base);
+  char* ws = base + align_up(sizeof(float) * (size_t)A->n_rows);
   mapi_opts o1 = *mapi_o;
   o1.final_l2 = 1;     // the hand-over vector has unit l2 norm
-  if ((s = run_dense(c, A, w0, mid, &o1, info_mapi, false)) != MAPI_OK) return s;
-  return run_dense(c, A, mid, w_out, rpi_o, info_rpi, true);
+  if ((s = run_dense(c, A, w0, mid, &o1, info_mapi, false, ws)) != MAPI_OK) return s;
+  return run_dense(c, A, mid, w_out, rpi_o, info_rpi, true, ws);
 }
 
 mapi_status mapi_quantize(mapi_ctx* c, const float* A, int64_t n_rows, int64_t n_cols, int64_t lda, int32_t dtype,
@@ -654,8 +899,9 @@ static mapi_status gram_ws(mapi_ctx* c, int64_t D, int64_t N, int op, double** o
   *out = nullptr;
   if (need == 0) return MAPI_OK;
   mapi_status s;
-  if ((s = ensure(&c->gws, &c->gws_bytes, need, c)) != MAPI_OK) return s;
-  *out = static_cast<double*>(c->gws);
+  char* base = nullptr;
+  if ((s = acquire(c, &c->gws, &c->gws_bytes, need, &base)) != MAPI_OK) return s;
+  *out = reinterpret_cast<double*>(base);
   return MAPI_OK;
 }
 
@@ -692,28 +938,23 @@ mapi_status mapi_pca_topk(mapi_ctx* c, const float* X, int64_t D, int64_t N, int
   mapi_status s;
   if ((s = check_opts(opts)) != MAPI_OK) return s;
   HIP_TRY(hipSetDevice(c->device));
-  const int64_t ldA = (D + 3) / 4 * 4;
-  Layout L;
-  const size_t o_A = L.take(sizeof(float) * D * ldA);
-  const size_t o_Ai = L.take(sizeof(float) * D * ldA);
-  const size_t o_P = L.take(sizeof(double) * D * k);
-  const size_t o_Q = L.take(sizeof(double) * D * k);
-  const size_t o_qp = L.take(sizeof(double) * D * deflate_qpart_count());
-  const size_t o_w = L.take(sizeof(float) * D);
-  if ((s = ensure(&c->big, &c->big_bytes, L.off, c)) != MAPI_OK) return s;
-  char* base = static_cast<char*>(c->big);
-  float* A = reinterpret_cast<float*>(base + o_A);
-  float* Ai = reinterpret_cast<float*>(base + o_Ai);
-  double* P = reinterpret_cast<double*>(base + o_P);
-  double* Q = reinterpret_cast<double*>(base + o_Q);
-  double* qpart = reinterpret_cast<double*>(base + o_qp);
-  float* wtmp = reinterpret_cast<float*>(base + o_w);
   const bool rpi = method == MAPI_METHOD_RPI;
-  double* gw = nullptr;
-  if ((s = gram_ws(c, D, N, rpi ? MAPI_OP_DOT : opts->op, &gw)) != MAPI_OK) return s;
+  const int gop = rpi ? MAPI_OP_DOT : opts->op;
+  const PcaLayout l = pca_layout(D, k, gram_workspace_bytes(D, N, gop), c->cu_count);
+  const int64_t ldA = l.ldA;
+  char* base = nullptr;
+  if ((s = acquire(c, &c->big, &c->big_bytes, l.total, &base)) != MAPI_OK) return s;
+  float* A = reinterpret_cast<float*>(base + l.o_A);
+  float* Ai = reinterpret_cast<float*>(base + l.o_Ai);
+  double* P = reinterpret_cast<double*>(base + l.o_PQ);
+  double* Q = P + (size_t)D * k;
+  double* qpart = reinterpret_cast<double*>(base + l.o_qp);
+  float* wtmp = reinterpret_cast<float*>(base + l.o_w);
+  double* gw = gram_workspace_bytes(D, N, gop) ? reinterpret_cast<double*>(base + l.o_g) : nullptr;
+  char* dws = base + l.o_d;
   {
     Timed tm(c, MAPI_K_GRAM);
-    HIP_TRY(launch_gram(X, D, N, ldx, scale, rpi ? MAPI_OP_DOT : opts->op, A, ldA, gw, c->stream));
+    HIP_TRY(launch_gram(X, D, N, ldx, scale, gop, A, ldA, gw, c->stream));
   }
   mapi_opts o = *opts;
   o.final_l2 = 0;
@@ -726,7 +967,7 @@ mapi_status mapi_pca_topk(mapi_ctx* c, const float* X, int64_t D, int64_t N, int
     }
     mapi_dense desc{Acur, D, D, ldA, MAPI_F32, nullptr};
     mapi_info inf{};
-    s = run_dense(c, &desc, W0 + (int64_t)i * D, wtmp, &o, &inf, rpi);
+    s = run_dense(c, &desc, W0 + (int64_t)i * D, wtmp, &o, &inf, rpi, dws);
     if (info_k) info_k[i] = inf;
     if (s != MAPI_OK) return s;
     {
@@ -752,43 +993,33 @@ mapi_status mapi_image_reconstruct(mapi_ctx* c, const float* V, int64_t P, int32
   mapi_status s;
   if ((s = check_opts(opts)) != MAPI_OK) return s;
   const bool rpi = method == MAPI_METHOD_RPI;
-  if (!rpi && opts->op != MAPI_OP_MIN1) return fail(MAPI_ERR_UNSUPPORTED, "the min-outer deflation is built for min1");
+  if (!rpi && opts->op != MAPI_OP_MIN1 && opts->op != MAPI_OP_MIN2)
+    return fail(MAPI_ERR_UNSUPPORTED, "the min-outer deflation is built for the min1 and min2 products");
   if (!aligned16(w0)) return fail(MAPI_ERR_ARG, "w0 must be 16-byte aligned");
   HIP_TRY(hipSetDevice(c->device));
-  const int64_t ldA = (P + 3) / 4 * 4;     // 16-byte rows for the product kernel
-  const int64_t ldc = (N + 3) / 4 * 4;     // centred images, 16-byte rows for the Gram kernel
-  const int G = (int)std::min<int64_t>(64, P);
-  Layout L;
-  const size_t o_C = L.take(sizeof(float) * P * ldA);
-  const size_t o_C2 = L.take(sizeof(float) * P * ldA);
-  const size_t o_Vc = L.take(sizeof(float) * P * ldc);
-  const size_t o_m = L.take(sizeof(float) * P);
-  const size_t o_perm = L.take(sizeof(int32_t) * P);
-  const size_t o_sums = L.take(sizeof(double) * 2 * (size_t)G * P);
-  const size_t o_P = L.take(sizeof(double) * P);
-  const size_t o_Q = L.take(sizeof(double) * P);
-  const size_t o_qp = L.take(sizeof(double) * P * deflate_qpart_count());
-  const size_t o_pf = L.take(sizeof(float) * P);
-  if ((s = ensure(&c->big, &c->big_bytes, L.off, c)) != MAPI_OK) return s;
-  char* base = static_cast<char*>(c->big);
-  float* C = reinterpret_cast<float*>(base + o_C);
-  float* C2 = reinterpret_cast<float*>(base + o_C2);
-  float* Vc = reinterpret_cast<float*>(base + o_Vc);
-  float* m = reinterpret_cast<float*>(base + o_m);
-  int32_t* perm = reinterpret_cast<int32_t*>(base + o_perm);
-  double* sums = reinterpret_cast<double*>(base + o_sums);
-  double* Pm = reinterpret_cast<double*>(base + o_P);
-  double* Qm = reinterpret_cast<double*>(base + o_Q);
-  double* qpart = reinterpret_cast<double*>(base + o_qp);
+  const int gop = rpi ? MAPI_OP_DOT : opts->op;
+  const ImageLayout l = image_layout(P, N, gram_workspace_bytes(P, N, gop), c->cu_count);
+  const int64_t ldA = l.ldA, ldc = l.ldc;
+  const int G = l.G;
+  char* base = nullptr;
+  if ((s = acquire(c, &c->big, &c->big_bytes, l.total, &base)) != MAPI_OK) return s;
+  float* C = reinterpret_cast<float*>(base + l.o_C);
+  float* C2 = reinterpret_cast<float*>(base + l.o_C2);
+  float* Vc = reinterpret_cast<float*>(base + l.o_Vc);
+  float* m = reinterpret_cast<float*>(base + l.o_m);
+  int32_t* perm = reinterpret_cast<int32_t*>(base + l.o_perm);
+  double* sums = reinterpret_cast<double*>(base + l.o_sums);
+  double* Pm = reinterpret_cast<double*>(base + l.o_P);
+  double* Qm = reinterpret_cast<double*>(base + l.o_Q);
+  double* qpart = reinterpret_cast<double*>(base + l.o_qp);
+  double* gw = gram_workspace_bytes(P, N, gop) ? reinterpret_cast<double*>(base + l.o_g) : nullptr;
+  char* dws = base + l.o_d;
   float* w1 = W;
   float* w2 = W + P;
   HIP_TRY(launch_img_center(V, P, N, ldv, Vc, ldc, m, c->stream));
-  double* gw = nullptr;
-  if ((s = gram_ws(c, P, N, rpi ? MAPI_OP_DOT : MAPI_OP_MIN1, &gw)) != MAPI_OK) return s;
   {
     Timed tm(c, MAPI_K_GRAM);
-    HIP_TRY(launch_gram(Vc, P, N, ldc, 1.0 / (double)(N - 1), rpi ? MAPI_OP_DOT : MAPI_OP_MIN1, C, ldA, gw,
-                        c->stream));
+    HIP_TRY(launch_gram(Vc, P, N, ldc, 1.0 / (double)(N - 1), gop, C, ldA, gw, c->stream));
   }
   // MAPI vectors as Algorithm 1 returns them (l1 units: w (+) w = ||w||_1 = 1 makes
   // w (+) w^T act on w as w w^T does for an l2 unit vector); RPI vectors l2 units
@@ -796,24 +1027,24 @@ mapi_status mapi_image_reconstruct(mapi_ctx* c, const float* V, int64_t P, int32
   o.final_l2 = rpi ? 1 : 0;
   mapi_dense d1{C, P, P, ldA, MAPI_F32, nullptr};
   mapi_info i1{}, i2{};
-  s = run_dense(c, &d1, w0, w1, &o, &i1, rpi);
+  s = run_dense(c, &d1, w0, w1, &o, &i1, rpi, dws);
   if (info2) info2[0] = i1;
   if (s != MAPI_OK) return s;
   {
     Timed tm(c, MAPI_K_DEFLATE);
     if (rpi) {
-      HIP_TRY(launch_mgs_append(Pm, P, 0, w1, reinterpret_cast<float*>(base + o_pf), c->stream));
+      HIP_TRY(launch_mgs_append(Pm, P, 0, w1, reinterpret_cast<float*>(base + l.o_pf), c->stream));
       HIP_TRY(launch_deflate_q(C, P, ldA, Pm, Qm, qpart, c->stream));
       HIP_TRY(launch_deflate_apply(C, P, ldA, Pm, Qm, 1, C2, ldA, c->stream));
     } else {
-      HIP_TRY(launch_img_minouter_deflate(C, P, ldA, w1, perm, sums, G, C2, c->stream));
+      HIP_TRY(launch_img_minouter_deflate(gop, C, P, ldA, w1, perm, sums, G, C2, c->stream));
     }
   }
   mapi_dense d2{C2, P, P, ldA, MAPI_F32, nullptr};
-  s = run_dense(c, &d2, w0, w2, &o, &i2, rpi);
+  s = run_dense(c, &d2, w0, w2, &o, &i2, rpi, dws);
   if (info2) info2[1] = i2;
   if (s != MAPI_OK) return s;
-  HIP_TRY(launch_img_reconstruct(rpi ? MAPI_OP_DOT : MAPI_OP_MIN1, W, Vc, P, N, ldc, m, R, ldr, c->stream));
+  HIP_TRY(launch_img_reconstruct(gop, W, Vc, P, N, ldc, m, R, ldr, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   collect_timing(c);
   return MAPI_OK;
@@ -831,19 +1062,24 @@ mapi_status mapi_minibatch(mapi_ctx* c, const float* X, int64_t N, int64_t D, in
   if (op != MAPI_OP_MIN1 && op != MAPI_OP_DOT) return fail(MAPI_ERR_ARG, "op must be MAPI_OP_MIN1 or MAPI_OP_DOT");
   if (!(std::fabs(beta) < INFINITY)) return fail(MAPI_ERR_ARG, "beta must be finite");
   HIP_TRY(hipSetDevice(c->device));
+  // batch matrices of `range` steps of t are built ahead per launch: the library's choice,
+  // or as many as the caller's workspace holds (at least one)
+  int range = minibatch_range((int)D, T, runs);
+  if (c->user_ws)
+    while (range > 1 && minibatch_bytes((int)D, range, runs) > c->user_ws_bytes) range = range / 2;
   Layout L;
   const size_t o_run = L.take(sizeof(MbRun) * (size_t)runs);
   const size_t o_bad = L.take(sizeof(int32_t));
-  const size_t o_mb = L.take(minibatch_workspace_bytes((int)D, T, runs));
+  const size_t o_mb = L.off;
   mapi_status st;
-  if ((st = ensure(&c->ws, &c->ws_bytes, L.off, c)) != MAPI_OK) return st;
-  char* base = static_cast<char*>(c->ws);
+  char* base = nullptr;
+  if ((st = acquire(c, &c->ws, &c->ws_bytes, minibatch_bytes((int)D, range, runs), &base)) != MAPI_OK) return st;
   int32_t* bad = reinterpret_cast<int32_t*>(base + o_bad);
   HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int32_t), c->stream));
   {
     Timed tm(c, MAPI_K_MINIBATCH);
     HIP_TRY(launch_minibatch(X, N, (int)D, ldx, batch_idx, s, T, (float)beta, op, runs, w0, w_out, final_l2,
-                             reinterpret_cast<MbRun*>(base + o_run), bad, base + o_mb, c->stream));
+                             reinterpret_cast<MbRun*>(base + o_run), bad, range, base + o_mb, c->stream));
   }
   std::vector<MbRun> host(runs);
   int32_t bad_h = 0;

@@ -172,6 +172,15 @@ int64_t realtime_hz() { return 100000000; }   // s_memrealtime runs at 100 MHz o
 
 }  // namespace mapi
 
+mapi_status mapi_batch_free_arena(mapi_ctx* c) {
+  if (c->batch && c->batch->arena) {
+    HIP_TRY(hipFree(c->batch->arena));
+    c->batch->arena = nullptr;
+    c->batch->bytes = 0;
+  }
+  return MAPI_OK;
+}
+
 void mapi_batch_release(mapi_ctx* c) {
   if (c->batch) {
     if (c->batch->arena) (void)hipFree(c->batch->arena);
@@ -213,35 +222,68 @@ mapi_status mapi_generate_dense(mapi_ctx* c, int64_t n, uint64_t seed, float* A,
   return MAPI_OK;
 }
 
-mapi_status mapi_solve_batched(mapi_ctx* c, int32_t count, const mapi_problem* probs, mapi_info* infos) {
-  if (!c || count < 0 || (count > 0 && !probs)) return fail(MAPI_ERR_ARG, "bad arguments");
-  if (count == 0) return MAPI_OK;
+// Arena of one batched solve: instances, queue, control block, queue items, error
+// flags, then every instance's buffers.  Fills H and mbytes from the problems.
+struct ArenaLayout {
+  uint32_t cap;
+  size_t o_inst, o_q, o_ctl, o_item, o_err, o_bufs, total;
+};
+static mapi_status batch_layout(mapi_ctx* c, int32_t count, const mapi_problem* probs, std::vector<BInst>& H,
+                                std::vector<int64_t>& mbytes, ArenaLayout* a) {
+  if (count < 1 || !probs) return fail(MAPI_ERR_ARG, "bad arguments");
   if ((uint32_t)count > kMaxInstances) return fail(MAPI_ERR_ARG, "too many instances");
-  HIP_TRY(hipSetDevice(c->device));
-  mapi_status s;
-  std::vector<BInst> H(count);
-  std::vector<int64_t> mbytes(count);
+  H.assign(count, BInst{});
+  mbytes.assign(count, 0);
   uint64_t items = 0, first_items = 0;
   size_t inst_total = 0;
+  mapi_status s;
   for (int i = 0; i < count; ++i) {
     if ((s = describe(c, probs[i], &H[i], &mbytes[i])) != MAPI_OK) return fail(s, "problem %d: %s", i, mapi_last_error());
-    if (!probs[i].w_out) return fail(MAPI_ERR_ARG, "problem %d: w_out is NULL", i);
     int ph;
     first_items += first_phase_tiles(H[i], &ph);
     items += max_tiles(H[i]);
     inst_total += instance_bytes(H[i], mbytes[i]);
   }
-  const uint32_t cap = pow2_at_least(items + first_items + 64);
+  a->cap = pow2_at_least(items + first_items + 64);
   Layout L;
-  const size_t o_inst = L.take(sizeof(BInst) * count);
-  const size_t o_q = L.take(sizeof(BQueue));
-  const size_t o_ctl = L.take(sizeof(BCtl));
-  const size_t o_item = L.take(sizeof(unsigned long long) * cap);
-  const size_t o_err = L.take(sizeof(int32_t) * count);
-  const size_t o_bufs = L.take(inst_total);
+  a->o_inst = L.take(sizeof(BInst) * count);
+  a->o_q = L.take(sizeof(BQueue));
+  a->o_ctl = L.take(sizeof(BCtl));
+  a->o_item = L.take(sizeof(unsigned long long) * a->cap);
+  a->o_err = L.take(sizeof(int32_t) * count);
+  a->o_bufs = L.take(inst_total);
+  a->total = L.off;
+  return MAPI_OK;
+}
+
+mapi_status mapi_solve_batched_workspace_size(mapi_ctx* c, int32_t count, const mapi_problem* probs, size_t* bytes) {
+  if (!c || !bytes) return fail(MAPI_ERR_ARG, "ctx and bytes are required");
+  *bytes = 0;
+  if (count == 0) return MAPI_OK;
+  std::vector<BInst> H;
+  std::vector<int64_t> mbytes;
+  ArenaLayout a;
+  const mapi_status s = batch_layout(c, count, probs, H, mbytes, &a);
+  if (s == MAPI_OK) *bytes = a.total;
+  return s;
+}
+
+mapi_status mapi_solve_batched(mapi_ctx* c, int32_t count, const mapi_problem* probs, mapi_info* infos) {
+  if (!c || count < 0 || (count > 0 && !probs)) return fail(MAPI_ERR_ARG, "bad arguments");
+  if (count == 0) return MAPI_OK;
+  HIP_TRY(hipSetDevice(c->device));
+  mapi_status s;
+  std::vector<BInst> H;
+  std::vector<int64_t> mbytes;
+  ArenaLayout a;
+  if ((s = batch_layout(c, count, probs, H, mbytes, &a)) != MAPI_OK) return s;
+  for (int i = 0; i < count; ++i)
+    if (!probs[i].w_out) return fail(MAPI_ERR_ARG, "problem %d: w_out is NULL", i);
+  const uint32_t cap = a.cap;
+  const size_t o_inst = a.o_inst, o_q = a.o_q, o_ctl = a.o_ctl, o_item = a.o_item, o_err = a.o_err, o_bufs = a.o_bufs;
   if (!c->batch) c->batch = new BatchState();
-  if ((s = ensure(&c->batch->arena, &c->batch->bytes, L.off, c)) != MAPI_OK) return s;
-  char* base = static_cast<char*>(c->batch->arena);
+  char* base = nullptr;
+  if ((s = acquire(c, &c->batch->arena, &c->batch->bytes, a.total, &base)) != MAPI_OK) return s;
   BInst* d_inst = reinterpret_cast<BInst*>(base + o_inst);
   BQueue* d_q = reinterpret_cast<BQueue*>(base + o_q);
   BCtl* d_ctl = reinterpret_cast<BCtl*>(base + o_ctl);
@@ -358,8 +400,19 @@ mapi_status mapi_autotune_batched(mapi_ctx* c, int32_t dtype, int64_t n, int32_t
   if (!c || n <= 0 || n > 16384 || count < 1 || iters < 1) return fail(MAPI_ERR_ARG, "bad arguments");
   if (dtype != MAPI_F32 && dtype != MAPI_BF16) return fail(MAPI_ERR_ARG, "dtype F32 or BF16");
   HIP_TRY(hipSetDevice(c->device));
+  // the candidates' results: the tail of the caller's workspace (the solves get the
+  // rest), else a temporary allocation
   float* out = nullptr;
-  HIP_TRY(hipMalloc(&out, sizeof(float) * (size_t)n * count));
+  const size_t out_bytes = align_up(sizeof(float) * (size_t)n * count);
+  char* const user_ws = c->user_ws;
+  const size_t user_bytes = c->user_ws_bytes;
+  if (user_ws) {
+    if (user_bytes < out_bytes) return fail(MAPI_ERR_ARG, "the workspace set by mapi_set_workspace is too small");
+    c->user_ws_bytes = (user_bytes - out_bytes) / 256 * 256;
+    out = reinterpret_cast<float*>(user_ws + c->user_ws_bytes);
+  } else {
+    HIP_TRY(hipMalloc(&out, sizeof(float) * (size_t)n * count));
+  }
   std::vector<mapi_problem> P(count);
   for (int i = 0; i < count; ++i) {
     mapi_problem p{};
@@ -390,7 +443,8 @@ mapi_status mapi_autotune_batched(mapi_ctx* c, int32_t dtype, int64_t n, int32_t
       best = rows;
     }
   }
-  (void)hipFree(out);
+  if (user_ws) c->user_ws_bytes = user_bytes;
+  else (void)hipFree(out);
   if (s != MAPI_OK) {
     if (saved > 0) c->batch_rows[key] = saved;
     else c->batch_rows.erase(key);

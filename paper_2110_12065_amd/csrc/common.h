@@ -274,6 +274,33 @@ hipError_t launch_csr_product(int method, const int32_t* row_ptr, const int32_t*
                               hipStream_t s);
 int csr_part_count(int64_t n);
 
+// Column-split copy of a CSR link matrix (k_csr_split.hip): the entries of each of 8
+// source blocks contiguous, per-row lengths per block, per-chunk offsets, and the
+// products' per-block partial row sums.
+struct SplitCsr {
+  int64_t n = 0, nnz = 0, nch = 0;
+  uint8_t* len = nullptr;
+  int32_t* base = nullptr;
+  int32_t* col = nullptr;
+  float* val = nullptr;
+  void* part = nullptr;
+  int32_t* flags = nullptr;
+};
+// Device bytes of the split copy for an iterate of es bytes per element, and its placement.
+size_t split_csr_bytes(int64_t n, int64_t nnz, size_t es);
+SplitCsr split_csr_place(void* ws, int64_t n, int64_t nnz, size_t es);
+// Count block-row lengths (flags must be zero; bit 0 set when a block row is too long for
+// the split layout), then, only if it is not, fill the offsets and the split entries.
+hipError_t launch_split_count(const int32_t* row_ptr, const int32_t* col, const SplitCsr& s, hipStream_t st);
+hipError_t launch_split_fill(const int32_t* row_ptr, const int32_t* col, const float* val, const SplitCsr& s,
+                             hipStream_t st);
+// Normaliser partials written by the split product (its combine kernel's grid).
+int split_combine_blocks(int64_t n);
+// One split product: the per-block partial sums, then y and the normaliser partials.
+template <typename T>
+hipError_t launch_csr_split_product(int method, const SplitCsr& s, const T* w, T* y, double* nparts, SolveState* st,
+                                    double alpha, double c, double inv_n, hipStream_t stream);
+
 hipError_t launch_deflate_q(const float* A, int64_t D, int64_t lda, const double* p, double* q, double* qpart,
                             hipStream_t s);
 int deflate_qpart_count();
@@ -289,7 +316,9 @@ hipError_t launch_read16(const void* src, int64_t n16, uint32_t* sink, int cu_co
 int image_max_n();
 hipError_t launch_img_center(const float* V, int64_t P, int N, int64_t ldv, float* Vc, int64_t ldc, float* m,
                              hipStream_t s);
-hipError_t launch_img_minouter_deflate(const float* C, int64_t P, int64_t ldc, const float* w, int32_t* perm,
+// Doubles of the deflation's segment sums per (segment, column): sums holds G * P times this.
+int image_defl_sums_per_column();
+hipError_t launch_img_minouter_deflate(int op, const float* C, int64_t P, int64_t ldc, const float* w, int32_t* perm,
                                        double* sums, int G, float* Cd, hipStream_t s);
 hipError_t launch_img_reconstruct(int op, const float* W, const float* Vc, int64_t P, int N, int64_t ldc,
                                   const float* m, float* R, int64_t ldr, hipStream_t s);
@@ -300,11 +329,13 @@ struct MbRun {
   double nu;       // last normaliser
 };
 int minibatch_max_d();
-// Device workspace of launch_minibatch: the stored batch matrices of one range of t
+// Steps of t whose batch matrices are built ahead in one launch (at most 256 MiB of them).
+int minibatch_range(int D, int T, int runs);
+// Device workspace of launch_minibatch: the stored batch matrices of `range` steps of t
 // and a state record per run.
-size_t minibatch_workspace_bytes(int D, int T, int runs);
+size_t minibatch_workspace_bytes(int D, int range, int runs);
 hipError_t launch_minibatch(const float* X, int64_t N, int D, int64_t ldx, const int32_t* idx, int s, int T, float beta,
                             int op, int runs, const float* w0, float* w_out, int final_l2, MbRun* run_info,
-                            int32_t* bad_index, void* ws, hipStream_t st);
+                            int32_t* bad_index, int range, void* ws, hipStream_t st);
 
 }  // namespace mapi

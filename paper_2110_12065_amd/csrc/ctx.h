@@ -45,6 +45,8 @@ inline int64_t elem_size(int dtype) {
 struct mapi_ctx;
 // Frees the batched solver's arena and stream of a context (batch.hip).
 void mapi_batch_release(mapi_ctx* c);
+// Frees the batched solver's arena only (batch.hip).
+mapi_status mapi_batch_free_arena(mapi_ctx* c);
 
 struct mapi_ctx {
   int device = 0;
@@ -53,6 +55,12 @@ struct mapi_ctx {
   int max_lds = 65536;               // LDS bytes one block may use
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // device workspace given by the caller (mapi_set_workspace): while it is set, every
+  // call takes its buffers from it and the context allocates no device memory
+  char* user_ws = nullptr;
+  size_t user_ws_bytes = 0;
+  // PageRank graphs of at least this many nodes use the column-split product (0: never)
+  int64_t csr_split_min_n = int64_t(1) << 20;
   mapi::SolveState* st_host = nullptr;     // pinned copy of the device state
   // matrices owned by the PCA driver
   void* big = nullptr;
@@ -98,6 +106,22 @@ inline mapi_status ensure(void** buf, size_t* have, size_t need, mapi_ctx* c) {
     return fail(MAPI_ERR_ALLOC, "hipMalloc of %zu bytes failed", need);
   }
   *have = need;
+  return MAPI_OK;
+}
+
+// Device memory of one call: `need` bytes of the caller's workspace when one is set
+// (MAPI_ERR_ARG if it is smaller), else the context's own buffer *own, grown as needed.
+inline mapi_status acquire(mapi_ctx* c, void** own, size_t* have, size_t need, char** out) {
+  if (c->user_ws) {
+    if (need > c->user_ws_bytes)
+      return fail(MAPI_ERR_ARG, "the workspace set by mapi_set_workspace holds %zu bytes; this call needs %zu",
+                  c->user_ws_bytes, need);
+    *out = c->user_ws;
+    return MAPI_OK;
+  }
+  const mapi_status s = ensure(own, have, need, c);
+  if (s != MAPI_OK) return s;
+  *out = static_cast<char*>(*own);
   return MAPI_OK;
 }
 
@@ -183,6 +207,14 @@ inline void collect_timing(mapi_ctx* c) {
   }
   c->pending.clear();
 }
+
+// Dense power iteration (api.hip): device bytes of one solve's buffers, the argument
+// checks of mapi_solve / rpi_solve, and the solve itself in a region `ws` of
+// dense_ws_bytes(n, cu_count) bytes on the context's device (device already current).
+size_t dense_ws_bytes(int64_t n, int cu_count);
+mapi_status check_solve_args(const mapi_dense* A, const float* w0, const float* w_out, const mapi_opts* o, bool rpi);
+mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* w_out, const mapi_opts* o,
+                      mapi_info* info, bool rpi, char* ws);
 
 inline mapi_status sync_and_state(mapi_ctx* c, const SolveState* st_dev) {
   HIP_TRY(hipMemcpyAsync(c->st_host, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, c->stream));

@@ -4,10 +4,13 @@
 // the Gram and dense-product kernels.
 //
 // Deflation without the O(P^3) product.  With a = |w1| and s = sign(w1),
-// (w1 (+) w1^T)_ij = s_i s_j min(a_i, a_j).  In the order of increasing a (ties by
-// index), row i of rank r of the product with C is
+// (w1 (+) w1^T)_ij = s_i s_j min(a_i, a_j) for min1 (eq. 3).  In the order of
+// increasing a (ties by index), row i of rank r of the product with C is
 //   s_i [ sum_{q <= r} a_(q) s_(q) C_(q),:  +  a_i sum_{q > r} s_(q) C_(q),: ],
 // a prefix scan over C's rows in that order: two float64 running sums per column.
+// For min2 (eq. 4) the entry is 1(s_i = s_j) min(a_i, a_j): the same scan kept
+// separately over the rows of positive and of negative w1 (four running sums), and
+// row i takes the pair of its own sign (a zero w1_i gives a zero row).
 // The scan is split into G row segments: pass 1 sums each segment, pass 2 starts
 // each segment from the sums of the segments before it (fixed order, so the result
 // does not depend on scheduling).  Traffic: C read twice, C' written once.
@@ -52,45 +55,72 @@ k_img_rank(const float* __restrict__ w, int64_t P, int32_t* __restrict__ perm) {
   if (i < P) perm[rank] = (int32_t)i;
 }
 
-// Pass 1: per row segment g and column c, SA = sum a_(q) s_(q) C_(q),c and
-// SB = sum s_(q) C_(q),c over the segment's ranks.
+// Running sums per column of one scan: min1 keeps (SA, SB) = (sum a s C, sum s C); min2
+// keeps (SA+, SB+, SA-, SB-) = (sum a C, sum C) over the rows of positive and of
+// negative w1.
+template <int OP> struct DeflSums { static constexpr int K = OP == MAPI_OP_MIN2 ? 4 : 2; };
+
+template <int OP>
+__device__ __forceinline__ void defl_add(double* acc, float wi, double x) {
+  const double ai = (double)fabsf(wi);
+  if constexpr (OP == MAPI_OP_MIN2) {
+    if (wi > 0.0f) {
+      acc[0] += ai * x;
+      acc[1] += x;
+    } else if (wi < 0.0f) {
+      acc[2] += ai * x;
+      acc[3] += x;
+    }
+  } else {
+    const double sx = wi > 0.0f ? x : (wi < 0.0f ? -x : 0.0);
+    acc[0] += ai * sx;
+    acc[1] += sx;
+  }
+}
+
+// Pass 1: per row segment g and column c, the segment's sums over its ranks.
+template <int OP>
 __global__ void __launch_bounds__(kImgThreads)
 k_img_defl_sums(const float* __restrict__ C, int64_t P, int64_t ldc, const float* __restrict__ w,
                 const int32_t* __restrict__ perm, int64_t seg, double* __restrict__ sums) {
+  constexpr int K = DeflSums<OP>::K;
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t g = blockIdx.y;
   if (c >= P) return;
   const int64_t r0 = g * seg, r1 = (r0 + seg < P) ? r0 + seg : P;
-  double sa = 0.0, sb = 0.0;
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
   for (int64_t r = r0; r < r1; ++r) {
     const int32_t i = perm[r];
-    const float wi = w[i];
-    const double x = (double)C[(int64_t)i * ldc + c];
-    const double sx = wi > 0.0f ? x : (wi < 0.0f ? -x : 0.0);
-    sa += (double)fabsf(wi) * sx;
-    sb += sx;
+    defl_add<OP>(acc, w[i], (double)C[(int64_t)i * ldc + c]);
   }
-  sums[(g * P + c) * 2 + 0] = sa;
-  sums[(g * P + c) * 2 + 1] = sb;
+#pragma unroll
+  for (int k = 0; k < K; ++k) sums[(g * P + c) * K + k] = acc[k];
 }
 
-// Pass 2: C'_(r),c = C_(r),c - s_(r) (PA_r + a_(r) (TB - PB_r)), PA / PB the prefix sums
-// up to and including rank r, TB the total of s C over all rows.
+// Pass 2: C'_(r),c = C_(r),c - M_(r),c with, for min1, M = s_(r) (PA_r + a_(r) (TB - PB_r))
+// (PA / PB the prefix sums up to and including rank r, TB the total of s C over all rows)
+// and, for min2, M = PA_r + a_(r) (TB - PB_r) over the rows of w1's sign at rank r.
+template <int OP>
 __global__ void __launch_bounds__(kImgThreads)
 k_img_defl_apply(const float* __restrict__ C, int64_t P, int64_t ldc, const float* __restrict__ w,
                  const int32_t* __restrict__ perm, int64_t seg, int G, const double* __restrict__ sums,
                  float* __restrict__ Cd) {
+  constexpr int K = DeflSums<OP>::K;
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t g = blockIdx.y;
   if (c >= P) return;
-  double pa = 0.0, pb = 0.0, tb = 0.0;
+  double pre[K], tot[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) pre[k] = tot[k] = 0.0;
   for (int64_t h = 0; h < G; ++h) {
-    const double b = sums[(h * P + c) * 2 + 1];
-    if (h < g) {
-      pa += sums[(h * P + c) * 2 + 0];
-      pb += b;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double v = sums[(h * P + c) * K + k];
+      if (h < g) pre[k] += v;
+      tot[k] += v;
     }
-    tb += b;
   }
   const int64_t r0 = g * seg, r1 = (r0 + seg < P) ? r0 + seg : P;
   for (int64_t r = r0; r < r1; ++r) {
@@ -98,11 +128,14 @@ k_img_defl_apply(const float* __restrict__ C, int64_t P, int64_t ldc, const floa
     const float wi = w[i];
     const double ai = (double)fabsf(wi);
     const double x = (double)C[(int64_t)i * ldc + c];
-    const double sx = wi > 0.0f ? x : (wi < 0.0f ? -x : 0.0);
-    pa += ai * sx;
-    pb += sx;
-    const double mc = ai * (tb - pb) + pa;
-    const double d = wi > 0.0f ? mc : (wi < 0.0f ? -mc : 0.0);
+    defl_add<OP>(pre, wi, x);
+    double d;
+    if constexpr (OP == MAPI_OP_MIN2) {
+      d = wi > 0.0f ? pre[0] + ai * (tot[1] - pre[1]) : (wi < 0.0f ? pre[2] + ai * (tot[3] - pre[3]) : 0.0);
+    } else {
+      const double mc = ai * (tot[1] - pre[1]) + pre[0];
+      d = wi > 0.0f ? mc : (wi < 0.0f ? -mc : 0.0);
+    }
     Cd[(int64_t)i * ldc + c] = (float)(x - d);
   }
 }
@@ -163,14 +196,26 @@ hipError_t launch_img_center(const float* V, int64_t P, int N, int64_t ldv, floa
   return hipGetLastError();
 }
 
-hipError_t launch_img_minouter_deflate(const float* C, int64_t P, int64_t ldc, const float* w, int32_t* perm,
+int image_defl_sums_per_column() { return 4; }
+
+hipError_t launch_img_minouter_deflate(int op, const float* C, int64_t P, int64_t ldc, const float* w, int32_t* perm,
                                        double* sums, int G, float* Cd, hipStream_t s) {
   const unsigned cb = (unsigned)((P + kImgThreads - 1) / kImgThreads);
   const int64_t seg = (P + G - 1) / G;
   hipLaunchKernelGGL(k_img_rank, dim3(cb), dim3(kImgThreads), 0, s, w, P, perm);
-  hipLaunchKernelGGL(k_img_defl_sums, dim3(cb, (unsigned)G), dim3(kImgThreads), 0, s, C, P, ldc, w, perm, seg, sums);
-  hipLaunchKernelGGL(k_img_defl_apply, dim3(cb, (unsigned)G), dim3(kImgThreads), 0, s, C, P, ldc, w, perm, seg, G,
-                     sums, Cd);
+  if (op == MAPI_OP_MIN1) {
+    hipLaunchKernelGGL(k_img_defl_sums<MAPI_OP_MIN1>, dim3(cb, (unsigned)G), dim3(kImgThreads), 0, s, C, P, ldc, w,
+                       perm, seg, sums);
+    hipLaunchKernelGGL(k_img_defl_apply<MAPI_OP_MIN1>, dim3(cb, (unsigned)G), dim3(kImgThreads), 0, s, C, P, ldc, w,
+                       perm, seg, G, sums, Cd);
+  } else if (op == MAPI_OP_MIN2) {
+    hipLaunchKernelGGL(k_img_defl_sums<MAPI_OP_MIN2>, dim3(cb, (unsigned)G), dim3(kImgThreads), 0, s, C, P, ldc, w,
+                       perm, seg, sums);
+    hipLaunchKernelGGL(k_img_defl_apply<MAPI_OP_MIN2>, dim3(cb, (unsigned)G), dim3(kImgThreads), 0, s, C, P, ldc, w,
+                       perm, seg, G, sums, Cd);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -303,7 +303,7 @@ int minibatch_max_d() { return kMbMaxD; }
 static size_t mb_align(size_t x) { return (x + 255) / 256 * 256; }
 
 // Batches per range of t: as many as keep runs x range x D^2 stored floats within kMbBufBytes.
-static int mb_range(int D, int T, int runs) {
+int minibatch_range(int D, int T, int runs) {
   const size_t per_t = (size_t)runs * (size_t)D * (size_t)D * sizeof(float);
   size_t r = kMbBufBytes / (per_t > 0 ? per_t : 1);
   if (r < 1) r = 1;
@@ -311,16 +311,16 @@ static int mb_range(int D, int T, int runs) {
   return (int)(r < 1 ? 1 : r);
 }
 
-size_t minibatch_workspace_bytes(int D, int T, int runs) {
-  const size_t buf = (size_t)runs * (size_t)mb_range(D, T, runs) * (size_t)D * (size_t)D * sizeof(float);
+size_t minibatch_workspace_bytes(int D, int range, int runs) {
+  const size_t buf = (size_t)runs * (size_t)(range < 1 ? 1 : range) * (size_t)D * (size_t)D * sizeof(float);
   return mb_align(buf) + (size_t)runs * sizeof(MbState);
 }
 
 hipError_t launch_minibatch(const float* X, int64_t N, int D, int64_t ldx, const int32_t* idx, int s, int T, float beta,
                             int op, int runs, const float* w0, float* w_out, int final_l2, MbRun* ri,
-                            int32_t* bad_index, void* ws, hipStream_t st) {
+                            int32_t* bad_index, int range, void* ws, hipStream_t st) {
   if (op != MAPI_OP_MIN1 && op != MAPI_OP_DOT) return hipErrorInvalidValue;
-  const int R = mb_range(D, T, runs);
+  const int R = range < 1 ? 1 : range;
   float* Abuf = static_cast<float*>(ws);
   MbState* states = reinterpret_cast<MbState*>(static_cast<char*>(ws) +
                                                mb_align((size_t)runs * (size_t)R * D * D * sizeof(float)));

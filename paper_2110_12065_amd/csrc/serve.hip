@@ -25,60 +25,13 @@
 
 #include "batched.h"
 #include "ctx.h"
+#include "host_pool.h"
 
 using namespace mapi;
 
 namespace {
 
 using Clock = std::chrono::steady_clock;
-
-// First-fit allocator over one device allocation (offsets, 256-byte granules).
-class Pool {
- public:
-  void reset(size_t bytes) {
-    free_.clear();
-    free_[0] = bytes;
-    used_ = peak_ = 0;
-  }
-  bool alloc(size_t bytes, size_t* off) {
-    bytes = align_up(bytes);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        *off = it->first;
-        const size_t rest = it->second - bytes;
-        const size_t at = it->first + bytes;
-        free_.erase(it);
-        if (rest) free_[at] = rest;
-        used_ += bytes;
-        peak_ = std::max(peak_, used_);
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    bytes = align_up(bytes);
-    used_ -= bytes;
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t peak() const { return peak_; }
-
- private:
-  std::map<size_t, size_t> free_;
-  size_t used_ = 0, peak_ = 0;
-};
 
 struct Ticket {
   mapi_request req{};
@@ -241,7 +194,10 @@ void scheduler(mapi_server* s) {
         }
         t->bytes = request_bytes(t->req, I, mbytes);
         t->tiles = max_tiles(I);
-        if (t->bytes > s->budget) {
+        const Admission adm = admit_request(s->pool, s->out_pool, s->budget, t->bytes, sizeof(float) * (size_t)I.n,
+                                            !s->free_slots.empty(), s->live_tiles, t->tiles, kQueueCap / 2, &t->off,
+                                            &t->out_off);
+        if (adm == Admission::kReject) {
           s->queued.pop_front();
           finish_ticket(s, *t, MAPI_ERR_BUDGET);
           ++s->rejected;
@@ -249,12 +205,7 @@ void scheduler(mapi_server* s) {
           progressed = true;
           continue;
         }
-        if (s->free_slots.empty() || s->live_tiles + t->tiles > kQueueCap / 2 || !s->pool.alloc(t->bytes, &t->off))
-          break;     // wait for completions to free a slot or memory
-        if (!s->out_pool.alloc(sizeof(float) * (size_t)I.n, &t->out_off)) {
-          s->pool.release(t->off, t->bytes);
-          break;
-        }
+        if (adm == Admission::kWait) break;     // wait for completions to free a slot or memory
         s->queued.pop_front();
         t->slot = s->free_slots.back();
         s->free_slots.pop_back();

@@ -15,18 +15,21 @@ TOL = 1e-5
 COS = 1 - 1e-6
 
 
-@pytest.mark.parametrize("D,method,T", [(16, "mapi", 30), (16, "rpi", 60), (30, "mapi", 25), (48, "mapi", 20),
-                                        (48, "rpi", 40)])
-def test_image_reconstruction_matches_oracle(D, method, T):
-    print(f"[case] image D={D} {method} T={T}", flush=True)
+@pytest.mark.parametrize("D,method,T,op", [(16, "mapi", 30, "min1"), (16, "rpi", 60, "min1"), (30, "mapi", 25, "min1"),
+                                           (48, "mapi", 20, "min1"), (48, "rpi", 40, "min1"), (16, "mapi", 30, "min2"),
+                                           (30, "mapi", 25, "min2"), (48, "mapi", 20, "min2")])
+def test_image_reconstruction_matches_oracle(D, method, T, op):
+    # min2 (eq. 4) in every step: the min-covariance, both solves, the sign-split
+    # deflation and the reconstruction
+    print(f"[case] image D={D} {method} T={T} {op}", flush=True)
     P, N = D * D, 10
     clean, V = synth.occluded_images(D, N, seed=D)
     w0 = synth.start_vector(P, D + 1)
-    R, W, infos = mp.mapi_image_reconstruct(torch.from_numpy(V).cuda(), to_dev(w0), method, max_iters=T)
+    R, W, infos = mp.mapi_image_reconstruct(torch.from_numpy(V).cuda(), to_dev(w0), method, max_iters=T, op=op)
     assert [i["iters"] for i in infos] == [T, T]
-    Rr, Wr, _ = oracle.image_reconstruct(V, T, w0.astype(np.float64), method=method)
+    Rr, Wr, _ = oracle.image_reconstruct(V, T, w0.astype(np.float64), method=method, op=op)
     for k in range(2):
-        e, c = report(f"image {method} D={D} w{k + 1}", W[:, k].cpu().numpy(), Wr[:, k])
+        e, c = report(f"image {method} {op} D={D} w{k + 1}", W[:, k].cpu().numpy(), Wr[:, k])
         assert e <= TOL and c > COS
     e = rel_l1(R.cpu().numpy(), Rr)
     print(f"[parity] image {method} D={D} R: rel_l1={e:.3e}", flush=True)
@@ -41,15 +44,15 @@ def test_image_full_size_runs_and_improves_on_the_inputs():
     D, N = 128, 10
     clean, V = synth.occluded_images(D, N, seed=1)
     w0 = synth.start_vector(D * D, 2)
-    for method in ("mapi", "rpi"):
+    for method, op in (("mapi", "min1"), ("mapi", "min2"), ("rpi", "min1")):
         R, W, infos = mp.mapi_image_reconstruct(torch.from_numpy(V).cuda(), to_dev(w0), method, max_iters=200,
-                                                tol=1e-6, check_every=8, stall_iters=10)
+                                                tol=1e-6, check_every=8, stall_iters=10, op=op)
         Wn = W.cpu().numpy().astype(np.float64)
         norms = np.abs(Wn).sum(axis=0) if method == "mapi" else np.linalg.norm(Wn, axis=0)
         np.testing.assert_allclose(norms, 1.0, rtol=1e-6)
         p_out = np.mean([oracle.psnr(R[:, i].cpu().numpy(), clean) for i in range(N)])
         p_in = np.mean([oracle.psnr(V[:, i], clean) for i in range(N)])
-        print(f"[image] {method}: iterations {[i['iters'] for i in infos]}, PSNR inputs {p_in:.2f} dB, "
+        print(f"[image] {method} {op}: iterations {[i['iters'] for i in infos]}, PSNR inputs {p_in:.2f} dB, "
               f"reconstructions {p_out:.2f} dB", flush=True)
         assert np.isfinite(p_out) and p_out > p_in + 3.0
 
@@ -63,4 +66,8 @@ def test_image_argument_checks():
     V17 = torch.zeros((64, 17), dtype=torch.float32, device="cuda")
     with pytest.raises(mp.MapiError) as ei:
         mp.mapi_image_reconstruct(V17, w0)
+    assert ei.value.status == 6
+    V4 = torch.ones((64, 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(mp.MapiError) as ei:
+        mp.mapi_image_reconstruct(V4, w0, op="diamond")   # the min-outer deflation has min1 and min2 only
     assert ei.value.status == 6

@@ -108,3 +108,42 @@ def test_mapi_reconstruction_is_the_composition_of_the_pinned_steps():
     a2 = oracle.mapi(oracle.minouter_deflate(C, a1.w), w0, 25)
     np.testing.assert_array_equal(W[:, 1], a2.w)
     np.testing.assert_array_equal(R, oracle.minouter_reconstruct(np.stack([a1.w, a2.w], axis=1), Vc, m))
+
+
+def test_min2_minouter_deflation_and_reconstruction_of_flat_vectors():
+    # min2 (eq. 4): for w = c s, the term 1(s_i = s_j) min(c, c) gives w (+) w^T = c (1 1^T + s s^T) / 2,
+    # so Alg. 2's deflation is C - (c/2)(1 (1^T C) + s (s^T C)) and the reconstruction of
+    # W = [c1 s1, c2 s2] is sum_k (c_k/2)(1 (1^T Vc) + s_k (s_k^T Vc)) + m (numpy, fixed product order)
+    rng = np.random.default_rng(13)
+    P, N = 40, 6
+    X = rng.standard_normal((P, 7))
+    C = oracle.mingram(X, 1.0 / 6, "min2")
+    s, w = _flat(rng, P, 1.0 / P)
+    one = np.ones(P)
+    got = oracle.minouter_deflate(C, w, "min2")
+    want = C - (0.5 / P) * (np.outer(one, one @ C) + np.outer(s, s @ C))
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-14)
+    wrong = C - (0.5 / P) * (np.outer(C @ one, one) + np.outer(C @ s, s))
+    assert np.max(np.abs(wrong - want)) > 1e-3
+    s2, w2 = _flat(rng, P, 0.5 / P)
+    Vc = rng.standard_normal((P, N))
+    m = rng.uniform(size=P)
+    R = oracle.minouter_reconstruct(np.stack([w, w2], axis=1), Vc, m, "min2")
+    want = ((0.5 / P) * (np.outer(one, one @ Vc) + np.outer(s, s @ Vc))
+            + (0.25 / P) * (np.outer(one, one @ Vc) + np.outer(s2, s2 @ Vc)) + m[:, None])
+    np.testing.assert_allclose(R, want, rtol=0, atol=1e-14)
+
+
+def test_min2_reconstruction_is_the_composition_of_the_pinned_steps():
+    clean, V = synth.occluded_images(16, 10, seed=7)
+    w0 = synth.start_vector(256, 8).astype(np.float64)
+    R, W, _ = oracle.image_reconstruct(V, 20, w0, op="min2")
+    Vd = V.astype(np.float64)
+    m = Vd.mean(axis=1)
+    Vc = Vd - m[:, None]
+    C = oracle.mingram(Vc, 1.0 / 9, "min2")
+    a1 = oracle.mapi(C, w0, 20, op="min2")
+    np.testing.assert_array_equal(W[:, 0], a1.w)
+    a2 = oracle.mapi(oracle.minouter_deflate(C, a1.w, "min2"), w0, 20, op="min2")
+    np.testing.assert_array_equal(W[:, 1], a2.w)
+    np.testing.assert_array_equal(R, oracle.minouter_reconstruct(np.stack([a1.w, a2.w], axis=1), Vc, m, "min2"))
