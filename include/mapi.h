@@ -244,6 +244,22 @@ mapi_status mapi_read_reference(mapi_ctx* ctx, const void* src, size_t bytes, in
 mapi_status mapi_solve(mapi_ctx* ctx, const mapi_dense* A, const float* w0, float* w_out,
                        const mapi_opts* opts, mapi_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): mapi_solve with every
+ * buffer of the solve (state, partial sums, two iterates, two products) in a static
+ * device array of the library, 4 MiB on each device, held from the context's
+ * creation on that device until the process ends.  Same arguments, checks, kernels
+ * and results as mapi_solve; the caller still passes A, w0 and w_out (device).  No
+ * device or host memory is allocated and no event is created (kernel timing is not
+ * recorded for this call).  MAPI_ERR_ARG, before any device work, when the system
+ * needs more than the array holds (mapi_workspace_size with MAPI_WS_SOLVE gives the
+ * need; n up to about 250000 fits).  All calls on one device share that device's
+ * array, whatever their context, and it keeps the last call's contents: calls that
+ * overlap on one device (from two threads, or on two streams) race and must be
+ * serialised by the caller.                                                        */
+mapi_status mapi_solve_noalloc(mapi_ctx* ctx, const mapi_dense* A, const float* w0, float* w_out,
+                               const mapi_opts* opts, mapi_info* info);
+
 /* RPI, eq. (1): b <- A b / ||A b||_2 (float32 fused multiply-add products,
  * float64 norms), same stopping rule and arguments as mapi_solve (opts->op is
  * ignored).                                                                     */

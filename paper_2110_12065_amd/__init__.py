@@ -92,6 +92,8 @@ _SIGS = {
     "mapi_read_reference": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.POINTER(C.c_double)]),
     "mapi_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]),
     "rpi_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]),
+    "mapi_solve_noalloc": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts),
+                                     C.POINTER(Info)]),
     "mapi_quantize": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_void_p,
                                 C.c_int64, C.c_void_p]),
     "mapi_mingram": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_double, C.c_int32,
@@ -291,6 +293,14 @@ def mapi_solve(A, w0, max_iters=100, tol=0.0, op="min1", final_l2=False, check_e
     """MAPI (eq. 6, Algorithm 1) on a square dense matrix.  Returns (w, info)."""
     return _solve(lib().mapi_solve, A, w0, max_iters, tol, op, final_l2, check_every, stall_iters, row_scale,
                   w_out, ctx)
+
+
+def mapi_solve_noalloc(A, w0, max_iters=100, tol=0.0, op="min1", final_l2=False, check_every=0, stall_iters=0,
+                       row_scale=None, w_out=None, ctx=None):
+    """mapi_solve with the solve's buffers in the library's static device scratch array (no device
+    allocation by the library; w_out is allocated here when not given).  Returns (w, info)."""
+    return _solve(lib().mapi_solve_noalloc, A, w0, max_iters, tol, op, final_l2, check_every, stall_iters,
+                  row_scale, w_out, ctx)
 
 
 def rpi_solve(A, w0, max_iters=100, tol=0.0, final_l2=False, check_every=0, stall_iters=0, row_scale=None,

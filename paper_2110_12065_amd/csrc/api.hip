@@ -530,6 +530,11 @@ mapi_status mapi_create(int device, void* hip_stream, mapi_ctx** out) {
     if (prop.sharedMemPerBlock > 0) c->max_lds = (int)prop.sharedMemPerBlock;
   }
   load_tune_cache(c);
+  mapi_status ss = scratch_setup(device, &c->scratch);
+  if (ss != MAPI_OK) {
+    delete c;
+    return ss;
+  }
   if (hipHostMalloc(reinterpret_cast<void**>(&c->st_host), sizeof(SolveState), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return fail(MAPI_ERR_ALLOC, "pinned host allocation failed");

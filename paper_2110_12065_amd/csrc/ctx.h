@@ -59,6 +59,8 @@ struct mapi_ctx {
   // call takes its buffers from it and the context allocates no device memory
   char* user_ws = nullptr;
   size_t user_ws_bytes = 0;
+  // this device's copy of the library's static scratch array (mapi_solve_noalloc)
+  char* scratch = nullptr;
   // PageRank graphs of at least this many nodes use the column-split product (0: never)
   int64_t csr_split_min_n = int64_t(1) << 20;
   mapi::SolveState* st_host = nullptr;     // pinned copy of the device state
@@ -215,6 +217,10 @@ size_t dense_ws_bytes(int64_t n, int cu_count);
 mapi_status check_solve_args(const mapi_dense* A, const float* w0, const float* w_out, const mapi_opts* o, bool rpi);
 mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* w_out, const mapi_opts* o,
                       mapi_info* info, bool rpi, char* ws);
+
+// This device's address of the library's static scratch array (noalloc.hip); the
+// device must be current.  Called by mapi_create, once per device.
+mapi_status scratch_setup(int device, char** out);
 
 inline mapi_status sync_and_state(mapi_ctx* c, const SolveState* st_dev) {
   HIP_TRY(hipMemcpyAsync(c->st_host, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, c->stream));
