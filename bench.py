@@ -629,6 +629,27 @@ def bench_pca(mp, ctx, torch, D=4096, N=65536, k=8, seed=77):
         torch.cuda.synchronize()
         out[f"pca_{meth}_kernel_ms"] = {kind: ctx.timing_get(kind)[0] for kind in ("gram", "mavp", "finalize", "deflate")}
         ctx.timing(False)
+        if meth == "mapi":
+            p_mapi = P[:, 0].clone()
+    # the factored operator X (+) (X^T (+) w) / N (not a method of the paper): the first vector to
+    # the same stop rule, streaming X twice per iteration instead of building A once
+    log("PCA: factored operator, first vector")
+    mp.mapi_factored_solve(X, W0[:, 0].contiguous(), max_iters=2, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wf, inf = mp.mapi_factored_solve(X, W0[:, 0].contiguous(), max_iters=1000, tol=1e-6, check_every=8,
+                                     stall_iters=STALL, ctx=ctx)
+    torch.cuda.synchronize()
+    s = time.perf_counter() - t0
+    wf2 = wf.double() / torch.linalg.norm(wf.double())
+    out["factored_iters"] = inf["iters"]
+    out["factored_converged"] = inf["converged"]
+    out["factored_ms"] = s * 1e3
+    out["factored_ms_per_iteration"] = s * 1e3 / max(inf["iters"], 1)
+    out["factored_gbs"] = 2.0 * 4.0 * D * N * inf["iters"] / s / 1e9     # X read twice per iteration
+    out["factored_abs_cos_vs_mapi_vector"] = float(abs(torch.dot(wf2, p_mapi.double())))
+    log(f"PCA factored: {inf['iters']} iterations in {s * 1e3:.1f} ms, {out['factored_gbs']:.0f} GB/s, "
+        f"|cos| to the MAPI vector {out['factored_abs_cos_vs_mapi_vector']:.4f}")
     del X, clean
     return out
 

@@ -135,8 +135,9 @@ typedef enum mapi_ws_kind {
   MAPI_WS_IMAGE = 8,         /* mapi_image_reconstruct: n = P pixels, nnz = N images */
   MAPI_WS_MINIBATCH = 9,     /* mapi_minibatch as the context would run it: n = D,
                                 nnz = runs (batch matrices of up to 256 MiB)      */
-  MAPI_WS_MINIBATCH_MIN = 10 /* mapi_minibatch's least workspace (batch matrices of
+  MAPI_WS_MINIBATCH_MIN = 10,/* mapi_minibatch's least workspace (batch matrices of
                                 one step of t per launch): n = D, nnz = runs      */
+  MAPI_WS_FACTORED = 11      /* mapi_factored_solve: n = D, nnz = N samples        */
 } mapi_ws_kind;
 
 /* Bytes of caller workspace that any call of `kind` at that size needs (an upper
@@ -365,6 +366,21 @@ mapi_status mapi_mingram(mapi_ctx* ctx, const float* X, int64_t D, int64_t N, in
 mapi_status mapi_pca_topk(mapi_ctx* ctx, const float* X, int64_t D, int64_t N, int64_t ldx,
                           int32_t k, double scale, int32_t method, const float* W0,
                           float* P_out, const mapi_opts* opts, mapi_info* info_k);
+
+/* A variant that is NOT a method of the paper, for comparison with the PCA form:
+ * power iteration with the factored operator
+ *   z = X^T (+) w   (z_k = sum_i op(X_ik, w_i), the columns of X against w)
+ *   y = scale * (X (+) z)   (y_i = sum_k op(X_ik, z_k), the rows of X against z)
+ *   w <- y / ||y||_1, residual ||w_t - w_{t-1}||_1, stop rule as mapi_solve.
+ * The paper forms A = scale * X (+) X^T first (eq. 5) and iterates on A; (+) is not
+ * associative, so this is a different operator.  It never forms the D x D matrix and
+ * streams X twice per iteration.  X: device float32 D x N, row-major (samples as
+ * columns), base and row pitch ldx 16-byte aligned.  opts->op MAPI_OP_MIN1 or
+ * MAPI_OP_MIN2 (else MAPI_ERR_UNSUPPORTED); w0, w_out: device float[D] (may alias);
+ * info->norm is the normaliser of y, scale included.  Float32 sums (the column sums
+ * in row chunks added in a fixed order), float64 normaliser and residual.          */
+mapi_status mapi_factored_solve(mapi_ctx* ctx, const float* X, int64_t D, int64_t N, int64_t ldx, double scale,
+                                const float* w0, float* w_out, const mapi_opts* opts, mapi_info* info);
 
 /* ---------------------------------------------------------------- PageRank */
 

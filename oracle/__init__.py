@@ -26,6 +26,7 @@ from .pagerank import (  # noqa: F401
     pagerank_rpi_csr, pagerank,
 )
 from .minibatch import minibatch_mapi  # noqa: F401
+from .factored import factored_product, factored_mapi  # noqa: F401
 from .image import min_outer, minouter_deflate, minouter_reconstruct, image_reconstruct, psnr  # noqa: F401
 from .quant import (  # noqa: F401
     bf16_decode, bf16_encode, e4m3fn_table, e4m3fn_decode, e4m3fn_encode,

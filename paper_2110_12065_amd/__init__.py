@@ -22,7 +22,7 @@ OPS = {"min1": 0, "min2": 1, "diamond": 2, "dot": 3}
 METHODS = {"mapi": 0, "rpi": 1}
 KERNELS = {"mavp": 0, "finalize": 1, "gram": 2, "csr": 3, "deflate": 4, "batched": 5, "minibatch": 6}
 WORKSPACE = {"solve": 0, "hybrid": 1, "pagerank": 2, "pagerank_f64": 3, "product": 4, "mingram": 5, "pca": 6,
-             "pca_vector": 7, "image": 8, "minibatch": 9, "minibatch_min": 10}
+             "pca_vector": 7, "image": 8, "minibatch": 9, "minibatch_min": 10, "factored": 11}
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_ALLOC", 3: "ERR_HIP", 4: "ERR_DEGENERATE", 5: "ERR_BUDGET",
           6: "ERR_UNSUPPORTED", 7: "ERR_PENDING", 8: "ERR_TIMEOUT"}
 
@@ -105,6 +105,8 @@ _SIGS = {
     "mapi_pagerank_f64": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
                                     C.POINTER(Opts), C.POINTER(Info)]),
     "mapi_pagerank_split_config": (C.c_int, [C.c_void_p, C.c_int64]),
+    "mapi_factored_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_double,
+                                      C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]),
     "mapi_hybrid_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts),
                                     C.POINTER(Opts), C.POINTER(Info), C.POINTER(Info)]),
     "mapi_image_reconstruct": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_int32,
@@ -454,6 +456,25 @@ def mapi_pagerank(row_ptr, col, val, alpha=0.85, method="mapi", w0=None, max_ite
     _check(fn(c.handle, C.byref(H), float(alpha), METHODS[method],
               C.c_void_p(w0.data_ptr()) if w0 is not None else None,
               C.c_void_p(w_out.data_ptr()), C.byref(o), C.byref(info)))
+    return w_out, info.as_dict()
+
+
+def mapi_factored_solve(X, w0, scale=None, max_iters=100, tol=0.0, op="min1", final_l2=False, check_every=0,
+                        stall_iters=0, w_out=None, ctx=None):
+    """Power iteration with the factored operator X (+) (X^T (+) w) * scale (not a method of the
+    paper; see include/mapi.h).  X: device float32 D x N.  Returns (w, info)."""
+    import torch
+    c = _ctx_of(ctx, X)
+    if X.dtype != torch.float32 or X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a 2-D float32 tensor with unit column stride")
+    D, N = X.shape
+    if w_out is None:
+        w_out = torch.empty(D, dtype=torch.float32, device=X.device)
+    o = _opts(max_iters, tol, op, final_l2, check_every, stall_iters)
+    info = Info()
+    _check(lib().mapi_factored_solve(c.handle, C.c_void_p(X.data_ptr()), D, N, X.stride(0),
+                                     float(1.0 / N if scale is None else scale), C.c_void_p(_vec(w0, D, "w0")),
+                                     C.c_void_p(_vec(w_out, D, "w_out")), C.byref(o), C.byref(info)))
     return w_out, info.as_dict()
 
 

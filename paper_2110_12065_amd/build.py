@@ -20,7 +20,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmapi.so")
 
 SOURCES = ["k_dense_f32.hip", "k_dense_bf16.hip", "k_dense_fp8.hip", "k_dense.hip", "k_quant.hip", "k_csr.hip", "k_csr_split.hip",
-           "k_gram.hip", "k_small.hip", "k_minibatch.hip", "k_image.hip", "k_batched.hip", "batch.hip", "serve.hip", "api.hip", "noalloc.hip"]
+           "k_gram.hip", "k_factored.hip", "k_small.hip", "k_minibatch.hip", "k_image.hip", "k_batched.hip", "batch.hip", "serve.hip", "api.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

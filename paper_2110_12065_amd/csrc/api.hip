@@ -282,7 +282,7 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
     HIP_TRY(launch_finalize(0, yb[it & 1], wb[it & 1], wb[(it & 1) ^ 1], n, st, pp[it & 1], P, norm, part, nullptr,
                             0.0, 0.0, c->stream, it >= 1 ? rp[it & 1] : nullptr, P));
   }
-  HIP_TRY(launch_finish(wb[0], wb[1], w_out, n, st, o->final_l2, c->stream));
+  HIP_TRY(launch_finish(wb[0], wb[1], w_out, n, st, o->final_l2, c->stream, part));
   if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
   fill_info(info, *c->st_host);
   if (c->st_host->status == MAPI_ERR_DEGENERATE)
@@ -395,6 +395,21 @@ size_t product_ws_bytes(int64_t n_rows, int64_t n_cols) {
   return align_up(sizeof(float) * (size_t)n_cols) + align_up(sizeof(float) * (size_t)n_rows);
 }
 
+// Region of mapi_factored_solve: a dense solve's buffers for the D rows of X, then the
+// column product's chunk partials (RC x N floats) and z (N floats).
+struct FactLayout {
+  size_t o_d, o_zp, o_z, total;
+};
+FactLayout factored_layout(int64_t D, int64_t N, int cu_count) {
+  FactLayout f;
+  Layout L;
+  f.o_d = L.take(dense_ws_bytes(D, cu_count));
+  f.o_zp = L.take(sizeof(float) * (size_t)col_product_chunks(D) * (size_t)N);
+  f.o_z = L.take(sizeof(float) * (size_t)N);
+  f.total = L.off;
+  return f;
+}
+
 // mapi_solve / rpi_solve: checks, then the solve in the context's (or the caller's) workspace.
 mapi_status solve_entry(mapi_ctx* c, const mapi_dense* A, const float* w0, float* w_out, const mapi_opts* o,
                         mapi_info* info, bool rpi) {
@@ -449,7 +464,7 @@ mapi_status pagerank_run(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t m
   if (split) {
     sp = split_csr_place(base + l.o_split, n, H->nnz, sizeof(T));
     HIP_TRY(hipMemsetAsync(sp.flags, 0, sizeof(int32_t), c->stream));
-    HIP_TRY(launch_split_count(H->row_ptr, H->col, sp, c->stream));
+    HIP_TRY(launch_split_count(H->row_ptr, H->col, H->val, sp, c->stream));
     int32_t flags_h = 0;
     HIP_TRY(hipMemcpyAsync(&flags_h, sp.flags, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -495,9 +510,9 @@ mapi_status pagerank_run(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t m
     }
   }
   if constexpr (sizeof(T) == 4)
-    HIP_TRY(launch_finish(wb[0], wb[1], w_out, n, st, o->final_l2, c->stream));
+    HIP_TRY(launch_finish(wb[0], wb[1], w_out, n, st, o->final_l2, c->stream, part));
   else
-    HIP_TRY(launch_finish_f64(wb[0], wb[1], w_out, n, st, o->final_l2, c->stream));
+    HIP_TRY(launch_finish_f64(wb[0], wb[1], w_out, n, st, o->final_l2, c->stream, part));
   if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
   fill_info(info, *c->st_host);
   if (c->st_host->status == MAPI_ERR_DEGENERATE)
@@ -601,6 +616,10 @@ mapi_status mapi_workspace_size(const mapi_ctx* c, int32_t kind, int64_t n, int6
       if (nnz <= 0 || nnz > INT32_MAX) return fail(MAPI_ERR_ARG, "nnz (the run count) must be positive");
       if (n > minibatch_max_d()) return fail(MAPI_ERR_UNSUPPORTED, "D > %d", minibatch_max_d());
       *bytes = minibatch_bytes((int)n, minibatch_range((int)n, INT32_MAX, (int)nnz), (int)nnz);
+      break;
+    case MAPI_WS_FACTORED:
+      if (nnz <= 0 || nnz > INT32_MAX) return fail(MAPI_ERR_ARG, "nnz (the sample count N) must be positive");
+      *bytes = factored_layout(n, nnz, cu).total;
       break;
     case MAPI_WS_MINIBATCH_MIN:
       if (nnz <= 0 || nnz > INT32_MAX) return fail(MAPI_ERR_ARG, "nnz (the run count) must be positive");
@@ -878,6 +897,63 @@ mapi_status mapi_hybrid_solve(mapi_ctx* c, const mapi_dense* A, const float* w0,
   o1.final_l2 = 1;     // the hand-over vector has unit l2 norm
   if ((s = run_dense(c, A, w0, mid, &o1, info_mapi, false, ws)) != MAPI_OK) return s;
   return run_dense(c, A, mid, w_out, rpi_o, info_rpi, true, ws);
+}
+
+mapi_status mapi_factored_solve(mapi_ctx* c, const float* X, int64_t D, int64_t N, int64_t ldx, double scale,
+                                const float* w0, float* w_out, const mapi_opts* o, mapi_info* info) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  if (!X || !w0 || !w_out) return fail(MAPI_ERR_ARG, "X, w0 and w_out must be device pointers");
+  if (D <= 0 || N <= 0 || ldx < N || D > INT32_MAX || N > INT32_MAX) return fail(MAPI_ERR_ARG, "bad shape");
+  if (!aligned16(X) || ldx % 4 != 0) return fail(MAPI_ERR_ARG, "X base and row pitch must be 16-byte aligned");
+  if (!(scale > 0.0) || !(scale < INFINITY)) return fail(MAPI_ERR_ARG, "scale must be positive and finite");
+  mapi_status s;
+  if ((s = check_opts(o)) != MAPI_OK) return s;
+  if (o->op != MAPI_OP_MIN1 && o->op != MAPI_OP_MIN2)
+    return fail(MAPI_ERR_UNSUPPORTED, "the factored operator is built for the min1 and min2 products");
+  HIP_TRY(hipSetDevice(c->device));
+  const FactLayout fl = factored_layout(D, N, c->cu_count);
+  char* base = nullptr;
+  if ((s = acquire(c, &c->ws, &c->ws_bytes, fl.total, &base)) != MAPI_OK) return s;
+  DenseBufs B;
+  dense_layout(D, c->cu_count, base + fl.o_d, &B);
+  float* zpart = reinterpret_cast<float*>(base + fl.o_zp);
+  float* z = reinterpret_cast<float*>(base + fl.o_z);
+  const DenseArgs da{X, ldx, D, N, MAPI_F32, nullptr};
+  const DenseTuning t = tuning_for(c, da);
+  const int P = dense_part_count(da, t, c->cu_count);
+  if (P > dense_part_bound(D, c->cu_count)) return fail(MAPI_ERR_ARG, "launch shape exceeds the partial bound");
+  SolveState* st = B.st;
+  HIP_TRY(hipMemcpyAsync(B.wb[0], w0, sizeof(float) * D, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(launch_state_init(st, o->max_iters, o->tol, o->stall_iters, c->stream));
+  const int check = o->check_every > 0 ? o->check_every : 16;
+  for (int it = 0; it < o->max_iters; ++it) {
+    float* wc = B.wb[it & 1];
+    {
+      Timed tm(c, MAPI_K_MAVP);
+      HIP_TRY(launch_col_product(o->op, X, D, N, ldx, wc, zpart, z, st, c->stream));
+    }
+    {
+      DenseArgs dl = da;
+      TimedLaunch tm(c, MAPI_K_MAVP, &dl);
+      HIP_TRY(launch_mavp_dense(dl, o->op, z, B.yb[0], B.pp[0], st, NORM_L1, t, c->cu_count, c->stream));
+    }
+    {
+      Timed tm(c, MAPI_K_FINALIZE);
+      HIP_TRY(launch_finalize(0, B.yb[0], wc, B.wb[(it & 1) ^ 1], D, st, B.pp[0], P, NORM_L1, B.part, nullptr, 0.0,
+                              0.0, c->stream));
+    }
+    if ((it + 1) % check == 0 && it + 1 < o->max_iters) {
+      if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
+      if (c->st_host->done) break;
+    }
+  }
+  HIP_TRY(launch_finish(B.wb[0], B.wb[1], w_out, D, st, o->final_l2, c->stream, B.part));
+  if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
+  fill_info(info, *c->st_host);
+  if (info) info->norm *= scale;    // the normaliser of scale * (X (+) z)
+  if (c->st_host->status == MAPI_ERR_DEGENERATE)
+    return fail(MAPI_ERR_DEGENERATE, "normaliser was zero or not finite after %d iterations", c->st_host->iter);
+  return MAPI_OK;
 }
 
 mapi_status mapi_quantize(mapi_ctx* c, const float* A, int64_t n_rows, int64_t n_cols, int64_t lda, int32_t dtype,

@@ -246,10 +246,12 @@ bool small_solve_fits(int64_t n, int op);
 constexpr int kSmallMaxIters = 1 << 16;   // longer solves launch per iteration
 hipError_t launch_solve_small(int op, const float* A, int64_t ld, int64_t n, const float* w0, float* out,
                               SolveState* st, int norm, int final_l2, hipStream_t s);
+// Vectors of more than 65536 elements use many blocks; `part` (device, at least
+// min(256, ceil(n / 4096)) doubles, free for this use) then holds their partial sums.
 hipError_t launch_finish(const float* w0buf, const float* w1buf, float* out, int64_t n, SolveState* st, int final_l2,
-                         hipStream_t s);
+                         hipStream_t s, double* part = nullptr);
 hipError_t launch_finish_f64(const double* w0buf, const double* w1buf, double* out, int64_t n, SolveState* st,
-                             int final_l2, hipStream_t s);
+                             int final_l2, hipStream_t s, double* part = nullptr);
 
 hipError_t launch_quant_bf16(const float* A, int64_t n_rows, int64_t n_cols, int64_t lda, uint16_t* out,
                              int64_t ldo, hipStream_t s);
@@ -285,13 +287,21 @@ struct SplitCsr {
   float* val = nullptr;
   void* part = nullptr;
   int32_t* flags = nullptr;
+  int32_t* deg = nullptr;      // estimated links per source (hub ranking)
+  int32_t* slot = nullptr;     // LDS slot of a hub source, -1 otherwise
+  int32_t* hubs = nullptr;     // hub sources per block, by slot
+  int32_t* nhub = nullptr;     // hubs per block
+  int32_t* thr = nullptr;      // hub degree threshold per block
+  int32_t* hist = nullptr;     // degree histogram per block
+  int32_t* tsum = nullptr;     // tile sums of the offset scan
 };
 // Device bytes of the split copy for an iterate of es bytes per element, and its placement.
 size_t split_csr_bytes(int64_t n, int64_t nnz, size_t es);
 SplitCsr split_csr_place(void* ws, int64_t n, int64_t nnz, size_t es);
 // Count block-row lengths (flags must be zero; bit 0 set when a block row is too long for
 // the split layout), then, only if it is not, fill the offsets and the split entries.
-hipError_t launch_split_count(const int32_t* row_ptr, const int32_t* col, const SplitCsr& s, hipStream_t st);
+hipError_t launch_split_count(const int32_t* row_ptr, const int32_t* col, const float* val, const SplitCsr& s,
+                              hipStream_t st);
 hipError_t launch_split_fill(const int32_t* row_ptr, const int32_t* col, const float* val, const SplitCsr& s,
                              hipStream_t st);
 // Normaliser partials written by the split product (its combine kernel's grid).
@@ -322,6 +332,13 @@ hipError_t launch_img_minouter_deflate(int op, const float* C, int64_t P, int64_
                                        double* sums, int G, float* Cd, hipStream_t s);
 hipError_t launch_img_reconstruct(int op, const float* W, const float* Vc, int64_t P, int N, int64_t ldc,
                                   const float* m, float* R, int64_t ldr, hipStream_t s);
+
+// Column products z = X^T (+) w (op MIN1 or MIN2) of the factored operator: RC =
+// col_product_chunks(D) row chunks written to zpart (RC x N floats), then summed in
+// chunk order into z (N floats).  Skipped once the solve state is done.
+int col_product_chunks(int64_t D);
+hipError_t launch_col_product(int op, const float* X, int64_t D, int64_t N, int64_t ldx, const float* w,
+                              float* zpart, float* z, const SolveState* st, hipStream_t s);
 
 // Per-run outcome of the mini-batch kernel.
 struct MbRun {

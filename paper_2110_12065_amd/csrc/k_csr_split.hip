@@ -18,6 +18,19 @@
 //   colS, valS       nnz     block 0's rows in order, then block 1's, ...; within a
 //                            block row the entries keep their order in the input row
 //   part[k * n + i]  T       block k's partial sum of row i (per product)
+//
+// Hub sources.  Out-degrees here are Zipf-distributed: a few thousand sources per
+// block hold about half of its links, and the gathers of each such source land on one
+// L2 line up to hundreds of thousands of times per product.  The kSplitHubSlots
+// sources of each block with the most links (above a power-of-two threshold chosen per
+// block) are therefore "hubs": every workgroup copies their iterate values into LDS
+// once per product, and their links carry the LDS slot (stored as ~slot, a negative
+// index) instead of the source, which takes about half of the gathers off the L2.
+// Which sources are hubs and which slot each gets changes no value.
+//   deg[j]           int32   estimated links with source j (1 / its link value, from a
+//                            sample of the rows)
+//   slot[j]          int32   LDS slot of hub j, -1 otherwise
+//   hubs[k * H + s]  int32   source held in slot s of block k; nhub[k] slots in use
 #include "common.h"
 
 namespace mapi {
@@ -25,9 +38,29 @@ namespace mapi {
 constexpr int kSplitBlocks = 8;      // column blocks: one per XCD
 constexpr int kSplitChunk = 64;      // rows per base entry (one wave, one lane per row)
 constexpr int kSplitMaxLen = 255;    // block-row lengths fit uint8 below this
+#ifndef MAPI_SPLIT_HUB_SLOTS
+#define MAPI_SPLIT_HUB_SLOTS 2048
+#endif
+constexpr int kSplitHubSlots = MAPI_SPLIT_HUB_SLOTS;   // hub sources per block held in LDS
+constexpr int kSplitHubMinDeg = 32;  // no hub below this many links
 
 int64_t split_block_cols(int64_t n) { return (n + kSplitBlocks - 1) / kSplitBlocks; }
 int64_t split_chunks(int64_t n) { return (n + kSplitChunk - 1) / kSplitChunk; }
+
+// j / bcols for 0 <= j < 2^31 without a 64-bit division: a float estimate corrected by
+// one step either way (the estimate is within one of the quotient).
+__device__ __forceinline__ int block_of(int32_t j, int32_t bcols, float inv_bcols) {
+  int k = (int)((float)j * inv_bcols);
+  if (k * bcols > j) --k;
+  else if ((k + 1) * bcols <= j) ++k;
+  return k;
+}
+
+// Hub ranking of a link: a column-stochastic link value of a graph is 1 / out-degree of
+// its source, so its reciprocal estimates that count.
+__device__ __forceinline__ int32_t degree_estimate(float h) {
+  return (h > 0.0f && h <= 1.0f) ? (int32_t)fminf(1.0f / h + 0.5f, 1.0e9f) : 1;
+}
 
 // Exclusive prefix sum over the 64 lanes of a wave (int).
 __device__ __forceinline__ int wave_excl_scan(int v) {
@@ -45,9 +78,11 @@ __device__ __forceinline__ int wave_excl_scan(int v) {
 // rows) and each chunk's total per block.  flags bit 0: some block row has kSplitMaxLen
 // or more entries (the split layout is not used); the CSR was validated before.
 __global__ void __launch_bounds__(256)
-k_split_count(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, int64_t n, int64_t bcols,
-              uint8_t* __restrict__ len, int32_t* __restrict__ csum, int64_t nch, int32_t* __restrict__ flags) {
+k_split_count(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const float* __restrict__ val,
+              int64_t n, int64_t bcols, uint8_t* __restrict__ len, int32_t* __restrict__ csum, int64_t nch,
+              int32_t* __restrict__ flags, int32_t* __restrict__ deg) {
   const int lane = threadIdx.x & (kWave - 1);
+  const float inv_bcols = 1.0f / (float)bcols;
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
   for (int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; c < nch; c += waves) {
     const int64_t i = c * kSplitChunk + lane;
@@ -56,10 +91,16 @@ k_split_count(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ c
     for (int k = 0; k < kSplitBlocks; ++k) cnt[k] = 0;
     if (i < n) {
       const int32_t p1 = row_ptr[i + 1];
+      // hub ranking from the link values (no atomic per link: the busiest sources have
+      // millions); rows i = 0 mod 8 suffice to see every source with more than a few
+      // dozen links, and any estimate is valid -- a hub only moves where its value is read
+      const bool sample = (i & 7) == 0;
       for (int32_t p = row_ptr[i]; p < p1; ++p) {
-        const int kb = (int)((int64_t)col[p] / bcols);
+        const int32_t j = col[p];
+        const int kb = block_of(j, (int32_t)bcols, inv_bcols);
 #pragma unroll
         for (int k = 0; k < kSplitBlocks; ++k) cnt[k] += (kb == k) ? 1 : 0;
+        if (sample) deg[j] = degree_estimate(val[p]);
       }
     }
     bool over = false;
@@ -76,32 +117,129 @@ k_split_count(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ c
   }
 }
 
-// Exclusive scan of the chunk totals of every block in block order, in place, by one
-// block of 1024 threads: thread t sums a contiguous segment of the totals, the segment
-// sums are scanned across the block, then each thread rewrites its segment with running
-// offsets -- absolute positions in colS / valS.
-__global__ void __launch_bounds__(1024) k_split_scan(int32_t* __restrict__ csum, int64_t total) {
-  __shared__ int64_t sh[16];
+// Exclusive scan of the chunk totals of every block in block order, in place, so that
+// they become absolute positions in colS / valS: tiles of 1024 totals (256 threads, four
+// consecutive totals each) are summed, the tile sums scanned by one block, and each tile
+// rescanned from its offset.  Integer sums, so the order does not matter.
+constexpr int kScanTile = 1024;
+
+__device__ __forceinline__ int block_excl_scan_256(int v, int* sh, int* total) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int64_t seg = (total + blockDim.x - 1) / blockDim.x;
-  const int64_t b = (int64_t)threadIdx.x * seg, e = b + seg < total ? b + seg : total;
-  int64_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += csum[i];
-  // exclusive scan of the segment sums: within the wave, then across waves
-  int64_t x = s;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int64_t y = __shfl_up(x, off, kWave);
-    if (lane >= off) x += y;
-  }
-  if (lane == kWave - 1) sh[wave] = x;
+  const int ex = wave_excl_scan(v);
+  if (lane == kWave - 1) sh[wave] = ex + v;
   __syncthreads();
-  int64_t run = x - s;
-  for (int q = 0; q < wave; ++q) run += sh[q];
-  for (int64_t i = b; i < e; ++i) {
-    const int32_t v = csum[i];
-    csum[i] = (int32_t)run;
-    run += v;
+  int off = 0, tot = 0;
+  for (int q = 0; q < 4; ++q) {
+    if (q < wave) off += sh[q];
+    tot += sh[q];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + ex;
+}
+
+__global__ void __launch_bounds__(256) k_scan_tile_sums(const int32_t* __restrict__ v, int64_t total,
+                                                        int32_t* __restrict__ tsum) {
+  __shared__ int sh[4];
+  int s = 0;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t i = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4 + q;
+    s += i < total ? v[i] : 0;
+  }
+  int tot;
+  (void)block_excl_scan_256(s, sh, &tot);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(256) k_scan_tile_offsets(int32_t* __restrict__ tsum, int ntiles) {
+  __shared__ int sh[4];
+  int carry = 0;
+  for (int t0 = 0; t0 < ntiles; t0 += 256) {
+    const int t = t0 + threadIdx.x;
+    const int v = t < ntiles ? tsum[t] : 0;
+    int tot;
+    const int ex = block_excl_scan_256(v, sh, &tot);
+    if (t < ntiles) tsum[t] = carry + ex;
+    carry += tot;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_scan_tile_apply(int32_t* __restrict__ v, int64_t total,
+                                                         const int32_t* __restrict__ toff) {
+  __shared__ int sh[4];
+  int x[4], s = 0;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t i = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4 + q;
+    x[q] = i < total ? v[i] : 0;
+    s += x[q];
+  }
+  int tot;
+  int run = toff[blockIdx.x] + block_excl_scan_256(s, sh, &tot);
+  for (int q = 0; q < 4; ++q) {
+    const int64_t i = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4 + q;
+    if (i < total) v[i] = run;
+    run += x[q];
+  }
+}
+
+// Per block, a histogram of floor(log2(degree)) of its sources (32 bins).
+__global__ void __launch_bounds__(256)
+k_split_hub_hist(const int32_t* __restrict__ deg, int64_t n, int64_t bcols, int32_t* __restrict__ hist) {
+  __shared__ int32_t lh[kSplitBlocks * 32];
+  const float inv_bcols = 1.0f / (float)bcols;
+  for (int q = threadIdx.x; q < kSplitBlocks * 32; q += blockDim.x) lh[q] = 0;
+  __syncthreads();
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const int d = deg[j];
+    if (d >= kSplitHubMinDeg) atomicAdd(&lh[block_of((int32_t)j, (int32_t)bcols, inv_bcols) * 32 + (31 - __clz(d))], 1);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < kSplitBlocks * 32; q += blockDim.x)
+    if (lh[q]) atomicAdd(&hist[q], lh[q]);
+}
+
+// Per block, the smallest power-of-two degree threshold (at least kSplitHubMinDeg) above
+// which at most kSplitHubSlots sources lie; the sources at or above it are the hubs.
+__global__ void k_split_hub_threshold(const int32_t* __restrict__ hist, int32_t* __restrict__ thr,
+                                      int32_t* __restrict__ nhub) {
+  const int k = threadIdx.x;
+  if (k >= kSplitBlocks) return;
+  int cum = 0, b = 31;
+  for (; b >= 0; --b) {
+    if (cum + hist[k * 32 + b] > kSplitHubSlots) break;
+    cum += hist[k * 32 + b];
+  }
+  const int t = b + 1;    // bins t..31 fit the slots
+  thr[k] = t >= 31 ? INT32_MAX : max(kSplitHubMinDeg, 1 << t);
+  nhub[k] = 0;
+}
+
+// Slots of the hubs (any order: a slot only places a value in LDS).
+__global__ void __launch_bounds__(256)
+k_split_hub_assign(const int32_t* __restrict__ deg, int64_t n, int64_t bcols, const int32_t* __restrict__ thr,
+                   int32_t* __restrict__ nhub, int32_t* __restrict__ slot, int32_t* __restrict__ hubs) {
+  // one atomic per wave and block: the wave's hubs of block k take consecutive slots
+  const int lane = threadIdx.x & (kWave - 1);
+  const float inv_bcols = 1.0f / (float)bcols;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); j0 < n; j0 += stride) {
+    const int64_t j = j0 + lane;
+    const int k = j < n ? block_of((int32_t)j, (int32_t)bcols, inv_bcols) : -1;
+    const bool hub = j < n && deg[j] >= thr[k];
+    int32_t s = -1;
+#pragma unroll
+    for (int kk = 0; kk < kSplitBlocks; ++kk) {
+      const uint64_t m = __ballot(hub && k == kk);
+      if (m == 0) continue;
+      const int first = __ffsll((unsigned long long)m) - 1;
+      int base = 0;
+      if (lane == first) base = atomicAdd(&nhub[kk], __popcll(m));
+      base = __shfl(base, first, kWave);
+      if (hub && k == kk) s = base + __popcll(m & ((1ull << lane) - 1ull));
+    }
+    if (s >= kSplitHubSlots) s = -1;    // cannot happen: the threshold admits at most kSplitHubSlots
+    if (s >= 0) hubs[k * kSplitHubSlots + s] = (int32_t)j;
+    if (j < n) slot[j] = s;
   }
 }
 
@@ -110,7 +248,9 @@ __global__ void __launch_bounds__(1024) k_split_scan(int32_t* __restrict__ csum,
 __global__ void __launch_bounds__(256)
 k_split_scatter(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const float* __restrict__ val,
                 int64_t n, int64_t bcols, const uint8_t* __restrict__ len, const int32_t* __restrict__ base,
-                int64_t nch, int32_t* __restrict__ colS, float* __restrict__ valS) {
+                int64_t nch, const int32_t* __restrict__ slot, const int32_t* __restrict__ thr,
+                int32_t* __restrict__ colS, float* __restrict__ valS) {
+  const float inv_bcols = 1.0f / (float)bcols;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
   for (int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; c < nch; c += waves) {
@@ -125,7 +265,7 @@ k_split_scatter(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__
       const int32_t p1 = row_ptr[i + 1];
       for (int32_t p = row_ptr[i]; p < p1; ++p) {
         const int32_t j = col[p];
-        const int kb = (int)((int64_t)j / bcols);
+        const int kb = block_of(j, (int32_t)bcols, inv_bcols);
         int dst = 0;
 #pragma unroll
         for (int k = 0; k < kSplitBlocks; ++k) {
@@ -134,77 +274,185 @@ k_split_scatter(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__
             pos[k] += 1;
           }
         }
-        colS[dst] = j;
-        valS[dst] = val[p];
+        // only a link whose own value ranks its source as a hub looks up the slot (a few
+        // thousand sources: the lookups stay in cache); a source without a slot is
+        // gathered from memory
+        const float h = val[p];
+        const int32_t hs = degree_estimate(h) >= thr[kb] ? slot[j] : -1;
+        colS[dst] = hs >= 0 ? ~hs : j;
+        valS[dst] = h;
       }
     }
   }
 }
 
-// Block k's partial sum of every row: workgroup b takes block b % K and chunks
-// b / K, b / K + G, ... (G = gridDim.x / K); within a wave lane l sums row c * 64 + l's
-// entries of the block in order.  Terms as in the plain product (k_csr.hip).
+// Block k's partial sum of every row: workgroup b takes block b % K; its waves take
+// groups of kSplitBatch consecutive chunks of 64 rows, lane l row c * 64 + l of each.
+// A chunk's links of one block are contiguous in colS / valS (about 115 here), so the
+// wave first copies them into its LDS with coalesced loads -- every byte crosses HBM
+// once -- and each lane then reads its row's links from LDS and gathers w.  A row's
+// links of one block are few (about two), so the lane issues the gathers of its first
+// kSplitFirst links together.  Working on kSplitBatch chunks at once keeps more loads in
+// flight per wave.  A chunk with more than kSplitCap links is read from HBM lane by
+// lane instead.  Each row's terms are added in link order, as in the plain product
+// (k_csr.hip).
+#ifndef MAPI_SPLIT_BATCH
+#define MAPI_SPLIT_BATCH 2
+#endif
+#ifndef MAPI_SPLIT_FIRST
+#define MAPI_SPLIT_FIRST 4
+#endif
+constexpr int kSplitBatch = MAPI_SPLIT_BATCH;
+constexpr int kSplitFirst = MAPI_SPLIT_FIRST;
+constexpr int kSplitCap = 192;        // links of one chunk staged in LDS
+constexpr int kSplitWaves = 4;        // waves per workgroup
+
 template <int METHOD, typename T>
-__global__ void __launch_bounds__(256)
+__device__ __forceinline__ T split_term(T acc, float h, T wj, float af, float cf, double ad, double cd) {
+  if constexpr (METHOD == MAPI_METHOD_MAPI) {
+    if constexpr (sizeof(T) == 4) {
+      const float g = fmaf(af, h, cf);
+      return acc + (__builtin_amdgcn_fmed3f(wj, -g, g) - __builtin_amdgcn_fmed3f(wj, -cf, cf));
+    } else {
+      const double g = ad * (double)h + cd;
+      return acc + (fmin(fmax(wj, -g), g) - fmin(fmax(wj, -cd), cd));
+    }
+  } else {
+    return fma((T)h, wj, acc);
+  }
+}
+
+template <int METHOD, typename T>
+__global__ void __launch_bounds__(kSplitWaves * kWave)
 k_csr_split_product(const uint8_t* __restrict__ len, const int32_t* __restrict__ base, const int32_t* __restrict__ colS,
                     const float* __restrict__ valS, int64_t n, int64_t nch, const T* __restrict__ w,
+                    const int32_t* __restrict__ hubs, const int32_t* __restrict__ nhub,
                     T* __restrict__ part, const SolveState* __restrict__ st, double alpha, double c) {
+  constexpr int R = kSplitBatch, E = kSplitFirst, CAP = kSplitCap;
+  constexpr int SWEEPS = CAP / kWave;
+  __shared__ int32_t lcol[kSplitWaves][R][CAP];
+  __shared__ float lval[kSplitWaves][R][CAP];
+  __shared__ T lhub[kSplitHubSlots > 0 ? kSplitHubSlots : 1];
   if (state_done(st)) return;
   const int k = blockIdx.x % kSplitBlocks;
+  if constexpr (kSplitHubSlots > 0) {
+    const int nh = min(nhub[k], kSplitHubSlots);
+    for (int q = threadIdx.x; q < nh; q += blockDim.x) lhub[q] = w[hubs[k * kSplitHubSlots + q]];
+    __syncthreads();
+  }
+  // w of a link's source: a hub's from LDS (stored as ~slot), any other's from memory
+  auto wsrc = [&](int32_t jj) -> T { return jj >= 0 ? w[jj] : lhub[~jj]; };
   const int64_t groups = gridDim.x / kSplitBlocks;
   const int lane = threadIdx.x & (kWave - 1);
-  const int wpb = blockDim.x / kWave;
+  const int wv = threadIdx.x / kWave;
   const double ad = sizeof(T) == 4 ? (double)(float)alpha : alpha;
   const double cd = sizeof(T) == 4 ? (double)(float)c : c;
   const float af = (float)ad, cf = (float)cd;
   const uint8_t* lenk = len + (int64_t)k * n;
   const int32_t* basek = base + (int64_t)k * nch;
   T* partk = part + (int64_t)k * n;
-  for (int64_t ch = (int64_t)(blockIdx.x / kSplitBlocks) * wpb + threadIdx.x / kWave; ch < nch; ch += groups * wpb) {
-    const int64_t i = ch * kSplitChunk + lane;
-    const int l = i < n ? (int)lenk[i] : 0;
-    const int32_t p0 = basek[ch] + wave_excl_scan(l);
-    T acc = T(0);
-    // two entries per step: both index and value loads issue before either gather
-    int e = 0;
-    for (; e + 1 < l; e += 2) {
-      const int32_t j0 = __builtin_nontemporal_load(colS + p0 + e);
-      const int32_t j1 = __builtin_nontemporal_load(colS + p0 + e + 1);
-      const float h0 = __builtin_nontemporal_load(valS + p0 + e);
-      const float h1 = __builtin_nontemporal_load(valS + p0 + e + 1);
-      const T w0 = w[j0], w1 = w[j1];
-      if constexpr (METHOD == MAPI_METHOD_MAPI) {
-        if constexpr (sizeof(T) == 4) {
-          const float g0 = fmaf(af, h0, cf), g1 = fmaf(af, h1, cf);
-          acc += __builtin_amdgcn_fmed3f(w0, -g0, g0) - __builtin_amdgcn_fmed3f(w0, -cf, cf);
-          acc += __builtin_amdgcn_fmed3f(w1, -g1, g1) - __builtin_amdgcn_fmed3f(w1, -cf, cf);
-        } else {
-          const double g0 = ad * (double)h0 + cd, g1 = ad * (double)h1 + cd;
-          acc += fmin(fmax(w0, -g0), g0) - fmin(fmax(w0, -cd), cd);
-          acc += fmin(fmax(w1, -g1), g1) - fmin(fmax(w1, -cd), cd);
+  const int64_t wid = (int64_t)(blockIdx.x / kSplitBlocks) * kSplitWaves + wv;
+  const int64_t nwaves = groups * kSplitWaves;
+  for (int64_t c0 = wid * R; c0 < nch; c0 += nwaves * R) {
+    int l[R], off[R], tot[R];
+    int32_t b0[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = (c0 + r) * kSplitChunk + lane;
+      l[r] = (c0 + r < nch && i < n) ? (int)lenk[i] : 0;
+      b0[r] = c0 + r < nch ? basek[c0 + r] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      off[r] = wave_excl_scan(l[r]);
+      tot[r] = __shfl(off[r] + l[r], kWave - 1, kWave);
+    }
+    // the chunks' links into LDS: coalesced, every load of all R chunks issued first
+    int32_t sc[R][SWEEPS];
+    float sv[R][SWEEPS];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int q = 0; q < SWEEPS; ++q) {
+        const int e = q * kWave + lane;
+        sc[r][q] = 0;
+        sv[r][q] = 0.0f;
+        if (tot[r] <= CAP && e < tot[r]) {
+          sc[r][q] = __builtin_nontemporal_load(colS + b0[r] + e);
+          sv[r][q] = __builtin_nontemporal_load(valS + b0[r] + e);
         }
-      } else {
-        acc = fma((T)h0, w0, acc);
-        acc = fma((T)h1, w1, acc);
+      }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int q = 0; q < SWEEPS; ++q) {
+        const int e = q * kWave + lane;
+        if (tot[r] <= CAP && e < tot[r]) {
+          lcol[wv][r][e] = sc[r][q];
+          lval[wv][r][e] = sv[r][q];
+        }
+      }
+    // the wave's LDS writes before its reads of other lanes' entries
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // first E links of every row: indices and values, then all gathers, then the terms
+    int32_t j[R][E];
+    float h[R][E];
+    T wj[R][E];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        j[r][e] = 0;
+        h[r][e] = 0.0f;
+        if (e < l[r]) {
+          if (tot[r] <= CAP) {
+            j[r][e] = lcol[wv][r][off[r] + e];
+            h[r][e] = lval[wv][r][off[r] + e];
+          } else {
+            j[r][e] = __builtin_nontemporal_load(colS + b0[r] + off[r] + e);
+            h[r][e] = __builtin_nontemporal_load(valS + b0[r] + off[r] + e);
+          }
+        }
+      }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int e = 0; e < E; ++e) wj[r][e] = e < l[r] ? wsrc(j[r][e]) : T(0);
+    T acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      acc[r] = T(0);
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (e < l[r]) acc[r] = split_term<METHOD, T>(acc[r], h[r][e], wj[r][e], af, cf, ad, cd);
+    }
+    // links past the first E of a row, one at a time
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      for (int e = E; e < l[r]; ++e) {
+        int32_t jj;
+        float hh;
+        if (tot[r] <= CAP) {
+          jj = lcol[wv][r][off[r] + e];
+          hh = lval[wv][r][off[r] + e];
+        } else {
+          jj = __builtin_nontemporal_load(colS + b0[r] + off[r] + e);
+          hh = __builtin_nontemporal_load(valS + b0[r] + off[r] + e);
+        }
+        acc[r] = split_term<METHOD, T>(acc[r], hh, wsrc(jj), af, cf, ad, cd);
       }
     }
-    if (e < l) {
-      const int32_t j0 = __builtin_nontemporal_load(colS + p0 + e);
-      const float h0 = __builtin_nontemporal_load(valS + p0 + e);
-      const T w0 = w[j0];
-      if constexpr (METHOD == MAPI_METHOD_MAPI) {
-        if constexpr (sizeof(T) == 4) {
-          const float g0 = fmaf(af, h0, cf);
-          acc += __builtin_amdgcn_fmed3f(w0, -g0, g0) - __builtin_amdgcn_fmed3f(w0, -cf, cf);
-        } else {
-          const double g0 = ad * (double)h0 + cd;
-          acc += fmin(fmax(w0, -g0), g0) - fmin(fmax(w0, -cd), cd);
-        }
-      } else {
-        acc = fma((T)h0, w0, acc);
-      }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = (c0 + r) * kSplitChunk + lane;
+      if (c0 + r < nch && i < n) partk[i] = acc[r];
     }
-    if (i < n) partk[i] = acc;
+    // every lane's LDS reads of this group before the next group's writes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -242,7 +490,9 @@ size_t split_csr_bytes(int64_t n, int64_t nnz, size_t es) {
   const int64_t nch = split_chunks(n);
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   return al((size_t)kSplitBlocks * n) + al(sizeof(int32_t) * kSplitBlocks * nch) + al(sizeof(int32_t) * nnz) +
-         al(sizeof(float) * nnz) + al(es * kSplitBlocks * n) + al(sizeof(int32_t));
+         al(sizeof(float) * nnz) + al(es * kSplitBlocks * n) + al(sizeof(int32_t)) + 2 * al(sizeof(int32_t) * n) +
+         al(sizeof(int32_t) * kSplitBlocks * (kSplitHubSlots + 34)) +
+         al(sizeof(int32_t) * ((kSplitBlocks * nch + kScanTile - 1) / kScanTile));
 }
 
 SplitCsr split_csr_place(void* ws, int64_t n, int64_t nnz, size_t es) {
@@ -264,20 +514,59 @@ SplitCsr split_csr_place(void* ws, int64_t n, int64_t nnz, size_t es) {
   s.part = p;
   p += al(es * kSplitBlocks * n);
   s.flags = reinterpret_cast<int32_t*>(p);
+  p += al(sizeof(int32_t));
+  s.deg = reinterpret_cast<int32_t*>(p);
+  p += al(sizeof(int32_t) * n);
+  s.slot = reinterpret_cast<int32_t*>(p);
+  p += al(sizeof(int32_t) * n);
+  s.hubs = reinterpret_cast<int32_t*>(p);          // kSplitBlocks * slots, then 8 counts,
+  s.nhub = s.hubs + kSplitBlocks * kSplitHubSlots;  // 8 thresholds and 8 x 32 histogram bins
+  s.thr = s.nhub + kSplitBlocks;
+  s.hist = s.thr + kSplitBlocks;
+  p += al(sizeof(int32_t) * kSplitBlocks * (kSplitHubSlots + 34));
+  s.tsum = reinterpret_cast<int32_t*>(p);
   return s;
 }
 
-hipError_t launch_split_count(const int32_t* row_ptr, const int32_t* col, const SplitCsr& s, hipStream_t st) {
-  hipLaunchKernelGGL(k_split_count, dim3(split_grid(s.nch, 4, 16384)), dim3(256), 0, st, row_ptr, col, s.n,
-                     split_block_cols(s.n), s.len, s.base, s.nch, s.flags);
+__global__ void k_split_fill_i32(int32_t* __restrict__ p, int64_t count, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_split_zero(int32_t* __restrict__ p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+hipError_t launch_split_count(const int32_t* row_ptr, const int32_t* col, const float* val, const SplitCsr& s,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_split_zero, dim3(split_grid(s.n, 256, 4096)), dim3(256), 0, st, s.deg, s.n);
+  hipLaunchKernelGGL(k_split_zero, dim3(1), dim3(256), 0, st, s.hist, (int64_t)kSplitBlocks * 32);
+  hipLaunchKernelGGL(k_split_count, dim3(split_grid(s.nch, 4, 16384)), dim3(256), 0, st, row_ptr, col, val, s.n,
+                     split_block_cols(s.n), s.len, s.base, s.nch, s.flags, s.deg);
   return hipGetLastError();
 }
 
 hipError_t launch_split_fill(const int32_t* row_ptr, const int32_t* col, const float* val, const SplitCsr& s,
                              hipStream_t st) {
-  hipLaunchKernelGGL(k_split_scan, dim3(1), dim3(1024), 0, st, s.base, (int64_t)kSplitBlocks * s.nch);
+  const int64_t total = (int64_t)kSplitBlocks * s.nch;
+  const int ntiles = (int)((total + kScanTile - 1) / kScanTile);
+  hipLaunchKernelGGL(k_scan_tile_sums, dim3(ntiles), dim3(256), 0, st, s.base, total, s.tsum);
+  hipLaunchKernelGGL(k_scan_tile_offsets, dim3(1), dim3(256), 0, st, s.tsum, ntiles);
+  hipLaunchKernelGGL(k_scan_tile_apply, dim3(ntiles), dim3(256), 0, st, s.base, total, s.tsum);
+  const int64_t bcols = split_block_cols(s.n);
+  const int ng = split_grid(s.n, 256, 4096);
+  if (kSplitHubSlots > 0) {
+    hipLaunchKernelGGL(k_split_hub_hist, dim3(ng), dim3(256), 0, st, s.deg, s.n, bcols, s.hist);
+    hipLaunchKernelGGL(k_split_hub_threshold, dim3(1), dim3(64), 0, st, s.hist, s.thr, s.nhub);
+  } else {
+    hipLaunchKernelGGL(k_split_zero, dim3(1), dim3(64), 0, st, s.nhub, (int64_t)kSplitBlocks);
+    hipLaunchKernelGGL(k_split_fill_i32, dim3(1), dim3(64), 0, st, s.thr, (int64_t)kSplitBlocks, INT32_MAX);
+  }
+  hipLaunchKernelGGL(k_split_hub_assign, dim3(ng), dim3(256), 0, st, s.deg, s.n, bcols, s.thr, s.nhub, s.slot,
+                     s.hubs);
   hipLaunchKernelGGL(k_split_scatter, dim3(split_grid(s.nch, 4, 16384)), dim3(256), 0, st, row_ptr, col, val, s.n,
-                     split_block_cols(s.n), s.len, s.base, s.nch, s.col, s.val);
+                     bcols, s.len, s.base, s.nch, s.slot, s.thr, s.col, s.val);
   return hipGetLastError();
 }
 
@@ -291,13 +580,13 @@ hipError_t launch_csr_split_product(int method, const SplitCsr& s, const T* w, T
   const dim3 grid((unsigned)(groups * kSplitBlocks));
   T* part = static_cast<T*>(s.part);
   if (method == MAPI_METHOD_MAPI) {
-    hipLaunchKernelGGL((k_csr_split_product<MAPI_METHOD_MAPI, T>), grid, dim3(256), 0, stream, s.len, s.base, s.col,
-                       s.val, s.n, s.nch, w, part, st, alpha, c);
+    hipLaunchKernelGGL((k_csr_split_product<MAPI_METHOD_MAPI, T>), grid, dim3(kSplitWaves * kWave), 0, stream, s.len,
+                       s.base, s.col, s.val, s.n, s.nch, w, s.hubs, s.nhub, part, st, alpha, c);
     hipLaunchKernelGGL((k_csr_split_combine<MAPI_METHOD_MAPI, T>), dim3(split_combine_blocks(s.n)), dim3(256), 0,
                        stream, part, s.n, y, nparts, st, alpha, c, inv_n);
   } else {
-    hipLaunchKernelGGL((k_csr_split_product<MAPI_METHOD_RPI, T>), grid, dim3(256), 0, stream, s.len, s.base, s.col,
-                       s.val, s.n, s.nch, w, part, st, alpha, c);
+    hipLaunchKernelGGL((k_csr_split_product<MAPI_METHOD_RPI, T>), grid, dim3(kSplitWaves * kWave), 0, stream, s.len,
+                       s.base, s.col, s.val, s.n, s.nch, w, s.hubs, s.nhub, part, st, alpha, c);
     hipLaunchKernelGGL((k_csr_split_combine<MAPI_METHOD_RPI, T>), dim3(split_combine_blocks(s.n)), dim3(256), 0,
                        stream, part, s.n, y, nparts, st, alpha, c, inv_n);
   }

@@ -148,6 +148,46 @@ k_finish(const T* __restrict__ w0buf, const T* __restrict__ w1buf, T* __restrict
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) out[i] = final_l2 ? (T)((double)src[i] * scale) : src[i];
 }
 
+// The same for long vectors (more than kFinishOneBlock elements), over many blocks: the
+// squares summed per block into part[], then every block sums those in block order (the
+// same bits in each) and scales or copies its share.
+constexpr int64_t kFinishOneBlock = 65536;
+static int finish_blocks(int64_t n) {
+  const int64_t b = (n + 4095) / 4096;
+  return (int)(b > 256 ? 256 : (b < 1 ? 1 : b));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_finish_sq(const T* __restrict__ w0buf, const T* __restrict__ w1buf, int64_t n, const SolveState* __restrict__ st,
+            double* __restrict__ part) {
+  __shared__ double sh[16];
+  const T* src = (st->iter & 1) ? w1buf : w0buf;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += (double)src[i] * (double)src[i];
+  s = block_sum_f64(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_finish_out(const T* __restrict__ w0buf, const T* __restrict__ w1buf, T* __restrict__ out, int64_t n,
+             SolveState* __restrict__ st, int final_l2, const double* __restrict__ part, int nparts) {
+  const T* src = (st->iter & 1) ? w1buf : w0buf;
+  double scale = 1.0;
+  if (final_l2) {
+    const double s = wave_sum_parts(part, nparts);
+    if (!(s > 0.0) || !(s < INFINITY)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) st->status = MAPI_ERR_DEGENERATE;
+      return;
+    }
+    scale = 1.0 / sqrt(s);
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = final_l2 ? (T)((double)src[i] * scale) : src[i];
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_state_init(SolveState* st, int max_iters, double tol, int stall_iters, hipStream_t s) {
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, max_iters, tol, stall_iters);
@@ -281,16 +321,27 @@ hipError_t launch_finalize(int mode, const float* y, const float* w_old, float* 
   return hipGetLastError();
 }
 
-hipError_t launch_finish(const float* w0buf, const float* w1buf, float* out, int64_t n, SolveState* st, int final_l2,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_finish<float>, dim3(1), dim3(1024), 0, s, w0buf, w1buf, out, n, st, final_l2);
+template <typename T>
+static hipError_t finish_any(const T* w0buf, const T* w1buf, T* out, int64_t n, SolveState* st, int final_l2,
+                             double* part, hipStream_t s) {
+  if (n <= kFinishOneBlock || part == nullptr) {
+    hipLaunchKernelGGL(k_finish<T>, dim3(1), dim3(1024), 0, s, w0buf, w1buf, out, n, st, final_l2);
+  } else {
+    const int b = finish_blocks(n);
+    if (final_l2) hipLaunchKernelGGL(k_finish_sq<T>, dim3(b), dim3(256), 0, s, w0buf, w1buf, n, st, part);
+    hipLaunchKernelGGL(k_finish_out<T>, dim3(b), dim3(256), 0, s, w0buf, w1buf, out, n, st, final_l2, part, b);
+  }
   return hipGetLastError();
 }
 
+hipError_t launch_finish(const float* w0buf, const float* w1buf, float* out, int64_t n, SolveState* st, int final_l2,
+                         hipStream_t s, double* part) {
+  return finish_any<float>(w0buf, w1buf, out, n, st, final_l2, part, s);
+}
+
 hipError_t launch_finish_f64(const double* w0buf, const double* w1buf, double* out, int64_t n, SolveState* st,
-                             int final_l2, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish<double>, dim3(1), dim3(1024), 0, s, w0buf, w1buf, out, n, st, final_l2);
-  return hipGetLastError();
+                             int final_l2, hipStream_t s, double* part) {
+  return finish_any<double>(w0buf, w1buf, out, n, st, final_l2, part, s);
 }
 
 hipError_t launch_finalize_f64(int mode, const double* y, const double* w_old, double* w_new, int64_t n,

@@ -160,6 +160,19 @@ def test_minibatch_in_caller_workspace(kind):
         _too_small(kind, D, runs, lambda c: mp.mapi_minibatch(X, batches, 0.2, W0, ctx=c))
 
 
+@pytest.mark.parametrize("op", ["min1", "min2"])
+def test_factored_in_caller_workspace(op):
+    D, N = 150, 2050
+    X = to_dev(synth.pca_data(D, N, seed=14))
+    w0 = to_dev(synth.start_vector(D, 15))
+    own, user, ws = _pair("factored", D, N)
+    a, ia = mp.mapi_factored_solve(X, w0, max_iters=9, op=op, ctx=own)
+    b, ib = mp.mapi_factored_solve(X, w0, max_iters=9, op=op, ctx=user)
+    assert ia == ib and _written(ws)
+    np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+    _too_small("factored", D, N, lambda c: mp.mapi_factored_solve(X, w0, max_iters=2, op=op, ctx=c))
+
+
 def test_product_calls_in_caller_workspace():
     n = 1000
     A = to_dev(synth.dense_cov(n, 1200, seed=12))
