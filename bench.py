@@ -126,7 +126,7 @@ def setup(autotune=True):
         mats[dt] = mp.mapi_quantize(C, dt, ctx=ctx)
     for dt, (A, rs) in mats.items():
         if autotune:
-            shape, ms = mp.mapi_autotune_dense(A, "min1", reps=3, row_scale=rs, ctx=ctx)
+            shape, ms = mp.mapi_autotune_dense(A, "min1", reps=4, row_scale=rs, ctx=ctx)
             log(f"autotuned {dt}: {shape} {ms * 1e3:.1f} us")
         else:
             log(f"launch shape {dt}: {mp.mapi_tuning_get(mp._dtype_code(A), N, N, ctx=ctx)}")
@@ -153,11 +153,24 @@ def run_kernels_mode():
     plain = mp.Context()
     mp.mapi_pagerank_split_config(0, ctx=plain)
     mp.mapi_pagerank(rp, col, val, 0.85, "mapi", max_iters=3, check_every=3, ctx=plain)
+    del rp, col, val
+    # one min-covariance build (min1) of the PCA workload, 4096 x 65536
+    import synth
+    X, clean = synth.pca_data_device(4096, 65536, 77, "cuda")
+    del clean
+    mp.mapi_mingram(X, 1.0 / 65536, "min1", ctx=ctx)
     torch.cuda.synchronize()
     log("kernels mode done")
 
 
 # ------------------------------------------------------------------ profile summaries
+def _bench_line(path):
+    """The last JSON line of a benchmark log (a profiler may print after it)."""
+    with open(path) as f:
+        lines = [x for x in f.read().splitlines() if x.startswith("{")]
+    return json.loads(lines[-1]) if lines else {}
+
+
 def _read_csvs(d, pattern):
     rows = []
     for p in glob.glob(os.path.join(d, "**", pattern), recursive=True):
@@ -196,8 +209,7 @@ def summarize_sections(stats_dir, cmd, bench_json=None):
     stats = _read_csvs(stats_dir, "*kernel_stats.csv")
     det = {}
     if bench_json and os.path.exists(bench_json):
-        with open(bench_json) as f:
-            det = json.loads(f.read().strip().splitlines()[-1]).get("detail", {})
+        det = _bench_line(bench_json).get("detail", {})
     lines = ["# Kernel time summary: PCA 4096 x 65536 (min-covariance and covariance builds, top-8 "
              "solves), the n = 256 solve, mini-batch MAPI (Alg. 3)", "", f"Command: `{cmd}`", "",
              "Kernels of these sections by total time (the product and normalisation rows include the "
@@ -267,17 +279,20 @@ def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write, 
     trace = _read_csvs(stats_dir, "*kernel_trace.csv")
     live = {}
     if bench_json and os.path.exists(bench_json):
-        with open(bench_json) as f:
-            det = json.loads(f.read().strip().splitlines()[-1]).get("detail", {})
+        det = _bench_line(bench_json).get("detail", {})
         live = {dt: det.get(f"mapi_{dt}", {}).get("product_kernel_us") for dt in ("f32", "bf16", "fp8")}
         live.update({f"read_{dt}": v.get("us") for dt, v in det.get("read_reference", {}).items()})
     if trace:
-        lines += ["", "Timed launches (last 100 dispatches of the MAPI min1 product per storage type) "
-                  "against the benchmark's own HIP-event timing of the same launches:", "",
+        lines += ["", "Timed launches (the last 100 dispatches of the MAPI min1 product per storage type before "
+                  "the read reference, which follows the solves; later sections launch the same kernels on "
+                  "other shapes) against the benchmark's own HIP-event timing of the same launches:", "",
                   "| storage | kernel | rocprofv3 average (us) | benchmark events (us) |", "|---|---|---|---|"]
+        reads = [int(r["Start_Timestamp"]) for r in trace if "k_read16" in r["Kernel_Name"]]
+        t_read = min(reads) if reads else float("inf")
         for dt, code in (("f32", "0"), ("bf16", "1"), ("fp8", "2")):
             ds = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), r["Kernel_Name"])
-                        for r in trace if r["Kernel_Name"].startswith(f"void mapi::k_mavp_dense<{code}, 0,"))
+                        for r in trace if r["Kernel_Name"].startswith(f"void mapi::k_mavp_dense<{code}, 0,")
+                        and int(r["Start_Timestamp"]) < t_read)
             if not ds:
                 continue
             last = ds[-100:]
@@ -362,6 +377,46 @@ def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write, 
     with open(os.path.join(ROOT, "profiles", "mavp_dense_n16384_traffic.md"), "w") as f:
         f.write("\n".join(md) + "\n")
     print(json.dumps(out, indent=1))
+
+
+LIMITER_KERNELS = (("k_mavp_dense<0, 0,", "f32 product (min1)"), ("k_mavp_dense<1, 0,", "bf16 product (min1)"),
+                   ("k_mavp_dense<2, 0,", "fp8 product (min1)"), ("k_read16", "read reference"),
+                   ("k_copy16", "copy reference"), ("k_csr_split_product<0,", "PageRank split product (MAPI)"),
+                   ("k_csr_split_combine<0,", "PageRank split combine (MAPI)"),
+                   ("k_csr_product<0,", "PageRank plain product (MAPI)"), ("k_gram_min<0,", "min-Gram build (min1)"))
+
+
+def summarize_counters(dirs, cmds, out_name="kernel_limiters_counters.md"):
+    """profiles/ summary of limiter counters (one rocprofv3 --pmc pass per directory) for the
+    dense products, the bandwidth references, the PageRank products and the min-Gram build:
+    the mean value per dispatch of each counter."""
+    table = {}
+    counters = []
+    for d in dirs:
+        for r in _read_csvs(d, "*counter_collection.csv"):
+            nm = r.get("Kernel_Name", "")
+            for key, label in LIMITER_KERNELS:
+                if key in nm:
+                    c = r["Counter_Name"]
+                    if c not in counters:
+                        counters.append(c)
+                    table.setdefault(label, {}).setdefault(c, []).append(float(r["Counter_Value"]))
+    lines = ["# Limiter counters: dense products, bandwidth references, PageRank products, min-Gram build", "",
+             "One `rocprofv3 --pmc` pass per row group of counters, each over `bench.py --mode kernels` "
+             "(n = 16384 products in the tuned shapes, the 1 GiB read and copy references, three MAPI PageRank "
+             "products at 2^22 nodes with the split and the plain layout, one min1 build at 4096 x 65536). "
+             "Values are means per dispatch.", ""]
+    lines += [f"Pass {i + 1}: `{c}`" for i, c in enumerate(cmds)] + [""]
+    lines += ["| kernel | " + " | ".join(counters) + " |", "|---" * (len(counters) + 1) + "|"]
+    for _, label in LIMITER_KERNELS:
+        if label not in table:
+            continue
+        vals = [table[label].get(c) for c in counters]
+        lines.append(f"| {label} | " + " | ".join(f"{sum(v) / len(v):.4g}" if v else "-" for v in vals) + " |")
+    out = os.path.join(ROOT, "profiles", out_name)
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    log(f"wrote {out}")
 
 
 # ------------------------------------------------------------------ other workloads
@@ -999,9 +1054,14 @@ def main():
     ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--summarize-sections", metavar="STATS_DIR",
                     help="write the kernel summary of the pca, small and minibatch sections (first --commands entry)")
-    ap.add_argument("--commands", nargs=3, default=["", "", ""], help="commands that produced the three dirs")
+    ap.add_argument("--commands", nargs="+", default=["", "", ""], help="commands that produced the dirs")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_DIR",
+                    help="write the limiter counter summary from rocprofv3 --pmc directories (with --commands)")
     ap.add_argument("--bench-json", default=None, help="JSON line printed by the profiled benchmark command")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.commands)
+        return
     if args.summarize_sections:
         summarize_sections(args.summarize_sections, args.commands[0], bench_json=args.bench_json)
         return

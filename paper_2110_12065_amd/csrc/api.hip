@@ -206,6 +206,34 @@ mapi_status check_solve_args(const mapi_dense* A, const float* w0, const float* 
   return MAPI_OK;
 }
 
+// Iteration `it` of a dense solve, enqueued: the product of w_it (which, with w staged in
+// LDS, the product forms itself from the previous y and partials: FusedPrev) and, without
+// LDS staging, the normalisation launch.  With c->alternate, odd iterations sweep the
+// rows in mirrored order, so each product starts on the rows the previous one read last,
+// which the memory-side cache may still hold.  timed: record the launches in the
+// context's kernel timing.
+hipError_t enqueue_dense_iteration(mapi_ctx* c, const DenseArgs& da, int op, int norm, const DenseTuning& t, int P,
+                                   const DenseBufs& B, int it, bool timed) {
+  const bool fused = t.w_in_lds != 0;
+  const int b = fused ? (it & 1) : 0;   // y and partials alternate when a product reads the previous ones
+  {
+    DenseArgs dl = da;
+    dl.reverse = c->alternate ? (it & 1) : 0;
+    TimedLaunch tm(c, MAPI_K_MAVP, timed ? &dl : nullptr);
+    const FusedPrev fp{B.yb[b ^ 1], B.pp[b ^ 1], P, B.wb[it & 1], it, B.wb[(it & 1) ^ 1],
+                       it >= 2 ? B.rp[b ^ 1] : nullptr, B.rp[b]};
+    hipError_t e = launch_mavp_dense(dl, op, B.wb[it & 1], B.yb[b], B.pp[b], B.st, norm, t, c->cu_count, c->stream,
+                                     (fused && it > 0) ? &fp : nullptr);
+    if (e != hipSuccess) return e;
+  }
+  if (!fused) {
+    Timed tm(c, MAPI_K_FINALIZE, timed);
+    return launch_finalize(0, B.yb[0], B.wb[it & 1], B.wb[(it & 1) ^ 1], da.n_rows, B.st, B.pp[0], P, norm, B.part,
+                           nullptr, 0.0, 0.0, c->stream);
+  }
+  return hipSuccess;
+}
+
 // Power iteration on a dense square matrix: MAPI (op, l1) or RPI (dot, l2).  Arguments
 // checked by check_solve_args; ws: device region of dense_ws_bytes(n) bytes.
 mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* w_out, const mapi_opts* o,
@@ -254,21 +282,8 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
   const int check = o->check_every > 0 ? o->check_every : 16;
   int launched = 0;
   for (int it = 0; it < o->max_iters; ++it) {
-    const int b = fused ? (it & 1) : 0;   // y and partials alternate when a product reads the previous ones
-    {
-      DenseArgs dl = da;
-      TimedLaunch tm(c, MAPI_K_MAVP, &dl);
-      const FusedPrev fp{yb[b ^ 1], pp[b ^ 1], P, wb[it & 1], it, wb[(it & 1) ^ 1], it >= 2 ? rp[b ^ 1] : nullptr,
-                         rp[b]};
-      HIP_TRY(launch_mavp_dense(dl, op, wb[it & 1], yb[b], pp[b], st, norm, t, c->cu_count, c->stream,
-                                (fused && it > 0) ? &fp : nullptr));
-    }
+    HIP_TRY(enqueue_dense_iteration(c, da, op, norm, t, P, B, it, true));
     launched = it + 1;
-    if (!fused) {
-      Timed tm(c, MAPI_K_FINALIZE);
-      HIP_TRY(launch_finalize(0, yb[0], wb[it & 1], wb[(it & 1) ^ 1], n, st, pp[0], P, norm, part, nullptr, 0.0, 0.0,
-                              c->stream));
-    }
     if ((it + 1) % check == 0 && it + 1 < o->max_iters) {
       if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
       if (c->st_host->done) break;
@@ -393,6 +408,12 @@ size_t minibatch_bytes(int D, int range, int runs) {
 // w and y, mapi_read_reference's sink).
 size_t product_ws_bytes(int64_t n_rows, int64_t n_cols) {
   return align_up(sizeof(float) * (size_t)n_cols) + align_up(sizeof(float) * (size_t)n_rows);
+}
+
+// The autotuner's: that scratch and, for a square matrix, a dense solve's buffers (its
+// trials run solve iterations).
+size_t autotune_ws_bytes(int64_t n_rows, int64_t n_cols, int cu_count) {
+  return product_ws_bytes(n_rows, n_cols) + (n_rows == n_cols ? dense_ws_bytes(n_rows, cu_count) : 0);
 }
 
 // Region of mapi_factored_solve: a dense solve's buffers for the D rows of X, then the
@@ -545,6 +566,7 @@ mapi_status mapi_create(int device, void* hip_stream, mapi_ctx** out) {
     if (prop.sharedMemPerBlock > 0) c->max_lds = (int)prop.sharedMemPerBlock;
   }
   load_tune_cache(c);
+  if (const char* e = std::getenv("MAPI_DENSE_ALTERNATE")) c->alternate = std::atoi(e) != 0;
   mapi_status ss = scratch_setup(device, &c->scratch);
   if (ss != MAPI_OK) {
     delete c;
@@ -597,7 +619,7 @@ mapi_status mapi_workspace_size(const mapi_ctx* c, int32_t kind, int64_t n, int6
       break;
     case MAPI_WS_PRODUCT:
       if (nnz <= 0) return fail(MAPI_ERR_ARG, "nnz (the column count) must be positive");
-      *bytes = product_ws_bytes(n, nnz);
+      *bytes = autotune_ws_bytes(n, nnz, cu);
       break;
     case MAPI_WS_MINGRAM:
       if (nnz <= 0) return fail(MAPI_ERR_ARG, "nnz (the sample count N) must be positive");
@@ -731,6 +753,36 @@ static mapi_status time_product(mapi_ctx* c, const DenseArgs& da, int op, const 
   return MAPI_OK;
 }
 
+// Average time of one solve iteration in shape t (square matrices): `reps` iterations
+// enqueued exactly as a solve enqueues them, after two untimed ones, on a state that never
+// stops (tolerance 0, no stall rule).  ws: dense_ws_bytes(n) bytes.  *degenerate: the
+// matrix gave a zero normaliser, so the launches returned early and the time means nothing.
+static mapi_status time_iterations(mapi_ctx* c, const DenseArgs& da, int op, const float* w0, char* ws,
+                                   const DenseTuning& t, int reps, double* avg_ms, bool* degenerate) {
+  DenseBufs B;
+  dense_layout(da.n_rows, c->cu_count, ws, &B);
+  const int norm = op == MAPI_OP_DOT ? NORM_L2 : NORM_L1;
+  const int P = dense_part_count(da, t, c->cu_count);
+  hipEvent_t a = get_event(c), b = get_event(c);
+  if (!a || !b) return fail(MAPI_ERR_HIP, "event creation failed");
+  HIP_TRY(hipMemcpyAsync(B.wb[0], w0, sizeof(float) * da.n_rows, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(launch_state_init(B.st, reps + 8, 0.0, 0, c->stream));
+  HIP_TRY(enqueue_dense_iteration(c, da, op, norm, t, P, B, 0, false));
+  HIP_TRY(enqueue_dense_iteration(c, da, op, norm, t, P, B, 1, false));
+  HIP_TRY(hipEventRecord(a, c->stream));
+  for (int it = 2; it < reps + 2; ++it) HIP_TRY(enqueue_dense_iteration(c, da, op, norm, t, P, B, it, false));
+  HIP_TRY(hipEventRecord(b, c->stream));
+  mapi_status s;
+  if ((s = sync_and_state(c, B.st)) != MAPI_OK) return s;
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, a, b));
+  c->pool.push_back(a);
+  c->pool.push_back(b);
+  *avg_ms = ms / reps;
+  *degenerate = c->st_host->done != 0;
+  return MAPI_OK;
+}
+
 mapi_status mapi_mavp_timed(mapi_ctx* c, const mapi_dense* A, const float* w, float* y, int32_t op,
                             const mapi_tuning* tu, int32_t reps, double* avg_ms) {
   if (!c || !avg_ms) return fail(MAPI_ERR_ARG, "ctx or avg_ms is NULL");
@@ -783,14 +835,20 @@ mapi_status mapi_autotune_dense(mapi_ctx* c, const mapi_dense* A, int32_t op, in
   HIP_TRY(hipSetDevice(c->device));
   const DenseArgs da = dense_args(A);
   char* base = nullptr;
-  if ((s = acquire(c, &c->ws, &c->ws_bytes, product_ws_bytes(da.n_rows, da.n_cols), &base)) != MAPI_OK) return s;
+  if ((s = acquire(c, &c->ws, &c->ws_bytes, autotune_ws_bytes(da.n_rows, da.n_cols, c->cu_count), &base)) != MAPI_OK)
+    return s;
   float* w = reinterpret_cast<float*>(base);
   float* y = reinterpret_cast<float*>(base + align_up(sizeof(float) * (size_t)da.n_cols));
+  char* dws = base + product_ws_bytes(da.n_rows, da.n_cols);
   HIP_TRY(launch_fill_f32(w, da.n_cols, 1.0f / (float)da.n_cols, c->stream));
   DenseTuning bt = dense_default_tuning(da, c->cu_count, c->max_lds);
   double bms = 1e30;
   DenseTuning bl = bt;      // fastest shape that stages w in LDS
   double blms = 1e30;
+  // A square matrix is tuned on solve iterations (the product as a solve launches it,
+  // with the iterate formed inside it or by the normalisation launch, in the solve's
+  // sweep order), unless its normaliser is zero; a rectangular one on plain products.
+  bool iterate = da.n_rows == da.n_cols;
   for (int rw : {1, 2, 4, 8}) {
     if (rw > 1 && rw > da.n_rows) continue;
     for (int waves : {4, 8})
@@ -803,7 +861,14 @@ mapi_status mapi_autotune_dense(mapi_ctx* c, const mapi_dense* A, int32_t op, in
                 continue;
               DenseTuning t{rw, waves, 0, lds, bpc, un, nt};
               double ms = 0.0;
-              if ((s = time_product(c, da, op, w, y, t, reps, &ms)) != MAPI_OK) return s;
+              bool degenerate = false;
+              if (iterate && (s = time_iterations(c, da, op, w, dws, t, reps, &ms, &degenerate)) != MAPI_OK) return s;
+              if (degenerate) {   // start over on plain products
+                iterate = false;
+                bms = blms = 1e30;
+                bt = bl = dense_default_tuning(da, c->cu_count, c->max_lds);
+              }
+              if (!iterate && (s = time_product(c, da, op, w, y, t, reps, &ms)) != MAPI_OK) return s;
               if (ms < bms) {
                 bms = ms;
                 bt = t;
@@ -814,10 +879,10 @@ mapi_status mapi_autotune_dense(mapi_ctx* c, const mapi_dense* A, int32_t op, in
               }
             }
   }
-  // Shapes that stage w in LDS let a fixed-iteration solve form each iterate inside
-  // the next product (no normalisation launch, several microseconds an iteration):
-  // they are kept when within 3 % of the fastest product.
-  if (bt.w_in_lds == 0 && blms <= 1.03 * bms) {
+  // On plain products, shapes that stage w in LDS are kept when within 3 % of the
+  // fastest: in a solve they form each iterate inside the next product (no normalisation
+  // launch, several microseconds an iteration).
+  if (!iterate && bt.w_in_lds == 0 && blms <= 1.03 * bms) {
     bt = bl;
     bms = blms;
   }
@@ -933,7 +998,10 @@ mapi_status mapi_factored_solve(mapi_ctx* c, const float* X, int64_t D, int64_t 
       HIP_TRY(launch_col_product(o->op, X, D, N, ldx, wc, zpart, z, st, c->stream));
     }
     {
+      // the column product sweeps X's rows forward: the row product goes backward from
+      // where it ended, and the next column product starts where this one ends
       DenseArgs dl = da;
+      dl.reverse = c->alternate ? 1 : 0;
       TimedLaunch tm(c, MAPI_K_MAVP, &dl);
       HIP_TRY(launch_mavp_dense(dl, o->op, z, B.yb[0], B.pp[0], st, NORM_L1, t, c->cu_count, c->stream));
     }

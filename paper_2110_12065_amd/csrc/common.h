@@ -105,13 +105,23 @@ __device__ __forceinline__ double load_agent(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Fixed-order sum of part[0..count) by one wave (lane l takes l, l + 64, ...; then
-// a butterfly): every wave that calls it gets the same bits, whatever the block
-// size, so the normaliser is identical in every kernel that forms it.
+// Fixed-order sum of part[0..count) by one wave (lane l adds l, l + 64, ... in that
+// order; then a butterfly): every wave that calls it gets the same bits, whatever the
+// block size, so the normaliser is identical in every kernel that forms it.  The
+// partials were written by an earlier launch (visible from kernel start): plain loads,
+// four per lane in flight, so that the sum costs one memory round trip per 256 partials.
 __device__ __forceinline__ double wave_sum_parts(const double* part, int count) {
   const int lane = threadIdx.x & (kWave - 1);
   double s = 0.0;
-  for (int i = lane; i < count; i += kWave) s += load_agent(&part[i]);
+  int i = lane;
+  for (; i + 3 * kWave < count; i += 4 * kWave) {
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = part[i + k * kWave];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s += v[k];
+  }
+  for (; i < count; i += kWave) s += part[i];
   return wave_sum_f64(s);
 }
 
@@ -161,6 +171,46 @@ __device__ __forceinline__ void state_advance(SolveState* st, double r) {
   }
 }
 
+// The stop rule's inputs as a kernel found them, read by the one thread that will
+// advance the rule together with the kernel's other first loads, so that advancing
+// it later waits for no memory round trip.
+struct StopSnap {
+  double best_r, tol;
+  int32_t iter, stall, max_iters, stall_iters;
+};
+__device__ __forceinline__ StopSnap stop_snap(const SolveState* st) {
+  return StopSnap{st->best_r, st->tol, st->iter, st->stall, st->max_iters, st->stall_iters};
+}
+// state_advance on a snapshot of a state that no other thread changes meanwhile; returns
+// whether the solve is done now.
+__device__ __forceinline__ bool state_advance_from(SolveState* st, const StopSnap& s, double r) {
+  const int32_t iter = s.iter + 1;
+  st->iter = iter;
+  st->r = r;
+  if (r < s.tol) {
+    st->converged = 1;
+    st->done = 1;
+    return true;
+  }
+  if (iter >= s.max_iters) {
+    st->done = 1;
+    return true;
+  }
+  if (s.stall_iters > 0) {
+    if (r < s.best_r) {
+      st->best_r = r;
+      st->stall = 0;
+    } else {
+      st->stall = s.stall + 1;
+      if (s.stall + 1 >= s.stall_iters) {
+        st->done = 1;
+        return true;
+      }
+    }
+  }
+  return false;
+}
+
 // ---------------------------------------------------------------- launchers
 struct DenseArgs {
   const void* A;
@@ -170,6 +220,7 @@ struct DenseArgs {
   const float* row_scale;
   hipEvent_t ev_start = nullptr;   // when set, attached to the launch's dispatch (kernel time)
   hipEvent_t ev_stop = nullptr;
+  int reverse = 0;                 // sweep the rows in mirrored order (see k_mavp_dense)
 };
 
 struct DenseTuning {

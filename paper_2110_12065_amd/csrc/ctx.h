@@ -63,6 +63,9 @@ struct mapi_ctx {
   char* scratch = nullptr;
   // PageRank graphs of at least this many nodes use the column-split product (0: never)
   int64_t csr_split_min_n = int64_t(1) << 20;
+  // dense solves sweep the matrix forward and backward in turn (MAPI_DENSE_ALTERNATE=1);
+  // off by default: on MI355X it measured no faster than forward sweeps only
+  bool alternate = false;
   mapi::SolveState* st_host = nullptr;     // pinned copy of the device state
   // matrices owned by the PCA driver
   void* big = nullptr;
@@ -153,8 +156,8 @@ struct Timed {
   mapi_ctx* c;
   int kind;
   hipEvent_t a = nullptr;
-  Timed(mapi_ctx* c_, int k) : c(c_), kind(k) {
-    if (c->timing) {
+  Timed(mapi_ctx* c_, int k, bool on = true) : c(c_), kind(k) {
+    if (on && c->timing) {
       a = get_event(c);
       if (a) (void)hipEventRecord(a, c->stream);
     }
@@ -177,8 +180,9 @@ struct TimedLaunch {
   mapi_ctx* c;
   int kind;
   hipEvent_t a = nullptr, b = nullptr;
+  // da == nullptr: not timed
   TimedLaunch(mapi_ctx* c_, int k, DenseArgs* da) : c(c_), kind(k) {
-    if (c->timing) {
+    if (da && c->timing) {
       a = get_event(c);
       b = get_event(c);
       if (a && b) {

@@ -194,12 +194,13 @@ template <int DT, int OP, int RW, int U, int WL, bool NT>
 __global__ void __launch_bounds__(512)
 k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, int n_cols,
              const float* __restrict__ rscale, const float* __restrict__ w, float* __restrict__ y,
-             double* __restrict__ part, SolveState* __restrict__ st, int norm, FusedPrev fp) {
+             double* __restrict__ part, SolveState* __restrict__ st, int norm, FusedPrev fp, int rev) {
   extern __shared__ float4 w_lds4[];
   float* w_lds = reinterpret_cast<float*>(w_lds4);
   __shared__ double sh[16];
 
-  if (st != nullptr && state_done(st)) return;
+  // a product that forms its iterate checks the state after its first loads (below)
+  if (!(WL != 0 && fp.y_prev != nullptr) && st != nullptr && state_done(st)) return;
 
   constexpr bool PF = WL == 2 && DT == MAPI_FP8_E4M3;
   constexpr bool WLDS = WL != 0;
@@ -223,7 +224,17 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
     const int64_t per = ((int64_t)n_cols + gridDim.x - 1) / gridDim.x;
     const int64_t e0 = (int64_t)blockIdx.x * per, e1 = min((int64_t)n_cols, e0 + per);
     float ys = 0.0f, wo = 0.0f;
+    // The state, the previous launch's partials and the first part of y_prev are all
+    // loaded before any of them is used, so the prologue waits for one memory round
+    // trip; a solve that is already done returns after these (harmless) loads.
+    bool done0 = false;
+    double tol = 0.0;
+    StopSnap snap{};
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (fused) {
+      done0 = state_done(st);
+      tol = st->tol;
+      if (lead) snap = stop_snap(st);
 #pragma unroll
       for (int q = 0; q < PQ; ++q) {
         const int k = threadIdx.x + q * blockDim.x;
@@ -236,6 +247,10 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
     }
     double inv = 0.0;
     if (fused) {
+      const double rprev = fp.rpart_prev != nullptr ? wave_sum_parts(fp.rpart_prev, fp.nparts) : 0.0;
+      const double tot = wave_sum_parts(fp.part_prev, fp.nparts);
+      if (done0) return;
+      bool stopped = false;
       if (fp.rpart_prev != nullptr) {
         // the stop rule for iteration t - 1, whose residual partials the previous
         // launch wrote: every block sums them in the same order and takes the same
@@ -243,14 +258,12 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
         // depends on earlier iterations, is decided there alone: a block that
         // carries on only forms w_t, which the result w_{t-1} does not share a
         // buffer with, and the next launch sees the solve done)
-        const double rprev = wave_sum_parts(fp.rpart_prev, fp.nparts);
-        if (blockIdx.x == 0 && threadIdx.x == 0) state_advance(st, rprev);
-        if (rprev < st->tol) return;
+        if (lead) stopped = state_advance_from(st, snap, rprev);
+        if (rprev < tol) return;
       }
-      const double tot = wave_sum_parts(fp.part_prev, fp.nparts);
       const double nu = (norm == NORM_L2) ? sqrt(tot) : tot;
       // block 0's thread 0 records nu_t unless it has just stopped the solve (stall rule)
-      const bool owner = blockIdx.x == 0 && threadIdx.x == 0 && !state_done(st);
+      const bool owner = lead && !stopped;
       if (owner) st->nu = nu;
       if (!(nu > 0.0) || !(nu < INFINITY)) {
         if (owner) {
@@ -313,7 +326,10 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
   const int ngroups = (n_rows + RW - 1) / RW;
   double nrm = 0.0;
 
-  for (int g = blockIdx.x * nw + wave; g < ngroups; g += gridDim.x * nw) {
+  // rev: the row groups in mirrored order, so that a sweep starts where the one before
+  // it (in forward order) ended; the rows each block owns change, the row sums do not
+  for (int g0 = blockIdx.x * nw + wave; g0 < ngroups; g0 += gridDim.x * nw) {
+    const int g = rev ? ngroups - 1 - g0 : g0;
     const unsigned char* rp[RW];
     float sc[RW];
 #pragma unroll
@@ -364,10 +380,10 @@ static hipError_t launch_k(const DenseArgs& a, const float* w, float* y, double*
   if (a.ev_start) {
     hipExtLaunchKernelGGL((k_mavp_dense<DT, OP, RW, U, WL, NT>), dim3(blocks), dim3(waves * kWave), (uint32_t)lds, s,
                           a.ev_start, a.ev_stop, 0u, A, ldb, (int)a.n_rows, (int)a.n_cols, a.row_scale, w, y, part,
-                          st, norm, f);
+                          st, norm, f, a.reverse);
   } else {
     hipLaunchKernelGGL((k_mavp_dense<DT, OP, RW, U, WL, NT>), dim3(blocks), dim3(waves * kWave), lds, s, A, ldb,
-                       (int)a.n_rows, (int)a.n_cols, a.row_scale, w, y, part, st, norm, f);
+                       (int)a.n_rows, (int)a.n_cols, a.row_scale, w, y, part, st, norm, f, a.reverse);
   }
   return hipGetLastError();
 }

@@ -21,9 +21,14 @@ k_finalize(const T* __restrict__ y, const T* __restrict__ w_old, T* __restrict__
            const double* __restrict__ rprev, int nrprev) {
   __shared__ double sh[16];
   __shared__ int sh_flag;
-  if (state_done(st)) return;
-  // The first PF elements' y and w_old do not depend on nu: their loads are issued
-  // before the partials are summed, so the two memory round trips overlap.
+  // The state, the first PF elements' y and w_old and the partials are all loaded before
+  // any of them is used, so the prologue waits for one memory round trip; a solve that
+  // is already done returns after these (harmless) loads.
+  const bool done0 = state_done(st);
+  const double tol = st->tol;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  StopSnap snap{};
+  if (lead) snap = stop_snap(st);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   T yp[PF], wp[PF];
@@ -33,19 +38,21 @@ k_finalize(const T* __restrict__ y, const T* __restrict__ w_old, T* __restrict__
     yp[k] = i < n ? y[i] : T(0);
     wp[k] = i < n ? w_old[i] : T(0);
   }
+  const double r0 = rprev != nullptr ? wave_sum_parts(rprev, nrprev) : 0.0;
+  const double tot = wave_sum_parts(pprod, nprod);
+  if (done0) return;
+  bool stopped = false;
   if (rprev != nullptr) {
     // the previous iteration's residual (its iterate was formed inside a product):
     // the same fixed-order sum and tolerance decision in every block; block 0
     // advances the stop rule for it
-    const double r0 = wave_sum_parts(rprev, nrprev);
-    if (blockIdx.x == 0 && threadIdx.x == 0) state_advance(st, r0);
-    if (r0 < st->tol) return;
+    if (lead) stopped = state_advance_from(st, snap, r0);
+    if (r0 < tol) return;
   }
-  const double tot = wave_sum_parts(pprod, nprod);
   const double nu = (norm == NORM_L2) ? sqrt(tot) : tot;
   // block 0's thread 0 alone writes the state; it skips this iteration if it has just
   // stopped the solve on the stall rule
-  const bool owner = blockIdx.x == 0 && threadIdx.x == 0 && !state_done(st);
+  const bool owner = lead && !stopped;
   if (owner) st->nu = nu;
   if (!(nu > 0.0) || !(nu < INFINITY)) {
     if (owner) {
