@@ -154,7 +154,8 @@ def test_zero_iterations_and_empty_batch():
 
 def test_autotune_batched_row_split():
     rows, ms = mp.mapi_autotune_batched(mp.MAPI_F32, 4096, count=16, iters=4)
-    assert rows in (2, 4, 8, 16, 32, 64, 128, 256) and ms > 0
+    # the candidate tile heights: powers of two from 4 to 1024 rows (mapi_batched_rows_set)
+    assert rows in (4, 8, 16, 32, 64, 128, 256, 512, 1024) and ms > 0
     assert mp.mapi_batched_rows_get(mp.MAPI_F32, 4096) == rows
     p = mp.problem_generated(4096, 77, "f32", "mapi", max_iters=5)
     mp.mapi_solve_batched([p])
