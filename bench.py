@@ -171,6 +171,9 @@ def _bench_line(path):
     return json.loads(lines[-1]) if lines else {}
 
 
+READ_REPS = 10          # timed launches per launch shape of the read reference
+
+
 def _read_csvs(d, pattern):
     rows = []
     for p in glob.glob(os.path.join(d, "**", pattern), recursive=True):
@@ -300,15 +303,18 @@ def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write, 
             ev = live.get(dt)
             lines.append(f"| {dt} | `{last[-1][2][:48]}` | {avg:.1f} | {ev:.1f} |" if ev else
                          f"| {dt} | `{last[-1][2][:48]}` | {avg:.1f} | - |")
-        # the read reference: 3 untimed + 10 timed launches per matrix, f32 then bf16 then fp8
+        # the read reference per matrix (f32, bf16, fp8): 12 launch shapes, each one untimed
+        # and READ_REPS timed launches; the reference is the fastest shape's average
         rd = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
                     for r in trace if "k_read16" in r["Kernel_Name"])
-        if len(rd) >= 39:
-            lines += ["", "Read reference (plain streaming read of the same matrix, `k_read16`), timed launches:", "",
+        per = 12 * (1 + READ_REPS)
+        if len(rd) >= 3 * per:
+            lines += ["", "Read reference (plain streaming read of the same matrix, `k_read16`; the fastest of 12 "
+                      "launch shapes), timed launches:", "",
                       "| matrix | rocprofv3 average (us) | benchmark events (us) |", "|---|---|---|"]
             for k, dt in enumerate(("f32", "bf16", "fp8")):
-                grp = rd[13 * k + 3:13 * k + 13]
-                avg = sum(x[1] for x in grp) / len(grp) / 1e3
+                grps = [rd[k * per + g * (1 + READ_REPS) + 1:k * per + (g + 1) * (1 + READ_REPS)] for g in range(12)]
+                avg = min(sum(x[1] for x in grp) / len(grp) for grp in grps) / 1e3
                 ev = live.get(f"read_{dt}")
                 lines.append(f"| {dt} | {avg:.1f} | {ev:.1f} |" if ev else f"| {dt} | {avg:.1f} | - |")
     with open(os.path.join(ROOT, "profiles", "mavp_dense_n16384_kernel_stats.md"), "w") as f:
@@ -417,6 +423,34 @@ def summarize_counters(dirs, cmds, out_name="kernel_limiters_counters.md"):
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     log(f"wrote {out}")
+
+
+def bench_launch_cost(mp, ctx, mats, w0, detail):
+    """Fixed and per-byte cost of one launch: bare products (no normaliser, the tuned shape of
+    the n = 16384 bucket) and the read reference on the first m rows of each stored matrix
+    (m = 2048 ... 16384, full rows), fitted as t = fixed + bytes / rate; beside them the solve's
+    own product launch (the iterate formed inside it) at m = n."""
+    out = {}
+    ms_rows = (2048, 4096, 8192, 16384)
+    for dt, (A, rs) in mats.items():
+        shape = mp.mapi_tuning_get(mp._dtype_code(A), N, N, ctx=ctx)
+        xs, tp, tr = [], [], []
+        for m in ms_rows:
+            Am = A[:m]
+            rm = rs[:m] if rs is not None else None
+            xs.append(float(Am.numel() * Am.element_size()))
+            tp.append(mp.mapi_mavp_timed(Am, w0, shape, "min1", reps=20, row_scale=rm, ctx=ctx) * 1e3)
+            tr.append(mp.mapi_read_reference(Am, reps=READ_REPS, ctx=ctx) * 1e3)
+        fp, fr = np.polyfit(xs, tp, 1), np.polyfit(xs, tr, 1)
+        solve_us = detail.get(f"mapi_{dt}", {}).get("product_kernel_us")
+        out[dt] = {"rows": list(ms_rows), "bytes": xs, "product_us": tp, "read_us": tr,
+                   "product_fixed_us": float(fp[1]), "product_rate_gbs": float(1e-3 / fp[0]),
+                   "read_fixed_us": float(fr[1]), "read_rate_gbs": float(1e-3 / fr[0]),
+                   "solve_product_us": solve_us,
+                   "solve_minus_bare_us": (solve_us - tp[-1]) if solve_us else None}
+        log(f"launch cost {dt}: product {fp[1]:.1f} us + bytes at {1e-3 / fp[0]:.0f} GB/s; read {fr[1]:.1f} us "
+            f"+ bytes at {1e-3 / fr[0]:.0f} GB/s; bare product at n {tp[-1]:.1f} us, in the solve {solve_us or 0:.1f} us")
+    return out
 
 
 # ------------------------------------------------------------------ other workloads
@@ -1119,11 +1153,11 @@ def main():
     reads = {}
     for dt, (A, _) in mats.items():
         nbytes = A.numel() * A.element_size()
-        mp.mapi_read_reference(A, reps=3, ctx=ctx)
-        ms = mp.mapi_read_reference(A, reps=10, ctx=ctx)
+        ms = mp.mapi_read_reference(A, reps=READ_REPS, ctx=ctx)
         reads[dt] = {"bytes": nbytes, "us": ms * 1e3, "gbs": nbytes / (ms * 1e-3) / 1e9}
         log(f"read reference {dt}: {ms * 1e3:.1f} us, {reads[dt]['gbs']:.0f} GB/s")
     detail["read_reference"] = reads
+    detail["launch_cost"] = bench_launch_cost(mp, ctx, mats, w0, detail)
 
     sections = [x for x in args.sections.split(",") if x]
     for name, fn in (("small", lambda: bench_small(mp, ctx, torch)), ("hybrid", lambda: bench_hybrid(mp, ctx, torch)),

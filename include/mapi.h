@@ -223,8 +223,9 @@ mapi_status mapi_copy_reference(mapi_ctx* ctx, const void* src, void* dst, size_
                                 double* avg_ms);
 /* Bandwidth reference: mean time in ms of `reps` plain streaming reads of `bytes`
  * (multiple of 16) at src (device, 16-byte aligned): non-temporal 16-byte loads,
- * four per lane in flight, nothing written back.  Uses 256 bytes of the context
- * workspace.                                                                     */
+ * nothing written back; the fastest of 12 launch shapes (1..32 blocks of 256
+ * threads per compute unit, four or eight loads per lane in flight), each timed
+ * over `reps` reads after one untimed.  Uses 256 bytes of the context workspace. */
 mapi_status mapi_read_reference(mapi_ctx* ctx, const void* src, size_t bytes, int32_t reps, double* avg_ms);
 
 /* ---------------------------------------------------------------- solvers */

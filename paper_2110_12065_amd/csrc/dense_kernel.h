@@ -92,14 +92,27 @@ __device__ __forceinline__ float decode_one(const unsigned char* row, int64_t j,
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// One 16-byte load of the matrix; NT marks it non-temporal (streamed once).
+// Reads of w staged in LDS through pointers in the LDS address space: through a generic
+// pointer the compiler may emit flat loads, which count against the vector-memory
+// counter, so waiting for w also waits for every matrix load in flight.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const f32x4 lds_f32x4;
+typedef __attribute__((address_space(3))) const u32x4 lds_u32x4;
+
+typedef __attribute__((address_space(1))) const u32x4 gmem_u32x4;
+typedef __attribute__((address_space(1))) const f32x4 gmem_f32x4;
+
+// One 16-byte load of the matrix (device memory, read as such: a pointer taken from an
+// instance descriptor would otherwise give a flat load); NT marks it non-temporal
+// (streamed once).
 template <bool NT>
 __device__ __forceinline__ uint4 load16(const unsigned char* p) {
+  const gmem_u32x4* gp = (const gmem_u32x4*)p;
   u32x4 v;
   if constexpr (NT) {
-    v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+    v = __builtin_nontemporal_load(gp);
   } else {
-    v = *reinterpret_cast<const u32x4*>(p);
+    v = *gp;
   }
   return make_uint4(v.x, v.y, v.z, v.w);
 }
@@ -118,7 +131,9 @@ __device__ __forceinline__ uint4 load16(const unsigned char* p) {
 // read of a wave covers one contiguous 1 KiB instead of a lane stride of VE * 4
 // bytes, which puts 2 (bf16) or 4 (FP8) lanes of every 8 on the same banks; the
 // ragged tail then reads wsign (w in global memory).
-template <int DT, int OP, int RW, int U, bool NT, bool PF = false, bool P2 = false, bool PERM = false>
+// WSP: address space of w when it is not in chunk-interleaved LDS order: 1 device
+// memory, 3 LDS, 0 either (generic reads).
+template <int DT, int OP, int RW, int U, bool NT, bool PF = false, bool P2 = false, bool PERM = false, int WSP = 0>
 __device__ __forceinline__ void rows_product(const unsigned char* const* rp, const float* sc, const float* wv,
                                              int n_cols, int lane, float* out, const uint32_t* smask = nullptr,
                                              const float* wsign = nullptr) {
@@ -132,16 +147,23 @@ __device__ __forceinline__ void rows_product(const unsigned char* const* rp, con
   auto vec = [&](int vv, const uint4* raws) {
     float wf[VE];
     uint32_t ws[VE];
-    const float4* wp = PERM ? reinterpret_cast<const float4*>(wv) + perm_base<DT>(vv)
-                            : reinterpret_cast<const float4*>(wv + (int64_t)vv * VE);
 #pragma unroll
     for (int q = 0; q < VE / 4; ++q) {
-      const float4 t = PERM ? wp[q * 64] : wp[q];
+      f32x4 t;
+      if constexpr (PERM)
+        t = ((lds_f32x4*)(wv + 4 * (int64_t)perm_base<DT>(vv)))[q * 64];
+      else if constexpr (WSP == 3)
+        t = ((lds_f32x4*)(wv + (int64_t)vv * VE))[q];
+      else if constexpr (WSP == 1)
+        t = ((gmem_f32x4*)(wv + (int64_t)vv * VE))[q];
+      else
+        t = reinterpret_cast<const f32x4*>(wv + (int64_t)vv * VE)[q];
       wf[4 * q] = t.x; wf[4 * q + 1] = t.y; wf[4 * q + 2] = t.z; wf[4 * q + 3] = t.w;
     }
     uint4 m = make_uint4(0u, 0u, 0u, 0u);
     if constexpr (PF) {
-      m = *reinterpret_cast<const uint4*>(smask + (int64_t)vv * 4);
+      const u32x4 mv = *((lds_u32x4*)(smask + (int64_t)vv * 4));
+      m = make_uint4(mv.x, mv.y, mv.z, mv.w);
 #pragma unroll
       for (int e = 0; e < VE; ++e) ws[e] = 0u;
     } else {
@@ -308,7 +330,21 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
       }
       k0 = threadIdx.x + PQ * blockDim.x;
     }
-    for (int k = k0; k < np4; k += blockDim.x) stage(k, src[k]);
+    // the rest in batches of PQ float4s per thread, every load of a batch issued before
+    // its first store (a block of 256 threads stages half of a 16384-float w here)
+    for (int kb = k0; kb < np4; kb += PQ * blockDim.x) {
+      float4 t[PQ];
+#pragma unroll
+      for (int q = 0; q < PQ; ++q) {
+        const int k = kb + q * blockDim.x;
+        t[q] = k < np4 ? src[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int q = 0; q < PQ; ++q) {
+        const int k = kb + q * blockDim.x;
+        if (k < np4) stage(k, t[q]);
+      }
+    }
     if (fused) {   // the tail cannot be read from w: it is formed here, after the staged vectors
       float* tl = w_lds + wfl;
       for (int j = nvec * VE + threadIdx.x; j < n_cols; j += blockDim.x)
@@ -343,10 +379,10 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
       bool p2 = true;
 #pragma unroll
       for (int r = 0; r < RW; ++r) p2 = p2 && pow2_scale(sc[r]);
-      if (p2) rows_product<DT, OP, RW, U, NT, PF, true, WLDS>(rp, sc, wv, n_cols, lane, sums, smask, wtail);
-      else rows_product<DT, OP, RW, U, NT, PF, false, WLDS>(rp, sc, wv, n_cols, lane, sums, smask, wtail);
+      if (p2) rows_product<DT, OP, RW, U, NT, PF, true, WLDS, 1>(rp, sc, wv, n_cols, lane, sums, smask, wtail);
+      else rows_product<DT, OP, RW, U, NT, PF, false, WLDS, 1>(rp, sc, wv, n_cols, lane, sums, smask, wtail);
     } else {
-      rows_product<DT, OP, RW, U, NT, PF, false, WLDS>(rp, sc, wv, n_cols, lane, sums, smask, wtail);
+      rows_product<DT, OP, RW, U, NT, PF, false, WLDS, 1>(rp, sc, wv, n_cols, lane, sums, smask, wtail);
     }
 #pragma unroll
     for (int r = 0; r < RW; ++r) {

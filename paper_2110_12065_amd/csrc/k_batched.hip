@@ -152,7 +152,8 @@ __device__ bool tile_arrive(BInst* I, uint32_t tiles, int* sh_flag) {
 // Rows [r0, r1) of one tile: each wave takes RW rows at a time (4 for float32 and
 // bf16 storage, 2 for FP8, whose decoded vectors need more registers) with two
 // 16-byte loads per row and lane in flight.
-template <int DT, int OP>
+// WSP: 3 when w was staged in LDS, 1 when it is read from device memory.
+template <int DT, int OP, int WSP>
 __device__ double dense_rows_t(const BInst* I, const float* wv, int r0, int r1, float* y, bool l2) {
   constexpr int RW = (DT == MAPI_FP8_E4M3) ? 2 : 4;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
@@ -173,10 +174,10 @@ __device__ double dense_rows_t(const BInst* I, const float* wv, int r0, int r1, 
       bool p2 = true;
 #pragma unroll
       for (int r = 0; r < RW; ++r) p2 = p2 && pow2_scale(sc[r]);
-      if (p2) rows_product<DT, OP, RW, 2, false, false, true>(rp, sc, wv, I->n, lane, s);
-      else rows_product<DT, OP, RW, 2, false>(rp, sc, wv, I->n, lane, s);
+      if (p2) rows_product<DT, OP, RW, 2, false, false, true, false, WSP>(rp, sc, wv, I->n, lane, s);
+      else rows_product<DT, OP, RW, 2, false, false, false, false, WSP>(rp, sc, wv, I->n, lane, s);
     } else {
-      rows_product<DT, OP, RW, 2, false>(rp, sc, wv, I->n, lane, s);
+      rows_product<DT, OP, RW, 2, false, false, false, false, WSP>(rp, sc, wv, I->n, lane, s);
     }
 #pragma unroll
     for (int r = 0; r < RW; ++r)
@@ -188,22 +189,30 @@ __device__ double dense_rows_t(const BInst* I, const float* wv, int r0, int r1, 
   return nrm;
 }
 
-template <int DT>
+template <int DT, int WSP>
 __device__ double dense_rows_op(const BInst* I, int op, const float* wv, int r0, int r1, float* y, bool l2) {
   switch (op) {
-    case MAPI_OP_MIN2: return dense_rows_t<DT, MAPI_OP_MIN2>(I, wv, r0, r1, y, l2);
-    case MAPI_OP_DOT: return dense_rows_t<DT, MAPI_OP_DOT>(I, wv, r0, r1, y, l2);
-    default: return dense_rows_t<DT, MAPI_OP_MIN1>(I, wv, r0, r1, y, l2);
+    case MAPI_OP_MIN2: return dense_rows_t<DT, MAPI_OP_MIN2, WSP>(I, wv, r0, r1, y, l2);
+    case MAPI_OP_DOT: return dense_rows_t<DT, MAPI_OP_DOT, WSP>(I, wv, r0, r1, y, l2);
+    default: return dense_rows_t<DT, MAPI_OP_MIN1, WSP>(I, wv, r0, r1, y, l2);
   }
+}
+
+// w in LDS (stage_w staged it: n fits) or in device memory, each read in its own
+// address space
+template <int DT>
+__device__ double dense_rows_w(const BInst* I, int op, const float* wv, int r0, int r1, float* y, bool l2) {
+  if (I->n <= kBatchLdsFloats) return dense_rows_op<DT, 3>(I, op, wv, r0, r1, y, l2);
+  return dense_rows_op<DT, 1>(I, op, wv, r0, r1, y, l2);
 }
 
 __device__ double dense_rows(const BInst* I, const float* wv, int r0, int r1, float* y) {
   const bool rpi = I->method == MAPI_METHOD_RPI;
   const int op = rpi ? MAPI_OP_DOT : I->op;
   switch (I->dtype) {
-    case MAPI_BF16: return dense_rows_op<MAPI_BF16>(I, op, wv, r0, r1, y, rpi);
-    case MAPI_FP8_E4M3: return dense_rows_op<MAPI_FP8_E4M3>(I, op, wv, r0, r1, y, rpi);
-    default: return dense_rows_op<MAPI_F32>(I, op, wv, r0, r1, y, rpi);
+    case MAPI_BF16: return dense_rows_w<MAPI_BF16>(I, op, wv, r0, r1, y, rpi);
+    case MAPI_FP8_E4M3: return dense_rows_w<MAPI_FP8_E4M3>(I, op, wv, r0, r1, y, rpi);
+    default: return dense_rows_w<MAPI_F32>(I, op, wv, r0, r1, y, rpi);
   }
 }
 

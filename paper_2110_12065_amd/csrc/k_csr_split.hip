@@ -340,8 +340,20 @@ k_csr_split_product(const uint8_t* __restrict__ len, const int32_t* __restrict__
     for (int q = threadIdx.x; q < nh; q += blockDim.x) lhub[q] = w[hubs[k * kSplitHubSlots + q]];
     __syncthreads();
   }
-  // w of a link's source: a hub's from LDS (stored as ~slot), any other's from memory
-  auto wsrc = [&](int32_t jj) -> T { return jj >= 0 ? w[jj] : lhub[~jj]; };
+  // w of a link's source: a hub's from LDS (stored as ~slot), any other's from memory.
+  // Each read goes through a pointer of its own address space: merged into one read
+  // through a generic pointer (a flat load), every gather would also wait on the LDS
+  // counter and every hub read on the vector-memory counter.
+  typedef __attribute__((address_space(1))) const T gmem_t;
+  typedef __attribute__((address_space(3))) const T lmem_t;
+  gmem_t* wg = (gmem_t*)w;
+  lmem_t* wl = (lmem_t*)lhub;
+  auto wsrc = [&](int32_t jj) -> T {
+    T v;
+    if (jj >= 0) v = wg[jj];
+    else v = wl[~jj];
+    return v;
+  };
   const int64_t groups = gridDim.x / kSplitBlocks;
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
@@ -365,7 +377,10 @@ k_csr_split_product(const uint8_t* __restrict__ len, const int32_t* __restrict__
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       off[r] = wave_excl_scan(l[r]);
-      tot[r] = __shfl(off[r] + l[r], kWave - 1, kWave);
+      // the chunk's link count, the same in every lane: a wave-uniform value, so that the
+      // staged and the unstaged reads below are separate branches, each through its own
+      // address space (not one flat load of either)
+      tot[r] = __builtin_amdgcn_readfirstlane(__shfl(off[r] + l[r], kWave - 1, kWave));
     }
     // the chunks' links into LDS: coalesced, every load of all R chunks issued first
     int32_t sc[R][SWEEPS];
@@ -401,21 +416,21 @@ k_csr_split_product(const uint8_t* __restrict__ len, const int32_t* __restrict__
     float h[R][E];
     T wj[R][E];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int r = 0; r < R; ++r) {
+      if (tot[r] <= CAP) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        j[r][e] = 0;
-        h[r][e] = 0.0f;
-        if (e < l[r]) {
-          if (tot[r] <= CAP) {
-            j[r][e] = lcol[wv][r][off[r] + e];
-            h[r][e] = lval[wv][r][off[r] + e];
-          } else {
-            j[r][e] = __builtin_nontemporal_load(colS + b0[r] + off[r] + e);
-            h[r][e] = __builtin_nontemporal_load(valS + b0[r] + off[r] + e);
-          }
+        for (int e = 0; e < E; ++e) {
+          j[r][e] = e < l[r] ? lcol[wv][r][off[r] + e] : 0;
+          h[r][e] = e < l[r] ? lval[wv][r][off[r] + e] : 0.0f;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          j[r][e] = e < l[r] ? __builtin_nontemporal_load(colS + b0[r] + off[r] + e) : 0;
+          h[r][e] = e < l[r] ? __builtin_nontemporal_load(valS + b0[r] + off[r] + e) : 0.0f;
         }
       }
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -431,17 +446,15 @@ k_csr_split_product(const uint8_t* __restrict__ len, const int32_t* __restrict__
     // links past the first E of a row, one at a time
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      for (int e = E; e < l[r]; ++e) {
-        int32_t jj;
-        float hh;
-        if (tot[r] <= CAP) {
-          jj = lcol[wv][r][off[r] + e];
-          hh = lval[wv][r][off[r] + e];
-        } else {
-          jj = __builtin_nontemporal_load(colS + b0[r] + off[r] + e);
-          hh = __builtin_nontemporal_load(valS + b0[r] + off[r] + e);
+      if (tot[r] <= CAP) {
+        for (int e = E; e < l[r]; ++e)
+          acc[r] = split_term<METHOD, T>(acc[r], lval[wv][r][off[r] + e], wsrc(lcol[wv][r][off[r] + e]), af, cf, ad, cd);
+      } else {
+        for (int e = E; e < l[r]; ++e) {
+          const int32_t jj = __builtin_nontemporal_load(colS + b0[r] + off[r] + e);
+          const float hh = __builtin_nontemporal_load(valS + b0[r] + off[r] + e);
+          acc[r] = split_term<METHOD, T>(acc[r], hh, wsrc(jj), af, cf, ad, cd);
         }
-        acc[r] = split_term<METHOD, T>(acc[r], hh, wsrc(jj), af, cf, ad, cd);
       }
     }
 #pragma unroll

@@ -274,20 +274,21 @@ hipError_t launch_copy16(const void* src, void* dst, int64_t n16, int cu_count, 
 
 typedef unsigned int vec_u32x4 __attribute__((ext_vector_type(4)));
 
-// Plain streaming read (16-byte non-temporal loads, four per lane in flight): the
+// Plain streaming read (16-byte non-temporal loads, U per lane in flight): the
 // attainable-read-bandwidth reference for the product kernels.  The loaded words
 // are folded into one value that is stored only if it equals a constant no input
 // here produces, so the loads stay but nothing is written.
+template <int U>
 __global__ void __launch_bounds__(256) k_read16(const vec_u32x4* __restrict__ src, int64_t n16, uint32_t* sink) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t acc = 0u;
-  for (; i + 3 * stride < n16; i += 4 * stride) {
-    vec_u32x4 v[4];
+  for (; i + (U - 1) * stride < n16; i += U * stride) {
+    vec_u32x4 v[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+    for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    for (int u = 0; u < U; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
   }
   for (; i < n16; i += stride) {
     const vec_u32x4 v = __builtin_nontemporal_load(src + i);
@@ -296,11 +297,14 @@ __global__ void __launch_bounds__(256) k_read16(const vec_u32x4* __restrict__ sr
   if (acc == 0x9E3779B9u) sink[0] = acc;
 }
 
-hipError_t launch_read16(const void* src, int64_t n16, uint32_t* sink, int cu_count, hipStream_t s) {
-  int64_t blocks = (n16 + 255) / 256;
-  if (blocks > (int64_t)cu_count * 32) blocks = (int64_t)cu_count * 32;
-  hipLaunchKernelGGL(k_read16, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s,
-                     static_cast<const vec_u32x4*>(src), n16, sink);
+hipError_t launch_read16(const void* src, int64_t n16, uint32_t* sink, int blocks, int unroll, hipStream_t s) {
+  int64_t b = (n16 + 255) / 256;
+  if (b > blocks) b = blocks;
+  const dim3 grid((unsigned)(b < 1 ? 1 : b));
+  const auto* p = static_cast<const vec_u32x4*>(src);
+  if (unroll == 8) hipLaunchKernelGGL(k_read16<8>, grid, dim3(256), 0, s, p, n16, sink);
+  else if (unroll == 4) hipLaunchKernelGGL(k_read16<4>, grid, dim3(256), 0, s, p, n16, sink);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -42,9 +42,13 @@ __device__ void gram_write_tile(const float* S, int i0, int j0, int D, float* __
 }
 
 // ---------------------------------------------------------------- min forms on the vector ALU
-// 1024 threads, each a 4 x 4 register tile of the 128 x 128 output tile: rows 4 ty .. 4 ty + 3,
-// columns 4 tx .. 4 tx + 3 (tx = tid % 32, ty = tid / 32), so that per sample a wave reads
-// two broadcast 16-byte row operands and 512 contiguous bytes of column operands from LDS.
+// Each thread holds a TM x 4 register tile of the 128 x 128 output tile: rows TM ty ..
+// TM ty + TM - 1, columns 4 tx .. 4 tx + 3 (tx = tid % 32, ty = tid / 32), so that per
+// sample a wave reads TM / 4 broadcast 16-byte row operands and 512 contiguous bytes of
+// column operands from LDS.  TM = 4 (1024 threads, 16 waves per compute unit) is the
+// build's shape: TM = 8 (512 threads) reads a quarter fewer LDS bytes per term but, at
+// 163 VGPRs, leaves 8 waves per compute unit, and measured 34.1 ms against 28.9 ms for
+// the min1 build at 4096 x 65536.
 // X is staged through LDS in slabs of NKS samples, transposed (sample-major: the tile's
 // 128 I rows then its 128 J rows, pitch NP floats), double-buffered through registers;
 // the next sample's operands are read before the current sample's terms.
@@ -53,17 +57,22 @@ __device__ void gram_write_tile(const float* S, int i0, int j0, int D, float* __
 // the product is exact, so the term and the sum equal those of a sign-bit flip and an
 // add, in one instruction; s is formed once per column and sample.
 // min2 term: med3(a ^ signbit(b), 0, |b|) and an add, as in the product kernels.
-constexpr int NTH = 1024;                    // threads per block
+// Every output element is summed over the samples in order, in float32 runs of 256
+// samples added into float64, whatever TM: the tile shape does not change the bits.
 constexpr int NKS = 32;                      // samples per slab
 constexpr int NP = 2 * MT + 4;               // staged pitch (floats); 16-byte aligned
 constexpr int NRUN = 256 / NKS;              // slabs per float32 run
 constexpr int NLPR = NKS / 4;                // loader threads per staged row (one float4 each)
-constexpr int NLP = 2 * MT * NLPR / NTH;     // float4s each thread loads per slab
+constexpr int kGramTM = 4;                   // rows of a thread's register tile
+constexpr int gram_threads(int tm) { return MT * MT / (tm * 4); }
 
-template <int OP, bool SPLIT>
-__global__ void __launch_bounds__(NTH)
+template <int OP, bool SPLIT, int TM>
+__global__ void __launch_bounds__(gram_threads(TM))
 k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t chunk, int tiles, double scale,
            float* __restrict__ A, int64_t lda, double* __restrict__ part) {
+  constexpr int NTH = gram_threads(TM);
+  constexpr int NLP = 2 * MT * NLPR / NTH;   // float4s each thread loads per slab
+  constexpr int TA = TM / 4;                 // 16-byte row operands per sample
   __shared__ float4 lds4[2 * NKS * NP / 4];
   float* lds = reinterpret_cast<float*>(lds4);
   const int T = (D + MT - 1) / MT;
@@ -112,10 +121,10 @@ k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t c
     }
   };
 
-  float accf[4][4];
-  double acc[4][4];
+  float accf[TM][4];
+  double acc[TM][4];
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+  for (int p = 0; p < TM; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       accf[p][q] = 0.0f;
@@ -130,23 +139,30 @@ k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t c
     const int buf = (int)(sl & 1);
     if (sl + 1 < nslabs) load(kb + (sl + 1) * NKS);
     const float* s = lds + buf * NKS * NP;
-    float4 a = *reinterpret_cast<const float4*>(s + ty * 4);
-    float4 b = *reinterpret_cast<const float4*>(s + MT + tx * 4);
+    float4 a[TA], b;
+#pragma unroll
+    for (int t = 0; t < TA; ++t) a[t] = *reinterpret_cast<const float4*>(s + ty * TM + 4 * t);
+    b = *reinterpret_cast<const float4*>(s + MT + tx * 4);
 #pragma unroll
     for (int k = 0; k < NKS; ++k) {
-      float4 an, bn;
+      float4 an[TA], bn;
       if (k + 1 < NKS) {
-        an = *reinterpret_cast<const float4*>(s + (k + 1) * NP + ty * 4);
+#pragma unroll
+        for (int t = 0; t < TA; ++t) an[t] = *reinterpret_cast<const float4*>(s + (k + 1) * NP + ty * TM + 4 * t);
         bn = *reinterpret_cast<const float4*>(s + (k + 1) * NP + MT + tx * 4);
       }
-      const float av[4] = {a.x, a.y, a.z, a.w};
+      float av[TM];
+#pragma unroll
+      for (int t = 0; t < TA; ++t) {
+        av[4 * t] = a[t].x; av[4 * t + 1] = a[t].y; av[4 * t + 2] = a[t].z; av[4 * t + 3] = a[t].w;
+      }
       const float bv[4] = {b.x, b.y, b.z, b.w};
       if constexpr (OP == MAPI_OP_MIN1) {
         float sg[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) sg[q] = __uint_as_float(sign_bit(bv[q]) | 0x3f800000u);
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
+        for (int p = 0; p < TM; ++p)
 #pragma unroll
           for (int q = 0; q < 4; ++q)
             accf[p][q] = fmaf(__builtin_amdgcn_fmed3f(av[p], -fabsf(bv[q]), fabsf(bv[q])), sg[q], accf[p][q]);
@@ -155,18 +171,19 @@ k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t c
 #pragma unroll
         for (int q = 0; q < 4; ++q) sb[q] = sign_bit(bv[q]);
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
+        for (int p = 0; p < TM; ++p)
 #pragma unroll
           for (int q = 0; q < 4; ++q) accf[p][q] = op_acc<OP>(accf[p][q], av[p], bv[q], sb[q]);
       }
       if (k + 1 < NKS) {
-        a = an;
+#pragma unroll
+        for (int t = 0; t < TA; ++t) a[t] = an[t];
         b = bn;
       }
     }
     if ((sl + 1) % NRUN == 0 || sl + 1 == nslabs) {
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
+      for (int p = 0; p < TM; ++p)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           acc[p][q] += (double)accf[p][q];
@@ -182,18 +199,18 @@ k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t c
   if constexpr (SPLIT) {
     double* out = part + ((int64_t)cidx * tiles + tile) * (MT * MT);
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < TM; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) out[(ty * 4 + p) * MT + tx * 4 + q] = acc[p][q];
+      for (int q = 0; q < 4; ++q) out[(ty * TM + p) * MT + tx * 4 + q] = acc[p][q];
   } else {
     // the tile is staged in the (now free) slab buffers so that it and its mirror are
     // written along rows
     static_assert(MT * MSP <= 2 * NKS * NP, "staged tile fits the slab buffers");
     __syncthreads();
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < TM; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) lds[(ty * 4 + p) * MSP + tx * 4 + q] = (float)(scale * acc[p][q]);
+      for (int q = 0; q < 4; ++q) lds[(ty * TM + p) * MSP + tx * 4 + q] = (float)(scale * acc[p][q]);
     __syncthreads();
     gram_write_tile(lds, i0, j0, D, A, lda, ti != tj);
   }
@@ -388,11 +405,12 @@ size_t gram_workspace_bytes(int64_t D, int64_t N, int op) {
 template <int OP>
 static void launch_gram_min(const GramSplit& g, const float* X, int64_t D, int64_t N, int64_t ldx, double scale,
                             float* A, int64_t lda, double* ws, hipStream_t s) {
+  constexpr int NTH = gram_threads(kGramTM);
   if (g.kc > 1)
-    hipLaunchKernelGGL((k_gram_min<OP, true>), dim3((unsigned)(g.tiles * g.kc)), dim3(NTH), 0, s, X, (int)D, N, ldx,
-                       g.chunk, (int)g.tiles, scale, A, lda, ws);
+    hipLaunchKernelGGL((k_gram_min<OP, true, kGramTM>), dim3((unsigned)(g.tiles * g.kc)), dim3(NTH), 0, s, X, (int)D, N,
+                       ldx, g.chunk, (int)g.tiles, scale, A, lda, ws);
   else
-    hipLaunchKernelGGL((k_gram_min<OP, false>), dim3((unsigned)g.tiles), dim3(NTH), 0, s, X, (int)D, N, ldx, g.chunk,
+    hipLaunchKernelGGL((k_gram_min<OP, false, kGramTM>), dim3((unsigned)g.tiles), dim3(NTH), 0, s, X, (int)D, N, ldx, g.chunk,
                        (int)g.tiles, scale, A, lda, nullptr);
 }
 
