@@ -171,6 +171,29 @@ __device__ __forceinline__ void state_advance(SolveState* st, double r) {
   }
 }
 
+// wave_sum_parts in two steps, so that other loads can be issued between the partials'
+// loads and their sum: parts_load loads lane l's first kPartsPre partials (l, l + 64,
+// ...), parts_sum adds them and any further ones in the same order as wave_sum_parts
+// (the same bits).
+constexpr int kPartsPre = 8;
+__device__ __forceinline__ void parts_load(const double* part, int count, double* v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int k = 0; k < kPartsPre; ++k) {
+    const int i = lane + k * kWave;
+    v[k] = i < count ? part[i] : 0.0;
+  }
+}
+__device__ __forceinline__ double parts_sum(const double* part, int count, const double* v) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kPartsPre; ++k)
+    if (lane + k * kWave < count) s += v[k];
+  for (int i = lane + kPartsPre * kWave; i < count; i += kWave) s += part[i];
+  return wave_sum_f64(s);
+}
+
 // The stop rule's inputs as a kernel found them, read by the one thread that will
 // advance the rule together with the kernel's other first loads, so that advancing
 // it later waits for no memory round trip.

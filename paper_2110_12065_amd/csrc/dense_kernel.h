@@ -134,9 +134,12 @@ __device__ __forceinline__ uint4 load16(const unsigned char* p) {
 // WSP: address space of w when it is not in chunk-interleaved LDS order: 1 device
 // memory, 3 LDS, 0 either (generic reads).
 template <int DT, int OP, int RW, int U, bool NT, bool PF = false, bool P2 = false, bool PERM = false, int WSP = 0>
+//
+// first, use_first: the loads of the lane's first U-vector step, issued earlier by the
+// caller (for a lane with such a step), are used in place of loading it again.
 __device__ __forceinline__ void rows_product(const unsigned char* const* rp, const float* sc, const float* wv,
-                                             int n_cols, int lane, float* out, const uint32_t* smask = nullptr,
-                                             const float* wsign = nullptr) {
+                                             int n_cols, int lane, float* out, const uint32_t* smask,
+                                             const float* wsign, const uint4 (&first)[U][RW], bool use_first) {
   constexpr int VE = Traits<DT>::VE;
   const int nvec = n_cols / VE;
   float acc[RW][2];
@@ -184,6 +187,11 @@ __device__ __forceinline__ void rows_product(const unsigned char* const* rp, con
   };
 
   int v = lane;
+  if (use_first && v + kWave * (U - 1) < nvec) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) vec(v + kWave * u, first[u]);
+    v += kWave * U;
+  }
   for (; v + kWave * (U - 1) < nvec; v += kWave * U) {
     uint4 raw[U][RW];
 #pragma unroll
@@ -232,6 +240,33 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
   const float* wtail = w;   // signed w of the columns past the last whole vector
   const uint32_t* smask = nullptr;
   double racc = 0.0;        // FusedPrev: this thread's part of ||w_t - w_{t-1}||_1
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  const int ngroups = (n_rows + RW - 1) / RW;
+  // The loads of the wave's first row group's first step need nothing the prologue
+  // forms: with w staged in LDS they are issued right after the prologue's own loads,
+  // so the matrix stream starts while the prologue waits and computes.
+  // (the heavier shapes keep their registers for the loop: there the loads issued ahead
+  // make the compiler spill)
+  constexpr bool kAhead = DT == MAPI_F32 ? RW * U <= (OP == MAPI_OP_DIAMOND ? 8 : 16)
+                                         : (RW * U <= 8 && (DT == MAPI_BF16 || RW <= 2));
+  uint4 first[U][RW];
+  bool have_first = false;
+  auto issue_first = [&]() {
+    const int g0 = blockIdx.x * nw + wave;
+    if (kAhead && g0 < ngroups && lane + kWave * (U - 1) < nvec) {
+      const int g = rev ? ngroups - 1 - g0 : g0;
+      const unsigned char* fp0[RW];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) fp0[r] = A + (int64_t)min(g * RW + r, n_rows - 1) * ld_bytes;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < RW; ++r) first[u][r] = load16<NT>(fp0[r] + (int64_t)(lane + kWave * u) * 16);
+      have_first = true;
+    }
+  };
   if constexpr (WLDS) {
     // FusedPrev: w = y_prev * (1 / nu), nu from the previous product's partials (the
     // normalisation kernel's arithmetic); this block also writes its share of w and
@@ -269,8 +304,12 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
     }
     double inv = 0.0;
     if (fused) {
-      const double rprev = fp.rpart_prev != nullptr ? wave_sum_parts(fp.rpart_prev, fp.nparts) : 0.0;
-      const double tot = wave_sum_parts(fp.part_prev, fp.nparts);
+      double pr[kPartsPre], pt[kPartsPre];
+      if (fp.rpart_prev != nullptr) parts_load(fp.rpart_prev, fp.nparts, pr);
+      parts_load(fp.part_prev, fp.nparts, pt);
+      issue_first();
+      const double rprev = fp.rpart_prev != nullptr ? parts_sum(fp.rpart_prev, fp.nparts, pr) : 0.0;
+      const double tot = parts_sum(fp.part_prev, fp.nparts, pt);
       if (done0) return;
       bool stopped = false;
       if (fp.rpart_prev != nullptr) {
@@ -322,6 +361,7 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
       reinterpret_cast<float4*>(w_lds)[perm_base<DT>(k / (VE / 4)) + (k % (VE / 4)) * 64] = t;
     };
     int k0 = threadIdx.x;
+    if (!fused) issue_first();
     if (fused) {
 #pragma unroll
       for (int q = 0; q < PQ; ++q) {
@@ -356,16 +396,14 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
     if constexpr (PF) smask = reinterpret_cast<const uint32_t*>(w_lds + wfl + kDenseTailFloats);
   }
 
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  const int nw = blockDim.x / kWave;
-  const int ngroups = (n_rows + RW - 1) / RW;
   double nrm = 0.0;
 
   // rev: the row groups in mirrored order, so that a sweep starts where the one before
   // it (in forward order) ended; the rows each block owns change, the row sums do not
   for (int g0 = blockIdx.x * nw + wave; g0 < ngroups; g0 += gridDim.x * nw) {
     const int g = rev ? ngroups - 1 - g0 : g0;
+    const bool fst = kAhead && have_first;   // the first group only
+    have_first = false;
     const unsigned char* rp[RW];
     float sc[RW];
 #pragma unroll
@@ -379,10 +417,10 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
       bool p2 = true;
 #pragma unroll
       for (int r = 0; r < RW; ++r) p2 = p2 && pow2_scale(sc[r]);
-      if (p2) rows_product<DT, OP, RW, U, NT, PF, true, WLDS, 1>(rp, sc, wv, n_cols, lane, sums, smask, wtail);
-      else rows_product<DT, OP, RW, U, NT, PF, false, WLDS, 1>(rp, sc, wv, n_cols, lane, sums, smask, wtail);
+      if (p2) rows_product<DT, OP, RW, U, NT, PF, true, WLDS, 1>(rp, sc, wv, n_cols, lane, sums, smask, wtail, first, fst);
+      else rows_product<DT, OP, RW, U, NT, PF, false, WLDS, 1>(rp, sc, wv, n_cols, lane, sums, smask, wtail, first, fst);
     } else {
-      rows_product<DT, OP, RW, U, NT, PF, false, WLDS, 1>(rp, sc, wv, n_cols, lane, sums, smask, wtail);
+      rows_product<DT, OP, RW, U, NT, PF, false, WLDS, 1>(rp, sc, wv, n_cols, lane, sums, smask, wtail, first, fst);
     }
 #pragma unroll
     for (int r = 0; r < RW; ++r) {

@@ -170,14 +170,15 @@ __device__ double dense_rows_t(const BInst* I, const float* wv, int r0, int r1, 
       sc[r] = (DT == MAPI_FP8_E4M3) ? I->row_scale[row] : 1.0f;
     }
     float s[RW];
+    const uint4 none[2][RW] = {};   // no step loaded ahead here
     if constexpr (DT == MAPI_FP8_E4M3) {
       bool p2 = true;
 #pragma unroll
       for (int r = 0; r < RW; ++r) p2 = p2 && pow2_scale(sc[r]);
-      if (p2) rows_product<DT, OP, RW, 2, false, false, true, false, WSP>(rp, sc, wv, I->n, lane, s);
-      else rows_product<DT, OP, RW, 2, false, false, false, false, WSP>(rp, sc, wv, I->n, lane, s);
+      if (p2) rows_product<DT, OP, RW, 2, false, false, true, false, WSP>(rp, sc, wv, I->n, lane, s, nullptr, nullptr, none, false);
+      else rows_product<DT, OP, RW, 2, false, false, false, false, WSP>(rp, sc, wv, I->n, lane, s, nullptr, nullptr, none, false);
     } else {
-      rows_product<DT, OP, RW, 2, false, false, false, false, WSP>(rp, sc, wv, I->n, lane, s);
+      rows_product<DT, OP, RW, 2, false, false, false, false, WSP>(rp, sc, wv, I->n, lane, s, nullptr, nullptr, none, false);
     }
 #pragma unroll
     for (int r = 0; r < RW; ++r)
