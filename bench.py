@@ -694,6 +694,25 @@ def bench_pca(mp, ctx, torch, D=4096, N=65536, k=8, seed=77):
             executed = T * (T + 1) / 2 * 128 * 128 * N
             out["gram_min1_executed_terms"] = executed
             out["gram_min1_valu_frac"] = executed * 2.25 / s / 78.6e12
+            out["gram_min1_term"] = ("fma(med3(a, -|b|, |b|), s_b, acc), s_b = +-1 from the sign bit of b: an "
+                                     "exact sign flip in one instruction with the add, not a product of data")
+            # the same build with the term as sign-bit flip, med3 and add (three instructions;
+            # the same bits): the multiply-free form's time beside it
+            os.environ["MAPI_GRAM_MIN1_FORM"] = "xor"
+            try:
+                Ax = mp.mapi_mingram(X, 1.0 / N, op, ctx=ctx)
+                torch.cuda.synchronize()
+                sx = float("inf")
+                for _ in range(3):
+                    t0 = time.perf_counter()
+                    Ax = mp.mapi_mingram(X, 1.0 / N, op, ctx=ctx)
+                    torch.cuda.synchronize()
+                    sx = min(sx, time.perf_counter() - t0)
+            finally:
+                del os.environ["MAPI_GRAM_MIN1_FORM"]
+            out["gram_min1_xor_form_ms"] = sx * 1e3
+            out["gram_min1_xor_form_same_bits"] = bool(torch.equal(Ax, A))
+            del Ax
         else:
             # the covariance runs on the matrix cores: 2 flops per term against the FP32 MFMA peak
             out["gram_dot_tflops"] = 2.0 * terms / s / 1e12

@@ -360,7 +360,11 @@ mapi_status mapi_mingram(mapi_ctx* ctx, const float* X, int64_t D, int64_t N, in
  * RPI (eq. 1) on the covariance of eq. (2); both built from X with `scale`.
  * Vector i is extracted from (I - P P^T) A, P the l2-normalised earlier vectors,
  * orthonormalised by modified Gram-Schmidt in float64, starting from column i of
- * W0.  W0, P_out: device float, D x k, column-major (column i at offset i*D).
+ * W0.  W0, P_out: device float, D x k, column-major (column i at offset i*D); one
+ * start per vector, so that each can be chosen (one start w0 for all: pass it k
+ * times).  W0 = NULL: seeded starts, vector i from the start vector that
+ * mapi_generate_dense gives for seed i (w_j = -+fl32(1 / sqrt(D)), the sign the
+ * top bit of splitmix64(splitmix64(i ^ 0x1B873593) + j)).
  * info_k: host array of k infos.  The built and deflated matrices (2 D^2 floats),
  * the Gram build's partial tiles (mapi_mingram) and the float64 basis are
  * workspace (MAPI_WS_PCA + (k - 1) MAPI_WS_PCA_VECTOR).                         */

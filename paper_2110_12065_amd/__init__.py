@@ -409,24 +409,28 @@ def mapi_mingram(X, scale, op="min1", ctx=None):
     return A
 
 
-def mapi_pca_topk(X, k, W0, method="mapi", scale=None, max_iters=100, tol=0.0, op="min1", check_every=0,
+def mapi_pca_topk(X, k, W0=None, method="mapi", scale=None, max_iters=100, tol=0.0, op="min1", check_every=0,
                   stall_iters=0, ctx=None):
-    """Top-k principal vectors with deflation.  W0: D x k start vectors (columns).
+    """Top-k principal vectors with deflation.  W0: D x k start vectors (columns), or None
+    for the seeded starts (vector i from the generated start vector of seed i).
     Returns (P as a D x k tensor, [info per vector])."""
     import torch
     c = _ctx_of(ctx, X)
     if X.dtype != torch.float32 or X.dim() != 2 or X.stride(1) != 1:
         raise ValueError("X must be a 2-D float32 tensor with unit column stride")
     D, N = X.shape
-    W0c = W0.t().contiguous()          # column i at offset i*D
-    if W0c.shape != (k, D) or W0c.dtype != torch.float32:
-        raise ValueError("W0 must be a D x k float32 tensor")
+    W0c = None
+    if W0 is not None:
+        W0c = W0.t().contiguous()          # column i at offset i*D
+        if W0c.shape != (k, D) or W0c.dtype != torch.float32:
+            raise ValueError("W0 must be a D x k float32 tensor")
     Pc = torch.empty((k, D), dtype=torch.float32, device=X.device)
     o = _opts(max_iters, tol, op, False, check_every, stall_iters)
     infos = (Info * k)()
     _check(lib().mapi_pca_topk(c.handle, C.c_void_p(X.data_ptr()), D, N, X.stride(0), int(k),
                                float(1.0 / N if scale is None else scale), METHODS[method],
-                               C.c_void_p(W0c.data_ptr()), C.c_void_p(Pc.data_ptr()), C.byref(o), infos))
+                               C.c_void_p(W0c.data_ptr() if W0c is not None else None),
+                               C.c_void_p(Pc.data_ptr()), C.byref(o), infos))
     return Pc.t(), [infos[i].as_dict() for i in range(k)]
 
 

@@ -1087,7 +1087,7 @@ mapi_status mapi_mingram(mapi_ctx* c, const float* X, int64_t D, int64_t N, int6
 mapi_status mapi_pca_topk(mapi_ctx* c, const float* X, int64_t D, int64_t N, int64_t ldx, int32_t k, double scale,
                           int32_t method, const float* W0, float* P_out, const mapi_opts* opts, mapi_info* info_k) {
   if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
-  if (!X || !W0 || !P_out) return fail(MAPI_ERR_ARG, "X, W0 and P_out must be device pointers");
+  if (!X || !P_out) return fail(MAPI_ERR_ARG, "X and P_out must be device pointers");
   if (D <= 0 || N <= 0 || ldx < N) return fail(MAPI_ERR_ARG, "bad shape");
   if (k < 1 || k > D) return fail(MAPI_ERR_ARG, "k must be in [1, D]");
   if (method != MAPI_METHOD_MAPI && method != MAPI_METHOD_RPI) return fail(MAPI_ERR_ARG, "method %d", method);
@@ -1125,7 +1125,9 @@ mapi_status mapi_pca_topk(mapi_ctx* c, const float* X, int64_t D, int64_t N, int
     }
     mapi_dense desc{Acur, D, D, ldA, MAPI_F32, nullptr};
     mapi_info inf{};
-    s = run_dense(c, &desc, W0 + (int64_t)i * D, wtmp, &o, &inf, rpi, dws);
+    const float* start = W0 ? W0 + (int64_t)i * D : wtmp;
+    if (!W0) HIP_TRY(launch_gen_start((int)D, (uint64_t)i, wtmp, c->stream));   // seeded start, seed i
+    s = run_dense(c, &desc, start, wtmp, &o, &inf, rpi, dws);
     if (info_k) info_k[i] = inf;
     if (s != MAPI_OK) return s;
     {

@@ -395,6 +395,8 @@ int pr_scalar_blocks(int64_t n);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, int cu_count, hipStream_t s);
+// Start vector of the generated problem with this seed (k_batched.hip).
+hipError_t launch_gen_start(int n, uint64_t seed, float* w, hipStream_t s);
 hipError_t launch_read16(const void* src, int64_t n16, uint32_t* sink, int blocks, int unroll, hipStream_t s);
 
 int image_max_n();

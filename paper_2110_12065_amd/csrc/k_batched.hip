@@ -777,6 +777,20 @@ hipError_t launch_gen_dense(int n, uint64_t seed, float* A, int64_t ld, float* w
   return hipGetLastError();
 }
 
+// The generated problem's start vector alone: w_i = -+fl32(1 / sqrt(n)) by the top bit
+// of splitmix64(splitmix64(seed ^ 0x1B873593) + i), as k_gen_dense writes it.
+__global__ void __launch_bounds__(256) k_gen_start(int n, uint64_t seed, float* w, float inv_sqrt_n) {
+  const uint64_t vbase = splitmix64(seed ^ 0x1B873593ull);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    w[i] = (splitmix64(vbase + (uint64_t)i) >> 63) ? -inv_sqrt_n : inv_sqrt_n;
+}
+
+hipError_t launch_gen_start(int n, uint64_t seed, float* w, hipStream_t s) {
+  const int grid = (n + 255) / 256 < 1024 ? ((n + 255) / 256 > 0 ? (n + 255) / 256 : 1) : 1024;
+  hipLaunchKernelGGL(k_gen_start, dim3(grid), dim3(256), 0, s, n, seed, w, gen_consts(n).w0);
+  return hipGetLastError();
+}
+
 int persistent_threads() { return kBT; }
 
 hipError_t launch_persistent(BQueue* q, BInst* inst, BCtl* ctl, int blocks, hipStream_t s) {

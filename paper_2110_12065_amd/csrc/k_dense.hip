@@ -214,7 +214,9 @@ DenseTuning dense_default_tuning(const DenseArgs& a, int cu_count, int max_lds_b
     t.rows_per_wave = (a.n_rows >= 4096) ? 4 : (a.n_rows >= 1024 ? 2 : 1);
     t.unroll = 2;
     t.blocks_per_cu = 1;
-    t.w_in_lds = 0;
+    // staged w lets a solve form each iterate inside the next product (no normalisation
+    // launch per iteration)
+    t.w_in_lds = lds_fits ? 1 : 0;
   } else {
     t.rows_per_wave = 1;
     t.unroll = (a.dtype == MAPI_BF16) ? 4 : 2;

@@ -10,6 +10,9 @@
 // chunks each block writes a float64 partial tile and k_gram_reduce sums the chunks
 // in order; with one chunk the block writes its tile (and the mirror) itself.  The
 // chunk count depends only on D and N, so results do not depend on the device.
+#include <cstdlib>
+#include <cstring>
+
 #include "common.h"
 
 namespace mapi {
@@ -66,7 +69,9 @@ constexpr int NLPR = NKS / 4;                // loader threads per staged row (o
 constexpr int kGramTM = 4;                   // rows of a thread's register tile
 constexpr int gram_threads(int tm) { return MT * MT / (tm * 4); }
 
-template <int OP, bool SPLIT, int TM>
+// XF (min1 only): the term as the product kernels write it, a sign-bit flip of a, med3
+// and an add (three instructions), instead of the FMA by +-1 (two); the same bits.
+template <int OP, bool SPLIT, int TM, bool XF = false>
 __global__ void __launch_bounds__(gram_threads(TM))
 k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t chunk, int tiles, double scale,
            float* __restrict__ A, int64_t lda, double* __restrict__ part) {
@@ -157,7 +162,7 @@ k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t c
         av[4 * t] = a[t].x; av[4 * t + 1] = a[t].y; av[4 * t + 2] = a[t].z; av[4 * t + 3] = a[t].w;
       }
       const float bv[4] = {b.x, b.y, b.z, b.w};
-      if constexpr (OP == MAPI_OP_MIN1) {
+      if constexpr (OP == MAPI_OP_MIN1 && !XF) {
         float sg[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) sg[q] = __uint_as_float(sign_bit(bv[q]) | 0x3f800000u);
@@ -402,16 +407,23 @@ size_t gram_workspace_bytes(int64_t D, int64_t N, int op) {
   return g.kc > 1 ? (size_t)g.kc * (size_t)g.tiles * MT * MT * sizeof(double) : 0;
 }
 
-template <int OP>
+template <int OP, bool XF = false>
 static void launch_gram_min(const GramSplit& g, const float* X, int64_t D, int64_t N, int64_t ldx, double scale,
                             float* A, int64_t lda, double* ws, hipStream_t s) {
   constexpr int NTH = gram_threads(kGramTM);
   if (g.kc > 1)
-    hipLaunchKernelGGL((k_gram_min<OP, true, kGramTM>), dim3((unsigned)(g.tiles * g.kc)), dim3(NTH), 0, s, X, (int)D, N,
-                       ldx, g.chunk, (int)g.tiles, scale, A, lda, ws);
+    hipLaunchKernelGGL((k_gram_min<OP, true, kGramTM, XF>), dim3((unsigned)(g.tiles * g.kc)), dim3(NTH), 0, s, X,
+                       (int)D, N, ldx, g.chunk, (int)g.tiles, scale, A, lda, ws);
   else
-    hipLaunchKernelGGL((k_gram_min<OP, false, kGramTM>), dim3((unsigned)g.tiles), dim3(NTH), 0, s, X, (int)D, N, ldx, g.chunk,
-                       (int)g.tiles, scale, A, lda, nullptr);
+    hipLaunchKernelGGL((k_gram_min<OP, false, kGramTM, XF>), dim3((unsigned)g.tiles), dim3(NTH), 0, s, X, (int)D, N,
+                       ldx, g.chunk, (int)g.tiles, scale, A, lda, nullptr);
+}
+
+// MAPI_GRAM_MIN1_FORM=xor selects the three-instruction min1 term (for comparison; the
+// result has the same bits), read at each build.
+static bool gram_min1_xor() {
+  const char* e = std::getenv("MAPI_GRAM_MIN1_FORM");
+  return e != nullptr && std::strcmp(e, "xor") == 0;
 }
 
 hipError_t launch_gram(const float* X, int64_t D, int64_t N, int64_t ldx, double scale, int op, float* A, int64_t lda,
@@ -427,7 +439,8 @@ hipError_t launch_gram(const float* X, int64_t D, int64_t N, int64_t ldx, double
       hipLaunchKernelGGL(k_gram_mfma<false>, dim3((unsigned)g.tiles), dim3(512), 0, s, X, (int)D, N, ldx, g.chunk,
                          (int)g.tiles, scale, A, lda, nullptr);
   } else if (op == MAPI_OP_MIN1) {
-    launch_gram_min<MAPI_OP_MIN1>(g, X, D, N, ldx, scale, A, lda, ws, s);
+    if (gram_min1_xor()) launch_gram_min<MAPI_OP_MIN1, true>(g, X, D, N, ldx, scale, A, lda, ws, s);
+    else launch_gram_min<MAPI_OP_MIN1>(g, X, D, N, ldx, scale, A, lda, ws, s);
   } else {
     launch_gram_min<MAPI_OP_MIN2>(g, X, D, N, ldx, scale, A, lda, ws, s);
   }

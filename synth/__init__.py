@@ -249,7 +249,6 @@ def generated_dense(n, seed):
     seed = _U64(seed)
     base = splitmix64(seed)
     sbase = splitmix64(seed ^ _U64(0x5BD1E995))
-    vbase = splitmix64(seed ^ _U64(0x1B873593))
     idx = np.arange(n, dtype=np.uint64)
     lo = np.minimum(idx[:, None], idx[None, :])
     hi = np.maximum(idx[:, None], idx[None, :])
@@ -260,9 +259,16 @@ def generated_dense(n, seed):
     sig = (_counter(sbase, idx) >> _U64(63)).astype(bool)
     same = sig[:, None] == sig[None, :]
     A = (x * s_n).astype(np.float32) + np.where(same, spike, -spike).astype(np.float32)
+    return A.astype(np.float32), generated_start(n, seed)
+
+
+def generated_start(n, seed):
+    """The start vector of the seed-generated problem (generated_dense) alone: w0_i =
+    -+fl32(1 / sqrt(n)) by the top bit of splitmix64(splitmix64(seed ^ 0x1B873593) + i)."""
+    vbase = splitmix64(_U64(seed) ^ _U64(0x1B873593))
+    idx = np.arange(n, dtype=np.uint64)
     inv = np.float32(1.0 / np.sqrt(float(n)))
-    w0 = np.where((_counter(vbase, idx) >> _U64(63)).astype(bool), -inv, inv).astype(np.float32)
-    return A.astype(np.float32), w0
+    return np.where((_counter(vbase, idx) >> _U64(63)).astype(bool), -inv, inv).astype(np.float32)
 
 
 # --------------------------------------------------------------------------

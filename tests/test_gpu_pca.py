@@ -73,6 +73,24 @@ def test_pca_topk_matches_oracle(method):
     np.testing.assert_allclose(P.T @ P, np.eye(k), atol=1e-6)
 
 
+@pytest.mark.parametrize("method", ["mapi", "rpi"])
+def test_pca_topk_seeded_starts(method):
+    # W0 = None: vector i starts from the generated start vector of seed i, the same bits as
+    # passing those vectors (written by the host generator) explicitly; and against the oracle
+    D, N, k, T = 200, 1500, 3, 25
+    X = synth.pca_data(D, N, seed=11)
+    W0 = np.stack([synth.generated_start(D, i) for i in range(k)], axis=1)
+    Pn, inn = mp.mapi_pca_topk(to_dev(X), k, None, method=method, max_iters=T)
+    Pe, ine = mp.mapi_pca_topk(to_dev(X), k, to_dev(W0), method=method, max_iters=T)
+    np.testing.assert_array_equal(Pn.cpu().numpy(), Pe.cpu().numpy())
+    assert [i["iters"] for i in inn] == [i["iters"] for i in ine] == [T] * k
+    Pr, _ = oracle.pca_topk(X, k, W0, method=method, T=T)
+    P = Pn.cpu().numpy().astype(np.float64)
+    for i in range(k):
+        e, c = report(f"pca seeded {method} vector {i}", P[:, i], Pr[:, i])
+        assert e <= TOL and c > 1 - 1e-6
+
+
 def test_pca_topk_tolerance_per_vector():
     D, N, k = 128, 2048, 3
     X = synth.pca_data(D, N, seed=7)
@@ -84,6 +102,19 @@ def test_pca_topk_tolerance_per_vector():
     for i in range(k):
         assert infos[i]["converged"]
         assert abs(cosine(P[:, i], V[:, -1 - i])) > 1 - 1e-5
+
+
+def test_gram_min1_xor_form_same_bits(monkeypatch):
+    # the three-instruction min1 term (sign-bit flip, med3, add) builds the same matrix, bit for
+    # bit, as the two-instruction one (med3, FMA by +-1); with the sample chunks split (D = 300,
+    # N = 5000) and whole
+    for D, N in ((300, 5000), (130, 700)):
+        X = synth.pca_data(D, N, seed=D + N)
+        A = mp.mapi_mingram(to_dev(X), 1.0 / N, "min1").cpu().numpy()
+        monkeypatch.setenv("MAPI_GRAM_MIN1_FORM", "xor")
+        B = mp.mapi_mingram(to_dev(X), 1.0 / N, "min1").cpu().numpy()
+        monkeypatch.delenv("MAPI_GRAM_MIN1_FORM")
+        np.testing.assert_array_equal(A, B)
 
 
 def test_full_size_gram_sampled_entries():

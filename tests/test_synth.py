@@ -78,3 +78,15 @@ def test_minibatch_indices_range_and_shape():
     b = synth.minibatch_indices(3, 4, 5, 17, seed=1)
     assert b.shape == (3, 4, 5) and b.dtype == np.int32
     assert b.min() >= 0 and b.max() < 17
+
+
+def test_generated_start_is_the_generated_problems_start():
+    # the start vector alone (the seeded PCA starts) equals the one generated_dense returns,
+    # has entries +-fl32(1/sqrt(n)) and unit l2 norm up to rounding, and differs between seeds
+    for n, seed in ((1, 0), (7, 3), (300, 12)):
+        _, w0 = synth.generated_dense(n, seed)
+        ws = synth.generated_start(n, seed)
+        np.testing.assert_array_equal(ws, w0)
+        assert set(np.abs(ws).tolist()) == {float(np.float32(1.0 / np.sqrt(n)))}
+        assert abs(float(np.linalg.norm(ws.astype(np.float64))) - 1.0) < 1e-6
+    assert not np.array_equal(synth.generated_start(300, 0), synth.generated_start(300, 1))
