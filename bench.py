@@ -51,7 +51,7 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("ops.h", "dense_kernel.h", "k_dense_f32.hip", "k_dense_bf16.hip", "k_dense_fp8.hip"):
+    for f in ("ops.h", "common.h", "dense_kernel.h", "k_dense_f32.hip", "k_dense_bf16.hip", "k_dense_fp8.hip"):
         with open(os.path.join(ROOT, "paper_2110_12065_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
