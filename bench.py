@@ -126,7 +126,7 @@ def setup(autotune=True):
         mats[dt] = mp.mapi_quantize(C, dt, ctx=ctx)
     for dt, (A, rs) in mats.items():
         if autotune:
-            shape, ms = mp.mapi_autotune_dense(A, "min1", reps=4, row_scale=rs, ctx=ctx)
+            shape, ms = mp.mapi_autotune_dense(A, "min1", reps=10, row_scale=rs, ctx=ctx)
             log(f"autotuned {dt}: {shape} {ms * 1e3:.1f} us")
         else:
             log(f"launch shape {dt}: {mp.mapi_tuning_get(mp._dtype_code(A), N, N, ctx=ctx)}")

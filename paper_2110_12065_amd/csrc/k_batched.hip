@@ -159,6 +159,7 @@ __device__ double dense_rows_t(const BInst* I, const float* wv, int r0, int r1, 
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
   const unsigned char* A = static_cast<const unsigned char*>(I->A);
   const int64_t ldb = I->ld * Traits<DT>::ESZ;
+  const int S = I->n / Traits<DT>::VE / kWave;   // whole wave-steps of a row
   double nrm = 0.0;
   for (int g = r0 + RW * wave; g < r1; g += RW * nw) {
     const unsigned char* rp[RW];
@@ -175,10 +176,10 @@ __device__ double dense_rows_t(const BInst* I, const float* wv, int r0, int r1, 
       bool p2 = true;
 #pragma unroll
       for (int r = 0; r < RW; ++r) p2 = p2 && pow2_scale(sc[r]);
-      if (p2) rows_product<DT, OP, RW, 2, false, false, true, false, WSP>(rp, sc, wv, I->n, lane, s, nullptr, nullptr, none, false);
-      else rows_product<DT, OP, RW, 2, false, false, false, false, WSP>(rp, sc, wv, I->n, lane, s, nullptr, nullptr, none, false);
+      if (p2) rows_product<DT, OP, RW, 2, false, false, true, false, WSP>(rp, sc, wv, I->n, lane, s, nullptr, nullptr, none, false, rot_step(g, S));
+      else rows_product<DT, OP, RW, 2, false, false, false, false, WSP>(rp, sc, wv, I->n, lane, s, nullptr, nullptr, none, false, rot_step(g, S));
     } else {
-      rows_product<DT, OP, RW, 2, false, false, false, false, WSP>(rp, sc, wv, I->n, lane, s, nullptr, nullptr, none, false);
+      rows_product<DT, OP, RW, 2, false, false, false, false, WSP>(rp, sc, wv, I->n, lane, s, nullptr, nullptr, none, false, rot_step(g, S));
     }
 #pragma unroll
     for (int r = 0; r < RW; ++r)

@@ -408,16 +408,18 @@ def test_stop_rule_in_the_product_matches_the_kernel_pair(dtype, meth, n):
 @pytest.mark.parametrize("n", [512, 1024, 4096])
 @pytest.mark.parametrize("meth", ["mapi", "rpi"])
 def test_stop_rule_in_the_product_exact_residuals(meth, n):
-    # A constant positive matrix and a positive start: the first iterate is the constant vector
-    # (1/n for MAPI, 1/sqrt(n) for RPI, exact for these n) and every later residual is exactly
-    # 0.  So the stop iteration of each rule is known exactly: a zero tolerance never converges;
+    # A constant positive matrix and a positive start, both dyadic (so every row sum is exact,
+    # whatever order the kernel adds its terms in, and all rows' sums are equal): the first
+    # iterate is the constant vector (1/n for MAPI, 1/sqrt(n) for RPI, exact for these n) and
+    # every later residual is exactly 0.  So the stop iteration of each rule is known exactly:
+    # a zero tolerance never converges;
     # tol 1e-300 stops at iteration 2; the stall rule with k = 3 stops at 2 + 3 = 5 (iteration 2
     # sets the smallest residual, 0, and three iterations do not beat it).  The lagged decision
     # is taken by the next product (T > t + 1), by the last normalisation (T = t + 1) or not at
     # all (T <= t).
     print(f"[case] exact stop rule {meth} n={n}", flush=True)
-    A = to_dev(np.full((n, n), 0.7, np.float32))
-    w0h = np.random.default_rng(n).uniform(0.1, 1.0, n).astype(np.float32)
+    A = to_dev(np.full((n, n), 0.75, np.float32))
+    w0h = (np.random.default_rng(n).integers(7, 65, n) / 64.0).astype(np.float32)
     w0 = to_dev(w0h)
     fn = mp.mapi_solve if meth == "mapi" else mp.rpi_solve
     const = 1.0 / n if meth == "mapi" else 1.0 / np.sqrt(n)
@@ -434,7 +436,7 @@ def test_stop_rule_in_the_product_exact_residuals(meth, n):
             if iters >= 2:
                 assert info["residual"] == 0.0
                 np.testing.assert_array_equal(w.cpu().numpy(), np.full(n, const, np.float32))
-            ref = (oracle.mapi if meth == "mapi" else oracle.rpi)(np.full((n, n), np.float32(0.7), np.float64),
+            ref = (oracle.mapi if meth == "mapi" else oracle.rpi)(np.full((n, n), 0.75, np.float64),
                                                                     w0h.astype(np.float64), iters)
             assert rel_l1(w.cpu().numpy(), ref.w) <= TOL
             assert info["norm"] == pytest.approx(ref.norms[-1], rel=1e-6)
