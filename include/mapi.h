@@ -127,7 +127,9 @@ typedef enum mapi_ws_kind {
   MAPI_WS_PAGERANK = 2,      /* mapi_pagerank: n = nodes, nnz = links              */
   MAPI_WS_PAGERANK_F64 = 3,  /* mapi_pagerank_f64: n = nodes, nnz = links          */
   MAPI_WS_PRODUCT = 4,       /* mapi_mavp, mapi_mavp_timed, mapi_autotune_dense,
-                                mapi_read_reference: n = rows, nnz = columns      */
+                                mapi_read_reference: n = rows, nnz = columns
+                                (n = nnz includes a solve's buffers: the
+                                autotuner times square matrices on iterations) */
   MAPI_WS_MINGRAM = 5,       /* mapi_mingram: n = D, nnz = N samples               */
   MAPI_WS_PCA = 6,           /* mapi_pca_topk with k = 1: n = D, nnz = N samples;
                                 each further vector adds MAPI_WS_PCA_VECTOR        */
@@ -200,12 +202,16 @@ typedef struct mapi_tuning {
 } mapi_tuning;
 
 /* Autotuner (project-written): times every admissible launch shape on A with
- * product `op` (`reps` launches each, HIP events on the context stream) and
- * stores the fastest in the context's table for A's bucket (storage type,
- * ceil(log2 n_rows), ceil(log2 n_cols)); later products and solves in that
- * bucket use it.  If the environment variable MAPI_TUNE_CACHE names a file,
- * tuned entries are appended to it and read back by mapi_create.
- * best / best_ms (optional, host) receive the choice and its mean time.        */
+ * product `op` and stores the fastest in the context's table for A's bucket
+ * (storage type, ceil(log2 n_rows), ceil(log2 n_cols)); later products and
+ * solves in that bucket use it.  A square matrix is timed on `reps` solve
+ * iterations per shape, enqueued as a solve enqueues them (the six fastest are
+ * timed three more times and the best of each one's timings decides); a
+ * rectangular one, or one whose normaliser is zero, on `reps` bare products.
+ * HIP events on the context stream.  If the environment variable
+ * MAPI_TUNE_CACHE names a file, tuned entries are appended to it and read back
+ * by mapi_create.  best / best_ms (optional, host) receive the choice and its
+ * mean time per launch (per iteration for a square matrix).                    */
 mapi_status mapi_autotune_dense(mapi_ctx* ctx, const mapi_dense* A, int32_t op, int32_t reps,
                                 mapi_tuning* best, double* best_ms);
 /* Read or overwrite the table entry used for a (dtype, n_rows, n_cols) bucket.
