@@ -209,11 +209,17 @@ DenseTuning dense_default_tuning(const DenseArgs& a, int cu_count, int max_lds_b
   const bool lds_fits = (int64_t)dense_lds_bytes(a.dtype, a.n_cols, 1) + 1024 <= (int64_t)max_lds_bytes;
   t.blocks = 0;
   t.waves = 8;
-  t.nontemporal = 1;
+  // non-temporal loads only for a matrix larger than the 256 MB Infinity Cache: a smaller
+  // one (the PCA's 4096 x 4096 matrices, 64 MiB) can stay there between products
+  const int64_t bytes = a.n_rows * a.n_cols * (a.dtype == MAPI_F32 ? 4 : a.dtype == MAPI_BF16 ? 2 : 1);
+  t.nontemporal = bytes > (int64_t(192) << 20) ? 1 : 0;
   if (a.dtype == MAPI_F32) {
-    t.rows_per_wave = (a.n_rows >= 4096) ? 4 : (a.n_rows >= 1024 ? 2 : 1);
+    // enough row groups for every compute unit's 8 waves twice over (4096 rows: one row
+    // per wave, two blocks per compute unit)
+    const int64_t per = 2 * (int64_t)cu_count * 8;
+    t.rows_per_wave = (a.n_rows >= 4 * per) ? 4 : (a.n_rows >= 2 * per ? 2 : 1);
     t.unroll = 2;
-    t.blocks_per_cu = 1;
+    t.blocks_per_cu = a.n_rows >= 4 * per ? 1 : 2;
     // staged w lets a solve form each iterate inside the next product (no normalisation
     // launch per iteration)
     t.w_in_lds = lds_fits ? 1 : 0;
@@ -224,7 +230,6 @@ DenseTuning dense_default_tuning(const DenseArgs& a, int cu_count, int max_lds_b
     t.blocks_per_cu = 2;
     t.w_in_lds = lds_fits ? 1 : 0;
   }
-  (void)cu_count;
   return t;
 }
 
