@@ -45,7 +45,10 @@ typedef enum mapi_status {
   MAPI_ERR_BUDGET = 5,       /* request larger than the serving memory budget     */
   MAPI_ERR_UNSUPPORTED = 6,  /* combination not implemented                        */
   MAPI_ERR_PENDING = 7,      /* serving: result not ready yet                      */
-  MAPI_ERR_TIMEOUT = 8       /* serving: wait timed out                            */
+  MAPI_ERR_TIMEOUT = 8,      /* serving: wait timed out                            */
+  MAPI_ERR_DEVICE_CHECK = 9  /* device-checked build (libmapi_checked.so): a
+                                kernel's index check failed; the message names
+                                the kernel's file id and line                     */
 } mapi_status;
 
 typedef enum mapi_dtype {

@@ -15,7 +15,9 @@ import os
 import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmapi.so")
+# MAPI_CHECKED=1 loads the device-checked build (libmapi_checked.so, built by
+# `python -m paper_2110_12065_amd.build --checked`)
+LIB_PATH = os.path.join(HERE, "libmapi_checked.so" if os.environ.get("MAPI_CHECKED") == "1" else "libmapi.so")
 
 MAPI_F32, MAPI_BF16, MAPI_FP8_E4M3 = 0, 1, 2
 OPS = {"min1": 0, "min2": 1, "diamond": 2, "dot": 3}

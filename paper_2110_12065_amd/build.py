@@ -1,9 +1,11 @@
 """Build libmapi.so (HIP, gfx950 only) in-tree with hipcc.
 
-    python -m paper_2110_12065_amd.build
+    python -m paper_2110_12065_amd.build [--checked]
 
 Objects go to paper_2110_12065_amd/_build/, the library to
-paper_2110_12065_amd/libmapi.so.  Every call recompiles.
+paper_2110_12065_amd/libmapi.so.  Every call recompiles.  --checked builds
+libmapi_checked.so (objects in _build/checked/) with MAPI_DEVICE_CHECKS: device-side
+index checks that record the first failure in the solve state, for debugging.
 """
 from __future__ import annotations
 
@@ -18,6 +20,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmapi.so")
+LIB_CHECKED = os.path.join(HERE, "libmapi_checked.so")
 
 SOURCES = ["k_dense_f32.hip", "k_dense_bf16.hip", "k_dense_fp8.hip", "k_dense.hip", "k_quant.hip", "k_csr.hip", "k_csr_split.hip",
            "k_gram.hip", "k_factored.hip", "k_small.hip", "k_minibatch.hip", "k_image.hip", "k_batched.hip", "batch.hip", "serve.hip", "api.hip", "noalloc.hip"]
@@ -35,9 +38,9 @@ FLAGS = [
 ]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src, checked=False):
+    obj = os.path.join(BUILD, "checked" if checked else "", os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, *(["-DMAPI_DEVICE_CHECKS"] if checked else []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     errs = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
                      if "not a recognized feature" not in l)
@@ -46,23 +49,24 @@ def _compile(src):
     return obj, errs
 
 
-def build(verbose=False):
+def build(verbose=False, checked=False):
     if not os.path.exists(HIPCC):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
-    os.makedirs(BUILD, exist_ok=True)
+    os.makedirs(os.path.join(BUILD, "checked") if checked else BUILD, exist_ok=True)
+    lib_path = LIB_CHECKED if checked else LIB
     with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
-        results = list(ex.map(_compile, SOURCES))
+        results = list(ex.map(lambda src: _compile(src, checked), SOURCES))
     for obj, msg in results:
         if verbose and msg.strip():
             print(msg)
-    tmp = LIB + ".tmp"
+    tmp = lib_path + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *[o for o, _ in results]]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    shutil.move(tmp, LIB)
-    return LIB
+    shutil.move(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, checked="--checked" in sys.argv))

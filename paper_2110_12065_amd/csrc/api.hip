@@ -279,6 +279,7 @@ mapi_status run_dense(mapi_ctx* c, const mapi_dense* A, const float* w0, float* 
 
   HIP_TRY(hipMemcpyAsync(wb[0], w0, sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(launch_state_init(st, o->max_iters, o->tol, o->stall_iters, c->stream));
+  if (c->dcheck_selftest) HIP_TRY(launch_dcheck_selftest(st, c->stream));
   const int check = o->check_every > 0 ? o->check_every : 16;
   int launched = 0;
   for (int it = 0; it < o->max_iters; ++it) {
@@ -567,6 +568,7 @@ mapi_status mapi_create(int device, void* hip_stream, mapi_ctx** out) {
   }
   load_tune_cache(c);
   if (const char* e = std::getenv("MAPI_DENSE_ALTERNATE")) c->alternate = std::atoi(e) != 0;
+  if (const char* e = std::getenv("MAPI_DCHECK_SELFTEST")) c->dcheck_selftest = std::atoi(e) != 0;
   mapi_status ss = scratch_setup(device, &c->scratch);
   if (ss != MAPI_OK) {
     delete c;

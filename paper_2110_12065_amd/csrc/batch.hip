@@ -390,6 +390,9 @@ mapi_status mapi_solve_batched(mapi_ctx* c, int32_t count, const mapi_problem* p
       infos[i].status = H[i].st.status;
     }
     if (H[i].st.status != MAPI_OK) worst = (mapi_status)H[i].st.status;
+    if (H[i].st.check != 0)   // only a device-checked build records failures
+      return fail(MAPI_ERR_DEVICE_CHECK, "device check failed in instance %d: file id %u, line %u", i,
+                  H[i].st.check >> 16, H[i].st.check & 0xFFFFu);
   }
   if (worst != MAPI_OK) return fail(worst, "at least one instance failed (see infos)");
   return MAPI_OK;

@@ -27,7 +27,7 @@ struct SolveState {
   int32_t stall;
   int32_t max_iters;
   int32_t stall_iters;
-  uint32_t cnt_a;     // arrival counter (spare)
+  uint32_t check;     // device-checked builds: the first failed check (file id << 16 | line)
   uint32_t cnt_b;     // arrival counter of the normalisation kernel's reduction
   int32_t pad;
 };
@@ -147,6 +147,21 @@ __device__ __forceinline__ double block_sum_parts(const double* part, int count,
   for (int i = threadIdx.x; i < count; i += blockDim.x) s += load_agent(&part[(size_t)i * stride + off]);
   return block_sum_f64(s, sh);
 }
+
+// Device checks.  In a build with MAPI_DEVICE_CHECKS (libmapi_checked.so) MAPI_DCHECK(st,
+// cond, file_id) evaluates cond and, when it fails, records file_id << 16 | line in st->check
+// (the first failure is kept) and yields false, so that the caller skips or clamps the
+// access it guards and the kernel still ends normally; the host turns a recorded failure
+// into MAPI_ERR_DEVICE_CHECK.  In the ordinary build it is the constant true.
+// File ids: 1 dense product, 2 CSR product, 3 column-split product, 4 batched kernel.
+__device__ __forceinline__ void dcheck_fail(const SolveState* st, uint32_t file_id, uint32_t line) {
+  if (st != nullptr) atomicCAS(const_cast<uint32_t*>(&st->check), 0u, (file_id << 16) | (line & 0xFFFFu));
+}
+#ifdef MAPI_DEVICE_CHECKS
+#define MAPI_DCHECK(st, cond, file_id) ((cond) ? true : (::mapi::dcheck_fail((st), (file_id), __LINE__), false))
+#else
+#define MAPI_DCHECK(st, cond, file_id) true
+#endif
 
 __device__ __forceinline__ bool state_done(const SolveState* st) {
   return __hip_atomic_load(const_cast<int32_t*>(&st->done), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
@@ -395,6 +410,8 @@ int pr_scalar_blocks(int64_t n);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, int cu_count, hipStream_t s);
+// One always-failing device check on st (a no-op outside device-checked builds).
+hipError_t launch_dcheck_selftest(SolveState* st, hipStream_t s);
 // Start vector of the generated problem with this seed (k_batched.hip).
 hipError_t launch_gen_start(int n, uint64_t seed, float* w, hipStream_t s);
 hipError_t launch_read16(const void* src, int64_t n16, uint32_t* sink, int blocks, int unroll, hipStream_t s);

@@ -66,6 +66,9 @@ struct mapi_ctx {
   // dense solves sweep the matrix forward and backward in turn (MAPI_DENSE_ALTERNATE=1);
   // off by default: on MI355X it measured no faster than forward sweeps only
   bool alternate = false;
+  // MAPI_DCHECK_SELFTEST=1: dense solves launch one always-failing device check (which
+  // only a device-checked build records), to test the reporting path
+  bool dcheck_selftest = false;
   mapi::SolveState* st_host = nullptr;     // pinned copy of the device state
   // matrices owned by the PCA driver
   void* big = nullptr;
@@ -230,6 +233,9 @@ inline mapi_status sync_and_state(mapi_ctx* c, const SolveState* st_dev) {
   HIP_TRY(hipMemcpyAsync(c->st_host, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   collect_timing(c);
+  if (c->st_host->check != 0)   // only a device-checked build records failures
+    return fail(MAPI_ERR_DEVICE_CHECK, "device check failed: file id %u, line %u", c->st_host->check >> 16,
+                c->st_host->check & 0xFFFFu);
   return MAPI_OK;
 }
 

@@ -437,6 +437,7 @@ k_mavp_dense(const unsigned char* __restrict__ A, int64_t ld_bytes, int n_rows, 
   // it (in forward order) ended; the rows each block owns change, the row sums do not
   for (int g0 = blockIdx.x * nw + wave; g0 < ngroups; g0 += gridDim.x * nw) {
     const int g = rev ? ngroups - 1 - g0 : g0;
+    if (!MAPI_DCHECK(st, g >= 0 && (int64_t)g * RW < n_rows, 1)) continue;
     const bool fst = kAhead && have_first;   // the first group only
     have_first = false;
     const unsigned char* rp[RW];

@@ -161,6 +161,7 @@ __device__ double dense_rows_t(const BInst* I, const float* wv, int r0, int r1, 
   const int64_t ldb = I->ld * Traits<DT>::ESZ;
   const int S = I->n / Traits<DT>::VE / kWave;   // whole wave-steps of a row
   double nrm = 0.0;
+  if (!MAPI_DCHECK(&I->st, r0 >= 0 && r1 <= I->n, 4)) return 0.0;   // a row tile outside the matrix
   for (int g = r0 + RW * wave; g < r1; g += RW * nw) {
     const unsigned char* rp[RW];
     float sc[RW];
@@ -257,7 +258,10 @@ __device__ double csr_rows(const BInst* I, const float* w, int r0, int r1, float
         h[r] = ok ? val[p0[r] + k] : 0.0f;
       }
 #pragma unroll
-      for (int r = 0; r < R; ++r) wj[r] = w[cj[r]];
+      for (int r = 0; r < R; ++r) {
+        if (!MAPI_DCHECK(&I->st, (uint32_t)cj[r] < (uint32_t)I->n, 4)) cj[r] = 0;   // a source outside 0..n-1
+        wj[r] = w[cj[r]];
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (k < len[r]) {

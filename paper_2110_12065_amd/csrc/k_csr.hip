@@ -122,7 +122,10 @@ k_csr_product(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ c
         h[r] = ok ? val[p0[r] + k] : 0.0f;
       }
 #pragma unroll
-      for (int r = 0; r < R; ++r) wj[r] = w[cj[r]];
+      for (int r = 0; r < R; ++r) {
+        if (!MAPI_DCHECK(st, (uint64_t)(uint32_t)cj[r] < (uint64_t)n, 2)) cj[r] = 0;   // a source outside 0..n-1
+        wj[r] = w[cj[r]];
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (k < len[r]) {

@@ -348,10 +348,17 @@ k_csr_split_product(const uint8_t* __restrict__ len, const int32_t* __restrict__
   typedef __attribute__((address_space(3))) const T lmem_t;
   gmem_t* wg = (gmem_t*)w;
   lmem_t* wl = (lmem_t*)lhub;
+  const int nh_k = kSplitHubSlots > 0 ? min(nhub[k], kSplitHubSlots) : 0;
   auto wsrc = [&](int32_t jj) -> T {
     T v;
-    if (jj >= 0) v = wg[jj];
-    else v = wl[~jj];
+    if (jj >= 0) {
+      if (!MAPI_DCHECK(st, (int64_t)jj < n, 3)) jj = 0;        // a source outside 0..n-1
+      v = wg[jj];
+    } else {
+      int32_t slot = ~jj;
+      if (!MAPI_DCHECK(st, slot < nh_k, 3)) slot = 0;          // a hub slot not staged in LDS
+      v = wl[slot];
+    }
     return v;
   };
   const int64_t groups = gridDim.x / kSplitBlocks;

@@ -195,6 +195,18 @@ k_finish_out(const T* __restrict__ w0buf, const T* __restrict__ w1buf, T* __rest
     out[i] = final_l2 ? (T)((double)src[i] * scale) : src[i];
 }
 
+// A check that always fails (device-checked builds, when the context was created with
+// MAPI_DCHECK_SELFTEST=1): exercises the path from a failed device check to the caller's
+// error without any out-of-bounds access.
+__global__ void k_dcheck_selftest(SolveState* st) {
+  if (threadIdx.x == 0) (void)MAPI_DCHECK(st, false, 15);
+}
+
+hipError_t launch_dcheck_selftest(SolveState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_dcheck_selftest, dim3(1), dim3(64), 0, s, st);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_state_init(SolveState* st, int max_iters, double tol, int stall_iters, hipStream_t s) {
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, max_iters, tol, stall_iters);

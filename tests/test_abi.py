@@ -38,6 +38,21 @@ def test_library_exports_every_declared_symbol(libpath):
     assert not missing, missing
 
 
+def test_checked_library_exports_the_same_symbols():
+    # the device-checked build (MAPI_DEVICE_CHECKS) is the same ABI
+    import paper_2110_12065_amd as pkg
+    from paper_2110_12065_amd import build
+    path = build.LIB_CHECKED
+    if not os.path.exists(path):
+        pytest.skip("libmapi_checked.so not built (python -m paper_2110_12065_amd.build --checked)")
+    lib = ctypes.CDLL(path)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    lib.mapi_version.restype = ctypes.c_char_p
+    assert lib.mapi_version()
+    assert os.path.basename(pkg.LIB_PATH) in ("libmapi.so", "libmapi_checked.so")
+
+
 def test_binding_signatures_cover_header(libpath):
     import paper_2110_12065_amd as pkg
     declared = set(_declared())
