@@ -16,7 +16,7 @@ import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 # MAPI_CHECKED=1 loads the device-checked build (libmapi_checked.so, built by
-# `python -m paper_2110_12065_amd.build --checked`)
+# `python -m paper_2110_12065_amd.build` beside libmapi.so)
 LIB_PATH = os.path.join(HERE, "libmapi_checked.so" if os.environ.get("MAPI_CHECKED") == "1" else "libmapi.so")
 
 MAPI_F32, MAPI_BF16, MAPI_FP8_E4M3 = 0, 1, 2

@@ -1,11 +1,12 @@
 """Build libmapi.so (HIP, gfx950 only) in-tree with hipcc.
 
-    python -m paper_2110_12065_amd.build [--checked]
+    python -m paper_2110_12065_amd.build [--no-checked]
 
 Objects go to paper_2110_12065_amd/_build/, the library to
-paper_2110_12065_amd/libmapi.so.  Every call recompiles.  --checked builds
-libmapi_checked.so (objects in _build/checked/) with MAPI_DEVICE_CHECKS: device-side
-index checks that record the first failure in the solve state, for debugging.
+paper_2110_12065_amd/libmapi.so.  Every call recompiles.  Unless --no-checked, the same
+call also links libmapi_checked.so (its checked objects in _build/checked/, compiled with
+MAPI_DEVICE_CHECKS: device-side index checks that record the first failure in the solve
+state, for debugging).
 """
 from __future__ import annotations
 
@@ -49,18 +50,15 @@ def _compile(src, checked=False):
     return obj, errs
 
 
-def build(verbose=False, checked=False):
-    if not os.path.exists(HIPCC):
-        raise RuntimeError(f"hipcc not found at {HIPCC}")
-    os.makedirs(os.path.join(BUILD, "checked") if checked else BUILD, exist_ok=True)
-    lib_path = LIB_CHECKED if checked else LIB
-    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
-        results = list(ex.map(lambda src: _compile(src, checked), SOURCES))
-    for obj, msg in results:
-        if verbose and msg.strip():
-            print(msg)
+# Translation units with device checks (MAPI_DCHECK); the checked library takes every
+# other object from the ordinary build (the macro does not occur in them).
+CHECKED_SOURCES = ["k_dense_f32.hip", "k_dense_bf16.hip", "k_dense_fp8.hip", "k_dense.hip", "k_csr.hip",
+                   "k_csr_split.hip", "k_batched.hip"]
+
+
+def _link(lib_path, objs):
     tmp = lib_path + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *[o for o, _ in results]]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
@@ -68,5 +66,25 @@ def build(verbose=False, checked=False):
     return lib_path
 
 
+def build(verbose=False, checked=True):
+    """Compile every source and link libmapi.so, and with `checked` also libmapi_checked.so
+    (the checked objects compile in the same pool).  Returns the ordinary library's path."""
+    if not os.path.exists(HIPCC):
+        raise RuntimeError(f"hipcc not found at {HIPCC}")
+    os.makedirs(os.path.join(BUILD, "checked"), exist_ok=True)
+    jobs = [(src, False) for src in SOURCES] + ([(src, True) for src in CHECKED_SOURCES] if checked else [])
+    # the largest units first, so that they do not start last
+    jobs.sort(key=lambda j: -os.path.getsize(os.path.join(CSRC, j[0])) - (1 << 20) * j[0].startswith("k_dense_"))
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        done = dict(zip(jobs, ex.map(lambda j: _compile(*j), jobs)))
+    for obj, msg in done.values():
+        if verbose and msg.strip():
+            print(msg)
+    _link(LIB, [done[(src, False)][0] for src in SOURCES])
+    if checked:
+        _link(LIB_CHECKED, [done[(src, src in CHECKED_SOURCES)][0] for src in SOURCES])
+    return LIB
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv, checked="--checked" in sys.argv))
+    print(build(verbose="-v" in sys.argv, checked="--no-checked" not in sys.argv))

@@ -44,7 +44,7 @@ def test_checked_library_exports_the_same_symbols():
     from paper_2110_12065_amd import build
     path = build.LIB_CHECKED
     if not os.path.exists(path):
-        pytest.skip("libmapi_checked.so not built (python -m paper_2110_12065_amd.build --checked)")
+        pytest.skip("libmapi_checked.so not built (python -m paper_2110_12065_amd.build)")
     lib = ctypes.CDLL(path)
     missing = [n for n in _declared() if not hasattr(lib, n)]
     assert not missing, missing
