@@ -781,24 +781,37 @@ def bench_pagerank(mp, ctx, torch, n=1 << 22, seed=2022):
     nnz = int(g["col"].size)
     bytes_iter = 8.0 * nnz + 4.0 * (n + 1) + 8.0 * n        # links, row pointers, w once, y once
     out = {"n": n, "nnz": nnz}
+    # `ctx` has the default policy (plain products for the first 4 iterations, the split layout
+    # built only if the solve is still running); `eager` builds the split layout before the first
+    # product, so its per-product times are the split kernel's alone
+    eager = mp.Context()
+    mp.mapi_pagerank_split_after(0, ctx=eager)
     for meth in ("mapi", "rpi"):
         log(f"PageRank {meth}")
         mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=2, ctx=ctx)
-        ctx.timing(True)
-        ctx.timing_reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         w, info = mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=300, tol=1e-8, stall_iters=10,
                                    check_every=4, ctx=ctx)
         torch.cuda.synchronize()
         s = time.perf_counter() - t0
-        ms, launches = ctx.timing_get("csr")
-        ctx.timing(False)
+        mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=2, ctx=eager)
+        eager.timing(True)
+        eager.timing_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=300, tol=1e-8, stall_iters=10, check_every=4,
+                         ctx=eager)
+        torch.cuda.synchronize()
+        s_eager = time.perf_counter() - t0
+        ms, launches = eager.timing_get("csr")
+        eager.timing(False)
         kms = ms / max(launches, 1)
         out[f"{meth}_iters"] = info["iters"]
         out[f"{meth}_converged"] = info["converged"]
         out[f"{meth}_final_residual"] = info["residual"]
         out[f"{meth}_ms_total"] = s * 1e3
+        out[f"{meth}_ms_total_split_from_first"] = s_eager * 1e3
         out[f"{meth}_csr_kernel_us"] = kms * 1e3
         out[f"{meth}_gedges_s"] = nnz / (kms * 1e-3) / 1e9
         out[f"{meth}_csr_kernel_gbs"] = bytes_iter / (kms * 1e-3) / 1e9
@@ -842,8 +855,11 @@ def bench_pagerank(mp, ctx, torch, n=1 << 22, seed=2022):
         plain.timing(False)
         out[f"{meth}_plain_csr_kernel_us"] = ms / max(launches, 1) * 1e3
     log(f"PageRank products: split {out['mapi_csr_kernel_us']:.0f} us (MAPI) / {out['rpi_csr_kernel_us']:.0f} us "
-        f"(RPI), plain {out['mapi_plain_csr_kernel_us']:.0f} / {out['rpi_plain_csr_kernel_us']:.0f} us")
+        f"(RPI), plain {out['mapi_plain_csr_kernel_us']:.0f} / {out['rpi_plain_csr_kernel_us']:.0f} us; solves "
+        f"{out['mapi_ms_total']:.1f} / {out['rpi_ms_total']:.1f} ms (split from the first product: "
+        f"{out['mapi_ms_total_split_from_first']:.1f} / {out['rpi_ms_total_split_from_first']:.1f} ms)")
     plain.close()
+    eager.close()
     # Sec. 3.3's comparison at the 1e-8 stop, with the float64 iterate (the float32 iterate's
     # floor, about 5e-8 in l1 at this n, stops RPI short of it): iterations and time to an l1
     # change below 1e-8, MAPI against RPI

@@ -414,6 +414,13 @@ mapi_status mapi_pagerank(mapi_ctx* ctx, const mapi_csr* H, double alpha, int32_
  * row holding 255 or more links in one block, and min_n <= 0 use the plain CSR
  * product.  The two differ only in the order of the float32 (float64) row sums.      */
 mapi_status mapi_pagerank_split_config(mapi_ctx* ctx, int64_t min_n);
+/* When the split layout applies, the first `iters` products of a solve (default 4) use
+ * the plain product and the layout is built only if the solve is still running then:
+ * building it costs about as much as 6 plain products at 2^22 nodes, which a solve that
+ * stops within a few iterations (MAPI PageRank, Sec. 3.3) never recovers.  iters = 0
+ * builds it before the first product.  Deterministic: the products switch at that
+ * iteration whatever the timing.  MAPI_ERR_ARG for iters < 0.                        */
+mapi_status mapi_pagerank_split_after(mapi_ctx* ctx, int32_t iters);
 
 /* The same with a float64 iterate: w0 / w_out are device double[n], every term and
  * row sum is float64 (the float32 iterate resolves about 6e-8 of w ~ 1/n, while the

@@ -107,6 +107,7 @@ _SIGS = {
     "mapi_pagerank_f64": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
                                     C.POINTER(Opts), C.POINTER(Info)]),
     "mapi_pagerank_split_config": (C.c_int, [C.c_void_p, C.c_int64]),
+    "mapi_pagerank_split_after": (C.c_int, [C.c_void_p, C.c_int32]),
     "mapi_factored_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_double,
                                       C.c_void_p, C.c_void_p, C.POINTER(Opts), C.POINTER(Info)]),
     "mapi_hybrid_solve": (C.c_int, [C.c_void_p, C.POINTER(Dense), C.c_void_p, C.c_void_p, C.POINTER(Opts),
@@ -488,6 +489,13 @@ def mapi_pagerank_split_config(min_n, ctx=None):
     """PageRank graphs with at least min_n nodes use the column-split product (min_n <= 0: never)."""
     c = ctx if ctx is not None else default_context()
     _check(lib().mapi_pagerank_split_config(c.handle, int(min_n)))
+
+
+def mapi_pagerank_split_after(iters, ctx=None):
+    """Build the column-split layout only after `iters` plain products of a solve (0: before
+    the first); see mapi_pagerank_split_config."""
+    c = ctx if ctx is not None else default_context()
+    _check(lib().mapi_pagerank_split_after(c.handle, int(iters)))
 
 
 # ------------------------------------------------------------------ launch shapes

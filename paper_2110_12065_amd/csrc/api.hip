@@ -481,19 +481,25 @@ mapi_status pagerank_run(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t m
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (err_h) return fail(MAPI_ERR_ARG, "invalid CSR arrays (code %d)", err_h);
   // the column-split copy of the validated matrix, unless a row has too many links in
-  // one block for its layout (then the plain product runs)
+  // one block for its layout (then the plain product runs); built before the product of
+  // iteration c->csr_split_after, if the solve gets that far
   SplitCsr sp;
-  if (split) {
+  const int split_at = split ? c->csr_split_after : -1;
+  split = false;
+  auto build_split = [&]() -> mapi_status {
     sp = split_csr_place(base + l.o_split, n, H->nnz, sizeof(T));
     HIP_TRY(hipMemsetAsync(sp.flags, 0, sizeof(int32_t), c->stream));
     HIP_TRY(launch_split_count(H->row_ptr, H->col, H->val, sp, c->stream));
     int32_t flags_h = 0;
     HIP_TRY(hipMemcpyAsync(&flags_h, sp.flags, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    if (flags_h) split = false;
-    else HIP_TRY(launch_split_fill(H->row_ptr, H->col, H->val, sp, c->stream));
-  }
-  const int PP = split ? split_combine_blocks(n) : csr_part_count(n);
+    if (!flags_h) {
+      HIP_TRY(launch_split_fill(H->row_ptr, H->col, H->val, sp, c->stream));
+      split = true;
+    }
+    return MAPI_OK;
+  };
+  if (split_at == 0 && (s = build_split()) != MAPI_OK) return s;
 
   const double inv_n = 1.0 / (double)n;
   const double cc = (1.0 - alpha) * inv_n;
@@ -511,6 +517,12 @@ mapi_status pagerank_run(mapi_ctx* c, const mapi_csr* H, double alpha, int32_t m
   for (int it = 0; it < o->max_iters; ++it) {
     T* wc = wb[it & 1];
     T* wn = wb[(it & 1) ^ 1];
+    if (it > 0 && it == split_at) {   // still running: switch to the split product from here
+      if ((s = sync_and_state(c, st)) != MAPI_OK) return s;
+      if (c->st_host->done) break;
+      if ((s = build_split()) != MAPI_OK) return s;
+    }
+    const int PP = split ? split_combine_blocks(n) : csr_part_count(n);
     {
       Timed tm(c, MAPI_K_CSR);
       if (split)
@@ -674,6 +686,13 @@ mapi_status mapi_set_workspace(mapi_ctx* c, void* dev_ptr, size_t bytes) {
   mapi_batch_free_arena(c);
   c->user_ws = static_cast<char*>(dev_ptr);
   c->user_ws_bytes = dev_ptr ? bytes : 0;
+  return MAPI_OK;
+}
+
+mapi_status mapi_pagerank_split_after(mapi_ctx* c, int32_t iters) {
+  if (!c) return fail(MAPI_ERR_ARG, "ctx is NULL");
+  if (iters < 0) return fail(MAPI_ERR_ARG, "iters must be >= 0");
+  c->csr_split_after = iters;
   return MAPI_OK;
 }
 

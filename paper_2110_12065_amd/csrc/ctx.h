@@ -63,6 +63,8 @@ struct mapi_ctx {
   char* scratch = nullptr;
   // PageRank graphs of at least this many nodes use the column-split product (0: never)
   int64_t csr_split_min_n = int64_t(1) << 20;
+  // ... built only after this many plain products of a solve (0: before the first)
+  int csr_split_after = 4;
   // dense solves sweep the matrix forward and backward in turn (MAPI_DENSE_ALTERNATE=1);
   // off by default: on MI355X it measured no faster than forward sweeps only
   bool alternate = false;

@@ -23,9 +23,12 @@ def _dev(g):
             torch.from_numpy(np.ascontiguousarray(g["val"])).cuda())
 
 
-def _ctx(split):
+def _ctx(split, after=0):
+    # split: every graph takes the split layout, built before the first product (after = 0)
+    # unless `after` says otherwise
     c = mp.Context()
     mp.mapi_pagerank_split_config(1 if split else 0, ctx=c)
+    mp.mapi_pagerank_split_after(after, ctx=c)
     return c
 
 
@@ -110,6 +113,7 @@ def test_full_size_split_against_csr_oracle_and_plain_product():
     g = synth.powerlaw_graph(n, seed=2022)
     rp, col, val = _dev(g)
     c_split, c_plain = mp.Context(), _ctx(False)
+    mp.mapi_pagerank_split_after(0, ctx=c_split)     # the default layout rule, split from the first product
     for method in ("mapi", "rpi"):
         print(f"[case] split pagerank 2^22 {method}", flush=True)
         w, info = mp.mapi_pagerank(rp, col, val, 0.85, method, max_iters=3, ctx=c_split)
@@ -119,3 +123,40 @@ def test_full_size_split_against_csr_oracle_and_plain_product():
         assert e <= TOL
         w2, _ = mp.mapi_pagerank(rp, col, val, 0.85, method, max_iters=3, ctx=c_plain)
         assert rel_l1(wg, w2.cpu().numpy()) <= 1e-6
+
+
+@pytest.mark.parametrize("method", ["mapi", "rpi"])
+def test_split_built_after_the_first_products(method):
+    # the default policy: plain products for the first `after` iterations, then the split layout
+    # if the solve is still running.  T <= after: the plain product's bits; T > after: against
+    # the oracle, close to both single-layout runs, and bitwise repeatable
+    n = 5000
+    g = synth.powerlaw_graph(n, seed=31)
+    rp, col, val = _dev(g)
+    lazy = _ctx(True, after=4)
+    a, ia = mp.mapi_pagerank(rp, col, val, 0.85, method, max_iters=4, ctx=lazy)
+    b, _ = mp.mapi_pagerank(rp, col, val, 0.85, method, max_iters=4, ctx=_ctx(False))
+    np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+    T = 11
+    w, info = mp.mapi_pagerank(rp, col, val, 0.85, method, max_iters=T, ctx=lazy)
+    assert info["iters"] == T
+    ref = oracle.pagerank(n, g["row_ptr"], g["col"], g["val"], 0.85, method, synth.uniform_start(n), T,
+                          form="dense")
+    e, _ = report(f"lazy split pagerank {method} T={T}", w.cpu().numpy(), ref.w)
+    assert e <= TOL
+    for other in (_ctx(True), _ctx(False)):
+        w2, _ = mp.mapi_pagerank(rp, col, val, 0.85, method, max_iters=T, ctx=other)
+        assert rel_l1(w.cpu().numpy(), w2.cpu().numpy()) <= 1e-6
+    w3, _ = mp.mapi_pagerank(rp, col, val, 0.85, method, max_iters=T, ctx=lazy)
+    np.testing.assert_array_equal(w.cpu().numpy(), w3.cpu().numpy())
+    # a tolerance solve that stops before the switch: the plain product's bits and count
+    t1, i1 = mp.mapi_pagerank(rp, col, val, 0.85, method, max_iters=300, tol=1e-2, check_every=1, ctx=_ctx(True, 50))
+    t2, i2 = mp.mapi_pagerank(rp, col, val, 0.85, method, max_iters=300, tol=1e-2, check_every=1, ctx=_ctx(False))
+    assert i1["iters"] == i2["iters"] < 50
+    np.testing.assert_array_equal(t1.cpu().numpy(), t2.cpu().numpy())
+
+
+def test_split_after_rejects_negative():
+    with pytest.raises(mp.MapiError) as ei:
+        mp.mapi_pagerank_split_after(-1)
+    assert ei.value.status == 1
