@@ -145,10 +145,11 @@ def run_kernels_mode():
         for _ in range(5):
             mp.mapi_mavp(A, w0, "min1", row_scale=rs, ctx=ctx)
     del src, dst
-    # three MAPI PageRank products on the 2^22-node graph: the column-split product (the default
-    # at this size), then the plain CSR product
+    # three MAPI PageRank products on the 2^22-node graph: the column-split product (the layout
+    # of this size, here built before the first product), then the plain CSR product
     g = _graph(PR_N, PR_SEED)
     rp, col, val = (torch.from_numpy(g[x]).cuda() for x in ("row_ptr", "col", "val"))
+    mp.mapi_pagerank_split_after(0, ctx=ctx)
     mp.mapi_pagerank(rp, col, val, 0.85, "mapi", max_iters=3, check_every=3, ctx=ctx)
     plain = mp.Context()
     mp.mapi_pagerank_split_config(0, ctx=plain)
