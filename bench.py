@@ -532,6 +532,24 @@ def bench_small(mp, ctx, torch, n=256, iters=200, tol=1e-7, seed=SEED, copies=25
         sec = (time.perf_counter() - t0) / reps
         out[f"{meth}_iters"] = info["iters"]
         out[f"{meth}_plain_us_per_iter"] = sec / max(info["iters"], 1) * 1e6
+        if meth == "mapi":
+            # the one-block solve writes the min1 term as fma(med3(a, -|w|, |w|), s_w, acc) with
+            # s_w = +-1 (an exact sign flip); the multiply-free form (sign flip, med3, add; the
+            # same bits) timed beside it
+            out["mapi_term"] = "fma(med3(a, -|w|, |w|), s_w, acc), s_w = +-1 from the sign bit of w"
+            os.environ["MAPI_MIN1_FORM"] = "xor"
+            try:
+                wx, ix = fn(C, w0, max_iters=iters, tol=tol, check_every=16, ctx=ctx)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    fn(C, w0, max_iters=iters, tol=tol, check_every=16, ctx=ctx)
+                torch.cuda.synchronize()
+                out["mapi_xor_form_us_per_iter"] = (time.perf_counter() - t0) / reps / max(ix["iters"], 1) * 1e6
+            finally:
+                del os.environ["MAPI_MIN1_FORM"]
+            wf, _ = fn(C, w0, max_iters=iters, tol=tol, check_every=16, ctx=ctx)
+            out["mapi_xor_form_same_bits"] = bool(torch.equal(wx, wf))
         # the FP64 oracle at the same iteration count (rounding only: same matrix, same start)
         import oracle
         wg, _ = fn(C, w0, max_iters=info["iters"], check_every=16, ctx=ctx)
@@ -699,7 +717,7 @@ def bench_pca(mp, ctx, torch, D=4096, N=65536, k=8, seed=77):
                                      "exact sign flip in one instruction with the add, not a product of data")
             # the same build with the term as sign-bit flip, med3 and add (three instructions;
             # the same bits): the multiply-free form's time beside it
-            os.environ["MAPI_GRAM_MIN1_FORM"] = "xor"
+            os.environ["MAPI_MIN1_FORM"] = "xor"
             try:
                 Ax = mp.mapi_mingram(X, 1.0 / N, op, ctx=ctx)
                 torch.cuda.synchronize()
@@ -710,7 +728,7 @@ def bench_pca(mp, ctx, torch, D=4096, N=65536, k=8, seed=77):
                     torch.cuda.synchronize()
                     sx = min(sx, time.perf_counter() - t0)
             finally:
-                del os.environ["MAPI_GRAM_MIN1_FORM"]
+                del os.environ["MAPI_MIN1_FORM"]
             out["gram_min1_xor_form_ms"] = sx * 1e3
             out["gram_min1_xor_form_same_bits"] = bool(torch.equal(Ax, A))
             del Ax

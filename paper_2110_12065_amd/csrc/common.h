@@ -410,6 +410,9 @@ int pr_scalar_blocks(int64_t n);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, int cu_count, hipStream_t s);
+// MAPI_MIN1_FORM=xor in the environment: the min-Gram build and the one-block solve write
+// the min1 term as sign flip, med3 and add instead of med3 and an FMA by +-1 (k_gram.hip).
+bool min1_xor_form();
 // One always-failing device check on st (a no-op outside device-checked builds).
 hipError_t launch_dcheck_selftest(SolveState* st, hipStream_t s);
 // Start vector of the generated problem with this seed (k_batched.hip).

@@ -419,10 +419,10 @@ static void launch_gram_min(const GramSplit& g, const float* X, int64_t D, int64
                        ldx, g.chunk, (int)g.tiles, scale, A, lda, nullptr);
 }
 
-// MAPI_GRAM_MIN1_FORM=xor selects the three-instruction min1 term (for comparison; the
+// MAPI_MIN1_FORM=xor selects the three-instruction min1 term (for comparison; the
 // result has the same bits), read at each build.
-static bool gram_min1_xor() {
-  const char* e = std::getenv("MAPI_GRAM_MIN1_FORM");
+bool min1_xor_form() {
+  const char* e = std::getenv("MAPI_MIN1_FORM");
   return e != nullptr && std::strcmp(e, "xor") == 0;
 }
 
@@ -439,7 +439,7 @@ hipError_t launch_gram(const float* X, int64_t D, int64_t N, int64_t ldx, double
       hipLaunchKernelGGL(k_gram_mfma<false>, dim3((unsigned)g.tiles), dim3(512), 0, s, X, (int)D, N, ldx, g.chunk,
                          (int)g.tiles, scale, A, lda, nullptr);
   } else if (op == MAPI_OP_MIN1) {
-    if (gram_min1_xor()) launch_gram_min<MAPI_OP_MIN1, true>(g, X, D, N, ldx, scale, A, lda, ws, s);
+    if (min1_xor_form()) launch_gram_min<MAPI_OP_MIN1, true>(g, X, D, N, ldx, scale, A, lda, ws, s);
     else launch_gram_min<MAPI_OP_MIN1>(g, X, D, N, ldx, scale, A, lda, ws, s);
   } else {
     launch_gram_min<MAPI_OP_MIN2>(g, X, D, N, ldx, scale, A, lda, ws, s);

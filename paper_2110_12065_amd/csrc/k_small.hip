@@ -51,7 +51,8 @@ __device__ __forceinline__ float wave_rows16(RowPartial part, int lane) {
   return s;
 }
 
-template <int OP>
+// XF (min1 only): the term as sign-bit flip, med3 and add (MAPI_MIN1_FORM=xor), the same bits.
+template <int OP, bool XF = false>
 __global__ void __launch_bounds__(kSmallThreads)
 k_solve_small(const float* __restrict__ A, int64_t ld, int n, const float* __restrict__ w0, float* __restrict__ out,
               SolveState* __restrict__ st, int norm, int final_l2) {
@@ -102,7 +103,7 @@ k_solve_small(const float* __restrict__ A, int64_t ld, int n, const float* __res
           float t = 0.0f;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            if constexpr (OP == MAPI_OP_MIN1)
+            if constexpr (OP == MAPI_OP_MIN1 && !XF)
               t = fmaf(__builtin_amdgcn_fmed3f(a[r][e], -fabsf(wv[e]), fabsf(wv[e])), sg[e], t);
             else
               t = op_acc<OP>(t, a[r][e], wv[e], ws[e]);
@@ -189,8 +190,12 @@ hipError_t launch_solve_small(int op, const float* A, int64_t ld, int64_t n, con
   const int ni = (int)n;
   switch (op) {
     case MAPI_OP_MIN1:
-      hipLaunchKernelGGL(k_solve_small<MAPI_OP_MIN1>, dim3(1), dim3(kSmallThreads), 0, s, A, ld, ni, w0, out, st, norm,
-                         final_l2);
+      if (min1_xor_form())
+        hipLaunchKernelGGL((k_solve_small<MAPI_OP_MIN1, true>), dim3(1), dim3(kSmallThreads), 0, s, A, ld, ni, w0, out,
+                           st, norm, final_l2);
+      else
+        hipLaunchKernelGGL(k_solve_small<MAPI_OP_MIN1>, dim3(1), dim3(kSmallThreads), 0, s, A, ld, ni, w0, out, st,
+                           norm, final_l2);
       break;
     case MAPI_OP_MIN2:
       hipLaunchKernelGGL(k_solve_small<MAPI_OP_MIN2>, dim3(1), dim3(kSmallThreads), 0, s, A, ld, ni, w0, out, st, norm,

@@ -111,9 +111,9 @@ def test_gram_min1_xor_form_same_bits(monkeypatch):
     for D, N in ((300, 5000), (130, 700)):
         X = synth.pca_data(D, N, seed=D + N)
         A = mp.mapi_mingram(to_dev(X), 1.0 / N, "min1").cpu().numpy()
-        monkeypatch.setenv("MAPI_GRAM_MIN1_FORM", "xor")
+        monkeypatch.setenv("MAPI_MIN1_FORM", "xor")
         B = mp.mapi_mingram(to_dev(X), 1.0 / N, "min1").cpu().numpy()
-        monkeypatch.delenv("MAPI_GRAM_MIN1_FORM")
+        monkeypatch.delenv("MAPI_MIN1_FORM")
         np.testing.assert_array_equal(A, B)
 
 

@@ -135,3 +135,18 @@ def test_long_solves_launch_per_iteration():
     assert info["converged"] and launches >= info["iters"] > 1
     ref = oracle.mapi(A.astype(np.float64), w0, info["iters"])
     assert rel_l1(w.cpu().numpy(), ref.w) <= TOL
+
+
+def test_small_solve_min1_xor_form_same_bits(monkeypatch):
+    # the one-block solve's min1 term as sign flip, med3 and add (MAPI_MIN1_FORM=xor) gives the
+    # bits of the FMA-by-+-1 form
+    import synth
+    for n in (64, 200, 256):
+        C = to_dev(synth.dense_cov(n, 3 * n, seed=n))
+        w0 = to_dev(synth.start_vector(n, n + 1))
+        a, ia = mp.mapi_solve(C, w0, max_iters=40, tol=1e-7)
+        monkeypatch.setenv("MAPI_MIN1_FORM", "xor")
+        b, ib = mp.mapi_solve(C, w0, max_iters=40, tol=1e-7)
+        monkeypatch.delenv("MAPI_MIN1_FORM")
+        assert ia["iters"] == ib["iters"]
+        np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
