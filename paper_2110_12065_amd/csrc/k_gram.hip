@@ -66,18 +66,27 @@ constexpr int NKS = 32;                      // samples per slab
 constexpr int NP = 2 * MT + 4;               // staged pitch (floats); 16-byte aligned
 constexpr int NRUN = 256 / NKS;              // slabs per float32 run
 constexpr int NLPR = NKS / 4;                // loader threads per staged row (one float4 each)
-constexpr int kGramTM = 4;                   // rows of a thread's register tile
-constexpr int gram_threads(int tm) { return MT * MT / (tm * 4); }
+#ifndef MAPI_GRAM_TM
+#define MAPI_GRAM_TM 4
+#endif
+#ifndef MAPI_GRAM_TN
+#define MAPI_GRAM_TN 4
+#endif
+constexpr int kGramTM = MAPI_GRAM_TM;        // rows of a thread's register tile
+constexpr int kGramTN = MAPI_GRAM_TN;        // columns of a thread's register tile (2 or 4)
+constexpr int gram_threads(int tm, int tn) { return MT * MT / (tm * tn); }
 
 // XF (min1 only): the term as the product kernels write it, a sign-bit flip of a, med3
 // and an add (three instructions), instead of the FMA by +-1 (two); the same bits.
-template <int OP, bool SPLIT, int TM, bool XF = false>
-__global__ void __launch_bounds__(gram_threads(TM))
+template <int OP, bool SPLIT, int TM, bool XF = false, int TN = 4>
+__global__ void __launch_bounds__(gram_threads(TM, TN))
 k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t chunk, int tiles, double scale,
            float* __restrict__ A, int64_t lda, double* __restrict__ part) {
-  constexpr int NTH = gram_threads(TM);
+  constexpr int NTH = gram_threads(TM, TN);
   constexpr int NLP = 2 * MT * NLPR / NTH;   // float4s each thread loads per slab
   constexpr int TA = TM / 4;                 // 16-byte row operands per sample
+  constexpr int CT = MT / TN;                // threads along the tile's columns
+  typedef float bvec __attribute__((ext_vector_type(TN)));
   __shared__ float4 lds4[2 * NKS * NP / 4];
   float* lds = reinterpret_cast<float*>(lds4);
   const int T = (D + MT - 1) / MT;
@@ -88,7 +97,7 @@ k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t c
   const int i0 = ti * MT, j0 = tj * MT;
   const int64_t kb = (int64_t)cidx * chunk;
   const int64_t ke = min(N, kb + chunk);
-  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  const int tid = threadIdx.x, tx = tid % CT, ty = tid / CT;
 
   // loader: staged row sr = lrow + (NTH / NLPR) p is row sr of the I block (sr < 128)
   // or row sr - 128 of the J block; lk selects one of the slab's NLPR float4s
@@ -126,12 +135,12 @@ k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t c
     }
   };
 
-  float accf[TM][4];
-  double acc[TM][4];
+  float accf[TM][TN];
+  double acc[TM][TN];
 #pragma unroll
   for (int p = 0; p < TM; ++p)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < TN; ++q) {
       accf[p][q] = 0.0f;
       acc[p][q] = 0.0;
     }
@@ -144,41 +153,45 @@ k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t c
     const int buf = (int)(sl & 1);
     if (sl + 1 < nslabs) load(kb + (sl + 1) * NKS);
     const float* s = lds + buf * NKS * NP;
-    float4 a[TA], b;
+    float4 a[TA];
+    bvec b;
 #pragma unroll
     for (int t = 0; t < TA; ++t) a[t] = *reinterpret_cast<const float4*>(s + ty * TM + 4 * t);
-    b = *reinterpret_cast<const float4*>(s + MT + tx * 4);
+    b = *reinterpret_cast<const bvec*>(s + MT + tx * TN);
 #pragma unroll
     for (int k = 0; k < NKS; ++k) {
-      float4 an[TA], bn;
+      float4 an[TA];
+      bvec bn;
       if (k + 1 < NKS) {
 #pragma unroll
         for (int t = 0; t < TA; ++t) an[t] = *reinterpret_cast<const float4*>(s + (k + 1) * NP + ty * TM + 4 * t);
-        bn = *reinterpret_cast<const float4*>(s + (k + 1) * NP + MT + tx * 4);
+        bn = *reinterpret_cast<const bvec*>(s + (k + 1) * NP + MT + tx * TN);
       }
       float av[TM];
 #pragma unroll
       for (int t = 0; t < TA; ++t) {
         av[4 * t] = a[t].x; av[4 * t + 1] = a[t].y; av[4 * t + 2] = a[t].z; av[4 * t + 3] = a[t].w;
       }
-      const float bv[4] = {b.x, b.y, b.z, b.w};
-      if constexpr (OP == MAPI_OP_MIN1 && !XF) {
-        float sg[4];
+      float bv[TN];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sg[q] = __uint_as_float(sign_bit(bv[q]) | 0x3f800000u);
+      for (int q = 0; q < TN; ++q) bv[q] = b[q];
+      if constexpr (OP == MAPI_OP_MIN1 && !XF) {
+        float sg[TN];
+#pragma unroll
+        for (int q = 0; q < TN; ++q) sg[q] = __uint_as_float(sign_bit(bv[q]) | 0x3f800000u);
 #pragma unroll
         for (int p = 0; p < TM; ++p)
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
+          for (int q = 0; q < TN; ++q)
             accf[p][q] = fmaf(__builtin_amdgcn_fmed3f(av[p], -fabsf(bv[q]), fabsf(bv[q])), sg[q], accf[p][q]);
       } else {
-        uint32_t sb[4];
+        uint32_t sb[TN];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sb[q] = sign_bit(bv[q]);
+        for (int q = 0; q < TN; ++q) sb[q] = sign_bit(bv[q]);
 #pragma unroll
         for (int p = 0; p < TM; ++p)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) accf[p][q] = op_acc<OP>(accf[p][q], av[p], bv[q], sb[q]);
+          for (int q = 0; q < TN; ++q) accf[p][q] = op_acc<OP>(accf[p][q], av[p], bv[q], sb[q]);
       }
       if (k + 1 < NKS) {
 #pragma unroll
@@ -190,7 +203,7 @@ k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t c
 #pragma unroll
       for (int p = 0; p < TM; ++p)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < TN; ++q) {
           acc[p][q] += (double)accf[p][q];
           accf[p][q] = 0.0f;
         }
@@ -206,7 +219,7 @@ k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t c
 #pragma unroll
     for (int p = 0; p < TM; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) out[(ty * TM + p) * MT + tx * 4 + q] = acc[p][q];
+      for (int q = 0; q < TN; ++q) out[(ty * TM + p) * MT + tx * TN + q] = acc[p][q];
   } else {
     // the tile is staged in the (now free) slab buffers so that it and its mirror are
     // written along rows
@@ -215,7 +228,7 @@ k_gram_min(const float* __restrict__ X, int D, int64_t N, int64_t ldx, int64_t c
 #pragma unroll
     for (int p = 0; p < TM; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) lds[(ty * TM + p) * MSP + tx * 4 + q] = (float)(scale * acc[p][q]);
+      for (int q = 0; q < TN; ++q) lds[(ty * TM + p) * MSP + tx * TN + q] = (float)(scale * acc[p][q]);
     __syncthreads();
     gram_write_tile(lds, i0, j0, D, A, lda, ti != tj);
   }
@@ -410,13 +423,13 @@ size_t gram_workspace_bytes(int64_t D, int64_t N, int op) {
 template <int OP, bool XF = false>
 static void launch_gram_min(const GramSplit& g, const float* X, int64_t D, int64_t N, int64_t ldx, double scale,
                             float* A, int64_t lda, double* ws, hipStream_t s) {
-  constexpr int NTH = gram_threads(kGramTM);
+  constexpr int NTH = gram_threads(kGramTM, kGramTN);
   if (g.kc > 1)
-    hipLaunchKernelGGL((k_gram_min<OP, true, kGramTM, XF>), dim3((unsigned)(g.tiles * g.kc)), dim3(NTH), 0, s, X,
-                       (int)D, N, ldx, g.chunk, (int)g.tiles, scale, A, lda, ws);
+    hipLaunchKernelGGL((k_gram_min<OP, true, kGramTM, XF, kGramTN>), dim3((unsigned)(g.tiles * g.kc)), dim3(NTH), 0,
+                       s, X, (int)D, N, ldx, g.chunk, (int)g.tiles, scale, A, lda, ws);
   else
-    hipLaunchKernelGGL((k_gram_min<OP, false, kGramTM, XF>), dim3((unsigned)g.tiles), dim3(NTH), 0, s, X, (int)D, N,
-                       ldx, g.chunk, (int)g.tiles, scale, A, lda, nullptr);
+    hipLaunchKernelGGL((k_gram_min<OP, false, kGramTM, XF, kGramTN>), dim3((unsigned)g.tiles), dim3(NTH), 0, s, X,
+                       (int)D, N, ldx, g.chunk, (int)g.tiles, scale, A, lda, nullptr);
 }
 
 // MAPI_MIN1_FORM=xor selects the three-instruction min1 term (for comparison; the
