@@ -194,6 +194,8 @@ def _kernel_dtype(name):
         return "csr_split"
     if "k_csr_split_combine<0," in name:
         return "csr_combine"
+    if "k_split_hub_values<float>" in name:
+        return "csr_hubval"
     if "k_mavp_dense" not in name:
         return None
     # template argument order: storage type, product, ... (0 = f32, 1 = bf16, 2 = fp8)
@@ -362,23 +364,24 @@ def summarize(stats_dir, fetch_dir, write_dir, cmd_stats, cmd_fetch, cmd_write, 
     if all(k in fetch and k in write for k in parts) and f_scale is not None and w_scale is not None:
         nnz = int(_graph(PR_N, PR_SEED)["col"].size)
         alg = csr_bytes(PR_N, nnz)
-        per = {k: fetch[k] * 1024.0 * f_scale + write[k] * 1024.0 * w_scale for k in parts + ("csr_plain",)
-               if k in fetch and k in write}
-        b = per["csr_split"] + per["csr_combine"]
+        per = {k: fetch[k] * 1024.0 * f_scale + write[k] * 1024.0 * w_scale
+               for k in ("csr_hubval",) + parts + ("csr_plain",) if k in fetch and k in write}
+        b = per["csr_split"] + per["csr_combine"] + per.get("csr_hubval", 0.0)
         out["csr"] = {"source_sha256_16": csr_source_hash(), "n": PR_N, "nnz": nnz,
                       "fetch_kib": {k: fetch[k] for k in per}, "write_kib": {k: write[k] for k in per},
                       "bytes_per_launch": b, "bytes_per_kernel": per, "algorithmic_bytes_per_launch": alg}
         md += ["", f"PageRank MAPI product at n = 2^22 ({nnz} links; algorithmic bytes = 8 per link + 4 per row "
-                   "pointer + 8 per node for w and y). One product is the column-split kernel plus its combine "
-                   "kernel (the default at this size); the plain CSR product is measured beside it:", "",
+                   "pointer + 8 per node for w and y). One product is the gather of the hub values, the "
+                   "column-split kernel and its combine kernel (the default at this size); the plain CSR product "
+                   "is measured beside it:", "",
                "| kernel | FETCH KiB | WRITE KiB | scaled HBM-side bytes | algorithmic bytes | ratio |",
                "|---|---|---|---|---|---|"]
-        names = {"csr_split": "`k_csr_split_product`", "csr_combine": "`k_csr_split_combine`",
-                 "csr_plain": "`k_csr_product` (plain)"}
+        names = {"csr_hubval": "`k_split_hub_values`", "csr_split": "`k_csr_split_product`",
+                 "csr_combine": "`k_csr_split_combine`", "csr_plain": "`k_csr_product` (plain)"}
         for k, v in per.items():
             md.append(f"| {names[k]} | {fetch[k]:.0f} | {write[k]:.0f} | {v:.4e} | "
-                      f"{alg if k != 'csr_combine' else 0:.4e} | {v / alg:.3f} |")
-        md.append(f"| split product + combine | | | {b:.4e} | {alg:.4e} | {b / alg:.3f} |")
+                      f"{alg if k in ('csr_split', 'csr_plain') else 0:.4e} | {v / alg:.3f} |")
+        md.append(f"| split product (hub values, product, combine) | | | {b:.4e} | {alg:.4e} | {b / alg:.3f} |")
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
     with open(os.path.join(ROOT, "profiles", "mavp_dense_n16384_traffic.md"), "w") as f:
@@ -815,14 +818,17 @@ def bench_pagerank(mp, ctx, torch, n=1 << 22, seed=2022):
         torch.cuda.synchronize()
         s = time.perf_counter() - t0
         mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=2, ctx=eager)
-        eager.timing(True)
-        eager.timing_reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=300, tol=1e-8, stall_iters=10, check_every=4,
                          ctx=eager)
         torch.cuda.synchronize()
         s_eager = time.perf_counter() - t0
+        # per product: a fixed 10-product run (tol 0), so that every timed launch does its
+        # work (after the stop rule has fired, the launches of a converged run return at once)
+        eager.timing(True)
+        eager.timing_reset()
+        mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=10, ctx=eager)
         ms, launches = eager.timing_get("csr")
         eager.timing(False)
         kms = ms / max(launches, 1)
@@ -884,21 +890,16 @@ def bench_pagerank(mp, ctx, torch, n=1 << 22, seed=2022):
     # change below 1e-8, MAPI against RPI
     for meth in ("mapi", "rpi"):
         mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=2, f64=True, ctx=ctx)
-        ctx.timing(True)
-        ctx.timing_reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, inf = mp.mapi_pagerank(rp, col, val, 0.85, meth, max_iters=500, tol=1e-8, check_every=4, f64=True,
                                   ctx=ctx)
         torch.cuda.synchronize()
         s = time.perf_counter() - t0
-        ms, launches = ctx.timing_get("csr")
-        ctx.timing(False)
         out[f"{meth}_f64_to_1e-8_iters"] = inf["iters"]
         out[f"{meth}_f64_to_1e-8_converged"] = inf["converged"]
         out[f"{meth}_f64_to_1e-8_residual"] = inf["residual"]
         out[f"{meth}_f64_to_1e-8_ms"] = s * 1e3
-        out[f"{meth}_f64_csr_kernel_us_1e-8_run"] = ms / max(launches, 1) * 1e3
         log(f"PageRank float64 {meth} to 1e-8: {inf['iters']} iterations, converged {inf['converged']}, "
             f"{s * 1e3:.1f} ms")
     # counter bytes of the MAPI product (FETCH_SIZE + WRITE_SIZE, scaled; the gathers of w are

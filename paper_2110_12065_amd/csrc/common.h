@@ -382,6 +382,7 @@ struct SplitCsr {
   int32_t* nhub = nullptr;     // hubs per block
   int32_t* thr = nullptr;      // hub degree threshold per block
   int32_t* hist = nullptr;     // degree histogram per block
+  void* hval = nullptr;        // iterate values of the hubs per block, by slot (per product)
   int32_t* tsum = nullptr;     // tile sums of the offset scan
 };
 // Device bytes of the split copy for an iterate of es bytes per element, and its placement.

@@ -31,6 +31,9 @@
 //                            sample of the rows)
 //   slot[j]          int32   LDS slot of hub j, -1 otherwise
 //   hubs[k * H + s]  int32   source held in slot s of block k; nhub[k] slots in use
+//   hval[k * H + s]  T       the iterate value of that source (gathered per product)
+#include <algorithm>
+
 #include "common.h"
 
 namespace mapi {
@@ -39,10 +42,17 @@ constexpr int kSplitBlocks = 8;      // column blocks: one per XCD
 constexpr int kSplitChunk = 64;      // rows per base entry (one wave, one lane per row)
 constexpr int kSplitMaxLen = 255;    // block-row lengths fit uint8 below this
 #ifndef MAPI_SPLIT_HUB_SLOTS
-#define MAPI_SPLIT_HUB_SLOTS 2048
+#define MAPI_SPLIT_HUB_SLOTS 3072
+#endif
+#ifndef MAPI_SPLIT_HUB_VALUES
+#define MAPI_SPLIT_HUB_VALUES 1
 #endif
 constexpr int kSplitHubSlots = MAPI_SPLIT_HUB_SLOTS;   // hub sources per block held in LDS
 constexpr int kSplitHubMinDeg = 32;  // no hub below this many links
+// Hub values gathered once per product into a slot-ordered array, so that every
+// workgroup fills its LDS copy with contiguous reads (otherwise each workgroup gathers
+// them from the iterate itself)
+constexpr bool kSplitHubValues = MAPI_SPLIT_HUB_VALUES != 0;
 
 int64_t split_block_cols(int64_t n) { return (n + kSplitBlocks - 1) / kSplitBlocks; }
 int64_t split_chunks(int64_t n) { return (n + kSplitChunk - 1) / kSplitChunk; }
@@ -322,11 +332,26 @@ __device__ __forceinline__ T split_term(T acc, float h, T wj, float af, float cf
   }
 }
 
+// The iterate values of block k's hubs in slot order (one gather per hub and product).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_split_hub_values(const T* __restrict__ w, int64_t n, const int32_t* __restrict__ hubs,
+                   const int32_t* __restrict__ nhub, T* __restrict__ hval, const SolveState* __restrict__ st) {
+  if (state_done(st)) return;
+  const int k = blockIdx.y;
+  const int nh = min(nhub[k], kSplitHubSlots);
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nh; q += gridDim.x * blockDim.x) {
+    int32_t j = hubs[k * kSplitHubSlots + q];
+    if (!MAPI_DCHECK(st, j >= 0 && (int64_t)j < n, 3)) j = 0;   // a hub outside 0..n-1
+    hval[k * kSplitHubSlots + q] = w[j];
+  }
+}
+
 template <int METHOD, typename T>
 __global__ void __launch_bounds__(kSplitWaves * kWave)
 k_csr_split_product(const uint8_t* __restrict__ len, const int32_t* __restrict__ base, const int32_t* __restrict__ colS,
                     const float* __restrict__ valS, int64_t n, int64_t nch, const T* __restrict__ w,
-                    const int32_t* __restrict__ hubs, const int32_t* __restrict__ nhub,
+                    const int32_t* __restrict__ hubs, const int32_t* __restrict__ nhub, const T* __restrict__ hval,
                     T* __restrict__ part, const SolveState* __restrict__ st, double alpha, double c) {
   constexpr int R = kSplitBatch, E = kSplitFirst, CAP = kSplitCap;
   constexpr int SWEEPS = CAP / kWave;
@@ -337,7 +362,11 @@ k_csr_split_product(const uint8_t* __restrict__ len, const int32_t* __restrict__
   const int k = blockIdx.x % kSplitBlocks;
   if constexpr (kSplitHubSlots > 0) {
     const int nh = min(nhub[k], kSplitHubSlots);
-    for (int q = threadIdx.x; q < nh; q += blockDim.x) lhub[q] = w[hubs[k * kSplitHubSlots + q]];
+    if constexpr (kSplitHubValues) {
+      for (int q = threadIdx.x; q < nh; q += blockDim.x) lhub[q] = hval[k * kSplitHubSlots + q];
+    } else {
+      for (int q = threadIdx.x; q < nh; q += blockDim.x) lhub[q] = w[hubs[k * kSplitHubSlots + q]];
+    }
     __syncthreads();
   }
   // w of a link's source: a hub's from LDS (stored as ~slot), any other's from memory.
@@ -511,7 +540,7 @@ size_t split_csr_bytes(int64_t n, int64_t nnz, size_t es) {
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   return al((size_t)kSplitBlocks * n) + al(sizeof(int32_t) * kSplitBlocks * nch) + al(sizeof(int32_t) * nnz) +
          al(sizeof(float) * nnz) + al(es * kSplitBlocks * n) + al(sizeof(int32_t)) + 2 * al(sizeof(int32_t) * n) +
-         al(sizeof(int32_t) * kSplitBlocks * (kSplitHubSlots + 34)) +
+         al(sizeof(int32_t) * kSplitBlocks * (kSplitHubSlots + 34)) + al(es * kSplitBlocks * kSplitHubSlots) +
          al(sizeof(int32_t) * ((kSplitBlocks * nch + kScanTile - 1) / kScanTile));
 }
 
@@ -544,6 +573,8 @@ SplitCsr split_csr_place(void* ws, int64_t n, int64_t nnz, size_t es) {
   s.thr = s.nhub + kSplitBlocks;
   s.hist = s.thr + kSplitBlocks;
   p += al(sizeof(int32_t) * kSplitBlocks * (kSplitHubSlots + 34));
+  s.hval = p;
+  p += al(es * kSplitBlocks * kSplitHubSlots);
   s.tsum = reinterpret_cast<int32_t*>(p);
   return s;
 }
@@ -592,21 +623,48 @@ hipError_t launch_split_fill(const int32_t* row_ptr, const int32_t* col, const f
 
 int split_combine_blocks(int64_t n) { return split_grid(n, 1024, 2048); }
 
+// Workgroups per column block of the product: as many as the device keeps resident at
+// once (its occupancy: registers and LDS, with the hub copy), so that none runs in a
+// second round and fills its hub copy again.  The result does not depend on it.
+template <typename T>
+static int split_product_groups(int method) {
+  static int groups[2] = {0, 0};   // per method, from the first call's device
+  int& g = groups[method == MAPI_METHOD_MAPI ? 0 : 1];
+  if (g == 0) {
+    int dev = 0, cus = 256, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    const hipError_t e = method == MAPI_METHOD_MAPI
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_csr_split_product<MAPI_METHOD_MAPI, T>,
+                                                       kSplitWaves * kWave, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_csr_split_product<MAPI_METHOD_RPI, T>,
+                                                       kSplitWaves * kWave, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 4;
+    g = std::max(1, per_cu * cus / kSplitBlocks);
+  }
+  return g;
+}
+
 template <typename T>
 hipError_t launch_csr_split_product(int method, const SplitCsr& s, const T* w, T* y, double* nparts, SolveState* st,
                                     double alpha, double c, double inv_n, hipStream_t stream) {
-  // 256 workgroups per column block (32 per compute unit), persistent over the chunks
-  const int groups = split_grid(s.nch, 4, 256);
+  // workgroups persistent over the chunks, as many per column block as stay resident
+  const int groups = split_grid(s.nch, 4, split_product_groups<T>(method));
   const dim3 grid((unsigned)(groups * kSplitBlocks));
   T* part = static_cast<T*>(s.part);
+  T* hval = static_cast<T*>(s.hval);
+  if (kSplitHubValues && kSplitHubSlots > 0)
+    hipLaunchKernelGGL(k_split_hub_values<T>, dim3((kSplitHubSlots + 255) / 256, kSplitBlocks), dim3(256), 0, stream, w,
+                       s.n, s.hubs, s.nhub, hval, st);
   if (method == MAPI_METHOD_MAPI) {
     hipLaunchKernelGGL((k_csr_split_product<MAPI_METHOD_MAPI, T>), grid, dim3(kSplitWaves * kWave), 0, stream, s.len,
-                       s.base, s.col, s.val, s.n, s.nch, w, s.hubs, s.nhub, part, st, alpha, c);
+                       s.base, s.col, s.val, s.n, s.nch, w, s.hubs, s.nhub, hval, part, st, alpha, c);
     hipLaunchKernelGGL((k_csr_split_combine<MAPI_METHOD_MAPI, T>), dim3(split_combine_blocks(s.n)), dim3(256), 0,
                        stream, part, s.n, y, nparts, st, alpha, c, inv_n);
   } else {
     hipLaunchKernelGGL((k_csr_split_product<MAPI_METHOD_RPI, T>), grid, dim3(kSplitWaves * kWave), 0, stream, s.len,
-                       s.base, s.col, s.val, s.n, s.nch, w, s.hubs, s.nhub, part, st, alpha, c);
+                       s.base, s.col, s.val, s.n, s.nch, w, s.hubs, s.nhub, hval, part, st, alpha, c);
     hipLaunchKernelGGL((k_csr_split_combine<MAPI_METHOD_RPI, T>), dim3(split_combine_blocks(s.n)), dim3(256), 0,
                        stream, part, s.n, y, nparts, st, alpha, c, inv_n);
   }
