@@ -626,23 +626,19 @@ int split_combine_blocks(int64_t n) { return split_grid(n, 1024, 2048); }
 // Workgroups per column block of the product: as many as the device keeps resident at
 // once (its occupancy: registers and LDS, with the hub copy), so that none runs in a
 // second round and fills its hub copy again.  The result does not depend on it.
-template <typename T>
-static int split_product_groups(int method) {
-  static int groups[2] = {0, 0};   // per method, from the first call's device
-  int& g = groups[method == MAPI_METHOD_MAPI ? 0 : 1];
-  if (g == 0) {
+template <int METHOD, typename T>
+static int split_product_groups() {
+  // computed once per instance, on the first call's device (thread-safe initialisation)
+  static const int g = [] {
     int dev = 0, cus = 256, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       cus = 256;
-    const hipError_t e = method == MAPI_METHOD_MAPI
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_csr_split_product<MAPI_METHOD_MAPI, T>,
-                                                       kSplitWaves * kWave, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_csr_split_product<MAPI_METHOD_RPI, T>,
-                                                       kSplitWaves * kWave, 0);
-    if (e != hipSuccess || per_cu < 1) per_cu = 4;
-    g = std::max(1, per_cu * cus / kSplitBlocks);
-  }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_csr_split_product<METHOD, T>, kSplitWaves * kWave,
+                                                     0) != hipSuccess || per_cu < 1)
+      per_cu = 4;
+    return std::max(1, per_cu * cus / kSplitBlocks);
+  }();
   return g;
 }
 
@@ -650,7 +646,8 @@ template <typename T>
 hipError_t launch_csr_split_product(int method, const SplitCsr& s, const T* w, T* y, double* nparts, SolveState* st,
                                     double alpha, double c, double inv_n, hipStream_t stream) {
   // workgroups persistent over the chunks, as many per column block as stay resident
-  const int groups = split_grid(s.nch, 4, split_product_groups<T>(method));
+  const int groups = split_grid(s.nch, 4, method == MAPI_METHOD_MAPI ? split_product_groups<MAPI_METHOD_MAPI, T>()
+                                                                     : split_product_groups<MAPI_METHOD_RPI, T>());
   const dim3 grid((unsigned)(groups * kSplitBlocks));
   T* part = static_cast<T*>(s.part);
   T* hval = static_cast<T*>(s.hval);
