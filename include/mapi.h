@@ -470,7 +470,9 @@ mapi_status mapi_solve_batched(mapi_ctx* ctx, int32_t count, const mapi_problem*
  * problems are checked as mapi_solve_batched checks them).                        */
 mapi_status mapi_solve_batched_workspace_size(mapi_ctx* ctx, int32_t count, const mapi_problem* probs,
                                               size_t* bytes);
-/* Persistent grid: compute units * blocks_per_cu blocks (1..8, default 4).      */
+/* Persistent grid: compute units * blocks_per_cu blocks (1..8, default 2: the
+ * kernel is built for two resident blocks per compute unit; more wait for a
+ * resident block to exit).                                                       */
 mapi_status mapi_batched_config(mapi_ctx* ctx, int32_t blocks_per_cu);
 /* Product tile height (row split) used for dense instances of a storage type and
  * size bucket (ceil(log2 n)); the autotuner sets it from measurements.  Default:
@@ -492,7 +494,7 @@ mapi_status mapi_generate_dense(mapi_ctx* ctx, int64_t n, uint64_t seed, float* 
 typedef struct mapi_server mapi_server;
 
 typedef struct mapi_serve_cfg {
-  int32_t blocks_per_cu;     /* persistent grid (0 = 3)                            */
+  int32_t blocks_per_cu;     /* persistent grid (0 = 2)                            */
   int32_t max_slots;         /* concurrently admitted instances (0 = 2048)         */
   double idle_exit_ms;       /* an idle block exits after this long (0 = 20)       */
 } mapi_serve_cfg;

@@ -96,7 +96,7 @@ struct mapi_ctx {
   // persistent batched solver: arena and launch settings
   mapi::BatchState* batch = nullptr;
   hipStream_t side = nullptr;        // stream the batched graph is captured on
-  int batch_blocks_per_cu = 4;
+  int batch_blocks_per_cu = 2;
   std::map<std::tuple<int, int>, int> batch_rows;   // (dtype, log2 n) -> product tile rows
 };
 

@@ -336,7 +336,7 @@ mapi_status mapi_serve_create(int device, size_t hbm_budget, const mapi_serve_cf
   // Three persistent blocks per compute unit leave a quarter of the register file
   // free, so other work on the device (the caller's own kernels) runs beside the
   // long-lived persistent kernel instead of waiting for it to go idle.
-  const int bpc = (cfg && cfg->blocks_per_cu > 0) ? cfg->blocks_per_cu : 3;
+  const int bpc = (cfg && cfg->blocks_per_cu > 0) ? cfg->blocks_per_cu : 2;
   s->blocks = s->ctx->cu_count * bpc;
   s->idle_ms = (cfg && cfg->idle_exit_ms > 0) ? cfg->idle_exit_ms : 20.0;
   if (s->max_slots > (int)kMaxInstances) s->max_slots = (int)kMaxInstances;
