@@ -224,32 +224,48 @@ __global__ void k_split_hub_threshold(const int32_t* __restrict__ hist, int32_t*
   nhub[k] = 0;
 }
 
-// Slots of the hubs (any order: a slot only places a value in LDS).
+// Slots of the hubs (any order: a slot only places a value in LDS).  Atomics on the
+// eight counters, which share a cache line, are serialised by the device, so each pass
+// of a workgroup over kHubPass sources counts its hubs per block in LDS and takes its
+// slots with one global atomic per block it touched (one per wave cost 0.3 ms with
+// about 24 000 hubs).
+constexpr int kHubPass = 16;       // sources per thread and pass
 __global__ void __launch_bounds__(256)
 k_split_hub_assign(const int32_t* __restrict__ deg, int64_t n, int64_t bcols, const int32_t* __restrict__ thr,
                    int32_t* __restrict__ nhub, int32_t* __restrict__ slot, int32_t* __restrict__ hubs) {
-  // one atomic per wave and block: the wave's hubs of block k take consecutive slots
-  const int lane = threadIdx.x & (kWave - 1);
+  __shared__ int cnt[kSplitBlocks], base[kSplitBlocks];
   const float inv_bcols = 1.0f / (float)bcols;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); j0 < n; j0 += stride) {
-    const int64_t j = j0 + lane;
-    const int k = j < n ? block_of((int32_t)j, (int32_t)bcols, inv_bcols) : -1;
-    const bool hub = j < n && deg[j] >= thr[k];
-    int32_t s = -1;
+  const int64_t span = (int64_t)blockDim.x * kHubPass;
+  for (int64_t jb = (int64_t)blockIdx.x * span; jb < n; jb += (int64_t)gridDim.x * span) {
+    if (threadIdx.x < kSplitBlocks) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int kq[kHubPass], lo[kHubPass];
 #pragma unroll
-    for (int kk = 0; kk < kSplitBlocks; ++kk) {
-      const uint64_t m = __ballot(hub && k == kk);
-      if (m == 0) continue;
-      const int first = __ffsll((unsigned long long)m) - 1;
-      int base = 0;
-      if (lane == first) base = atomicAdd(&nhub[kk], __popcll(m));
-      base = __shfl(base, first, kWave);
-      if (hub && k == kk) s = base + __popcll(m & ((1ull << lane) - 1ull));
+    for (int p = 0; p < kHubPass; ++p) {
+      const int64_t j = jb + (int64_t)p * blockDim.x + threadIdx.x;
+      kq[p] = -1;
+      lo[p] = 0;
+      if (j < n) {
+        const int k = block_of((int32_t)j, (int32_t)bcols, inv_bcols);
+        if (deg[j] >= thr[k]) {
+          kq[p] = k;
+          lo[p] = atomicAdd(&cnt[k], 1);
+        }
+      }
     }
-    if (s >= kSplitHubSlots) s = -1;    // cannot happen: the threshold admits at most kSplitHubSlots
-    if (s >= 0) hubs[k * kSplitHubSlots + s] = (int32_t)j;
-    if (j < n) slot[j] = s;
+    __syncthreads();
+    if (threadIdx.x < kSplitBlocks) base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&nhub[threadIdx.x], cnt[threadIdx.x]) : 0;
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kHubPass; ++p) {
+      const int64_t j = jb + (int64_t)p * blockDim.x + threadIdx.x;
+      if (j >= n) continue;
+      int32_t s = kq[p] >= 0 ? base[kq[p]] + lo[p] : -1;
+      if (s >= kSplitHubSlots) s = -1;    // cannot happen: the threshold admits at most kSplitHubSlots
+      if (s >= 0) hubs[kq[p] * kSplitHubSlots + s] = (int32_t)j;
+      slot[j] = s;
+    }
+    __syncthreads();   // base and cnt are rewritten by the next pass
   }
 }
 
@@ -614,8 +630,8 @@ hipError_t launch_split_fill(const int32_t* row_ptr, const int32_t* col, const f
     hipLaunchKernelGGL(k_split_zero, dim3(1), dim3(64), 0, st, s.nhub, (int64_t)kSplitBlocks);
     hipLaunchKernelGGL(k_split_fill_i32, dim3(1), dim3(64), 0, st, s.thr, (int64_t)kSplitBlocks, INT32_MAX);
   }
-  hipLaunchKernelGGL(k_split_hub_assign, dim3(ng), dim3(256), 0, st, s.deg, s.n, bcols, s.thr, s.nhub, s.slot,
-                     s.hubs);
+  hipLaunchKernelGGL(k_split_hub_assign, dim3(split_grid(s.n, 256 * kHubPass, 1024)), dim3(256), 0, st, s.deg, s.n,
+                     bcols, s.thr, s.nhub, s.slot, s.hubs);
   hipLaunchKernelGGL(k_split_scatter, dim3(split_grid(s.nch, 4, 16384)), dim3(256), 0, st, row_ptr, col, val, s.n,
                      bcols, s.len, s.base, s.nch, s.slot, s.thr, s.col, s.val);
   return hipGetLastError();
