@@ -31,12 +31,26 @@ __global__ void k_csr_check(const int32_t* __restrict__ row_ptr, const int32_t* 
   if (tid == 0 && (row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz)) atomicOr(err, 1);
   for (int64_t i = tid; i < n; i += stride)
     if (row_ptr[i] > row_ptr[i + 1]) atomicOr(err, 2);
-  for (int64_t p = tid; p < nnz; p += stride) {
-    const int32_t j = col[p];
-    if (j < 0 || (int64_t)j >= n) {
-      atomicOr(err, 4);
-    } else {
-      dangling[j] = 0;
+  // every source in range, and a source with an out-link not dangling.  The flag is read
+  // before it is cleared: most links come from sources with many links, and a read that
+  // finds the flag already clear costs less than another byte write.  Each thread loads
+  // U links before it touches their flags, so that the flag reads overlap.
+  constexpr int U = 4;
+  for (int64_t p0 = tid; p0 < nnz; p0 += stride * U) {
+    int32_t j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t p = p0 + u * stride;
+      j[u] = p < nnz ? col[p] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (p0 + u * stride >= nnz) continue;
+      if (j[u] < 0 || (int64_t)j[u] >= n) {
+        atomicOr(err, 4);
+      } else if (dangling[j[u]]) {
+        dangling[j[u]] = 0;
+      }
     }
   }
 }

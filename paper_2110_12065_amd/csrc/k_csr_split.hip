@@ -270,44 +270,93 @@ k_split_hub_assign(const int32_t* __restrict__ deg, int64_t n, int64_t bcols, co
 }
 
 // Scatter every entry to its block's run: lane = row, block rows start at the chunk's
-// offset plus the wave's exclusive scan of the block-row lengths.
+// offset plus the wave's exclusive scan of the block-row lengths.  A chunk's entries of
+// one block form one contiguous range of colS / valS, so a wave assembles its chunk in
+// LDS (its eight ranges back to back) and then writes each range with coalesced stores;
+// a chunk with more than kScatterCap links writes its entries one by one.
+constexpr int kScatterCap = 1536;    // links of a chunk assembled in LDS (per wave)
 __global__ void __launch_bounds__(256)
 k_split_scatter(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const float* __restrict__ val,
                 int64_t n, int64_t bcols, const uint8_t* __restrict__ len, const int32_t* __restrict__ base,
                 int64_t nch, const int32_t* __restrict__ slot, const int32_t* __restrict__ thr,
                 int32_t* __restrict__ colS, float* __restrict__ valS) {
+  __shared__ int32_t lc[256 / kWave][kScatterCap];
+  __shared__ float lv[256 / kWave][kScatterCap];
   const float inv_bcols = 1.0f / (float)bcols;
-  const int lane = threadIdx.x & (kWave - 1);
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
   for (int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; c < nch; c += waves) {
     const int64_t i = c * kSplitChunk + lane;
-    int pos[kSplitBlocks];
+    int pos[kSplitBlocks], start[kSplitBlocks];
+    int tot = 0;                                 // the chunk's links (the same in every lane)
 #pragma unroll
     for (int k = 0; k < kSplitBlocks; ++k) {
       const int l = i < n ? (int)len[k * n + i] : 0;
-      pos[k] = base[k * nch + c] + wave_excl_scan(l);
+      const int ex = wave_excl_scan(l);
+      start[k] = tot;
+      pos[k] = ex;
+      tot += __builtin_amdgcn_readfirstlane(__shfl(ex + l, kWave - 1, kWave));
     }
-    if (i < n) {
-      const int32_t p1 = row_ptr[i + 1];
-      for (int32_t p = row_ptr[i]; p < p1; ++p) {
-        const int32_t j = col[p];
-        const int kb = block_of(j, (int32_t)bcols, inv_bcols);
-        int dst = 0;
+    const bool staged = tot <= kScatterCap;
 #pragma unroll
-        for (int k = 0; k < kSplitBlocks; ++k) {
-          if (kb == k) {
-            dst = pos[k];
-            pos[k] += 1;
-          }
+    for (int k = 0; k < kSplitBlocks; ++k) pos[k] += staged ? start[k] : base[k * nch + c];
+    // the lane's links: destination, stored source (~slot for a hub) and value.  Only a
+    // link whose own value ranks its source as a hub looks up the slot (a few thousand
+    // sources: the lookups stay in cache); a source without a slot is gathered from memory
+    auto link = [&](int32_t p, int* dst, int32_t* cv, float* hv) {
+      const int32_t j = col[p];
+      const int kb = block_of(j, (int32_t)bcols, inv_bcols);
+      int d = 0;
+#pragma unroll
+      for (int k = 0; k < kSplitBlocks; ++k) {
+        if (kb == k) {
+          d = pos[k];
+          pos[k] += 1;
         }
-        // only a link whose own value ranks its source as a hub looks up the slot (a few
-        // thousand sources: the lookups stay in cache); a source without a slot is
-        // gathered from memory
-        const float h = val[p];
-        const int32_t hs = degree_estimate(h) >= thr[kb] ? slot[j] : -1;
-        colS[dst] = hs >= 0 ? ~hs : j;
-        valS[dst] = h;
       }
+      const float h = val[p];
+      const int32_t hs = degree_estimate(h) >= thr[kb] ? slot[j] : -1;
+      *dst = d;
+      *cv = hs >= 0 ? ~hs : j;
+      *hv = h;
+    };
+    if (i < n) {
+      const int32_t p0 = row_ptr[i], p1 = row_ptr[i + 1];
+      int d;
+      int32_t cv;
+      float hv;
+      if (staged) {
+        for (int32_t p = p0; p < p1; ++p) {
+          link(p, &d, &cv, &hv);
+          lc[wv][d] = cv;
+          lv[wv][d] = hv;
+        }
+      } else {
+        for (int32_t p = p0; p < p1; ++p) {
+          link(p, &d, &cv, &hv);
+          colS[d] = cv;
+          valS[d] = hv;
+        }
+      }
+    }
+    if (staged) {
+      // the wave's LDS writes before its reads of other lanes' entries
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int k = 0; k < kSplitBlocks; ++k) {
+        const int kt = (k + 1 < kSplitBlocks ? start[k + 1] : tot) - start[k];
+        const int64_t b0 = base[k * nch + c];
+        for (int e = lane; e < kt; e += kWave) {
+          colS[b0 + e] = lc[wv][start[k] + e];
+          valS[b0 + e] = lv[wv][start[k] + e];
+        }
+      }
+      // every lane's LDS reads before the next chunk's writes
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
 }

@@ -95,6 +95,28 @@ def test_long_block_row_keeps_the_plain_product():
         assert rel_l1(a.cpu().numpy(), ref.w) <= TOL
 
 
+def test_chunk_larger_than_the_lds_assembly_buffer():
+    # rows 0..63 (one chunk of 64 rows) hold 30 links from each of the 8 source blocks:
+    # 15360 links in one chunk, more than the layout scatter assembles in LDS (1536), so
+    # its entries are written one by one, while every block row (30 links) stays short
+    # enough for the split layout; the other chunks take the LDS assembly
+    n = 4096
+    edges = [(k * 512 + (i * 13 + t * 17) % 512, i) for i in range(64) for k in range(8) for t in range(30)]
+    edges += [(j, (j * 7) % n) for j in range(n)]
+    g = synth.tiny_graph([(j, i) for j, i in edges if j != i], n)
+    assert int(g["row_ptr"][64]) > 1536
+    rp, col, val = _dev(g)
+    for f64 in (False, True):
+        for method in ("mapi", "rpi"):
+            a, _ = mp.mapi_pagerank(rp, col, val, 0.85, method, max_iters=6, f64=f64, ctx=_ctx(True))
+            b, _ = mp.mapi_pagerank(rp, col, val, 0.85, method, max_iters=6, f64=f64, ctx=_ctx(False))
+            ref = oracle.pagerank(n, g["row_ptr"], g["col"], g["val"], 0.85, method, synth.uniform_start(n), 6,
+                                  form="dense")
+            e, _ = report(f"pagerank split big chunk {method} f64={f64}", a.cpu().numpy(), ref.w)
+            assert e <= (1e-12 if f64 else TOL)
+            assert rel_l1(a.cpu().numpy(), b.cpu().numpy()) <= (1e-13 if f64 else 1e-6)
+
+
 def test_split_repeat_is_bitwise_deterministic():
     n = 20000
     g = synth.powerlaw_graph(n, seed=3)
